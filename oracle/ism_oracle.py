@@ -1,0 +1,717 @@
+"""Plain CPU oracle of the interpolated stencil multigrid (ISM) pressure solve.
+
+TEST INFRASTRUCTURE.  Only the test-suite, the package smoke check and the CPU-baseline
+leg of the benchmark may import this module.  The HIP library and its Python binding never
+call it and it calls nothing of theirs: the two share no code, tables or constants.
+
+Paper: G. Tegze and G. I. Toth, "A GPU cluster optimized multigrid scheme for computing
+unsteady incompressible fluid flow".  Every function names the passage it follows.  The
+pins that tie each function to something other than itself live in
+``tests/test_oracle_pins.py``; a function without such a pin says "parity unpinned".
+
+Conventions
+-----------
+* Fine grid of nx x ny cells of size h; arrays have shape (ny, nx): row j, column i,
+  0-based, i along x.  Batches are handled by the caller, one grid at a time.
+* ``laplacian`` is A' = h^2 A, the 5-point cell-centred Laplacian in difference form,
+  (A'p)_C = (p_W - p_C) + (p_E - p_C) + (p_S - p_C) + (p_N - p_C), summed in that order.
+  A wall neighbour (the "symmetric" boundary condition of Sec. 4.1, read as a homogeneous
+  Neumann wall) contributes no term; a periodic axis wraps.
+* The pressure equation of Eq. 4 is solved as A x = b~ with b~ = b - mean(b); the solution
+  returned is the zero-mean one (the constants span the null space on these grids).
+* Coarse grid: tiles of n x n fine cells (Sec. 4: one work-group per coarse cell), coarse
+  cell (J, I) covers rows nJ..nJ+n-1 and columns nI..nI+n-1; its centre is the tile centre
+  (Fig. 1).
+* Float arithmetic follows the dtype of the arrays passed in: float64 arrays give FP64
+  arithmetic, float32 arrays give FP32 arithmetic (used to emulate the FP32 inner solve).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.fft
+import scipy.sparse
+import scipy.sparse.linalg
+
+NEUMANN = "neumann"
+PERIODIC = "periodic"
+
+
+# --------------------------------------------------------------------------------------
+# Fine-grid operators (Sec. 2.3: staggered grid, five-point pressure Laplacian)
+# --------------------------------------------------------------------------------------
+
+def _neighbours(p, bc_x, bc_y):
+    """Values of the W, E, S, N neighbour of every cell and whether that neighbour exists.
+
+    A missing neighbour (behind a wall) has value 0 and ``present`` False."""
+    zero = np.zeros((), dtype=p.dtype)
+    out = {}
+    if bc_x == PERIODIC:
+        allp = np.ones(p.shape, dtype=bool)
+        out["W"] = (np.roll(p, 1, axis=1), allp)
+        out["E"] = (np.roll(p, -1, axis=1), allp)
+    else:
+        w = np.full_like(p, zero)
+        w[:, 1:] = p[:, :-1]
+        pw = np.zeros(p.shape, dtype=bool)
+        pw[:, 1:] = True
+        e = np.full_like(p, zero)
+        e[:, :-1] = p[:, 1:]
+        pe = np.zeros(p.shape, dtype=bool)
+        pe[:, :-1] = True
+        out["W"] = (w, pw)
+        out["E"] = (e, pe)
+    if bc_y == PERIODIC:
+        allp = np.ones(p.shape, dtype=bool)
+        out["S"] = (np.roll(p, 1, axis=0), allp)
+        out["N"] = (np.roll(p, -1, axis=0), allp)
+    else:
+        s = np.full_like(p, zero)
+        s[1:, :] = p[:-1, :]
+        ps = np.zeros(p.shape, dtype=bool)
+        ps[1:, :] = True
+        nn = np.full_like(p, zero)
+        nn[:-1, :] = p[1:, :]
+        pn = np.zeros(p.shape, dtype=bool)
+        pn[:-1, :] = True
+        out["S"] = (s, ps)
+        out["N"] = (nn, pn)
+    return out
+
+
+def laplacian(p, bc_x=NEUMANN, bc_y=NEUMANN):
+    """A'p: sum over existing neighbours of (p_nb - p_C), in the order W, E, S, N.
+
+    Sec. 2.3 (five-point Laplacian) and Sec. 3.3 (its finite-volume reading: a sum of face
+    fluxes; a wall face carries none).  Pinned by the closed-form eigenpairs of the
+    discrete Laplacian and by an independently assembled dense matrix."""
+    nb = _neighbours(p, bc_x, bc_y)
+    zero = np.zeros((), dtype=p.dtype)
+    d = {k: np.where(pres, val - p, zero) for k, (val, pres) in nb.items()}
+    return ((d["W"] + d["E"]) + d["S"]) + d["N"]
+
+
+def neighbour_count(nx, ny, bc_x=NEUMANN, bc_y=NEUMANN):
+    """m_C, the number of existing neighbours of each cell (the magnitude of A's diagonal)."""
+    m = np.full((ny, nx), 4, dtype=np.int64)
+    if bc_x != PERIODIC:
+        m[:, 0] -= 1
+        m[:, -1] -= 1
+    if bc_y != PERIODIC:
+        m[0, :] -= 1
+        m[-1, :] -= 1
+    return m
+
+
+def red_black_gs(p, rhs, bc_x=NEUMANN, bc_y=NEUMANN, sweeps=1):
+    """Red-black Gauss-Seidel sweeps on A'p = rhs (Sec. 3.1; used on the fine grid, Sec. 4).
+
+    A sweep updates the red cells ((i + j) even) and then the black cells.  A cell is set
+    so that its own equation holds: p_C = (sum of existing neighbour values - rhs_C) / m_C,
+    with the neighbour values summed in the order W, E, S, N and the division taken as a
+    product with 1/m_C rounded to the working precision.  No over-relaxation factor is
+    given in the paper; this is plain Gauss-Seidel.  Pinned by a cell-by-cell sequential
+    sweep in red-black order on tiny grids and by the fixed point being the exact
+    solution."""
+    p = np.array(p, copy=True)
+    rhs = np.asarray(rhs, dtype=p.dtype)
+    ny, nx = p.shape
+    m = neighbour_count(nx, ny, bc_x, bc_y)
+    inv_m = np.ones((), dtype=p.dtype) / m.astype(p.dtype)
+    jj, ii = np.indices((ny, nx))
+    red = (ii + jj) % 2 == 0
+    for _ in range(sweeps):
+        for colour in (red, ~red):
+            nb = _neighbours(p, bc_x, bc_y)
+            s = ((nb["W"][0] + nb["E"][0]) + nb["S"][0]) + nb["N"][0]
+            new = (s - rhs) * inv_m
+            p = np.where(colour, new, p)
+    return p
+
+
+# --------------------------------------------------------------------------------------
+# MAC divergence and gradient (Sec. 2.2 projection step, Sec. 2.3 staggered grid)
+# --------------------------------------------------------------------------------------
+
+def div(u, v, h, bc_x=NEUMANN):
+    """D[u; v]: cell divergence of face velocities, ((u_e - u_w) + (v_n - v_s)) / h.
+
+    u has shape (ny, nx+1) (or (ny, nx) when periodic in x), v has shape (ny+1, nx).
+    Pinned by the discrete divergence theorem and by D G = A."""
+    if bc_x == PERIODIC:
+        du = np.roll(u, -1, axis=1) - u
+    else:
+        du = u[:, 1:] - u[:, :-1]
+    dv = v[1:, :] - v[:-1, :]
+    return (du + dv) / h
+
+
+def grad(p, h, bc_x=NEUMANN, bc_y=NEUMANN):
+    """G p on the faces: (p_C - p_{west or south neighbour}) / h; zero on wall faces.
+
+    A wall face carries no pressure gradient, which is what makes D G equal to the
+    cell-centred Laplacian with homogeneous Neumann walls.  Pinned by D G = A."""
+    ny, nx = p.shape
+    if bc_x == PERIODIC:
+        gu = (p - np.roll(p, 1, axis=1)) / h
+    else:
+        gu = np.zeros((ny, nx + 1), dtype=p.dtype)
+        gu[:, 1:nx] = (p[:, 1:] - p[:, :-1]) / h
+    gv = np.zeros((ny + 1, nx), dtype=p.dtype)
+    if bc_y == PERIODIC:
+        raise NotImplementedError("v faces are stored with ny+1 rows; periodic y is not used")
+    gv[1:ny, :] = (p[1:, :] - p[:-1, :]) / h
+    return gu, gv
+
+
+def div_adjoint(lam, h, bc_x=NEUMANN):
+    """D^T lam, the transpose of ``div``: for an x-face f, (lam_{f-1} - lam_f) / h with the
+    term of a missing cell left out.  Pinned by the dot-product identity
+    <D w, lam> = <w, D^T lam>."""
+    ny, nx = lam.shape
+    if bc_x == PERIODIC:
+        gu = (np.roll(lam, 1, axis=1) - lam) / h
+    else:
+        gu = np.zeros((ny, nx + 1), dtype=lam.dtype)
+        gu[:, 1:] += lam
+        gu[:, :-1] -= lam
+        gu /= h
+    gv = np.zeros((ny + 1, nx), dtype=lam.dtype)
+    gv[1:, :] += lam
+    gv[:-1, :] -= lam
+    gv /= h
+    return gu, gv
+
+
+def grad_adjoint(gu, gv, h, bc_x=NEUMANN):
+    """G^T w, the transpose of ``grad``.  Pinned by <G p, w> = <p, G^T w>."""
+    ny = gv.shape[0] - 1
+    nx = gv.shape[1]
+    out = np.zeros((ny, nx), dtype=gv.dtype)
+    if bc_x == PERIODIC:
+        out += gu - np.roll(gu, -1, axis=1)
+    else:
+        out[:, 1:] += gu[:, 1:nx]
+        out[:, :-1] -= gu[:, 1:nx]
+    out[1:, :] += gv[1:ny, :]
+    out[:-1, :] -= gv[1:ny, :]
+    return out / h
+
+
+# --------------------------------------------------------------------------------------
+# Grid transfer (Sec. 3.3, Eq. 5)
+# --------------------------------------------------------------------------------------
+
+def restrict_sum(r, n):
+    """R r: the sum of the fine values over each n x n tile, in FP64.
+
+    Sec. 3.3: the coarse right-hand side is the sum of quantities already computed on the
+    fine grid (the agglomeration of ACM).  Pinned by conservation (sum R r = sum r) and by
+    brute force."""
+    ny, nx = r.shape
+    return np.asarray(r, dtype=np.float64).reshape(ny // n, n, nx // n, n).sum(axis=(1, 3))
+
+
+def _interp_axis(nf, n, bc):
+    """For every fine index along one axis: lower and upper coarse centre and the weight
+    of the upper one (Eq. 5 coordinates divided by the rectangle size).
+
+    The coarse centre I sits at fine coordinate n (I + 1/2); fine centre i sits at i + 1/2.
+    Between a wall and the first centre the rule is constant extrapolation (the interpolant
+    is held at the value of the nearest centre), so the rectangle is clamped."""
+    nc = nf // n
+    pos = (np.arange(nf) + 0.5) / n - 0.5
+    lo = np.floor(pos).astype(np.int64)
+    t = pos - lo
+    hi = lo + 1
+    if bc == PERIODIC:
+        lo %= nc
+        hi %= nc
+    else:
+        lo = np.clip(lo, 0, nc - 1)
+        hi = np.clip(hi, 0, nc - 1)
+    return lo, hi, t
+
+
+def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN):
+    """P E: bilinear interpolation of the coarse values to every fine cell centre.
+
+    Eq. 5 with origin at the south-west centre Q11 of the surrounding rectangle:
+    p = Q11 (1-x)(1-y) + Q21 x (1-y) + Q12 (1-x) y + Q22 x y in coordinates scaled by the
+    rectangle size; the same interpolation serves the coarse stencil and the prolongation
+    (Sec. 3.3).  Pinned by exactness on constants and bilinear fields, dyadic weights and
+    the coarse-stencil identities."""
+    ncy, ncx = E.shape
+    ilo, ihi, tx = _interp_axis(ncx * n, n, bc_x)
+    jlo, jhi, ty = _interp_axis(ncy * n, n, bc_y)
+    E = np.asarray(E, dtype=np.float64)
+    q11 = E[np.ix_(jlo, ilo)]
+    q21 = E[np.ix_(jlo, ihi)]
+    q12 = E[np.ix_(jhi, ilo)]
+    q22 = E[np.ix_(jhi, ihi)]
+    X = tx[None, :]
+    Y = ty[:, None]
+    return q11 * (1 - X) * (1 - Y) + q21 * X * (1 - Y) + q12 * (1 - X) * Y + q22 * X * Y
+
+
+def inject_constant(E, n):
+    """P0 E: piecewise-constant injection (ACM adds the coarse value to every fine cell of
+    its block, Sec. 3.2)."""
+    return np.kron(np.asarray(E, dtype=np.float64), np.ones((n, n)))
+
+
+# --------------------------------------------------------------------------------------
+# Coarse operators (Sec. 3.2 ACM agglomeration, Sec. 3.3 interpolated stencil)
+# --------------------------------------------------------------------------------------
+
+def _fold(C, ncx, ncy, bc_x, bc_y):
+    """Move the coefficient of an off-grid neighbour of a Neumann axis onto the unknown the
+    clamped interpolation actually used (the cell itself at a wall)."""
+    C = C.copy()
+    if bc_x != PERIODIC:
+        C[:, 0, :, 1] += C[:, 0, :, 0]
+        C[:, 0, :, 0] = 0.0
+        C[:, -1, :, 1] += C[:, -1, :, 2]
+        C[:, -1, :, 2] = 0.0
+    if bc_y != PERIODIC:
+        C[0, :, 1, :] += C[0, :, 0, :]
+        C[0, :, 0, :] = 0.0
+        C[-1, :, 1, :] += C[-1, :, 2, :]
+        C[-1, :, 2, :] = 0.0
+    return C
+
+
+def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
+    """The ISM coarse 9-point stencil, built by summing interpolated face fluxes.
+
+    Sec. 3.3, Eq. 6 and Eq. 7.  For every coarse cell the equation is the sum, over the
+    fine faces that lie on its four faces, of the outward pressure gradient of the
+    bilinear interpolant of the coarse unknowns (interior fine fluxes cancel in the sum).
+    On a face between centres I and I+1 in x, Eq. 6 gives for the fine row whose centre has
+    scaled offset y from the lower centre Q11:
+        dp/dx = ((Q21 - Q11)(1 - y) + (Q22 - Q12) y) / n      (in fine-cell units),
+    and Eq. 7 the same with x and y exchanged.  A wall face carries no flux.
+
+    Returns C with shape (ncy, ncx, 3, 3): C[J, I, dj+1, di+1] multiplies the unknown at
+    (J+dj, I+di) (wrapped on a periodic axis).  Pinned by the brute-force product R A' P,
+    the closed-form interior stencil 1/4 [[1,2,1],[2,-12,2],[1,2,1]] and the closed-form
+    eigenvalues."""
+    C = np.zeros((ncy, ncx, 3, 3))
+    J, I = np.indices((ncy, ncx))
+    half = n // 2
+
+    def add(mask, dj, di, val):
+        # val is an array over (J, I) or a scalar; the stencil entry gets it where mask holds
+        C[:, :, dj + 1, di + 1] += np.where(mask, val, 0.0)
+
+    east_open = (I < ncx - 1) | (bc_x == PERIODIC)
+    west_open = (I > 0) | (bc_x == PERIODIC)
+    north_open = (J < ncy - 1) | (bc_y == PERIODIC)
+    south_open = (J > 0) | (bc_y == PERIODIC)
+    for k in range(n):
+        # fine row nJ + k: lower interpolation centre J-1 (k < n/2) or J (k >= n/2)
+        lo_off = -1 if k < half else 0
+        y = (k + 0.5) / n - 0.5 - lo_off  # scaled offset from the lower centre
+        w_lo, w_hi = (1.0 - y) / n, y / n
+        for sign, mask, d_lo in ((+1.0, east_open, 0), (-1.0, west_open, -1)):
+            # face between centres I + d_lo and I + d_lo + 1; outward sign +1 east, -1 west
+            add(mask, lo_off, d_lo + 1, sign * w_lo)
+            add(mask, lo_off, d_lo, -sign * w_lo)
+            add(mask, lo_off + 1, d_lo + 1, sign * w_hi)
+            add(mask, lo_off + 1, d_lo, -sign * w_hi)
+        # fine column nI + k on the north and south faces (Eq. 7)
+        x = y
+        w_lo, w_hi = (1.0 - x) / n, x / n
+        for sign, mask, d_lo in ((+1.0, north_open, 0), (-1.0, south_open, -1)):
+            add(mask, d_lo + 1, lo_off, sign * w_lo)
+            add(mask, d_lo, lo_off, -sign * w_lo)
+            add(mask, d_lo + 1, lo_off + 1, sign * w_hi)
+            add(mask, d_lo, lo_off + 1, -sign * w_hi)
+    return _fold(C, ncx, ncy, bc_x, bc_y)
+
+
+def coarse_stencil_acm(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
+    """ACM coarse stencil: the sum of the fine equations of a block with the pressure
+    assumed constant over each coarse cell (Sec. 3.2; Sec. 3.3 contrasts it with ISM).
+
+    Each of the n fine faces on a coarse face then carries E_nb - E_C, so the result is n
+    times the 5-point stencil (Sec. 4: summing fine equations gives a 5-point stencil).
+    Pinned by the brute-force product R A' P0."""
+    C = np.zeros((ncy, ncx, 3, 3))
+    J, I = np.indices((ncy, ncx))
+    opens = {
+        (0, 1): (I < ncx - 1) | (bc_x == PERIODIC),
+        (0, -1): (I > 0) | (bc_x == PERIODIC),
+        (1, 0): (J < ncy - 1) | (bc_y == PERIODIC),
+        (-1, 0): (J > 0) | (bc_y == PERIODIC),
+    }
+    for (dj, di), mask in opens.items():
+        for _ in range(n):  # one flux per fine face on the coarse face
+            C[:, :, dj + 1, di + 1] += np.where(mask, 1.0, 0.0)
+            C[:, :, 1, 1] -= np.where(mask, 1.0, 0.0)
+    return C
+
+
+def coarse_stencil_gmg5(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
+    """Aggressive-coarsening GMG variant: the 5-point stencil rediscretized at spacing nh
+    (Sec. 3.2 GMG; Sec. 4.3.2 compares ISM with this "five point coarse grid stencil").
+    With the restriction summing h^2-scaled residuals, the coarse equation in the same
+    units has unit coefficients.  Parity unpinned beyond its structure (a reading)."""
+    return coarse_stencil_acm(ncx, ncy, 1, bc_x, bc_y)
+
+
+def coarse_matrix(C, bc_x=NEUMANN, bc_y=NEUMANN):
+    """Sparse matrix of a (ncy, ncx, 3, 3) stencil; unknown (J, I) has index J*ncx + I."""
+    ncy, ncx = C.shape[:2]
+    rows, cols, vals = [], [], []
+    J, I = np.indices((ncy, ncx))
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            c = C[:, :, dj + 1, di + 1]
+            jj = J + dj
+            ii = I + di
+            if bc_y == PERIODIC:
+                jj %= ncy
+            if bc_x == PERIODIC:
+                ii %= ncx
+            ok = (c != 0.0) & (jj >= 0) & (jj < ncy) & (ii >= 0) & (ii < ncx)
+            rows.append((J * ncx + I)[ok])
+            cols.append((jj * ncx + ii)[ok])
+            vals.append(c[ok])
+    N = ncx * ncy
+    return scipy.sparse.csr_matrix(
+        (np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+class CoarseSolver:
+    """Exact zero-mean solve of A_c E = R_c (the limit of the paper's coarse iterations to a
+    vanishing tolerance; a direct solve on the coarsest grid, Sec. 3.2).
+
+    The singular system is bordered with the constraint sum(E) = 0 and factorized once by
+    sparse LU (a library primitive).  The bordered solve returns the E that satisfies
+    A_c E = R_c - mean(R_c), the same projection as dropping the constant mode.  The
+    paper's host-side Gauss-Seidel to a tolerance is `gauss_seidel`."""
+
+    def __init__(self, Ac):
+        N = Ac.shape[0]
+        ones = np.ones((N, 1))
+        K = scipy.sparse.bmat([[Ac, ones], [ones.T, None]], format="csc")
+        self.N = N
+        self.Ac = Ac.tocsr()
+        self.lu = scipy.sparse.linalg.splu(K)
+
+    def solve(self, Rc):
+        shape = Rc.shape
+        rhs = np.concatenate([np.asarray(Rc, dtype=np.float64).ravel(), [0.0]])
+        return self.lu.solve(rhs)[: self.N].reshape(shape)
+
+    def gauss_seidel(self, Rc, E0=None, tol_c=1e-6, max_iter=100000):
+        """Lexicographic Gauss-Seidel on A_c E = R_c until the absolute maximum residual is
+        below tol_c (Sec. 4: block-iterative GS on the host, which reduces to serial GS on
+        one node; Sec. 4.3.1 accommodative criterion).  Returns (E, iterations).  Parity
+        unpinned (an option of the oracle, not used by the library)."""
+        A = self.Ac
+        b = np.asarray(Rc, dtype=np.float64).ravel()
+        b = b - b.mean()
+        E = np.zeros_like(b) if E0 is None else np.asarray(E0, dtype=np.float64).ravel().copy()
+        L = scipy.sparse.tril(A, format="csr")
+        U = A - L
+        it = 0
+        while np.max(np.abs(b - A @ E)) >= tol_c and it < max_iter:
+            E = scipy.sparse.linalg.spsolve_triangular(L, b - U @ E, lower=True)
+            it += 1
+        return E.reshape(Rc.shape) - E.mean(), it
+
+
+# --------------------------------------------------------------------------------------
+# The exact discrete solution x* (what every solver must converge to)
+# --------------------------------------------------------------------------------------
+
+def laplacian_eigenvalues(nf, bc):
+    """Eigenvalues of the 1D three-point operator with the given boundary condition, in the
+    order of the DCT-II (Neumann) or FFT (periodic) basis: -4 sin^2(pi k / (2 nf)) and
+    -4 sin^2(pi k / nf) respectively."""
+    k = np.arange(nf)
+    if bc == PERIODIC:
+        return -4.0 * np.sin(np.pi * k / nf) ** 2
+    return -4.0 * np.sin(np.pi * k / (2.0 * nf)) ** 2
+
+
+def _spectral_solve(f, bc_x, bc_y):
+    """Zero-mean solution of A'x = f by diagonalizing A' (DCT-II on Neumann axes, FFT on
+    periodic ones)."""
+    ny, nx = f.shape
+    lam = laplacian_eigenvalues(ny, bc_y)[:, None] + laplacian_eigenvalues(nx, bc_x)[None, :]
+    lam[0, 0] = 1.0
+    if bc_x == PERIODIC and bc_y == PERIODIC:
+        fh = np.fft.fft2(f)
+        fh /= lam
+        fh[0, 0] = 0.0
+        return np.fft.ifft2(fh).real
+    if bc_x == PERIODIC:
+        fh = np.fft.fft(scipy.fft.dct(f, type=2, norm="ortho", axis=0), axis=1)
+        fh /= lam
+        fh[0, 0] = 0.0
+        return scipy.fft.idct(np.fft.ifft(fh, axis=1).real, type=2, norm="ortho", axis=0)
+    fh = scipy.fft.dctn(f, type=2, norm="ortho")
+    fh /= lam
+    fh[0, 0] = 0.0
+    return scipy.fft.idctn(fh, type=2, norm="ortho")
+
+
+def exact_solve(b, h, bc_x=NEUMANN, bc_y=NEUMANN, refine=2):
+    """x*: the zero-mean solution of A x = b - mean(b), by spectral diagonalization followed
+    by `refine` steps of FP64 iterative refinement with the difference-form residual.
+
+    Pinned by dense direct solves on small grids and by its residual."""
+    b = np.asarray(b, dtype=np.float64)
+    bp = h * h * (b - b.mean())
+    x = _spectral_solve(bp, bc_x, bc_y)
+    for _ in range(refine):
+        x = x + _spectral_solve(bp - laplacian(x, bc_x, bc_y), bc_x, bc_y)
+    return x - x.mean()
+
+
+def dense_laplacian(nx, ny, bc_x=NEUMANN, bc_y=NEUMANN):
+    """The matrix of A' assembled cell by cell from the neighbour lists (tiny grids)."""
+    N = nx * ny
+    A = np.zeros((N, N))
+    for j in range(ny):
+        for i in range(nx):
+            c = j * nx + i
+            for dj, di in ((0, -1), (0, 1), (-1, 0), (1, 0)):
+                jj, ii = j + dj, i + di
+                if bc_x == PERIODIC:
+                    ii %= nx
+                if bc_y == PERIODIC:
+                    jj %= ny
+                if 0 <= ii < nx and 0 <= jj < ny:
+                    A[c, jj * nx + ii] += 1.0
+                    A[c, c] -= 1.0
+    return A
+
+
+def dense_solve(b, h, bc_x=NEUMANN, bc_y=NEUMANN):
+    """x* on a tiny grid by a dense solve of the system bordered with sum(x) = 0."""
+    ny, nx = b.shape
+    A = dense_laplacian(nx, ny, bc_x, bc_y)
+    N = nx * ny
+    K = np.zeros((N + 1, N + 1))
+    K[:N, :N] = A
+    K[:N, N] = 1.0
+    K[N, :N] = 1.0
+    rhs = np.zeros(N + 1)
+    bb = np.asarray(b, dtype=np.float64)
+    rhs[:N] = (h * h * (bb - bb.mean())).ravel()
+    return np.linalg.solve(K, rhs)[:N].reshape(ny, nx)
+
+
+def relative_residual(b, x, h, bc_x=NEUMANN, bc_y=NEUMANN):
+    """||b~ - A x||_2 / ||b~||_2 with b~ = b - mean(b), residual in difference form (FP64)."""
+    b = np.asarray(b, dtype=np.float64)
+    bp = h * h * (b - b.mean())
+    r = bp - laplacian(np.asarray(x, dtype=np.float64), bc_x, bc_y)
+    return float(np.linalg.norm(r) / np.linalg.norm(bp))
+
+
+# --------------------------------------------------------------------------------------
+# The ISM two-level cycle (Sec. 3.3 stencil, Sec. 3.4 sparse V cycle, Sec. 4.3.1 cycling)
+# --------------------------------------------------------------------------------------
+
+def _stencil(kind, ncx, ncy, n, bc_x, bc_y):
+    return {"ism": coarse_stencil_ism, "acm": coarse_stencil_acm,
+            "gmg5": coarse_stencil_gmg5}[kind](ncx, ncy, n, bc_x, bc_y)
+
+
+def _prolong(kind, E, n, bc_x, bc_y):
+    return inject_constant(E, n) if kind == "acm" else prolong_bilinear(E, n, bc_x, bc_y)
+
+
+def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
+              max_cycles=100000, stencil="ism", coarse_tol=None):
+    """FP64 two-level ISM solve of A x = b - mean(b).
+
+    Sec. 3.4 (Fig. 2b): the fine grid is coupled directly to the n x n coarse grid.  Each
+    cycle: restrict the fine residual by tile sums, solve the coarse equations built with
+    the interpolated stencil, prolongate bilinearly and add (Sec. 3.3), then `nu` red-black
+    Gauss-Seidel sweeps on the fine grid (Sec. 4).  The order (coarse first, then fine
+    smoothing) is the paper's accommodative cycling (Sec. 4.3.1); here the coarse problem
+    is solved exactly (or, with coarse_tol, by Gauss-Seidel to that absolute tolerance) and
+    the fine stage has a fixed number of sweeps, repeated until
+    ||b~ - A x|| <= rtol ||b~||.  stencil="acm" or "gmg5" swaps the coarse operator (and,
+    for ACM, the prolongation) for the comparison schemes.
+
+    Returns (x, info) with x zero-mean and info = dict(cycles, sweeps, history)."""
+    b = np.asarray(b, dtype=np.float64)
+    ny, nx = b.shape
+    bp = h * h * (b - b.mean())
+    x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    ncx, ncy = nx // n, ny // n
+    cs = CoarseSolver(coarse_matrix(_stencil(stencil, ncx, ncy, n, bc_x, bc_y), bc_x, bc_y))
+    bnorm = np.linalg.norm(bp)
+    r = bp - laplacian(x, bc_x, bc_y)
+    hist = [float(np.linalg.norm(r) / bnorm)]
+    cycles = 0
+    while hist[-1] > rtol and cycles < max_cycles:
+        Rc = restrict_sum(r, n)
+        if coarse_tol is None:
+            E = cs.solve(Rc)
+        else:
+            E, _ = cs.gauss_seidel(Rc, tol_c=coarse_tol)
+        x = x + _prolong(stencil, E, n, bc_x, bc_y)
+        x = red_black_gs(x, bp, bc_x, bc_y, sweeps=nu)
+        r = bp - laplacian(x, bc_x, bc_y)
+        cycles += 1
+        hist.append(float(np.linalg.norm(r) / bnorm))
+    return x - x.mean(), dict(cycles=cycles, sweeps=cycles * nu, history=hist)
+
+
+def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
+                    inner_rtol=1e-3, stall_window=8, stall_drop=0.01, max_inner=100000,
+                    max_outer=50):
+    """ISM with FP32 fine arithmetic inside an FP64 defect-correction loop (emulated).
+
+    Not in the paper (its solver is FP32 throughout, Sec. 4.2).  Outer step in FP64:
+    r = b' - A'x; stop if ||r|| <= rtol ||b'||.  Inner solve of A'e = r from e = 0: the fine
+    arrays e and r32 = fp32(r) and every fine operation are FP32; restriction sums, the
+    coarse solve and the bilinear interpolation are FP64, the interpolated correction is
+    added to e in FP64 and rounded to FP32.  The first restriction sums the FP64 r.  The
+    inner loop stops when ||r32 - A'e|| <= max(inner_rtol ||r||, rtol ||b'|| / 2), or when
+    the residual fell by less than stall_drop over the last stall_window cycles, or at
+    max_inner.  Then x += e in FP64.  Returns (x, info)."""
+    b = np.asarray(b, dtype=np.float64)
+    ny, nx = b.shape
+    bp = h * h * (b - b.mean())
+    x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    ncx, ncy = nx // n, ny // n
+    cs = CoarseSolver(coarse_matrix(coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y), bc_x, bc_y))
+    bnorm = np.linalg.norm(bp)
+    outer_hist, cycles, outer = [], 0, 0
+    while True:
+        r = bp - laplacian(x, bc_x, bc_y)
+        rnorm = np.linalg.norm(r)
+        outer_hist.append(float(rnorm / bnorm))
+        if rnorm <= rtol * bnorm or outer >= max_outer:
+            break
+        outer += 1
+        target = max(inner_rtol * rnorm, 0.5 * rtol * bnorm)
+        r32 = r.astype(np.float32)
+        Rc = restrict_sum(r, n)
+        e = np.zeros_like(r32)
+        inner_hist = []
+        for _ in range(max_inner):
+            E = cs.solve(Rc)
+            e = (e.astype(np.float64) + prolong_bilinear(E, n, bc_x, bc_y)).astype(np.float32)
+            e = red_black_gs(e, r32, bc_x, bc_y, sweeps=nu)
+            res = r32 - laplacian(e, bc_x, bc_y)
+            res64 = res.astype(np.float64)
+            Rc = restrict_sum(res64, n)
+            cycles += 1
+            inner_hist.append(float(np.linalg.norm(res64)))
+            if inner_hist[-1] <= target:
+                break
+            if (len(inner_hist) > stall_window
+                    and inner_hist[-1] > (1.0 - stall_drop) * inner_hist[-1 - stall_window]):
+                break
+        x = x + e.astype(np.float64)
+    return x - x.mean(), dict(cycles=cycles, sweeps=cycles * nu, outer=outer,
+                              history=outer_hist)
+
+
+# --------------------------------------------------------------------------------------
+# ACM V(0,1) with a 2h hierarchy (Sec. 3.2, Sec. 4, Sec. 4.3.1)
+# --------------------------------------------------------------------------------------
+
+def acm_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, rtol=1e-10, x0=None, max_cycles=100000):
+    """Additive correction multigrid with 2x2 agglomeration down to spacing n h.
+
+    Sec. 3.2: coarse equations are sums of fine equations and the coarse result is added
+    to the fine solution without interpolation; Sec. 4: red-black GS on every level; Sec.
+    4.3.1: V cycles without pre-smoothing and one post-smoothing per level.  Summing the
+    2x2 fine equations of a 5-point operator gives twice the 5-point operator, so level l
+    (spacing 2^l h) carries 2^l A'.  The coarsest level is solved exactly (zero mean).
+    Launch count per cycle as a GPU implementation would issue them: per non-coarsest level
+    one residual+restriction, one correction and one fused sweep, plus the coarsest solve.
+    Returns (x, info)."""
+    b = np.asarray(b, dtype=np.float64)
+    ny, nx = b.shape
+    L = int(round(math.log2(n)))
+    bp = h * h * (b - b.mean())
+    x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    cs = CoarseSolver(coarse_matrix(coarse_stencil_acm(nx // n, ny // n, n, bc_x, bc_y),
+                                    bc_x, bc_y))
+
+    def vcycle(level, e, r):
+        scale = float(2 ** level)
+        if level == L:
+            return cs.solve(r)
+        res = r - scale * laplacian(e, bc_x, bc_y)
+        ec = vcycle(level + 1, np.zeros((e.shape[0] // 2, e.shape[1] // 2)), restrict_sum(res, 2))
+        e = e + inject_constant(ec, 2)
+        return red_black_gs(e, r / scale, bc_x, bc_y, sweeps=1)
+
+    bnorm = np.linalg.norm(bp)
+    hist = [float(np.linalg.norm(bp - laplacian(x, bc_x, bc_y)) / bnorm)]
+    cycles = 0
+    while hist[-1] > rtol and cycles < max_cycles:
+        x = vcycle(0, x, bp)
+        cycles += 1
+        hist.append(float(np.linalg.norm(bp - laplacian(x, bc_x, bc_y)) / bnorm))
+    launches = cycles * (3 * L + 1)
+    return x - x.mean(), dict(cycles=cycles, sweeps=cycles, launches=launches, history=hist,
+                              levels=L)
+
+
+# --------------------------------------------------------------------------------------
+# Dense analysis on tiny grids
+# --------------------------------------------------------------------------------------
+
+def _columns(fn, ncols, shape):
+    cols = []
+    for k in range(ncols):
+        e = np.zeros(ncols)
+        e[k] = 1.0
+        cols.append(np.asarray(fn(e.reshape(shape)), dtype=np.float64).ravel())
+    return np.array(cols).T
+
+
+def transfer_matrices(nx, ny, n, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
+    """Dense R (Nc x N), P (N x Nc) and A' (N x N) built by applying the oracle's own
+    functions to unit vectors."""
+    ncx, ncy = nx // n, ny // n
+    R = _columns(lambda f: restrict_sum(f, n), nx * ny, (ny, nx))
+    P = _columns(lambda E: _prolong(kind, E, n, bc_x, bc_y), ncx * ncy, (ncy, ncx))
+    A = _columns(lambda f: laplacian(f, bc_x, bc_y), nx * ny, (ny, nx))
+    return R, P, A
+
+
+def two_grid_matrix(nx, ny, n, nu, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
+    """Error propagation of one cycle, T = S^nu (I - P A_c^+ R A'), on the zero-mean
+    subspace (tiny grids).  S is the red-black sweep applied to errors (zero right-hand
+    side)."""
+    R, P, A = transfer_matrices(nx, ny, n, bc_x, bc_y, kind)
+    C = _stencil(kind, nx // n, ny // n, n, bc_x, bc_y)
+    Ac = coarse_matrix(C, bc_x, bc_y).toarray()
+    N = nx * ny
+    S = _columns(lambda f: red_black_gs(f, np.zeros_like(f), bc_x, bc_y, 1), N, (ny, nx))
+    K = np.eye(N) - P @ np.linalg.pinv(Ac) @ R @ A
+    T = np.linalg.matrix_power(S, nu) @ K
+    Pi = np.eye(N) - np.ones((N, N)) / N
+    return Pi @ T @ Pi
+
+
+# --------------------------------------------------------------------------------------
+# Cost accounting (Sec. 4.3)
+# --------------------------------------------------------------------------------------
+
+def cost_metrics(ncc_f, ncc_c, n):
+    """The paper's per-step cost figures from its synchronization counts (Sec. 4.3).
+
+    A fine red-black GS iteration needs two synchronizations (one per colour) and costs one
+    Laplacian per fine control volume; a coarse Gauss-Seidel iteration needs one
+    synchronization and costs 1/n^2 Laplacians per fine control volume, since the coarse
+    grid has n^2 times fewer cells.  Hence NCC_t = NCC_f + NCC_c and
+    N_Lap = NCC_f / 2 + NCC_c / n^2.  Pinned by the counts printed in Tables A.1 and A.3."""
+    return dict(ncc_t=ncc_f + ncc_c, n_lap=ncc_f / 2.0 + ncc_c / float(n * n))
