@@ -1,0 +1,178 @@
+/*
+ * ism.h - C ABI of the interpolated stencil multigrid (ISM) pressure-Poisson solver for
+ * MI355X (gfx950).
+ *
+ * The method is the two-level cycle of Tegze & Toth, "A GPU cluster optimized multigrid
+ * scheme for computing unsteady incompressible fluid flow": red-black Gauss-Seidel on the
+ * fine grid (Sec. 3.1, Sec. 4), restriction by sums over n x n tiles (Sec. 3.3), a coarse
+ * grid whose 9-point stencil is built from the bilinear interpolant of the coarse unknowns
+ * (Sec. 3.3, Eq. 5-7), bilinear prolongation (Sec. 3.3) and the sparse two-level V cycle
+ * (Sec. 3.4, Fig. 2b).
+ *
+ * Problem.  The pressure equation of the projection step (Sec. 2.2, Eq. 4) on a cell-centred
+ * nx x ny grid with square cells of size h = lx/nx = ly/ny, discretized with the 5-point
+ * Laplacian (Sec. 2.3): A x = b~, with (A x)_C = sum over existing neighbours of
+ * (x_nb - x_C) / h^2 and b~ = b - mean(b).  Walls are the paper's "symmetric" condition
+ * read as homogeneous Neumann (no flux through the wall face); an axis can instead be
+ * periodic (Sec. 4.1 lists both).  The returned x is the zero-mean solution.
+ *
+ * Conventions for every entry point.
+ *  - All array arguments are DEVICE pointers (HIP global memory), C-contiguous row-major
+ *    [batch][ny][nx] with x fastest; the caller owns them and they stay valid until the
+ *    call returns.  Staggered (MAC) face arrays: u is [batch][ny][nx+1] ([batch][ny][nx]
+ *    when periodic in x; face i is the west face of cell i), v is [batch][ny+1][nx] (face j
+ *    is the south face of cell j).
+ *  - Every device operation is ordered on the HIP stream given to ism_create.  ism_solve
+ *    and ism_solve_adjoint return after their last host synchronization, so their outputs
+ *    are ready; every other entry point only enqueues work.
+ *  - Return value: ISM_OK (0), ISM_NOT_CONVERGED (+1, a warning: x holds the last iterate),
+ *    or a negative error code.  Arguments are validated before any device call; no C++
+ *    exception crosses this interface.  ism_last_error() gives the text of the last error
+ *    of a handle (NULL handle: of the last failed ism_create on this thread).
+ *  - A handle is not thread-safe; independent handles are.
+ */
+#ifndef ISM_H
+#define ISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISM_OK 0
+#define ISM_NOT_CONVERGED 1
+#define ISM_ERR_INVALID (-1)     /* null pointer, non-positive size, bad enum value       */
+#define ISM_ERR_UNSUPPORTED (-2) /* nx or ny not a multiple of coarsen, lx/nx != ly/ny   */
+#define ISM_ERR_HIP (-3)         /* a HIP runtime call failed; see ism_last_error        */
+#define ISM_ERR_NONFINITE (-4)   /* NaN or Inf met in b or during the iteration          */
+
+#define ISM_BC_NEUMANN 0  /* wall: no flux across the boundary face ("symmetric", Sec. 4.1) */
+#define ISM_BC_PERIODIC 1 /* the axis wraps (Sec. 4.1)                                       */
+
+#define ISM_PREC_FP64 0  /* every fine-grid operation in FP64                                */
+#define ISM_PREC_MIXED 1 /* FP32 smoothing, restriction and prolongation inside an FP64
+                            defect-correction loop; outer residual, mean removal, the
+                            coarse solve and the update of x stay FP64                     */
+
+#define ISM_F64 0 /* element type selector of the stage entry points: double */
+#define ISM_F32 1 /*                                                  float  */
+
+typedef struct ism_ctx* ism_handle;
+
+typedef struct {
+  int32_t nx, ny;     /* fine cells along x and y (>= 2 * coarsen each)                     */
+  int32_t batch;      /* independent grids solved together (>= 1)                           */
+  int32_t bc_x, bc_y; /* ISM_BC_* on the x faces (west/east) and the y faces (south/north)   */
+  int32_t coarsen;    /* tile edge n of the n x n restriction: 4, 8, 16 or 32 (Sec. 3.4);
+                         nx and ny must be multiples of it                                  */
+  double lx, ly;      /* domain size; lx/nx must equal ly/ny (square cells)                 */
+  int32_t precision;  /* ISM_PREC_*                                                         */
+  int32_t nu;         /* red-black sweeps per cycle after the coarse correction (>= 1)      */
+  double rtol;        /* stop when ||b~ - A x||_2 <= rtol ||b~||_2 for every grid            */
+  double inner_rtol;  /* mixed form: an inner FP32 solve stops once its residual fell by
+                         this factor (or stagnated)                                         */
+  int32_t max_cycles; /* cap on two-level cycles per solve (all inner solves together)      */
+  int32_t max_outer;  /* cap on FP64 defect-correction steps                                */
+  int32_t check_every;/* cycles between convergence checks; 0 = adaptive (predicts the
+                         cycle that meets the target from the measured rate)               */
+  int32_t fused;      /* 1: one fused kernel per cycle (prolongation, nu sweeps, residual
+                         and restriction); 0: one kernel per step                          */
+} ism_config;
+
+typedef struct {
+  int32_t status;      /* return code of the solve                                          */
+  int32_t outer_iters; /* FP64 defect-correction steps taken                                */
+  int32_t cycles;      /* two-level cycles (coarse solve + prolongation + nu sweeps)        */
+  int32_t sweeps;      /* red-black sweeps = cycles * nu                                    */
+  int64_t launches;    /* kernels launched                                                  */
+  int64_t host_syncs;  /* device-to-host reads the host waited for                          */
+  double rel_res_l2;   /* max over the batch of ||b~ - A x||_2 / ||b~||_2 (FP64, difference
+                          form), measured before the final mean removal                     */
+  double rel_res_max;  /* max over the batch of max|b~ - A x| / max|b~|                     */
+  double seconds;      /* wall time of the call                                              */
+} ism_stats;
+
+/* Fill cfg with defaults for an nx x ny grid of unit cell size 1/nx (unit square), Neumann
+ * walls, coarsen 16, FP64, nu 2, rtol 1e-10, inner_rtol 1e-3, adaptive checks, fused. */
+int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch);
+
+/* Validate cfg, allocate the handle's device workspace and build the coarse tables
+ * (the 1D factors of the coarse operator and their eigenbases).  stream is a hipStream_t
+ * (NULL: the default stream).  On success *out owns device memory until ism_destroy. */
+int ism_create(const ism_config* cfg, void* stream, ism_handle* out);
+
+/* Synchronize the stream and release everything the handle owns.  NULL is accepted. */
+int ism_destroy(ism_handle h);
+
+/* Bytes of device memory the handle holds. */
+int ism_workspace_bytes(ism_handle h, size_t* bytes);
+
+/* Solve A x = b - mean(b) for every grid of the batch (Sec. 3.4 sparse two-level cycle,
+ * Sec. 4.3.1 cycling: coarse correction first, then nu fine sweeps, repeated).  b: FP64
+ * [batch][ny][nx], read only.  x: FP64 [batch][ny][nx], initial guess on entry (warm start),
+ * zero-mean solution on return.  st may be NULL. */
+int ism_solve(ism_handle h, const double* b, double* x, ism_stats* st);
+
+/* Adjoint solve A^T lam = g - mean(g).  A is symmetric for these boundary conditions, so
+ * this is the same solve; it exists so that a differentiable projection names its
+ * backward pass.  Same layouts and ownership as ism_solve. */
+int ism_solve_adjoint(ism_handle h, const double* g, double* lam, ism_stats* st);
+
+/* Staggered-grid operators of the projection step (Sec. 2.2, Sec. 2.3), FP64:
+ *   ism_div:          b = D[u; v],  b_C = ((u_e - u_w) + (v_n - v_s)) / h
+ *   ism_grad:         [gu; gv] = G p, gradient on faces, zero on wall faces, so D G = A
+ *   ism_div_adjoint:  [gu; gv] = D^T lam
+ *   ism_grad_adjoint: p = G^T [gu; gv]
+ * Layouts as above; outputs are overwritten. */
+int ism_div(ism_handle h, const double* u, const double* v, double* b);
+int ism_grad(ism_handle h, const double* p, double* gu, double* gv);
+int ism_div_adjoint(ism_handle h, const double* lam, double* gu, double* gv);
+int ism_grad_adjoint(ism_handle h, const double* gu, const double* gv, double* p);
+
+/* ---- Stage entry points: one step of the cycle each, for step-by-step verification.
+ * Fine arrays have the element type selected by dtype (ISM_F64 / ISM_F32) and layout
+ * [batch][ny][nx]; coarse arrays are FP64 [batch][ny/n][nx/n].  rhs is in h^2 units
+ * (the equation solved is A' e = rhs with A' = h^2 A). */
+
+/* nsweeps red-black Gauss-Seidel sweeps on A' e = rhs, red ((i + j) even) first; each cell
+ * takes the value that satisfies its own equation (Sec. 3.1). */
+int ism_smooth(ism_handle h, int32_t dtype, const void* rhs, void* e, int32_t nsweeps);
+
+/* rc = R (rhs - A' e): fine residual summed over every n x n tile (Sec. 3.3).  If sumsq is
+ * not NULL, sumsq[g] = sum of the squared residual of grid g (FP64). */
+int ism_restrict(ism_handle h, int32_t dtype, const void* rhs, const void* e, double* rc,
+                 double* sumsq);
+
+/* e += P E: bilinear interpolation of the coarse values to the fine cell centres (Eq. 5),
+ * constant extrapolation between a wall and the first coarse centre. */
+int ism_prolong(ism_handle h, int32_t dtype, const double* E, void* e);
+
+/* E = zero-mean solution of A_c E = rc - mean(rc) on each grid's coarse grid, where A_c is
+ * the interpolated 9-point stencil (Sec. 3.3, Eq. 6-7).  Exact up to FP64 rounding. */
+int ism_coarse_solve(ism_handle h, const double* rc, double* E);
+
+/* One two-level cycle on A' e = rhs: E = coarse solve of rc; e += P E; nsweeps red-black
+ * sweeps; rc = R (rhs - A' e) (rc is read and then overwritten).  With zero_e != 0 the
+ * incoming e is taken as zero.  Uses the fused kernel if the handle was created fused. */
+int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
+              int32_t zero_e, double* sumsq);
+
+/* The coarse 9-point stencil assembled on the device from the face sums of Eq. 6-7:
+ * coef is FP64 [ny/n][nx/n][9]; entry 3*(dj+1) + (di+1) multiplies the unknown at
+ * (J+dj, I+di) (wrapped on a periodic axis; a wall contribution is folded onto the unknown
+ * the clamped interpolation uses). */
+int ism_coarse_stencil(ism_handle h, double* coef);
+
+/* r = h^2 (b - mean(b)) - A' x in FP64 for every grid (the outer defect-correction
+ * residual, difference form). */
+int ism_outer_residual(ism_handle h, const double* b, const double* x, double* r);
+
+const char* ism_status_string(int status);
+const char* ism_last_error(ism_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISM_H */

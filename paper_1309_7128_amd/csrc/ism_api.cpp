@@ -1,0 +1,675 @@
+// Host side of the ISM library: the C ABI of include/ism.h, argument validation, the
+// device workspace, the coarse tables and the outer/inner iteration that strings the
+// kernels together.  Every device operation is enqueued on the handle's stream; the host
+// waits only for the few FP64 scalars that decide convergence.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ism.h"
+#include "ism_internal.h"
+
+using ism::Geo;
+using ism::Partials;
+
+namespace {
+
+// Slots of the per-grid device scalars; the array is slot-major, [kSlots][batch].
+enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, kSlots };
+
+thread_local std::string g_create_error;
+
+constexpr double kInnerMargin = 0.5;  // FP64 inner target = margin * rtol * ||b'||
+constexpr int kStallWindow = 8;       // cycles over which an inner residual must fall ...
+constexpr double kStallDrop = 0.01;   // ... by at least this fraction
+
+}  // namespace
+
+struct ism_ctx {
+  ism_config cfg{};
+  hipStream_t stream = nullptr;
+  Geo g{};
+  double h = 0.0, h2 = 0.0;
+  size_t tsize = 8;  // bytes per element of the inner fine arrays
+  // device memory (one allocation)
+  char* block = nullptr;
+  size_t bytes = 0;
+  void* rT = nullptr;   // inner right-hand side, type T
+  void* eA = nullptr;   // inner correction, ping
+  void* eB = nullptr;   // inner correction, pong
+  double *rc = nullptr, *E = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double *p_sq = nullptr, *p_max = nullptr, *p_bsq = nullptr, *p_bmax = nullptr, *p_sum = nullptr;
+  double* scal = nullptr;  // [kSlots][batch]
+  double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
+  void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
+  double* h_scal = nullptr;   // pinned mirror of scal
+  std::string err;
+  int64_t launches = 0, syncs = 0;
+};
+
+namespace {
+
+int set_err(ism_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return set_err((ctx), ISM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH(ctx, expr)   \
+  do {                      \
+    (ctx)->launches++;      \
+    HIPCHK(ctx, (expr));    \
+  } while (0)
+
+bool is_pow2_coarsen(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
+
+int validate(const ism_config* cfg, std::string& why) {
+  if (!cfg) return why = "config is NULL", ISM_ERR_INVALID;
+  if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->batch <= 0)
+    return why = "nx, ny and batch must be positive", ISM_ERR_INVALID;
+  if ((cfg->bc_x != ISM_BC_NEUMANN && cfg->bc_x != ISM_BC_PERIODIC) ||
+      (cfg->bc_y != ISM_BC_NEUMANN && cfg->bc_y != ISM_BC_PERIODIC))
+    return why = "bc_x/bc_y must be ISM_BC_NEUMANN or ISM_BC_PERIODIC", ISM_ERR_INVALID;
+  if (cfg->precision != ISM_PREC_FP64 && cfg->precision != ISM_PREC_MIXED)
+    return why = "precision must be ISM_PREC_FP64 or ISM_PREC_MIXED", ISM_ERR_INVALID;
+  if (!(cfg->lx > 0.0) || !(cfg->ly > 0.0) || !std::isfinite(cfg->lx) || !std::isfinite(cfg->ly))
+    return why = "lx and ly must be positive and finite", ISM_ERR_INVALID;
+  if (cfg->nu < 1) return why = "nu must be >= 1", ISM_ERR_INVALID;
+  if (!(cfg->rtol > 0.0)) return why = "rtol must be positive", ISM_ERR_INVALID;
+  if (!(cfg->inner_rtol > 0.0) || !(cfg->inner_rtol < 1.0))
+    return why = "inner_rtol must lie in (0, 1)", ISM_ERR_INVALID;
+  if (cfg->max_cycles < 1 || cfg->max_outer < 1 || cfg->check_every < 0)
+    return why = "max_cycles and max_outer must be >= 1, check_every >= 0", ISM_ERR_INVALID;
+  if (cfg->fused != 0 && cfg->fused != 1) return why = "fused must be 0 or 1", ISM_ERR_INVALID;
+  if (!is_pow2_coarsen(cfg->coarsen))
+    return why = "coarsen must be 4, 8, 16 or 32", ISM_ERR_UNSUPPORTED;
+  if (cfg->nx % cfg->coarsen || cfg->ny % cfg->coarsen)
+    return why = "nx and ny must be multiples of coarsen", ISM_ERR_UNSUPPORTED;
+  if (cfg->nx < 2 || cfg->ny < 2) return why = "the grid needs at least 2 cells per axis", ISM_ERR_UNSUPPORTED;
+  const double hx = cfg->lx / cfg->nx, hy = cfg->ly / cfg->ny;
+  if (std::fabs(hx - hy) > 1e-12 * hx) return why = "cells must be square (lx/nx == ly/ny)", ISM_ERR_UNSUPPORTED;
+  if (cfg->fused && cfg->nu > ism::fused_max_nu())
+    return why = "the fused cycle kernel supports nu <= 4; use fused = 0", ISM_ERR_UNSUPPORTED;
+  const double cells = double(cfg->nx) * cfg->ny * cfg->batch;
+  if (cells > 4.0e10) return why = "grid too large", ISM_ERR_UNSUPPORTED;
+  return ISM_OK;
+}
+
+// 1D eigenbasis of the coarse factors K = [1 -2 1] and M = [1 6 1]/8 with the boundary rule
+// of the axis (Neumann: one-sided K, M end entry 7/8; periodic: circulant).  Columns of V are
+// orthonormal eigenvectors; theta is the angle whose cosine gives the eigenvalues
+// lambda_K = -2 (1 - cos theta) and lambda_M = (3 + cos theta) / 4.
+void coarse_basis(int nc, bool periodic, std::vector<double>& V, std::vector<double>& theta) {
+  V.assign(size_t(nc) * nc, 0.0);
+  theta.assign(nc, 0.0);
+  const double pi = 3.14159265358979323846;
+  if (!periodic) {
+    for (int k = 0; k < nc; ++k) {
+      const double sc = std::sqrt((k == 0 ? 1.0 : 2.0) / nc);
+      theta[k] = pi * k / nc;
+      for (int I = 0; I < nc; ++I) V[size_t(I) * nc + k] = sc * std::cos(pi * k * (I + 0.5) / nc);
+    }
+    return;
+  }
+  for (int I = 0; I < nc; ++I) V[size_t(I) * nc] = std::sqrt(1.0 / nc);
+  int col = 1;
+  for (int m = 1; 2 * m < nc; ++m) {
+    const double sc = std::sqrt(2.0 / nc);
+    theta[col] = theta[col + 1] = 2.0 * pi * m / nc;
+    for (int I = 0; I < nc; ++I) {
+      V[size_t(I) * nc + col] = sc * std::cos(2.0 * pi * m * I / nc);
+      V[size_t(I) * nc + col + 1] = sc * std::sin(2.0 * pi * m * I / nc);
+    }
+    col += 2;
+  }
+  if (nc % 2 == 0 && nc > 1) {
+    theta[col] = pi;
+    for (int I = 0; I < nc; ++I) V[size_t(I) * nc + col] = (I % 2 ? -1.0 : 1.0) / std::sqrt(double(nc));
+  }
+}
+
+template <typename T>
+constexpr int dtype_of() {
+  return sizeof(T) == 4 ? ISM_F32 : ISM_F64;
+}
+
+// ------------------------------------------------------------------ coarse solve (FP64)
+// E = V_y ((V_y^T R_c V_x) .* Lambda^-1) V_x^T with the (0,0) entry of Lambda^-1 zero: the
+// zero-mean solution of K_x (x) M_y + M_x (x) K_y applied to E equal to R_c minus its mean.
+int coarse_solve(ism_ctx* c, const double* rc, double* E) {
+  const Geo& g = c->g;
+  const int nx = g.ncx, ny = g.ncy, B = g.batch;
+  const long long cp = g.cplane;
+  hipStream_t s = c->stream;
+  LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, rc, cp, nx, 0, c->Vx, 0, nx, c->t1, cp, nx, nullptr, B, s));
+  LAUNCH(c, ism::launch_gemm(ny, nx, ny, 1, c->Vy, 0, ny, 0, c->t1, cp, nx, c->t2, cp, nx, c->invLam, B, s));
+  LAUNCH(c, ism::launch_gemm(ny, nx, ny, 0, c->Vy, 0, ny, 0, c->t2, cp, nx, c->t1, cp, nx, nullptr, B, s));
+  LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, c->t1, cp, nx, 1, c->Vx, 0, nx, E, cp, nx, nullptr, B, s));
+  return ISM_OK;
+}
+
+int read_scalars(ism_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * kSlots * c->g.batch,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->syncs++;
+  return ISM_OK;
+}
+
+int finalize(ism_ctx* c, const double* part, ism::Reduce op, double scale, int slot) {
+  LAUNCH(c, ism::launch_finalize(part, int(c->g.cplane), c->g.cplane, c->g.batch, op, scale,
+                                 c->scal + size_t(slot) * c->g.batch, 1, 0, c->stream));
+  return ISM_OK;
+}
+
+void* scratch_fine(ism_ctx* c) {
+  if (!c->stage_tmp) {
+    if (hipMalloc(&c->stage_tmp, size_t(c->g.plane) * c->g.batch * sizeof(double)) != hipSuccess)
+      c->stage_tmp = nullptr;
+  }
+  return c->stage_tmp;
+}
+
+// One two-level cycle on A' e = rhs.  Reads e from *cur (ignored if zero_e), leaves the new
+// correction in *cur (swapping with *spare), overwrites rc with R(rhs - A'e) and psq with the
+// per-tile squared-residual sums.
+template <typename T>
+int run_cycle(ism_ctx* c, const T* rhs, T** cur, T** spare, double* rc, double* psq, int zero_e) {
+  const Geo& g = c->g;
+  hipStream_t s = c->stream;
+  int rcode = coarse_solve(c, rc, c->E);
+  if (rcode) return rcode;
+  if (c->cfg.fused) {
+    LAUNCH(c, ism::launch_cycle_fused<T>(g, rhs, *cur, *spare, c->E, rc, psq, c->cfg.nu, zero_e, s));
+    std::swap(*cur, *spare);
+    return ISM_OK;
+  }
+  LAUNCH(c, ism::launch_prolong<T>(g, c->E, *cur, zero_e, s));
+  for (int k = 0; k < c->cfg.nu; ++k) {
+    LAUNCH(c, ism::launch_rbgs<T>(g, rhs, *cur, *spare, s));
+    std::swap(*cur, *spare);
+  }
+  LAUNCH(c, ism::launch_restrict<T>(g, rhs, *cur, rc, psq, s));
+  return ISM_OK;
+}
+
+struct Check {
+  int cycle;
+  std::vector<double> res;
+};
+
+// Inner solve of A' e = rT from e = 0 in type T, until every grid's residual norm is below
+// its target, or the residual stagnates, or the cycle cap is reached.  rc holds R rT on entry.
+template <typename T>
+int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** e_out) {
+  const int B = c->g.batch;
+  T* cur = (T*)c->eA;
+  T* spare = (T*)c->eB;
+  const T* rhs = (const T*)c->rT;
+  std::vector<Check> hist;
+  const bool mixed = sizeof(T) == 4;
+  int k = 0, next = 1;
+  auto last_time = std::chrono::steady_clock::now();
+  int last_cycle = 0;
+  for (;;) {
+    int rcode = run_cycle<T>(c, rhs, &cur, &spare, c->rc, c->p_sq, k == 0);
+    if (rcode) return rcode;
+    ++k;
+    ++cycles;
+    if (k < next && cycles < c->cfg.max_cycles) continue;
+    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
+    if ((rcode = read_scalars(c))) return rcode;
+    auto now = std::chrono::steady_clock::now();
+    const double dt = std::chrono::duration<double>(now - last_time).count() / std::max(1, k - last_cycle);
+    last_time = now;
+    last_cycle = k;
+    Check ck{k, std::vector<double>(B)};
+    bool done = true, finite = true;
+    for (int b = 0; b < B; ++b) {
+      ck.res[b] = std::sqrt(c->h_scal[size_t(ISQ) * B + b]);
+      finite = finite && std::isfinite(ck.res[b]);
+      done = done && ck.res[b] <= target[b];
+    }
+    if (!finite) return set_err(c, ISM_ERR_NONFINITE, "non-finite residual in the inner iteration");
+    hist.push_back(ck);
+    if (done || cycles >= c->cfg.max_cycles) break;
+    // stagnation: the newest check against the latest one at least kStallWindow cycles older
+    const Check* old = nullptr;
+    for (auto it = hist.rbegin(); it != hist.rend(); ++it)
+      if (it->cycle <= k - kStallWindow) {
+        old = &*it;
+        break;
+      }
+    if (old) {
+      bool stalled = true;
+      for (int b = 0; b < B; ++b)
+        if (ck.res[b] > target[b] && ck.res[b] < (1.0 - kStallDrop) * old->res[b]) stalled = false;
+      if (stalled) break;
+    }
+    // schedule the next check
+    int gap;
+    if (c->cfg.check_every > 0) {
+      gap = c->cfg.check_every;
+    } else {
+      gap = 1;
+      if (hist.size() >= 2) {
+        const Check& p = hist[hist.size() - 2];
+        double need = 1.0;
+        for (int b = 0; b < B; ++b) {
+          if (ck.res[b] <= target[b]) continue;
+          const double rho = std::pow(ck.res[b] / p.res[b], 1.0 / double(k - p.cycle));
+          if (!(rho < 1.0) || !(rho > 0.0)) continue;
+          need = std::max(need, std::ceil(std::log(target[b] / ck.res[b]) / std::log(rho)));
+        }
+        gap = int(std::min(need, double(std::max(4, k))));
+      }
+      if (mixed) {  // keep stagnation visible: at most ~1 ms of device work between checks
+        const int cap = std::max(4, int(1.0e-3 / std::max(dt, 1e-7)));
+        gap = std::min(gap, cap);
+      }
+      gap = std::max(gap, 1);
+    }
+    next = k + gap;
+  }
+  *e_out = cur;
+  return ISM_OK;
+}
+
+template <typename T>
+int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  c->launches = 0;
+  c->syncs = 0;
+  const Geo& g = c->g;
+  const int B = g.batch;
+  hipStream_t s = c->stream;
+  int rcode;
+  LAUNCH(c, ism::launch_tile_sum(g, b, c->p_sum, s));
+  if ((rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(g.plane), MEAN_B))) return rcode;
+
+  std::vector<double> bnorm(B, 0.0), bmax(B, 0.0), den(B, 1.0), target(B);
+  int cycles = 0, outer = 0, status = ISM_OK;
+  double rel_l2 = 0.0, rel_max = 0.0;
+  for (bool first = true;; first = false) {
+    Partials p{c->p_sq, c->p_max, first ? c->p_bsq : nullptr, first ? c->p_bmax : nullptr};
+    LAUNCH(c, ism::launch_outer_residual<T>(g, b, x, c->scal + size_t(MEAN_B) * B, c->h2, (T*)c->rT,
+                                            c->rc, p, s));
+    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
+    if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
+    if (first) {
+      if ((rcode = finalize(c, c->p_bsq, ism::SUM, 1.0, BSQ))) return rcode;
+      if ((rcode = finalize(c, c->p_bmax, ism::MAX, 1.0, BMAX))) return rcode;
+    }
+    if ((rcode = read_scalars(c))) return rcode;
+    bool conv = true, finite = true;
+    rel_l2 = rel_max = 0.0;
+    for (int k = 0; k < B; ++k) {
+      if (first) {
+        bnorm[k] = std::sqrt(c->h_scal[size_t(BSQ) * B + k]);
+        bmax[k] = c->h_scal[size_t(BMAX) * B + k];
+        // a constant right-hand side has b~ = 0: the criterion becomes absolute
+        den[k] = bnorm[k] > 0.0 ? bnorm[k] : 1.0;
+      }
+      const double rn = std::sqrt(c->h_scal[size_t(RSQ) * B + k]);
+      const double rm = c->h_scal[size_t(RMAX) * B + k];
+      finite = finite && std::isfinite(rn) && std::isfinite(bnorm[k]);
+      rel_l2 = std::max(rel_l2, rn / den[k]);
+      rel_max = std::max(rel_max, rm / (bmax[k] > 0.0 ? bmax[k] : 1.0));
+      conv = conv && rn <= c->cfg.rtol * den[k];
+      const double inner = c->cfg.precision == ISM_PREC_FP64 ? 0.0 : c->cfg.inner_rtol * rn;
+      target[k] = std::max(inner, kInnerMargin * c->cfg.rtol * den[k]);
+    }
+    if (!finite) {
+      status = set_err(c, ISM_ERR_NONFINITE, "non-finite value in b, x or the residual");
+      break;
+    }
+    if (conv) break;
+    if (outer >= c->cfg.max_outer || cycles >= c->cfg.max_cycles) {
+      status = ISM_NOT_CONVERGED;
+      break;
+    }
+    ++outer;
+    T* e = nullptr;
+    if ((rcode = inner_solve<T>(c, target, cycles, &e))) return rcode;
+    LAUNCH(c, ism::launch_add_to<T>(g, x, e, s));
+  }
+  if (status >= 0) {
+    LAUNCH(c, ism::launch_tile_sum(g, x, c->p_sum, s));
+    if ((rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(g.plane), MEAN_X))) return rcode;
+    LAUNCH(c, ism::launch_sub_scalar(g, x, c->scal + size_t(MEAN_X) * B, 1, 0, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->syncs++;
+  if (st) {
+    st->status = status;
+    st->outer_iters = outer;
+    st->cycles = cycles;
+    st->sweeps = cycles * c->cfg.nu;
+    st->launches = c->launches;
+    st->host_syncs = c->syncs;
+    st->rel_res_l2 = rel_l2;
+    st->rel_res_max = rel_max;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch) {
+  if (!cfg) return ISM_ERR_INVALID;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->nx = nx;
+  cfg->ny = ny;
+  cfg->batch = batch;
+  cfg->bc_x = ISM_BC_NEUMANN;
+  cfg->bc_y = ISM_BC_NEUMANN;
+  cfg->coarsen = 16;
+  cfg->lx = 1.0;
+  cfg->ly = nx > 0 ? double(ny) / double(nx) : 1.0;
+  cfg->precision = ISM_PREC_FP64;
+  cfg->nu = 2;
+  cfg->rtol = 1e-10;
+  cfg->inner_rtol = 1e-3;
+  cfg->max_cycles = 100000;
+  cfg->max_outer = 50;
+  cfg->check_every = 0;
+  cfg->fused = 1;
+  return ISM_OK;
+}
+
+int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
+  if (!out) return set_err(nullptr, ISM_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  int v = validate(cfg, why);
+  if (v != ISM_OK) return set_err(nullptr, v, why);
+
+  ism_ctx* c = new (std::nothrow) ism_ctx();
+  if (!c) return set_err(nullptr, ISM_ERR_INVALID, "out of host memory");
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)stream;
+  Geo& g = c->g;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.batch = cfg->batch;
+  g.n = cfg->coarsen;
+  g.log2n = 0;
+  while ((1 << g.log2n) < g.n) ++g.log2n;
+  g.ncx = g.nx / g.n;
+  g.ncy = g.ny / g.n;
+  g.per_x = cfg->bc_x == ISM_BC_PERIODIC;
+  g.per_y = cfg->bc_y == ISM_BC_PERIODIC;
+  g.plane = (long long)g.nx * g.ny;
+  g.cplane = (long long)g.ncx * g.ncy;
+  c->h = cfg->lx / cfg->nx;
+  c->h2 = c->h * c->h;
+  c->tsize = cfg->precision == ISM_PREC_MIXED ? 4 : 8;
+
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) {
+    delete c;
+    return set_err(nullptr, ISM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  }
+  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t fine = align(size_t(g.plane) * g.batch * c->tsize);
+  const size_t coarse = align(size_t(g.cplane) * g.batch * sizeof(double));
+  const size_t scal = align(sizeof(double) * kSlots * g.batch);
+  const size_t tabs = align(sizeof(double) * g.ncx * g.ncx) + align(sizeof(double) * g.ncy * g.ncy) +
+                      align(sizeof(double) * g.cplane);
+  c->bytes = 3 * fine + 9 * coarse + scal + tabs;
+  he = hipMalloc((void**)&c->block, c->bytes);
+  if (he != hipSuccess) {
+    delete c;
+    return set_err(nullptr, ISM_ERR_HIP, std::string("hipMalloc workspace: ") + hipGetErrorString(he));
+  }
+  char* p = c->block;
+  c->rT = p; p += fine;
+  c->eA = p; p += fine;
+  c->eB = p; p += fine;
+  double** cbufs[9] = {&c->rc, &c->E, &c->t1, &c->t2, &c->p_sq, &c->p_max, &c->p_bsq, &c->p_bmax, &c->p_sum};
+  for (double** q : cbufs) {
+    *q = (double*)p;
+    p += coarse;
+  }
+  c->scal = (double*)p; p += scal;
+  c->Vx = (double*)p; p += align(sizeof(double) * g.ncx * g.ncx);
+  c->Vy = (double*)p; p += align(sizeof(double) * g.ncy * g.ncy);
+  c->invLam = (double*)p;
+
+  he = hipHostMalloc((void**)&c->h_scal, sizeof(double) * kSlots * g.batch, hipHostMallocDefault);
+  if (he != hipSuccess) {
+    (void)hipFree(c->block);
+    delete c;
+    return set_err(nullptr, ISM_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(he));
+  }
+
+  // coarse tables (host, FP64), uploaded once
+  std::vector<double> Vx, Vy, thx, thy;
+  coarse_basis(g.ncx, g.per_x, Vx, thx);
+  coarse_basis(g.ncy, g.per_y, Vy, thy);
+  std::vector<double> inv(size_t(g.cplane));
+  for (int l = 0; l < g.ncy; ++l)
+    for (int k = 0; k < g.ncx; ++k) {
+      const double kx = -2.0 * (1.0 - std::cos(thx[k])), mx = (3.0 + std::cos(thx[k])) / 4.0;
+      const double ky = -2.0 * (1.0 - std::cos(thy[l])), my = (3.0 + std::cos(thy[l])) / 4.0;
+      const double lam = kx * my + mx * ky;
+      inv[size_t(l) * g.ncx + k] = (l == 0 && k == 0) ? 0.0 : 1.0 / lam;
+    }
+  he = hipMemcpyAsync(c->Vx, Vx.data(), sizeof(double) * Vx.size(), hipMemcpyHostToDevice, c->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(c->Vy, Vy.data(), sizeof(double) * Vy.size(), hipMemcpyHostToDevice, c->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(c->invLam, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, c->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(c->scal, 0, scal, c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) {
+    (void)hipHostFree(c->h_scal);
+    (void)hipFree(c->block);
+    delete c;
+    return set_err(nullptr, ISM_ERR_HIP, std::string("uploading coarse tables: ") + hipGetErrorString(he));
+  }
+  *out = c;
+  return ISM_OK;
+}
+
+int ism_destroy(ism_handle c) {
+  if (!c) return ISM_OK;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->stage_tmp) (void)hipFree(c->stage_tmp);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  if (c->block) (void)hipFree(c->block);
+  delete c;
+  return ISM_OK;
+}
+
+int ism_workspace_bytes(ism_handle c, size_t* bytes) {
+  if (!c || !bytes) return ISM_ERR_INVALID;
+  *bytes = c->bytes + (c->stage_tmp ? size_t(c->g.plane) * c->g.batch * sizeof(double) : 0);
+  return ISM_OK;
+}
+
+int ism_solve(ism_handle c, const double* b, double* x, ism_stats* st) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!b || !x) return set_err(c, ISM_ERR_INVALID, "b and x must be device pointers");
+  return c->tsize == 4 ? solve_impl<float>(c, b, x, st) : solve_impl<double>(c, b, x, st);
+}
+
+int ism_solve_adjoint(ism_handle c, const double* g, double* lam, ism_stats* st) {
+  // A is symmetric (cell-centred 5-point operator with Neumann or periodic boundaries), and
+  // the mean projection is self-adjoint, so the adjoint solve is the forward solve.
+  return ism_solve(c, g, lam, st);
+}
+
+int ism_div(ism_handle c, const double* u, const double* v, double* b) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!u || !v || !b) return set_err(c, ISM_ERR_INVALID, "NULL array");
+  LAUNCH(c, ism::launch_div(c->g, u, v, c->h, b, c->stream));
+  return ISM_OK;
+}
+
+int ism_grad(ism_handle c, const double* p, double* gu, double* gv) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!p || !gu || !gv) return set_err(c, ISM_ERR_INVALID, "NULL array");
+  LAUNCH(c, ism::launch_grad(c->g, p, c->h, gu, gv, c->stream));
+  return ISM_OK;
+}
+
+int ism_div_adjoint(ism_handle c, const double* lam, double* gu, double* gv) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!lam || !gu || !gv) return set_err(c, ISM_ERR_INVALID, "NULL array");
+  LAUNCH(c, ism::launch_div_adjoint(c->g, lam, c->h, gu, gv, c->stream));
+  return ISM_OK;
+}
+
+int ism_grad_adjoint(ism_handle c, const double* gu, const double* gv, double* p) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!gu || !gv || !p) return set_err(c, ISM_ERR_INVALID, "NULL array");
+  LAUNCH(c, ism::launch_grad_adjoint(c->g, gu, gv, c->h, p, c->stream));
+  return ISM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int smooth_impl(ism_ctx* c, const T* rhs, T* e, int nsweeps) {
+  T* tmp = (T*)scratch_fine(c);
+  if (!tmp) return set_err(c, ISM_ERR_HIP, "hipMalloc of the stage scratch failed");
+  T* cur = e;
+  T* spare = tmp;
+  for (int k = 0; k < nsweeps; ++k) {
+    LAUNCH(c, ism::launch_rbgs<T>(c->g, rhs, cur, spare, c->stream));
+    std::swap(cur, spare);
+  }
+  if (cur != e)
+    HIPCHK(c, hipMemcpyAsync(e, cur, sizeof(T) * size_t(c->g.plane) * c->g.batch,
+                             hipMemcpyDeviceToDevice, c->stream));
+  return ISM_OK;
+}
+
+template <typename T>
+int cycle_impl(ism_ctx* c, const T* rhs, T* e, double* rc, int zero_e, double* sumsq) {
+  T* tmp = (T*)scratch_fine(c);
+  if (!tmp) return set_err(c, ISM_ERR_HIP, "hipMalloc of the stage scratch failed");
+  T* cur = e;
+  T* spare = tmp;
+  int rcode = run_cycle<T>(c, rhs, &cur, &spare, rc, sumsq ? c->p_sq : nullptr, zero_e);
+  if (rcode) return rcode;
+  if (cur != e)
+    HIPCHK(c, hipMemcpyAsync(e, cur, sizeof(T) * size_t(c->g.plane) * c->g.batch,
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (sumsq)
+    LAUNCH(c, ism::launch_finalize(c->p_sq, int(c->g.cplane), c->g.cplane, c->g.batch, ism::SUM, 1.0,
+                                   sumsq, 1, 0, c->stream));
+  return ISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ism_smooth(ism_handle c, int32_t dtype, const void* rhs, void* e, int32_t nsweeps) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!rhs || !e || nsweeps < 0) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  if (dtype == ISM_F32) return smooth_impl<float>(c, (const float*)rhs, (float*)e, nsweeps);
+  if (dtype == ISM_F64) return smooth_impl<double>(c, (const double*)rhs, (double*)e, nsweeps);
+  return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
+}
+
+int ism_restrict(ism_handle c, int32_t dtype, const void* rhs, const void* e, double* rc, double* sumsq) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!rhs || !e || !rc) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  double* psq = sumsq ? c->p_sq : nullptr;
+  if (dtype == ISM_F32)
+    LAUNCH(c, ism::launch_restrict<float>(c->g, (const float*)rhs, (const float*)e, rc, psq, c->stream));
+  else if (dtype == ISM_F64)
+    LAUNCH(c, ism::launch_restrict<double>(c->g, (const double*)rhs, (const double*)e, rc, psq, c->stream));
+  else
+    return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
+  if (sumsq)
+    LAUNCH(c, ism::launch_finalize(c->p_sq, int(c->g.cplane), c->g.cplane, c->g.batch, ism::SUM, 1.0,
+                                   sumsq, 1, 0, c->stream));
+  return ISM_OK;
+}
+
+int ism_prolong(ism_handle c, int32_t dtype, const double* E, void* e) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!E || !e) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  if (dtype == ISM_F32) LAUNCH(c, ism::launch_prolong<float>(c->g, E, (float*)e, 0, c->stream));
+  else if (dtype == ISM_F64) LAUNCH(c, ism::launch_prolong<double>(c->g, E, (double*)e, 0, c->stream));
+  else return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
+  return ISM_OK;
+}
+
+int ism_coarse_solve(ism_handle c, const double* rc, double* E) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!rc || !E) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  return coarse_solve(c, rc, E);
+}
+
+int ism_cycle(ism_handle c, int32_t dtype, const void* rhs, void* e, double* rc, int32_t zero_e,
+              double* sumsq) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!rhs || !e || !rc) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  if (dtype == ISM_F32) return cycle_impl<float>(c, (const float*)rhs, (float*)e, rc, zero_e, sumsq);
+  if (dtype == ISM_F64) return cycle_impl<double>(c, (const double*)rhs, (double*)e, rc, zero_e, sumsq);
+  return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
+}
+
+int ism_coarse_stencil(ism_handle c, double* coef) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!coef) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  LAUNCH(c, ism::launch_coarse_assemble(c->g, coef, c->stream));
+  return ISM_OK;
+}
+
+int ism_outer_residual(ism_handle c, const double* b, const double* x, double* r) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!b || !x || !r) return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  LAUNCH(c, ism::launch_tile_sum(c->g, b, c->p_sum, c->stream));
+  int rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(c->g.plane), MEAN_B);
+  if (rcode) return rcode;
+  Partials p{nullptr, nullptr, nullptr, nullptr};
+  LAUNCH(c, ism::launch_outer_residual<double>(c->g, b, x, c->scal + size_t(MEAN_B) * c->g.batch, c->h2,
+                                               r, nullptr, p, c->stream));
+  return ISM_OK;
+}
+
+const char* ism_status_string(int status) {
+  switch (status) {
+    case ISM_OK: return "ok";
+    case ISM_NOT_CONVERGED: return "not converged";
+    case ISM_ERR_INVALID: return "invalid argument";
+    case ISM_ERR_UNSUPPORTED: return "unsupported configuration";
+    case ISM_ERR_HIP: return "HIP runtime error";
+    case ISM_ERR_NONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* ism_last_error(ism_handle c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal interface between the host orchestration (ism_api.cpp) and the kernel launchers
+// (ism_kernels.hip).  Not installed; the public interface is include/ism.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ism {
+
+// Geometry of one handle, passed to every kernel by value.
+struct Geo {
+  int nx, ny, batch;   // fine grid and number of independent grids
+  int n, ncx, ncy;     // tile edge and coarse grid
+  int per_x, per_y;    // 1 if the axis is periodic
+  int log2n;           // log2 of the tile edge
+  long long plane;     // nx * ny
+  long long cplane;    // ncx * ncy
+};
+
+enum Reduce { SUM = 0, MAX = 1 };
+
+// Per-tile partial results written by the residual kernels, [batch][ncy][ncx] each.
+struct Partials {
+  double* sumsq;  // sum of squared residuals of the tile (or nullptr)
+  double* maxabs; // max |residual| of the tile (or nullptr)
+  double* bsumsq; // sum of squared right-hand side (outer residual, first call only)
+  double* bmaxabs;
+};
+
+// ---- launchers (ism_kernels.hip); every one enqueues on `s` and returns hipGetLastError()
+// One red-black sweep; e_in and e_out must not alias (workgroups read halos of their
+// neighbours' tiles).
+template <typename T>
+hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* e_in, T* e_out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_restrict(const Geo& g, const T* rhs, const T* e, double* rc, double* part_sumsq,
+                           hipStream_t s);
+
+template <typename T>
+hipError_t launch_prolong(const Geo& g, const double* E, T* e, int assign, hipStream_t s);
+
+// One fused cycle: e = (zero_e ? 0 : e) + P E, nu red-black sweeps on A'e = rhs, then
+// rc = R (rhs - A'e) and per-tile sums of squares.  Tile TXxTY of fine cells per workgroup.
+// e_in and e_out must not alias.
+template <typename T>
+hipError_t launch_cycle_fused(const Geo& g, const T* rhs, const T* e_in, T* e_out,
+                              const double* E, double* rc, double* part_sumsq, int nu,
+                              int zero_e, hipStream_t s);
+int fused_max_nu();
+
+template <typename T>
+hipError_t launch_outer_residual(const Geo& g, const double* b, const double* x,
+                                 const double* mean_b, double h2, T* rT, double* rc,
+                                 Partials p, hipStream_t s);
+
+hipError_t launch_tile_sum(const Geo& g, const double* x, double* part, hipStream_t s);
+
+hipError_t launch_finalize(const double* part, int count, long long part_stride, int batch,
+                           Reduce op, double scale, double* out, int out_stride, int slot,
+                           hipStream_t s);
+
+template <typename T>
+hipError_t launch_add_to(const Geo& g, double* x, const T* e, hipStream_t s);
+
+hipError_t launch_sub_scalar(const Geo& g, double* x, const double* vals, int val_stride,
+                             int slot, hipStream_t s);
+
+// C[b] = op(A[b]) op(B[b]) (then times S elementwise if S != nullptr), FP64, row-major.
+hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long long sA, int lda,
+                       int transB, const double* B, long long sB, int ldb, double* C,
+                       long long sC, int ldc, const double* S, int batch, hipStream_t s);
+
+hipError_t launch_coarse_assemble(const Geo& g, double* coef, hipStream_t s);
+
+hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
+                      hipStream_t s);
+hipError_t launch_grad(const Geo& g, const double* p, double h, double* gu, double* gv,
+                       hipStream_t s);
+hipError_t launch_div_adjoint(const Geo& g, const double* lam, double h, double* gu,
+                              double* gv, hipStream_t s);
+hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv, double h,
+                               double* p, hipStream_t s);
+
+}  // namespace ism

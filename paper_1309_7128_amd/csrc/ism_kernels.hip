@@ -1,0 +1,991 @@
+// HIP kernels of the interpolated stencil multigrid (ISM) solver, written for gfx950
+// (MI355X: wave64, 160 KB LDS per CU, HBM3E).
+//
+// Every fine-grid kernel streams a 5-point stencil and is bound by HBM bandwidth; none of
+// them is a dense contraction, so nothing here uses MFMA.  Fine arrays are row-major
+// [batch][ny][nx]; a wave covers 64 consecutive cells of a row so every global access is a
+// full 256 B (FP32) or 512 B (FP64) row segment.
+//
+// Arithmetic conventions (shared by every kernel so that a cell value never depends on the
+// kernel that produced it):
+//  * A'e (the 5-point Laplacian times h^2) in difference form,
+//    ((e_W - e_C) + (e_E - e_C)) + (e_S - e_C)) + (e_N - e_C), a wall neighbour's term being
+//    absent (Sec. 2.3 stencil, Sec. 4.1 walls).
+//  * Red-black Gauss-Seidel (Sec. 3.1): red is (i + j) even; a cell is set to
+//    (((e_W + e_E) + e_S) + e_N - rhs_C) * (1 / m_C), m_C its number of existing neighbours
+//    and a missing neighbour contributing 0.
+//  * Bilinear prolongation (Eq. 5) evaluated in FP64 and added to the fine value in FP64,
+//    then rounded to the fine type.
+// The library is compiled with -ffp-contract=off so these expressions round exactly as
+// written; products that are meant to fuse (the coarse transforms) call fma explicitly.
+
+#include <hip/hip_runtime.h>
+
+#include "ism_internal.h"
+
+namespace ism {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int imod(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int floordiv(int a, int n) {
+  return a >= 0 ? a / n : -((-a + n - 1) / n);
+}
+
+// Map an unwrapped cell coordinate onto the grid: wraps periodic axes, rejects cells behind
+// a wall.
+__device__ __forceinline__ bool map_cell(const Geo& g, int& i, int& j) {
+  if (g.per_x) {
+    i = imod(i, g.nx);
+  } else if (i < 0 || i >= g.nx) {
+    return false;
+  }
+  if (g.per_y) {
+    j = imod(j, g.ny);
+  } else if (j < 0 || j >= g.ny) {
+    return false;
+  }
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ T inv_count(const Geo& g, int i, int j) {
+  int m = 4;
+  if (!g.per_x) m -= (i == 0) + (i == g.nx - 1);
+  if (!g.per_y) m -= (j == 0) + (j == g.ny - 1);
+  constexpr T third = T(1) / T(3);
+  return m == 4 ? T(0.25) : (m == 3 ? third : (m == 2 ? T(0.5) : T(1)));
+}
+
+// A'e at a cell from its four neighbours, difference form; absent terms skipped.
+template <typename T>
+__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, bool hw, bool he, bool hs, bool hn) {
+  T dw = hw ? T(w - c) : T(0);
+  T de = he ? T(e - c) : T(0);
+  T ds = hs ? T(s - c) : T(0);
+  T dn = hn ? T(n - c) : T(0);
+  return ((dw + de) + ds) + dn;
+}
+
+__device__ __forceinline__ double wave_sum_group(double v, int group) {
+  for (int off = 1; off < group; off <<= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_group(double v, int group) {
+  for (int off = 1; off < group; off <<= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Interpolation coordinate along one axis (Eq. 5): fine index -> lower coarse index
+// (unwrapped, may be -1 or the last+1) and the offset t = (2k+1)/(2n) of the fine centre
+// from the lower coarse centre, in units of the rectangle size n.
+__device__ __forceinline__ void interp_coord(int gi, int n, int& lo, double& t) {
+  int s = gi - (n >> 1);
+  lo = floordiv(s, n);
+  int k = s - lo * n;
+  t = double(2 * k + 1) / double(2 * n);
+}
+
+// p = Q11 (1-X)(1-Y) + Q21 X (1-Y) + Q12 (1-X) Y + Q22 X Y, in this order (Eq. 5).
+__device__ __forceinline__ double bilinear(double q11, double q21, double q12, double q22,
+                                           double X, double Y) {
+  double a = q11 * (1.0 - X) * (1.0 - Y);
+  double b = q21 * X * (1.0 - Y);
+  double c = q12 * (1.0 - X) * Y;
+  double d = q22 * X * Y;
+  return ((a + b) + c) + d;
+}
+
+// ----------------------------------------------------------------------------------------
+// One red-black sweep (red on the tile plus one ring, black on the tile), LDS-staged.
+// Tile 64 x 32 cells per workgroup; e is staged with a halo of 2, rhs with a halo of 1.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rhs,
+                                                 const T* __restrict__ ein,
+                                                 T* __restrict__ eout) {
+  constexpr int TX = 64, TY = 32;
+  constexpr int LE = TX + 4, HE = TY + 4;
+  constexpr int LR = TX + 2, HR = TY + 2;
+  __shared__ T se[HE * LE];
+  __shared__ T sr[HR * LR];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const long long off = (long long)blockIdx.z * g.plane;
+  const T* rb = rhs + off;
+  const T* eb = ein + off;
+  T* ob = eout + off;
+
+  for (int t = threadIdx.x; t < HE * LE; t += kBlock) {
+    int ly = t / LE, lx = t - ly * LE;
+    int i = x0 + lx - 2, j = y0 + ly - 2;
+    T v = T(0);
+    if (map_cell(g, i, j)) v = eb[(long long)j * g.nx + i];
+    se[t] = v;
+  }
+  for (int t = threadIdx.x; t < HR * LR; t += kBlock) {
+    int ly = t / LR, lx = t - ly * LR;
+    int i = x0 + lx - 1, j = y0 + ly - 1;
+    T v = T(0);
+    if (map_cell(g, i, j)) v = rb[(long long)j * g.nx + i];
+    sr[t] = v;
+  }
+  __syncthreads();
+
+  // red cells of rows/cols 1 .. TY+2 / TX+2 of the staged region
+  constexpr int RW = (TX + 2) / 2;
+  for (int t = threadIdx.x; t < (TY + 2) * RW; t += kBlock) {
+    int r = t / RW, k = t - r * RW;
+    int ly = r + 1;
+    int j = y0 + ly - 2;
+    int lx = 1 + ((j + 1) & 1) + 2 * k;  // (i + j) even, x0 even
+    int i = x0 + lx - 2;
+    if (!map_cell(g, i, j)) continue;
+    int idx = ly * LE + lx;
+    T s = ((se[idx - 1] + se[idx + 1]) + se[idx - LE]) + se[idx + LE];
+    se[idx] = (s - sr[(ly - 1) * LR + (lx - 1)]) * inv_count<T>(g, i, j);
+  }
+  __syncthreads();
+  constexpr int BW = TX / 2;
+  for (int t = threadIdx.x; t < TY * BW; t += kBlock) {
+    int r = t / BW, k = t - r * BW;
+    int ly = r + 2;
+    int j = y0 + r;
+    int lx = 2 + ((j + 1) & 1) + 2 * k;  // (i + j) odd
+    int i = x0 + lx - 2;
+    if (i >= g.nx || j >= g.ny) continue;
+    int idx = ly * LE + lx;
+    T s = ((se[idx - 1] + se[idx + 1]) + se[idx - LE]) + se[idx + LE];
+    se[idx] = (s - sr[(ly - 1) * LR + (lx - 1)]) * inv_count<T>(g, i, j);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TY * TX; t += kBlock) {
+    int r = t / TX, c = t - r * TX;
+    int i = x0 + c, j = y0 + r;
+    if (i < g.nx && j < g.ny) ob[(long long)j * g.nx + i] = se[(r + 2) * LE + c + 2];
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Residual + restriction: rc = R (rhs - A'e).  A workgroup covers 64 columns by one row of
+// coarse tiles (n rows); lane = column, wave w takes rows w, w+4, ...  Tile sums are formed
+// with xor shuffles inside groups of n lanes, then across the 4 waves through LDS.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geo g, const T* __restrict__ rhs,
+                                                     const T* __restrict__ e,
+                                                     double* __restrict__ rc,
+                                                     double* __restrict__ psq) {
+  __shared__ double s1[4][16], s2[4][16];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int x0 = blockIdx.x * kWave, J = blockIdx.y;
+  const long long off = (long long)blockIdx.z * g.plane;
+  const T* rb = rhs + off;
+  const T* eb = e + off;
+  const int i = x0 + lane;
+  double acc = 0.0, acc2 = 0.0;
+  if (i < g.nx) {
+    const int iw = g.per_x ? imod(i - 1, g.nx) : i - 1;
+    const int ie = g.per_x ? imod(i + 1, g.nx) : i + 1;
+    const bool hw = g.per_x || i > 0, he = g.per_x || i < g.nx - 1;
+    for (int r = wave; r < g.n; r += 4) {
+      const int j = J * g.n + r;
+      const int js = g.per_y ? imod(j - 1, g.ny) : j - 1;
+      const int jn = g.per_y ? imod(j + 1, g.ny) : j + 1;
+      const bool hs = g.per_y || j > 0, hn = g.per_y || j < g.ny - 1;
+      const T* row = eb + (long long)j * g.nx;
+      T c = row[i];
+      T w = hw ? row[iw] : T(0);
+      T ee = he ? row[ie] : T(0);
+      T s = hs ? eb[(long long)js * g.nx + i] : T(0);
+      T nn = hn ? eb[(long long)jn * g.nx + i] : T(0);
+      T res = rb[(long long)j * g.nx + i] - lap5<T>(c, w, ee, s, nn, hw, he, hs, hn);
+      double d = double(res);
+      acc += d;
+      acc2 += d * d;
+    }
+  }
+  acc = wave_sum_group(acc, g.n);
+  acc2 = wave_sum_group(acc2, g.n);
+  if ((lane & (g.n - 1)) == 0) {
+    s1[wave][lane >> g.log2n] = acc;
+    s2[wave][lane >> g.log2n] = acc2;
+  }
+  __syncthreads();
+  const int tiles = kWave >> g.log2n;
+  if ((int)threadIdx.x < tiles) {
+    const int I = (x0 >> g.log2n) + threadIdx.x;
+    if (I < g.ncx) {
+      const long long o = (long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I;
+      const int t = threadIdx.x;
+      rc[o] = ((s1[0][t] + s1[1][t]) + s1[2][t]) + s1[3][t];
+      if (psq) psq[o] = ((s2[0][t] + s2[1][t]) + s2[2][t]) + s2[3][t];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Prolongation + correction: e (+)= P E, one thread per fine cell.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restrict__ E,
+                                                    T* __restrict__ e, int assign) {
+  const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int j = blockIdx.y * 4 + threadIdx.x / kWave;
+  if (i >= g.nx || j >= g.ny) return;
+  const double* Eb = E + (long long)blockIdx.z * g.cplane;
+  int ilo, jlo;
+  double X, Y;
+  interp_coord(i, g.n, ilo, X);
+  interp_coord(j, g.n, jlo, Y);
+  int ihi = ilo + 1, jhi = jlo + 1;
+  if (g.per_x) {
+    ilo = imod(ilo, g.ncx);
+    ihi = imod(ihi, g.ncx);
+  } else {
+    ilo = max(ilo, 0);
+    ihi = min(ihi, g.ncx - 1);
+  }
+  if (g.per_y) {
+    jlo = imod(jlo, g.ncy);
+    jhi = imod(jhi, g.ncy);
+  } else {
+    jlo = max(jlo, 0);
+    jhi = min(jhi, g.ncy - 1);
+  }
+  const double p = bilinear(Eb[jlo * g.ncx + ilo], Eb[jlo * g.ncx + ihi], Eb[jhi * g.ncx + ilo],
+                            Eb[jhi * g.ncx + ihi], X, Y);
+  T* ec = e + (long long)blockIdx.z * g.plane + (long long)j * g.nx + i;
+  *ec = assign ? T(p) : T(double(*ec) + p);
+}
+
+// ----------------------------------------------------------------------------------------
+// Fused two-level cycle kernel (temporal blocking of the red-black sweeps).
+//
+// A workgroup owns a 64 x 64 tile of fine cells.  It stages e with a halo of H = 2 NU + 1
+// cells and rhs with a halo of 2 NU in LDS, adds the bilinear coarse correction to every
+// staged cell, then performs the 2 NU red/black half-steps on shrinking regions (half-step s
+// updates the tile grown by H - 1 - s rings), so that after the last half-step e is exact on
+// the tile plus one ring.  It then forms the residual on the tile, writes the tile of e and
+// the sums of the residual (and its square) over each n x n coarse tile it contains.
+// Redundant halo work replaces the NU extra round trips through HBM: per cycle the kernel
+// reads e and rhs once and writes e once.
+// ----------------------------------------------------------------------------------------
+template <typename T, int NU, int LOG2N>
+__global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
+                                                  const T* __restrict__ ein,
+                                                  T* __restrict__ eout,
+                                                  const double* __restrict__ E,
+                                                  double* __restrict__ rc,
+                                                  double* __restrict__ psq, int zero_e) {
+  constexpr int TS = 64;
+  constexpr int N = 1 << LOG2N;
+  constexpr int H = 2 * NU + 1;
+  constexpr int LE = TS + 2 * H;
+  constexpr int HR = 2 * NU;
+  constexpr int LR = TS + 2 * HR;
+  constexpr int CE = (TS + 2 * H) / N + 3;
+  constexpr int NBW = (16 >> LOG2N) > 0 ? (16 >> LOG2N) : 1;  // coarse bands per wave
+  __shared__ T se[LE * LE];
+  __shared__ T sr[LR * LR];
+  __shared__ double sE[CE * CE];
+  __shared__ double red1[4][NBW][16];
+  __shared__ double red2[4][NBW][16];
+
+  const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS;
+  const long long off = (long long)blockIdx.z * g.plane;
+  const T* rb = rhs + off;
+  const T* eb = ein + off;
+  T* ob = eout + off;
+  const double* Eb = E + (long long)blockIdx.z * g.cplane;
+
+  // coarse values around the staged region, with the boundary rule applied at load time
+  const int cI0 = floordiv(x0 - H - (N >> 1), N);
+  const int cJ0 = floordiv(y0 - H - (N >> 1), N);
+  for (int t = threadIdx.x; t < CE * CE; t += kBlock) {
+    int cj = t / CE, ci = t - cj * CE;
+    int I = cI0 + ci, J = cJ0 + cj;
+    I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
+    J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
+    sE[t] = Eb[(long long)J * g.ncx + I];
+  }
+  __syncthreads();
+
+  for (int t = threadIdx.x; t < LE * LE; t += kBlock) {
+    int ly = t / LE, lx = t - ly * LE;
+    int gi = x0 + lx - H, gj = y0 + ly - H;
+    int i = gi, j = gj;
+    T v = T(0);
+    if (map_cell(g, i, j)) {
+      int ilo, jlo;
+      double X, Y;
+      interp_coord(gi, N, ilo, X);
+      interp_coord(gj, N, jlo, Y);
+      const double* q = sE + (jlo - cJ0) * CE + (ilo - cI0);
+      double p = bilinear(q[0], q[1], q[CE], q[CE + 1], X, Y);
+      double base = zero_e ? 0.0 : double(eb[(long long)j * g.nx + i]);
+      v = T(base + p);
+    }
+    se[t] = v;
+  }
+  for (int t = threadIdx.x; t < LR * LR; t += kBlock) {
+    int ly = t / LR, lx = t - ly * LR;
+    int i = x0 + lx - HR, j = y0 + ly - HR;
+    T v = T(0);
+    if (map_cell(g, i, j)) v = rb[(long long)j * g.nx + i];
+    sr[t] = v;
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int s = 0; s < 2 * NU; ++s) {
+    const int R = H - 1 - s;  // rings beyond the tile updated in this half-step
+    const int colour = s & 1;
+    const int L = TS + 2 * R;
+    const int HW = L / 2;
+    for (int t = threadIdx.x; t < L * HW; t += kBlock) {
+      int r = t / HW, k = t - r * HW;
+      int ly = H - R + r;
+      int gj = y0 + ly - H;
+      int lx = (H - R) + ((colour + R + gj) & 1) + 2 * k;
+      int gi = x0 + lx - H;
+      int i = gi, j = gj;
+      if (!map_cell(g, i, j)) continue;
+      int idx = ly * LE + lx;
+      T sum = ((se[idx - 1] + se[idx + 1]) + se[idx - LE]) + se[idx + LE];
+      se[idx] = (sum - sr[(ly - 1) * LR + (lx - 1)]) * inv_count<T>(g, i, j);
+    }
+    __syncthreads();
+  }
+
+  // residual on the tile, write-back, per-coarse-tile sums
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int gi = x0 + lane;
+  const bool hw = g.per_x || gi > 0, he = g.per_x || gi < g.nx - 1;
+  double acc[NBW], acc2[NBW];
+#pragma unroll
+  for (int q = 0; q < NBW; ++q) acc[q] = acc2[q] = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    const int r = 16 * wave + rr;
+    const int gj = y0 + r;
+    if (gi < g.nx && gj < g.ny) {
+      const bool hs = g.per_y || gj > 0, hn = g.per_y || gj < g.ny - 1;
+      const int idx = (r + H) * LE + (lane + H);
+      T c = se[idx];
+      T res = sr[(r + HR) * LR + (lane + HR)] -
+              lap5<T>(c, se[idx - 1], se[idx + 1], se[idx - LE], se[idx + LE], hw, he, hs, hn);
+      ob[(long long)gj * g.nx + gi] = c;
+      double d = double(res);
+      const int q = (LOG2N >= 4) ? 0 : (rr >> LOG2N);
+      acc[q] += d;
+      acc2[q] += d * d;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NBW; ++q) {
+    double a = wave_sum_group(acc[q], N);
+    double b = wave_sum_group(acc2[q], N);
+    if ((lane & (N - 1)) == 0) {
+      red1[wave][q][lane >> LOG2N] = a;
+      red2[wave][q][lane >> LOG2N] = b;
+    }
+  }
+  __syncthreads();
+  constexpr int TPS = TS / N;  // coarse tiles per tile side
+  if ((int)threadIdx.x < TPS * TPS) {
+    const int band = threadIdx.x / TPS, tc = threadIdx.x - band * TPS;
+    double a, b;
+    if (LOG2N == 5) {  // a band of 32 rows spans two waves
+      a = red1[2 * band][0][tc] + red1[2 * band + 1][0][tc];
+      b = red2[2 * band][0][tc] + red2[2 * band + 1][0][tc];
+    } else {
+      const int w = band / NBW, q = band - w * NBW;
+      a = red1[w][q][tc];
+      b = red2[w][q][tc];
+    }
+    const int I = (x0 >> LOG2N) + tc, J = (y0 >> LOG2N) + band;
+    if (I < g.ncx && J < g.ncy) {
+      const long long o = (long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I;
+      rc[o] = a;
+      if (psq) psq[o] = b;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Outer FP64 residual: r = h^2 (b - mean b) - A'x, written as T, with per-tile sums of r
+// (the first coarse right-hand side), sum of r^2, max |r| and, on request, the same two for
+// the right-hand side.  Same workgroup layout as k_restrict.
+// ----------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_outer_residual(Geo g, const double* __restrict__ b,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ mean_b,
+                                                           double h2, T* __restrict__ rT,
+                                                           double* __restrict__ rc,
+                                                           Partials pt) {
+  __shared__ double sh[6][4][16];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int x0 = blockIdx.x * kWave, J = blockIdx.y;
+  const long long off = (long long)blockIdx.z * g.plane;
+  const double* bb = b + off;
+  const double* xb = x + off;
+  const double mb = mean_b[blockIdx.z];
+  const int i = x0 + lane;
+  double acc = 0.0, acc2 = 0.0, amax = 0.0, bsq = 0.0, bmax = 0.0;
+  if (i < g.nx) {
+    const int iw = g.per_x ? imod(i - 1, g.nx) : i - 1;
+    const int ie = g.per_x ? imod(i + 1, g.nx) : i + 1;
+    const bool hw = g.per_x || i > 0, he = g.per_x || i < g.nx - 1;
+    for (int r = wave; r < g.n; r += 4) {
+      const int j = J * g.n + r;
+      const int js = g.per_y ? imod(j - 1, g.ny) : j - 1;
+      const int jn = g.per_y ? imod(j + 1, g.ny) : j + 1;
+      const bool hs = g.per_y || j > 0, hn = g.per_y || j < g.ny - 1;
+      const double* row = xb + (long long)j * g.nx;
+      double c = row[i];
+      double w = hw ? row[iw] : 0.0;
+      double ee = he ? row[ie] : 0.0;
+      double s = hs ? xb[(long long)js * g.nx + i] : 0.0;
+      double nn = hn ? xb[(long long)jn * g.nx + i] : 0.0;
+      double bp = h2 * (bb[(long long)j * g.nx + i] - mb);
+      double res = bp - lap5<double>(c, w, ee, s, nn, hw, he, hs, hn);
+      if (rT) rT[off + (long long)j * g.nx + i] = T(res);
+      acc += res;
+      acc2 += res * res;
+      amax = fmax(amax, fabs(res));
+      bsq += bp * bp;
+      bmax = fmax(bmax, fabs(bp));
+    }
+  }
+  acc = wave_sum_group(acc, g.n);
+  acc2 = wave_sum_group(acc2, g.n);
+  amax = wave_max_group(amax, g.n);
+  bsq = wave_sum_group(bsq, g.n);
+  bmax = wave_max_group(bmax, g.n);
+  if ((lane & (g.n - 1)) == 0) {
+    const int t = lane >> g.log2n;
+    sh[0][wave][t] = acc;
+    sh[1][wave][t] = acc2;
+    sh[2][wave][t] = amax;
+    sh[3][wave][t] = bsq;
+    sh[4][wave][t] = bmax;
+  }
+  __syncthreads();
+  const int tiles = kWave >> g.log2n;
+  if ((int)threadIdx.x < tiles) {
+    const int I = (x0 >> g.log2n) + threadIdx.x;
+    if (I < g.ncx) {
+      const long long o = (long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I;
+      const int t = threadIdx.x;
+      if (rc) rc[o] = ((sh[0][0][t] + sh[0][1][t]) + sh[0][2][t]) + sh[0][3][t];
+      if (pt.sumsq) pt.sumsq[o] = ((sh[1][0][t] + sh[1][1][t]) + sh[1][2][t]) + sh[1][3][t];
+      if (pt.maxabs) pt.maxabs[o] = fmax(fmax(sh[2][0][t], sh[2][1][t]), fmax(sh[2][2][t], sh[2][3][t]));
+      if (pt.bsumsq) pt.bsumsq[o] = ((sh[3][0][t] + sh[3][1][t]) + sh[3][2][t]) + sh[3][3][t];
+      if (pt.bmaxabs) pt.bmaxabs[o] = fmax(fmax(sh[4][0][t], sh[4][1][t]), fmax(sh[4][2][t], sh[4][3][t]));
+    }
+  }
+}
+
+// Per-tile sums of a FP64 field (for means).
+__global__ __launch_bounds__(kBlock) void k_tile_sum(Geo g, const double* __restrict__ x,
+                                                     double* __restrict__ part) {
+  __shared__ double s1[4][16];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int x0 = blockIdx.x * kWave, J = blockIdx.y;
+  const double* xb = x + (long long)blockIdx.z * g.plane;
+  const int i = x0 + lane;
+  double acc = 0.0;
+  if (i < g.nx)
+    for (int r = wave; r < g.n; r += 4) acc += xb[(long long)(J * g.n + r) * g.nx + i];
+  acc = wave_sum_group(acc, g.n);
+  if ((lane & (g.n - 1)) == 0) s1[wave][lane >> g.log2n] = acc;
+  __syncthreads();
+  const int tiles = kWave >> g.log2n;
+  if ((int)threadIdx.x < tiles) {
+    const int I = (x0 >> g.log2n) + threadIdx.x;
+    const int t = threadIdx.x;
+    if (I < g.ncx)
+      part[(long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I] =
+          ((s1[0][t] + s1[1][t]) + s1[2][t]) + s1[3][t];
+  }
+}
+
+// Second reduction stage: one workgroup per grid, fixed summation order (reproducible).
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ part, int count,
+                                                     long long stride, int op, double scale,
+                                                     double* __restrict__ out, int out_stride,
+                                                     int slot) {
+  __shared__ double sh[kBlock];
+  const double* p = part + (long long)blockIdx.x * stride;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < count; i += kBlock) a = op == MAX ? fmax(a, p[i]) : a + p[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      double o = sh[threadIdx.x + w];
+      sh[threadIdx.x] = op == MAX ? fmax(sh[threadIdx.x], o) : sh[threadIdx.x] + o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride + slot] = sh[0] * scale;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add_to(long long total, double* __restrict__ x,
+                                                   const T* __restrict__ e) {
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock)
+    x[k] += double(e[k]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub_scalar(long long plane, int batch,
+                                                       double* __restrict__ x,
+                                                       const double* __restrict__ vals,
+                                                       int val_stride, int slot) {
+  const long long total = plane * batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock)
+    x[k] -= vals[(k / plane) * val_stride + slot];
+}
+
+// ----------------------------------------------------------------------------------------
+// Small batched FP64 GEMM for the separable coarse solve: C = op(A) op(B) [.* S].
+// 32 x 32 output tile per workgroup, K staged through LDS in chunks of 32.
+// ----------------------------------------------------------------------------------------
+template <int TA, int TB>
+__global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const double* __restrict__ A,
+                                                 long long sA, int lda,
+                                                 const double* __restrict__ B, long long sB,
+                                                 int ldb, double* __restrict__ C, long long sC,
+                                                 int ldc, const double* __restrict__ S) {
+  constexpr int BT = 32;
+  __shared__ double As[BT][BT + 1];  // [k][m]
+  __shared__ double Bs[BT][BT + 1];  // [k][n]
+  A += (long long)blockIdx.z * sA;
+  B += (long long)blockIdx.z * sB;
+  C += (long long)blockIdx.z * sC;
+  const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+  const int tx = threadIdx.x & (BT - 1), ty = threadIdx.x / BT;  // ty in 0..7
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += BT) {
+    for (int t = threadIdx.x; t < BT * BT; t += kBlock) {
+      const int a = t / BT, c = t - a * BT;
+      {
+        const int m = TA ? c : a, k = TA ? a : c;
+        const int gm = m0 + m, gk = k0 + k;
+        double v = 0.0;
+        if (gm < M && gk < K) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+        As[k][m] = v;
+      }
+      {
+        const int k = TB ? c : a, nn = TB ? a : c;
+        const int gk = k0 + k, gn = n0 + nn;
+        double v = 0.0;
+        if (gk < K && gn < N) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
+        Bs[k][nn] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < BT; ++kk) {
+      const double bv = Bs[kk][tx];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(As[kk][ty + 8 * q], bv, acc[q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gm = m0 + ty + 8 * q, gn = n0 + tx;
+    if (gm < M && gn < N) {
+      double v = acc[q];
+      if (S) v *= S[(long long)gm * N + gn];
+      C[(long long)gm * ldc + gn] = v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Coarse 9-point stencil from the face sums of Eq. 6 (x faces) and Eq. 7 (y faces): for
+// each fine face on a coarse face, the outward derivative of the bilinear interpolant of
+// the coarse unknowns; walls carry no flux and the clamped interpolation folds an
+// off-grid neighbour onto the cell itself.  One thread per coarse cell.
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, double* __restrict__ coef) {
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= g.ncx * g.ncy) return;
+  const int J = cell / g.ncx, I = cell - J * g.ncx;
+  double c[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) c[a][b] = 0.0;
+  const int n = g.n, half = n / 2;
+  const bool openE = g.per_x || I < g.ncx - 1, openW = g.per_x || I > 0;
+  const bool openN = g.per_y || J < g.ncy - 1, openS = g.per_y || J > 0;
+  for (int k = 0; k < n; ++k) {
+    // along the face, the fine centre k of the coarse cell lies between coarse centres
+    // lo and lo + 1 (relative offsets -1/0 or 0/+1) at scaled distance t from the lower one
+    const int lo = k < half ? -1 : 0;
+    const double t = double(2 * k + 1 + (k < half ? n : -n)) / double(2 * n);
+    const double wl = (1.0 - t) / double(n), wh = t / double(n);
+    // x faces (Eq. 6): derivative across the face between columns d and d+1 (relative)
+    if (openE) {  // outward +x, columns 0 -> +1
+      c[lo + 1][2] += wl;
+      c[lo + 1][1] -= wl;
+      c[lo + 2][2] += wh;
+      c[lo + 2][1] -= wh;
+    }
+    if (openW) {  // outward -x, columns -1 -> 0
+      c[lo + 1][1] -= wl;
+      c[lo + 1][0] += wl;
+      c[lo + 2][1] -= wh;
+      c[lo + 2][0] += wh;
+    }
+    // y faces (Eq. 7)
+    if (openN) {
+      c[2][lo + 1] += wl;
+      c[1][lo + 1] -= wl;
+      c[2][lo + 2] += wh;
+      c[1][lo + 2] -= wh;
+    }
+    if (openS) {
+      c[1][lo + 1] -= wl;
+      c[0][lo + 1] += wl;
+      c[1][lo + 2] -= wh;
+      c[0][lo + 2] += wh;
+    }
+  }
+  if (!g.per_x) {
+    if (I == 0)
+      for (int a = 0; a < 3; ++a) {
+        c[a][1] += c[a][0];
+        c[a][0] = 0.0;
+      }
+    if (I == g.ncx - 1)
+      for (int a = 0; a < 3; ++a) {
+        c[a][1] += c[a][2];
+        c[a][2] = 0.0;
+      }
+  }
+  if (!g.per_y) {
+    if (J == 0)
+      for (int b = 0; b < 3; ++b) {
+        c[1][b] += c[0][b];
+        c[0][b] = 0.0;
+      }
+    if (J == g.ncy - 1)
+      for (int b = 0; b < 3; ++b) {
+        c[1][b] += c[2][b];
+        c[2][b] = 0.0;
+      }
+  }
+  double* o = coef + (long long)cell * 9;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) o[3 * a + b] = c[a][b];
+}
+
+// ----------------------------------------------------------------------------------------
+// Staggered-grid operators (FP64).  nxu = number of u faces per row.
+// ----------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_div(Geo g, const double* __restrict__ u,
+                                                const double* __restrict__ v, double h,
+                                                double* __restrict__ b) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long total = g.plane * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / g.plane;
+    const int rem = int(k - bi * g.plane);
+    const int j = rem / g.nx, i = rem - j * g.nx;
+    const double* ub = u + bi * (long long)g.ny * nxu + (long long)j * nxu;
+    const double* vb = v + bi * (long long)(g.ny + 1) * g.nx;
+    const int ie = g.per_x ? (i + 1 == g.nx ? 0 : i + 1) : i + 1;
+    const double du = ub[ie] - ub[i];
+    const double dv = vb[(long long)(j + 1) * g.nx + i] - vb[(long long)j * g.nx + i];
+    b[k] = (du + dv) / h;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_u(Geo g, const double* __restrict__ p, double h,
+                                                   double* __restrict__ gu) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long per = (long long)g.ny * nxu, total = per * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / per;
+    const int rem = int(k - bi * per);
+    const int j = rem / nxu, f = rem - j * nxu;
+    const double* pr = p + bi * g.plane + (long long)j * g.nx;
+    double val;
+    if (g.per_x) val = (pr[f] - pr[f == 0 ? g.nx - 1 : f - 1]) / h;
+    else val = (f == 0 || f == g.nx) ? 0.0 : (pr[f] - pr[f - 1]) / h;
+    gu[k] = val;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_v(Geo g, const double* __restrict__ p, double h,
+                                                   double* __restrict__ gv) {
+  const long long per = (long long)(g.ny + 1) * g.nx, total = per * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / per;
+    const int rem = int(k - bi * per);
+    const int f = rem / g.nx, i = rem - f * g.nx;
+    const double* pb = p + bi * g.plane;
+    gv[k] = (f == 0 || f == g.ny) ? 0.0
+                                  : (pb[(long long)f * g.nx + i] - pb[(long long)(f - 1) * g.nx + i]) / h;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_adjoint_u(Geo g, const double* __restrict__ lam,
+                                                          double h, double* __restrict__ gu) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long per = (long long)g.ny * nxu, total = per * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / per;
+    const int rem = int(k - bi * per);
+    const int j = rem / nxu, f = rem - j * nxu;
+    const double* lr = lam + bi * g.plane + (long long)j * g.nx;
+    double a, c;
+    if (g.per_x) {
+      a = lr[f == 0 ? g.nx - 1 : f - 1];
+      c = lr[f];
+    } else {
+      a = f >= 1 ? lr[f - 1] : 0.0;
+      c = f <= g.nx - 1 ? lr[f] : 0.0;
+    }
+    gu[k] = (a - c) / h;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_adjoint_v(Geo g, const double* __restrict__ lam,
+                                                          double h, double* __restrict__ gv) {
+  const long long per = (long long)(g.ny + 1) * g.nx, total = per * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / per;
+    const int rem = int(k - bi * per);
+    const int f = rem / g.nx, i = rem - f * g.nx;
+    const double* lb = lam + bi * g.plane;
+    const double a = f >= 1 ? lb[(long long)(f - 1) * g.nx + i] : 0.0;
+    const double c = f <= g.ny - 1 ? lb[(long long)f * g.nx + i] : 0.0;
+    gv[k] = (a - c) / h;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_adjoint(Geo g, const double* __restrict__ gu,
+                                                         const double* __restrict__ gv, double h,
+                                                         double* __restrict__ p) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long total = g.plane * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / g.plane;
+    const int rem = int(k - bi * g.plane);
+    const int j = rem / g.nx, i = rem - j * g.nx;
+    const double* ur = gu + bi * (long long)g.ny * nxu + (long long)j * nxu;
+    const double* vb = gv + bi * (long long)(g.ny + 1) * g.nx;
+    double t = 0.0;
+    if (g.per_x) {
+      t = ur[i] - ur[i + 1 == g.nx ? 0 : i + 1];
+    } else {
+      if (i >= 1) t += ur[i];
+      if (i <= g.nx - 2) t -= ur[i + 1];
+    }
+    if (j >= 1) t += vb[(long long)j * g.nx + i];
+    if (j <= g.ny - 2) t -= vb[(long long)(j + 1) * g.nx + i];
+    p[k] = t / h;
+  }
+}
+
+inline unsigned grid_stride_blocks(long long total) {
+  long long b = (total + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return unsigned(b);
+}
+
+inline dim3 strip_grid(const Geo& g) {
+  return dim3((g.nx + kWave - 1) / kWave, g.ncy, g.batch);
+}
+
+template <typename T, int NU, int LOG2N>
+hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                           double* rc, double* psq, int zero_e, hipStream_t s) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 63) / 64, g.batch);
+  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N>), grid, dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc,
+                     psq, zero_e);
+  return hipGetLastError();
+}
+
+template <typename T, int NU>
+hipError_t cycle_dispatch2(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                           double* rc, double* psq, int zero_e, hipStream_t s) {
+  switch (g.log2n) {
+    case 2: return cycle_dispatch3<T, NU, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 3: return cycle_dispatch3<T, NU, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 4: return cycle_dispatch3<T, NU, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 5: return cycle_dispatch3<T, NU, 5>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- launchers
+
+template <typename T>
+hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* ein, T* eout, hipStream_t s) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 31) / 32, g.batch);
+  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(const Geo& g, const T* rhs, const T* e, double* rc, double* psq,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_restrict<T>, strip_grid(g), dim3(kBlock), 0, s, g, rhs, e, rc, psq);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong(const Geo& g, const double* E, T* e, int assign, hipStream_t s) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.batch);
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, s, g, E, e, assign);
+  return hipGetLastError();
+}
+
+int fused_max_nu() { return 4; }
+
+template <typename T>
+hipError_t launch_cycle_fused(const Geo& g, const T* rhs, const T* ein, T* eout,
+                              const double* E, double* rc, double* psq, int nu, int zero_e,
+                              hipStream_t s) {
+  switch (nu) {
+    case 1: return cycle_dispatch2<T, 1>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 2: return cycle_dispatch2<T, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 3: return cycle_dispatch2<T, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 4: return cycle_dispatch2<T, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_outer_residual(const Geo& g, const double* b, const double* x,
+                                 const double* mean_b, double h2, T* rT, double* rc, Partials p,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_residual<T>, strip_grid(g), dim3(kBlock), 0, s, g, b, x, mean_b, h2,
+                     rT, rc, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sum(const Geo& g, const double* x, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_sum, strip_grid(g), dim3(kBlock), 0, s, g, x, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* part, int count, long long part_stride, int batch,
+                           Reduce op, double scale, double* out, int out_stride, int slot,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kBlock), 0, s, part, count, part_stride, int(op),
+                     scale, out, out_stride, slot);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add_to(const Geo& g, double* x, const T* e, hipStream_t s) {
+  const long long total = g.plane * g.batch;
+  hipLaunchKernelGGL(k_add_to<T>, dim3(grid_stride_blocks(total)), dim3(kBlock), 0, s, total, x, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_scalar(const Geo& g, double* x, const double* vals, int val_stride, int slot,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_scalar, dim3(grid_stride_blocks(g.plane * g.batch)), dim3(kBlock), 0, s,
+                     g.plane, g.batch, x, vals, val_stride, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long long sA, int lda,
+                       int transB, const double* B, long long sB, int ldb, double* C, long long sC,
+                       int ldc, const double* S, int batch, hipStream_t s) {
+  dim3 grid((N + 31) / 32, (M + 31) / 32, batch);
+  if (!transA && !transB)
+    hipLaunchKernelGGL((k_gemm<0, 0>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+  else if (transA && !transB)
+    hipLaunchKernelGGL((k_gemm<1, 0>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+  else if (!transA && transB)
+    hipLaunchKernelGGL((k_gemm<0, 1>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+  else
+    hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_assemble(const Geo& g, double* coef, hipStream_t s) {
+  const int cells = g.ncx * g.ncy;
+  hipLaunchKernelGGL(k_coarse_assemble, dim3((cells + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
+                     coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_div, dim3(grid_stride_blocks(g.plane * g.batch)), dim3(kBlock), 0, s, g, u,
+                     v, h, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const Geo& g, const double* p, double h, double* gu, double* gv,
+                       hipStream_t s) {
+  const long long nu_ = (long long)g.ny * (g.per_x ? g.nx : g.nx + 1) * g.batch;
+  const long long nv_ = (long long)(g.ny + 1) * g.nx * g.batch;
+  hipLaunchKernelGGL(k_grad_u, dim3(grid_stride_blocks(nu_)), dim3(kBlock), 0, s, g, p, h, gu);
+  hipLaunchKernelGGL(k_grad_v, dim3(grid_stride_blocks(nv_)), dim3(kBlock), 0, s, g, p, h, gv);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_adjoint(const Geo& g, const double* lam, double h, double* gu, double* gv,
+                              hipStream_t s) {
+  const long long nu_ = (long long)g.ny * (g.per_x ? g.nx : g.nx + 1) * g.batch;
+  const long long nv_ = (long long)(g.ny + 1) * g.nx * g.batch;
+  hipLaunchKernelGGL(k_div_adjoint_u, dim3(grid_stride_blocks(nu_)), dim3(kBlock), 0, s, g, lam, h, gu);
+  hipLaunchKernelGGL(k_div_adjoint_v, dim3(grid_stride_blocks(nv_)), dim3(kBlock), 0, s, g, lam, h, gv);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv, double h,
+                               double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_adjoint, dim3(grid_stride_blocks(g.plane * g.batch)), dim3(kBlock), 0,
+                     s, g, gu, gv, h, p);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_restrict<float>(const Geo&, const float*, const float*, double*, double*, hipStream_t);
+template hipError_t launch_restrict<double>(const Geo&, const double*, const double*, double*, double*, hipStream_t);
+template hipError_t launch_prolong<float>(const Geo&, const double*, float*, int, hipStream_t);
+template hipError_t launch_prolong<double>(const Geo&, const double*, double*, int, hipStream_t);
+template hipError_t launch_cycle_fused<float>(const Geo&, const float*, const float*, float*,
+                                              const double*, double*, double*, int, int, hipStream_t);
+template hipError_t launch_cycle_fused<double>(const Geo&, const double*, const double*, double*,
+                                               const double*, double*, double*, int, int, hipStream_t);
+template hipError_t launch_outer_residual<float>(const Geo&, const double*, const double*,
+                                                 const double*, double, float*, double*, Partials,
+                                                 hipStream_t);
+template hipError_t launch_outer_residual<double>(const Geo&, const double*, const double*,
+                                                  const double*, double, double*, double*, Partials,
+                                                  hipStream_t);
+template hipError_t launch_add_to<float>(const Geo&, double*, const float*, hipStream_t);
+template hipError_t launch_add_to<double>(const Geo&, double*, const double*, hipStream_t);
+
+}  // namespace ism

@@ -1,0 +1,84 @@
+"""Host-side checks of libism.so that need no GPU: it loads, it exports every entry point
+include/ism.h declares, the ctypes structs match the C layout, and invalid configurations
+are rejected with the documented status codes before any device call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1309_7128_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ism.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(ism_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.exported_names())
+
+
+def test_struct_layout():
+    # C layout: 6 int32, 2 double, 2 int32, 2 double, 4 int32
+    assert ctypes.sizeof(L.IsmConfig) == 80
+    assert L.IsmConfig.lx.offset == 24 and L.IsmConfig.rtol.offset == 48
+    assert ctypes.sizeof(L.IsmStats) == 56
+
+
+def test_config_defaults():
+    lib = L.load()
+    cfg = L.IsmConfig()
+    assert lib.ism_config_init(ctypes.byref(cfg), 256, 128, 2) == 0
+    assert (cfg.nx, cfg.ny, cfg.batch, cfg.coarsen, cfg.nu) == (256, 128, 2, 16, 2)
+    assert cfg.lx == 1.0 and cfg.ly == 0.5 and cfg.rtol == 1e-10 and cfg.fused == 1
+    assert lib.ism_config_init(None, 1, 1, 1) == L.ISM_ERR_INVALID
+
+
+def _create(**kw):
+    lib = L.load()
+    cfg = L.IsmConfig()
+    lib.ism_config_init(ctypes.byref(cfg), kw.pop("nx", 64), kw.pop("ny", 64), kw.pop("batch", 1))
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    h = ctypes.c_void_p()
+    code = lib.ism_create(ctypes.byref(cfg), None, ctypes.byref(h))
+    return code, h, lib
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=0), L.ISM_ERR_INVALID),
+    (dict(batch=0), L.ISM_ERR_INVALID),
+    (dict(bc_x=7), L.ISM_ERR_INVALID),
+    (dict(precision=3), L.ISM_ERR_INVALID),
+    (dict(nu=0), L.ISM_ERR_INVALID),
+    (dict(rtol=0.0), L.ISM_ERR_INVALID),
+    (dict(inner_rtol=1.5), L.ISM_ERR_INVALID),
+    (dict(max_cycles=0), L.ISM_ERR_INVALID),
+    (dict(lx=-1.0), L.ISM_ERR_INVALID),
+    (dict(coarsen=12), L.ISM_ERR_UNSUPPORTED),
+    (dict(nx=72, ny=64, lx=72 / 64), L.ISM_ERR_UNSUPPORTED),  # 72 % 16 != 0
+    (dict(ly=2.0), L.ISM_ERR_UNSUPPORTED),                    # non-square cells
+    (dict(nu=5, fused=1), L.ISM_ERR_UNSUPPORTED),
+])
+def test_invalid_configs_rejected_before_device(kw, code):
+    got, h, lib = _create(**kw)
+    assert got == code
+    assert h.value is None
+    assert lib.ism_last_error(None)  # a message is kept
+
+
+def test_null_arguments():
+    lib = L.load()
+    h = ctypes.c_void_p()
+    assert lib.ism_create(None, None, ctypes.byref(h)) == L.ISM_ERR_INVALID
+    assert lib.ism_solve(None, None, None, None) == L.ISM_ERR_INVALID
+    assert lib.ism_destroy(None) == L.ISM_OK
+    assert lib.ism_status_string(L.ISM_NOT_CONVERGED) == b"not converged"
