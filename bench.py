@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the ISM pressure solve on one MI355X.
+
+A step is one whole solve of A x = b - mean(b) from x = 0 to a relative FP64 residual of
+1e-10 (every kernel of the method: outer FP64 residuals, coarse solves, fused
+prolongation + smoothing + restriction cycles, updates, mean removal).  The inputs are
+resident in HBM before the timed region starts.  Default workload: the 8192 x 8192 Neumann
+cavity grid with the smooth-plus-noise right-hand side, 32h tiles, FP32 inner cycles inside
+the FP64 defect-correction loop; the FP64 form on the same grid is measured beside it.
+
+Prints one JSON line.  `value` is Mdof/s = batch * nx * ny / (seconds per solve) / 1e6.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+CYCLE_BYTES = {"mixed": (12, 8), "fp64": (24, 16)}  # per cell: (e read + rhs read + e write, first cycle)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cavity8192_mixed")
+    ap.add_argument("--nu", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the solver is a single-GPU library and this "
+              "benchmark has no multi-GPU mode (run it with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1309_7128_amd import inputs
+    from paper_1309_7128_amd.solver import Solver
+
+    torch.cuda.set_device(0)
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30) // 4)
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+
+    w = inputs.WORKLOADS[args.workload]
+    u, v = inputs.workload_fields(w.name, 0) if w.batch == 1 else (None, None)
+    if w.batch > 1:
+        uv = [inputs.workload_fields(w.name, k) for k in range(w.batch)]
+        u = np.stack([a for a, _ in uv])
+        v = np.stack([c for _, c in uv])
+        del uv
+    cells = w.batch * w.nx * w.ny
+
+    def make(prec):
+        return Solver(w.nx, w.ny, batch=w.batch, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=w.coarsen,
+                      lx=w.lx, ly=w.ly, precision=prec, nu=args.nu, rtol=w.rtol)
+
+    s = make(w.precision)
+    b = s.div(torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda())
+    del u, v
+    x = torch.zeros(s.cell_shape, dtype=torch.float64, device="cuda")
+
+    def run(solver, steps, profile):
+        stats = []
+        torch.cuda.synchronize()
+        if profile:
+            solver.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            _, st = solver.solve(b, x)
+            stats.append(st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = solver.profile_read() if profile else None
+        if profile:
+            solver.profile(False)
+        return dt, stats, prof
+
+    run(s, args.warmup, False)
+    dt, stats, prof = run(s, args.steps, not args.no_profile)
+    ms = 1e3 * dt / args.steps
+    value = cells / (dt / args.steps) / 1e6
+    last = stats[-1]
+    status_ok = all(st["status"] == 0 and st["rel_res_l2"] <= w.rtol for st in stats)
+
+    roofline = None
+    if prof is not None and prof["cycle"][1] > 0:
+        per, first = CYCLE_BYTES[w.precision]
+        launches = prof["cycle"][1]
+        firsts = sum(st["outer_iters"] for st in stats)
+        alg = (per * (launches - firsts) + first * firsts) * cells
+        avg_s = prof["cycle"][0] * 1e-3 / launches
+        achieved = alg / launches / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": f"k_cycle<{'float' if w.precision == 'mixed' else 'double'},{args.nu},"
+                              f"{w.coarsen.bit_length() - 1}>",
+                    "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                    "bytes_per_launch": int(alg / launches)}
+
+    out = {
+        "metric": "Mdof/s solved to 1e-10 rel. residual, ISM mixed vs FP64; smoother HBM GB/s",
+        "value": round(value, 2),
+        "unit": "Mdof/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if w.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "batch": w.batch,
+                   "bc": [w.bc_x, w.bc_y], "coarsen": w.coarsen, "nu": args.nu,
+                   "precision": w.precision, "rtol": w.rtol},
+        "solve": {"cycles": last["cycles"], "outer_iters": last["outer_iters"],
+                  "launches": last["launches"], "host_syncs": last["host_syncs"],
+                  "rel_res_l2": last["rel_res_l2"], "converged": status_ok},
+        "roofline": roofline,
+    }
+    if prof is not None:
+        out["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}
+
+    if not args.no_fp64 and w.precision == "mixed":
+        s.close()
+        s64 = make("fp64")
+        run(s64, 1, False)
+        k64 = max(1, min(3, args.steps))
+        dt64, st64, _ = run(s64, k64, False)
+        out["fp64"] = {"value": round(cells / (dt64 / k64) / 1e6, 2), "unit": "Mdof/s",
+                       "ms_per_step": round(1e3 * dt64 / k64, 3), "steps": k64,
+                       "cycles": st64[-1]["cycles"], "rel_res_l2": st64[-1]["rel_res_l2"]}
+        out["mixed_over_fp64"] = round(value / out["fp64"]["value"], 3)
+        s64.close()
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, b, last["cycles"], last["outer_iters"], args.nu)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, b_dev, gpu_cycles, gpu_outer, nu):
+    """The CPU oracle on the same input: one outer residual and one inner cycle of its ISM
+    iteration (in the precision form of the workload) timed on the host, extrapolated to the
+    number of cycles and outer steps the GPU solve took."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ism_oracle as O
+
+    b = b_dev.cpu().numpy()
+    if w.batch > 1:
+        b = b[0]
+    b = b.reshape(w.ny, w.nx)
+    bx, by, n, h = w.bc_x, w.bc_y, w.coarsen, w.h
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        cs = O.CoarseSolver(O.coarse_matrix(O.coarse_stencil_ism(w.nx // n, w.ny // n, n, bx, by), bx, by))
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        bp = h * h * (b - b.mean())
+        x = np.zeros_like(bp)
+        r = bp - O.laplacian(x, bx, by)
+        t_outer = time.perf_counter() - t0
+        ft = np.float32 if w.precision == "mixed" else np.float64
+        rT = r.astype(ft)
+        Rc = O.restrict_sum(r, n)
+        e = np.zeros_like(rT)
+        t0 = time.perf_counter()
+        E = cs.solve(Rc)
+        e = (e.astype(np.float64) + O.prolong_bilinear(E, n, bx, by)).astype(ft)
+        e = O.red_black_gs(e, rT, bx, by, sweeps=nu)
+        res = rT - O.laplacian(e, bx, by)
+        Rc = O.restrict_sum(res.astype(np.float64), n)
+        t_cycle = time.perf_counter() - t0
+    total = (gpu_cycles * t_cycle + (gpu_outer + 1) * t_outer) * w.batch
+    return {"value": round(w.nx * w.ny * w.batch / total / 1e6, 5), "unit": "Mdof/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one inner cycle ({t_cycle:.1f} s) and one outer residual ({t_outer:.1f} s) "
+                      f"of the oracle's ISM iteration on grid 0 of the same input, single thread, "
+                      f"extrapolated to the GPU solve's {gpu_cycles} cycles and {gpu_outer} outer "
+                      f"steps per grid; oracle coarse factorization ({t_setup:.1f} s) excluded like "
+                      f"the library's setup"}
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,22 @@ int ism_coarse_stencil(ism_handle h, double* coef);
  * residual, difference form). */
 int ism_outer_residual(ism_handle h, const double* b, const double* x, double* r);
 
+/* ---- Kernel timing.  While enabled, the handle brackets every launch of the kernel classes
+ * below with a pair of HIP events on its stream and accumulates their elapsed times at its
+ * host synchronizations (the events are created once and reused).  ism_profile(h, 1) resets
+ * the totals and starts timing, ism_profile(h, 0) stops it; ism_profile_read synchronizes
+ * the stream and returns the total milliseconds and the number of timed launches of one
+ * class since the last reset. */
+#define ISM_KERNEL_CYCLE 0    /* fused two-level cycle kernel                        */
+#define ISM_KERNEL_SMOOTH 1   /* one red-black sweep (unfused form)                  */
+#define ISM_KERNEL_RESTRICT 2 /* residual + restriction (unfused form)               */
+#define ISM_KERNEL_PROLONG 3  /* prolongation + correction (unfused form)            */
+#define ISM_KERNEL_COARSE 4   /* the four transform passes of one coarse solve       */
+#define ISM_KERNEL_OUTER 5    /* FP64 outer residual                                 */
+#define ISM_KERNEL_CLASSES 6
+int ism_profile(ism_handle h, int32_t enable);
+int ism_profile_read(ism_handle h, int32_t kind, double* total_ms, int64_t* launches);
+
 const char* ism_status_string(int status);
 const char* ism_last_error(ism_handle h);
 

@@ -26,6 +26,7 @@ ISM_PREC_FP64 = 0
 ISM_PREC_MIXED = 1
 ISM_F64 = 0
 ISM_F32 = 1
+KERNEL_CLASSES = {"cycle": 0, "smooth": 1, "restrict": 2, "prolong": 3, "coarse": 4, "outer": 5}
 
 
 class IsmConfig(ctypes.Structure):
@@ -73,6 +74,9 @@ _SIGNATURES = {
     "ism_cycle": (ctypes.c_int, [_P, _I, _P, _P, _P, _I, _P]),
     "ism_coarse_stencil": (ctypes.c_int, [_P, _P]),
     "ism_outer_residual": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ism_profile": (ctypes.c_int, [_P, _I]),
+    "ism_profile_read": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]),
     "ism_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ism_last_error": (ctypes.c_char_p, [_P]),
 }

@@ -53,6 +53,17 @@ struct ism_ctx {
   double* h_scal = nullptr;   // pinned mirror of scal
   std::string err;
   int64_t launches = 0, syncs = 0;
+  // kernel timing (ism_profile): event pairs recorded around launches, resolved at syncs
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<Pending> pending;
+  double prof_ms[ISM_KERNEL_CLASSES] = {};
+  int64_t prof_n[ISM_KERNEL_CLASSES] = {};
 };
 
 namespace {
@@ -75,6 +86,44 @@ int set_err(ism_ctx* c, int code, const std::string& msg) {
     (ctx)->launches++;      \
     HIPCHK(ctx, (expr));    \
   } while (0)
+
+// ---- kernel timing
+hipEvent_t prof_event(ism_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+hipEvent_t prof_start(ism_ctx* c) {
+  if (!c->prof) return nullptr;
+  hipEvent_t a = prof_event(c);
+  if (a) (void)hipEventRecord(a, c->stream);
+  return a;
+}
+
+void prof_stop(ism_ctx* c, int kind, hipEvent_t a) {
+  if (!c->prof || !a) return;
+  hipEvent_t b = prof_event(c);
+  if (!b) return;
+  (void)hipEventRecord(b, c->stream);
+  c->pending.push_back({kind, a, b});
+}
+
+// Resolve the recorded pairs; only called after the stream has been synchronized.
+void prof_collect(ism_ctx* c) {
+  for (const auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_ms[p.kind] += ms;
+      c->prof_n[p.kind]++;
+    }
+  }
+  c->pending.clear();
+  c->ev_used = 0;
+}
 
 bool is_pow2_coarsen(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
 
@@ -168,6 +217,7 @@ int read_scalars(ism_ctx* c) {
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->syncs++;
+  prof_collect(c);
   return ISM_OK;
 }
 
@@ -192,19 +242,29 @@ template <typename T>
 int run_cycle(ism_ctx* c, const T* rhs, T** cur, T** spare, double* rc, double* psq, int zero_e) {
   const Geo& g = c->g;
   hipStream_t s = c->stream;
+  hipEvent_t ev = prof_start(c);
   int rcode = coarse_solve(c, rc, c->E);
   if (rcode) return rcode;
+  prof_stop(c, ISM_KERNEL_COARSE, ev);
   if (c->cfg.fused) {
+    ev = prof_start(c);
     LAUNCH(c, ism::launch_cycle_fused<T>(g, rhs, *cur, *spare, c->E, rc, psq, c->cfg.nu, zero_e, s));
+    prof_stop(c, ISM_KERNEL_CYCLE, ev);
     std::swap(*cur, *spare);
     return ISM_OK;
   }
+  ev = prof_start(c);
   LAUNCH(c, ism::launch_prolong<T>(g, c->E, *cur, zero_e, s));
+  prof_stop(c, ISM_KERNEL_PROLONG, ev);
   for (int k = 0; k < c->cfg.nu; ++k) {
+    ev = prof_start(c);
     LAUNCH(c, ism::launch_rbgs<T>(g, rhs, *cur, *spare, s));
+    prof_stop(c, ISM_KERNEL_SMOOTH, ev);
     std::swap(*cur, *spare);
   }
+  ev = prof_start(c);
   LAUNCH(c, ism::launch_restrict<T>(g, rhs, *cur, rc, psq, s));
+  prof_stop(c, ISM_KERNEL_RESTRICT, ev);
   return ISM_OK;
 }
 
@@ -307,8 +367,10 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   double rel_l2 = 0.0, rel_max = 0.0;
   for (bool first = true;; first = false) {
     Partials p{c->p_sq, c->p_max, first ? c->p_bsq : nullptr, first ? c->p_bmax : nullptr};
+    hipEvent_t ev = prof_start(c);
     LAUNCH(c, ism::launch_outer_residual<T>(g, b, x, c->scal + size_t(MEAN_B) * B, c->h2, (T*)c->rT,
                                             c->rc, p, s));
+    prof_stop(c, ISM_KERNEL_OUTER, ev);
     if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
     if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
     if (first) {
@@ -355,6 +417,7 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   }
   HIPCHK(c, hipStreamSynchronize(s));
   c->syncs++;
+  prof_collect(c);
   if (st) {
     st->status = status;
     st->outer_iters = outer;
@@ -497,6 +560,7 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
 int ism_destroy(ism_handle c) {
   if (!c) return ISM_OK;
   (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->stage_tmp) (void)hipFree(c->stage_tmp);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   if (c->block) (void)hipFree(c->block);
@@ -655,6 +719,29 @@ int ism_outer_residual(ism_handle c, const double* b, const double* x, double* r
   Partials p{nullptr, nullptr, nullptr, nullptr};
   LAUNCH(c, ism::launch_outer_residual<double>(c->g, b, x, c->scal + size_t(MEAN_B) * c->g.batch, c->h2,
                                                r, nullptr, p, c->stream));
+  return ISM_OK;
+}
+
+int ism_profile(ism_handle c, int32_t enable) {
+  if (!c) return ISM_ERR_INVALID;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  for (int k = 0; k < ISM_KERNEL_CLASSES; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  c->prof = enable != 0;
+  return ISM_OK;
+}
+
+int ism_profile_read(ism_handle c, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!c) return ISM_ERR_INVALID;
+  if (kind < 0 || kind >= ISM_KERNEL_CLASSES || !total_ms || !launches)
+    return set_err(c, ISM_ERR_INVALID, "bad kernel class or NULL output");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
+  *total_ms = c->prof_ms[kind];
+  *launches = c->prof_n[kind];
   return ISM_OK;
 }
 

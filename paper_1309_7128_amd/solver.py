@@ -250,6 +250,20 @@ class Solver:
                                             self._arg(r, self.cell_shape)), self.handle)
         return r
 
+    def profile(self, enable=True):
+        """Start (reset) or stop per-kernel-class event timing inside the library."""
+        _check(self._lib.ism_profile(self.handle, int(bool(enable))), self.handle)
+
+    def profile_read(self):
+        """{class: (total_ms, launches)} since the last profile(True)."""
+        out = {}
+        for name, kind in L.KERNEL_CLASSES.items():
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(self._lib.ism_profile_read(self.handle, kind, ctypes.byref(ms), ctypes.byref(n)),
+                   self.handle)
+            out[name] = (ms.value, n.value)
+        return out
+
     def workspace_bytes(self):
         n = ctypes.c_size_t()
         _check(self._lib.ism_workspace_bytes(self.handle, ctypes.byref(n)), self.handle)
