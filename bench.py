@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (counter calibration)")
+    ap.add_argument("--cycles-only", type=int, default=0,
+                    help="only run this many fused cycles on the workload grid (short program "
+                         "for hardware-counter passes)")
     return ap.parse_args()
 
 
@@ -67,6 +70,8 @@ def main():
         return
 
     w = inputs.WORKLOADS[args.workload]
+    if args.cycles_only > 0:
+        return cycles_only(w, args)
     u, v = inputs.workload_fields(w.name, 0) if w.batch == 1 else (None, None)
     if w.batch > 1:
         uv = [inputs.workload_fields(w.name, k) for k in range(w.batch)]
@@ -163,6 +168,32 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, b, last["cycles"], last["outer_iters"], args.nu)
 
     print(json.dumps(out), flush=True)
+
+
+def cycles_only(w, args):
+    """A few fused two-level cycles on the workload grid (no convergence loop)."""
+    import torch
+
+    from paper_1309_7128_amd.solver import Solver
+
+    s = Solver(w.nx, w.ny, batch=w.batch, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=w.coarsen, lx=w.lx,
+               ly=w.ly, precision=w.precision, nu=args.nu, rtol=w.rtol)
+    dt = torch.float32 if w.precision == "mixed" else torch.float64
+    g = torch.Generator(device="cuda").manual_seed(5)
+    rhs = torch.randn(s.cell_shape, device="cuda", dtype=dt, generator=g)
+    e = torch.zeros(s.cell_shape, device="cuda", dtype=dt)
+    rc = s.restrict(rhs, e)
+    s.cycle(rhs, e, rc, zero_e=True)
+    s.profile(True)
+    for _ in range(args.cycles_only):
+        s.cycle(rhs, e, rc)
+    prof = s.profile_read()
+    ms, n = prof["cycle"]
+    cells = w.batch * w.nx * w.ny
+    per = CYCLE_BYTES[w.precision][0]
+    print(json.dumps({"cycles": n, "avg_launch_us": 1e3 * ms / max(n, 1),
+                      "achieved_GBs": per * cells / (1e-3 * ms / max(n, 1)) / 1e9 if n else None,
+                      "coarse_avg_us": 1e3 * prof["coarse"][0] / max(prof["coarse"][1], 1)}))
 
 
 def cpu_baseline(w, b_dev, gpu_cycles, gpu_outer, nu):

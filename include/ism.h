@@ -79,6 +79,8 @@ typedef struct {
                          cycle that meets the target from the measured rate)               */
   int32_t fused;      /* 1: one fused kernel per cycle (prolongation, nu sweeps, residual
                          and restriction); 0: one kernel per step                          */
+  int32_t stall_window; /* an inner solve also stops when its residual fell by less than   */
+  double stall_drop;    /* stall_drop (a fraction) over the last >= stall_window cycles     */
 } ism_config;
 
 typedef struct {
@@ -95,7 +97,8 @@ typedef struct {
 } ism_stats;
 
 /* Fill cfg with defaults for an nx x ny grid of unit cell size 1/nx (unit square), Neumann
- * walls, coarsen 16, FP64, nu 2, rtol 1e-10, inner_rtol 1e-3, adaptive checks, fused. */
+ * walls, coarsen 16, FP64, nu 2, rtol 1e-10, inner_rtol 1e-3, adaptive checks, fused,
+ * stall_window 8, stall_drop 0.02. */
 int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch);
 
 /* Validate cfg, allocate the handle's device workspace and build the coarse tables

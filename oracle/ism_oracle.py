@@ -569,7 +569,7 @@ def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
 
 
 def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
-                    inner_rtol=1e-3, stall_window=8, stall_drop=0.01, max_inner=100000,
+                    inner_rtol=1e-3, stall_window=8, stall_drop=0.02, max_inner=100000,
                     max_outer=50):
     """ISM with FP32 fine arithmetic inside an FP64 defect-correction loop (emulated).
 

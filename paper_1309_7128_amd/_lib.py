@@ -38,6 +38,7 @@ class IsmConfig(ctypes.Structure):
         ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
         ("max_cycles", ctypes.c_int32), ("max_outer", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("fused", ctypes.c_int32),
+        ("stall_window", ctypes.c_int32), ("stall_drop", ctypes.c_double),
     ]
 
 

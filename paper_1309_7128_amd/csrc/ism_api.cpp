@@ -28,8 +28,6 @@ enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, kSlots };
 thread_local std::string g_create_error;
 
 constexpr double kInnerMargin = 0.5;  // FP64 inner target = margin * rtol * ||b'||
-constexpr int kStallWindow = 8;       // cycles over which an inner residual must fall ...
-constexpr double kStallDrop = 0.01;   // ... by at least this fraction
 
 }  // namespace
 
@@ -145,6 +143,8 @@ int validate(const ism_config* cfg, std::string& why) {
   if (cfg->max_cycles < 1 || cfg->max_outer < 1 || cfg->check_every < 0)
     return why = "max_cycles and max_outer must be >= 1, check_every >= 0", ISM_ERR_INVALID;
   if (cfg->fused != 0 && cfg->fused != 1) return why = "fused must be 0 or 1", ISM_ERR_INVALID;
+  if (cfg->stall_window < 1 || !(cfg->stall_drop >= 0.0) || !(cfg->stall_drop < 1.0))
+    return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
   if (!is_pow2_coarsen(cfg->coarsen))
     return why = "coarsen must be 4, 8, 16 or 32", ISM_ERR_UNSUPPORTED;
   if (cfg->nx % cfg->coarsen || cfg->ny % cfg->coarsen)
@@ -308,17 +308,17 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
     if (!finite) return set_err(c, ISM_ERR_NONFINITE, "non-finite residual in the inner iteration");
     hist.push_back(ck);
     if (done || cycles >= c->cfg.max_cycles) break;
-    // stagnation: the newest check against the latest one at least kStallWindow cycles older
+    // stagnation: the newest check against the latest one at least stall_window cycles older
     const Check* old = nullptr;
     for (auto it = hist.rbegin(); it != hist.rend(); ++it)
-      if (it->cycle <= k - kStallWindow) {
+      if (it->cycle <= k - c->cfg.stall_window) {
         old = &*it;
         break;
       }
     if (old) {
       bool stalled = true;
       for (int b = 0; b < B; ++b)
-        if (ck.res[b] > target[b] && ck.res[b] < (1.0 - kStallDrop) * old->res[b]) stalled = false;
+        if (ck.res[b] > target[b] && ck.res[b] < (1.0 - c->cfg.stall_drop) * old->res[b]) stalled = false;
       if (stalled) break;
     }
     // schedule the next check
@@ -458,6 +458,8 @@ int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch) {
   cfg->max_outer = 50;
   cfg->check_every = 0;
   cfg->fused = 1;
+  cfg->stall_window = 8;
+  cfg->stall_drop = 0.02;
   return ISM_OK;
 }
 

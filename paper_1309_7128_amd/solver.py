@@ -46,7 +46,7 @@ class Solver:
     def __init__(self, nx, ny, batch=1, bc_x="neumann", bc_y="neumann", coarsen=16, lx=1.0,
                  ly=None, precision="fp64", nu=2, rtol=1e-10, inner_rtol=1e-3,
                  max_cycles=100000, max_outer=50, check_every=0, fused=True, device=None,
-                 raise_not_converged=False):
+                 raise_not_converged=False, stall_window=None, stall_drop=None):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the ISM solver runs on a GPU; torch.cuda is not available")
@@ -66,6 +66,10 @@ class Solver:
         cfg.max_outer = max_outer
         cfg.check_every = check_every
         cfg.fused = int(bool(fused))
+        if stall_window is not None:
+            cfg.stall_window = stall_window
+        if stall_drop is not None:
+            cfg.stall_drop = stall_drop
         self.cfg = cfg
         self.nx, self.ny, self.batch = nx, ny, batch
         self.bc_x, self.bc_y = bc_x, bc_y
