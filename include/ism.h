@@ -56,6 +56,10 @@ extern "C" {
                             defect-correction loop; outer residual, mean removal, the
                             coarse solve and the update of x stay FP64                     */
 
+#define ISM_COARSE_ISM 0  /* interpolated 9-point coarse stencil (Sec. 3.3, Eq. 5-7)            */
+#define ISM_COARSE_GMG5 1 /* 5-point stencil rediscretized at spacing n h: the aggressive-
+                             coarsening GMG scheme the paper compares with (Sec. 4.3.2)         */
+
 #define ISM_F64 0 /* element type selector of the stage entry points: double */
 #define ISM_F32 1 /*                                                  float  */
 
@@ -81,6 +85,8 @@ typedef struct {
                          and restriction); 0: one kernel per step                          */
   int32_t stall_window; /* an inner solve also stops when its residual fell by less than   */
   double stall_drop;    /* stall_drop (a fraction) over the last >= stall_window cycles     */
+  int32_t coarse_stencil; /* ISM_COARSE_ISM (default) or ISM_COARSE_GMG5                    */
+  int32_t reserved;       /* must be 0                                                      */
 } ism_config;
 
 typedef struct {
@@ -153,7 +159,8 @@ int ism_restrict(ism_handle h, int32_t dtype, const void* rhs, const void* e, do
 int ism_prolong(ism_handle h, int32_t dtype, const double* E, void* e);
 
 /* E = zero-mean solution of A_c E = rc - mean(rc) on each grid's coarse grid, where A_c is
- * the interpolated 9-point stencil (Sec. 3.3, Eq. 6-7).  Exact up to FP64 rounding. */
+ * the interpolated 9-point stencil (Sec. 3.3, Eq. 6-7), or the 5-point one when the handle
+ * was created with ISM_COARSE_GMG5.  Exact up to FP64 rounding. */
 int ism_coarse_solve(ism_handle h, const double* rc, double* E);
 
 /* One two-level cycle on A' e = rhs: E = coarse solve of rc; e += P E; nsweeps red-black
@@ -162,7 +169,8 @@ int ism_coarse_solve(ism_handle h, const double* rc, double* E);
 int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
               int32_t zero_e, double* sumsq);
 
-/* The coarse 9-point stencil assembled on the device from the face sums of Eq. 6-7:
+/* The coarse stencil assembled on the device (ISM: from the face sums of Eq. 6-7; GMG5:
+ * the 5-point stencil with one-sided wall rows):
  * coef is FP64 [ny/n][nx/n][9]; entry 3*(dj+1) + (di+1) multiplies the unknown at
  * (J+dj, I+di) (wrapped on a periodic axis; a wall contribution is folded onto the unknown
  * the clamped interpolation uses). */

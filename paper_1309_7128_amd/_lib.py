@@ -24,6 +24,8 @@ ISM_BC_NEUMANN = 0
 ISM_BC_PERIODIC = 1
 ISM_PREC_FP64 = 0
 ISM_PREC_MIXED = 1
+ISM_COARSE_ISM = 0
+ISM_COARSE_GMG5 = 1
 ISM_F64 = 0
 ISM_F32 = 1
 KERNEL_CLASSES = {"cycle": 0, "smooth": 1, "restrict": 2, "prolong": 3, "coarse": 4, "outer": 5}
@@ -39,6 +41,7 @@ class IsmConfig(ctypes.Structure):
         ("max_cycles", ctypes.c_int32), ("max_outer", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("fused", ctypes.c_int32),
         ("stall_window", ctypes.c_int32), ("stall_drop", ctypes.c_double),
+        ("coarse_stencil", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -27,7 +27,11 @@ enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, kSlots };
 
 thread_local std::string g_create_error;
 
-constexpr double kInnerMargin = 0.5;  // FP64 inner target = margin * rtol * ||b'||
+// An inner solve's residual target never goes below margin * rtol * ||b'||.  In FP64 the inner
+// residual r - A'e is the outer residual up to rounding, so the margin is 1; the FP32 inner
+// residual only estimates it, so the mixed form aims at half the tolerance.
+constexpr double kInnerMarginFP64 = 1.0;
+constexpr double kInnerMarginMixed = 0.5;
 
 }  // namespace
 
@@ -143,6 +147,9 @@ int validate(const ism_config* cfg, std::string& why) {
   if (cfg->max_cycles < 1 || cfg->max_outer < 1 || cfg->check_every < 0)
     return why = "max_cycles and max_outer must be >= 1, check_every >= 0", ISM_ERR_INVALID;
   if (cfg->fused != 0 && cfg->fused != 1) return why = "fused must be 0 or 1", ISM_ERR_INVALID;
+  if (cfg->coarse_stencil != ISM_COARSE_ISM && cfg->coarse_stencil != ISM_COARSE_GMG5)
+    return why = "coarse_stencil must be ISM_COARSE_ISM or ISM_COARSE_GMG5", ISM_ERR_INVALID;
+  if (cfg->reserved != 0) return why = "reserved must be 0", ISM_ERR_INVALID;
   if (cfg->stall_window < 1 || !(cfg->stall_drop >= 0.0) || !(cfg->stall_drop < 1.0))
     return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
   if (!is_pow2_coarsen(cfg->coarsen))
@@ -393,8 +400,9 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
       rel_l2 = std::max(rel_l2, rn / den[k]);
       rel_max = std::max(rel_max, rm / (bmax[k] > 0.0 ? bmax[k] : 1.0));
       conv = conv && rn <= c->cfg.rtol * den[k];
-      const double inner = c->cfg.precision == ISM_PREC_FP64 ? 0.0 : c->cfg.inner_rtol * rn;
-      target[k] = std::max(inner, kInnerMargin * c->cfg.rtol * den[k]);
+      const bool fp64 = c->cfg.precision == ISM_PREC_FP64;
+      const double inner = fp64 ? 0.0 : c->cfg.inner_rtol * rn;
+      target[k] = std::max(inner, (fp64 ? kInnerMarginFP64 : kInnerMarginMixed) * c->cfg.rtol * den[k]);
     }
     if (!finite) {
       status = set_err(c, ISM_ERR_NONFINITE, "non-finite value in b, x or the residual");
@@ -539,7 +547,8 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     for (int k = 0; k < g.ncx; ++k) {
       const double kx = -2.0 * (1.0 - std::cos(thx[k])), mx = (3.0 + std::cos(thx[k])) / 4.0;
       const double ky = -2.0 * (1.0 - std::cos(thy[l])), my = (3.0 + std::cos(thy[l])) / 4.0;
-      const double lam = kx * my + mx * ky;
+      // ISM: K_x (x) M_y + M_x (x) K_y; GMG5: K_x (x) I + I (x) K_y
+      const double lam = cfg->coarse_stencil == ISM_COARSE_GMG5 ? kx + ky : kx * my + mx * ky;
       inv[size_t(l) * g.ncx + k] = (l == 0 && k == 0) ? 0.0 : 1.0 / lam;
     }
   he = hipMemcpyAsync(c->Vx, Vx.data(), sizeof(double) * Vx.size(), hipMemcpyHostToDevice, c->stream);
@@ -708,7 +717,7 @@ int ism_cycle(ism_handle c, int32_t dtype, const void* rhs, void* e, double* rc,
 int ism_coarse_stencil(ism_handle c, double* coef) {
   if (!c) return ISM_ERR_INVALID;
   if (!coef) return set_err(c, ISM_ERR_INVALID, "bad arguments");
-  LAUNCH(c, ism::launch_coarse_assemble(c->g, coef, c->stream));
+  LAUNCH(c, ism::launch_coarse_assemble(c->g, c->cfg.coarse_stencil == ISM_COARSE_GMG5, coef, c->stream));
   return ISM_OK;
 }
 

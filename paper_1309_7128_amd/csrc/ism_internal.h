@@ -71,7 +71,7 @@ hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long lo
                        int transB, const double* B, long long sB, int ldb, double* C,
                        long long sC, int ldc, const double* S, int batch, hipStream_t s);
 
-hipError_t launch_coarse_assemble(const Geo& g, double* coef, hipStream_t s);
+hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStream_t s);
 
 hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
                       hipStream_t s);

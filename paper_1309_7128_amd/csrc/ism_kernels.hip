@@ -620,7 +620,8 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
 // the coarse unknowns; walls carry no flux and the clamped interpolation folds an
 // off-grid neighbour onto the cell itself.  One thread per coarse cell.
 // ----------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, double* __restrict__ coef) {
+__global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
+                                                            double* __restrict__ coef) {
   const int cell = blockIdx.x * kBlock + threadIdx.x;
   if (cell >= g.ncx * g.ncy) return;
   const int J = cell / g.ncx, I = cell - J * g.ncx;
@@ -630,7 +631,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, double* __res
   const int n = g.n, half = n / 2;
   const bool openE = g.per_x || I < g.ncx - 1, openW = g.per_x || I > 0;
   const bool openN = g.per_y || J < g.ncy - 1, openS = g.per_y || J > 0;
-  for (int k = 0; k < n; ++k) {
+  if (gmg5) {  // unit 5-point stencil at the coarse spacing, no flux through a wall
+    if (openE) c[1][2] += 1.0, c[1][1] -= 1.0;
+    if (openW) c[1][0] += 1.0, c[1][1] -= 1.0;
+    if (openN) c[2][1] += 1.0, c[1][1] -= 1.0;
+    if (openS) c[0][1] += 1.0, c[1][1] -= 1.0;
+  }
+  for (int k = 0; k < (gmg5 ? 0 : n); ++k) {
     // along the face, the fine centre k of the coarse cell lies between coarse centres
     // lo and lo + 1 (relative offsets -1/0 or 0/+1) at scaled distance t from the lower one
     const int lo = k < half ? -1 : 0;
@@ -930,10 +937,10 @@ hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long lo
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_assemble(const Geo& g, double* coef, hipStream_t s) {
+hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStream_t s) {
   const int cells = g.ncx * g.ncy;
   hipLaunchKernelGGL(k_coarse_assemble, dim3((cells + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
-                     coef);
+                     gmg5, coef);
   return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ class Solver:
     def __init__(self, nx, ny, batch=1, bc_x="neumann", bc_y="neumann", coarsen=16, lx=1.0,
                  ly=None, precision="fp64", nu=2, rtol=1e-10, inner_rtol=1e-3,
                  max_cycles=100000, max_outer=50, check_every=0, fused=True, device=None,
-                 raise_not_converged=False, stall_window=None, stall_drop=None):
+                 raise_not_converged=False, stall_window=None, stall_drop=None,
+                 coarse_stencil="ism"):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the ISM solver runs on a GPU; torch.cuda is not available")
@@ -70,6 +71,7 @@ class Solver:
             cfg.stall_window = stall_window
         if stall_drop is not None:
             cfg.stall_drop = stall_drop
+        cfg.coarse_stencil = {"ism": L.ISM_COARSE_ISM, "gmg5": L.ISM_COARSE_GMG5}[coarse_stencil]
         self.cfg = cfg
         self.nx, self.ny, self.batch = nx, ny, batch
         self.bc_x, self.bc_y = bc_x, bc_y

@@ -200,3 +200,19 @@ def test_batch8x1024_mixed():
     b, x = host(b_d), host(x)
     for k in range(w.batch):
         _check_full(b[k], x[k], w.h, N, w.rtol, 1e-5)
+
+
+@pytest.mark.parametrize("scheme", ["ism", "gmg5"])
+def test_gmg5_vs_ism_cycle_counts_match_oracle(scheme):
+    """The aggressive-coarsening 5-point variant (Sec. 4.3.2) against the oracle's, and ISM
+    needing fewer cycles than it."""
+    announce("gmg5_counts", scheme)
+    nx = ny = 256
+    rng = np.random.default_rng(220)
+    b = rng.standard_normal((ny, nx))
+    s = solver(nx=nx, ny=ny, coarsen=16, precision="fp64", rtol=1e-10, check_every=1,
+               coarse_stencil=scheme)
+    x, st = s.solve(dev(b))
+    assert O.relative_residual(b, host(x).reshape(ny, nx), 1 / nx) <= 1e-10
+    _, info = O.ism_solve(b, 1 / nx, 16, nu=2, rtol=1e-10, stencil=scheme)
+    assert abs(st["cycles"] - info["cycles"]) <= 1

@@ -226,3 +226,19 @@ def test_mac_operators_bitwise(bx):
         np.testing.assert_array_equal(dv[k], rdv)
         np.testing.assert_allclose(gp[k], O.grad_adjoint(u[k], v[k], h, bx), rtol=0,
                                    atol=1e-15 * np.abs(gp[k]).max())
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=_ids)
+def test_gmg5_stencil_and_coarse_solve(case):
+    announce("gmg5_stencil", case)
+    nx, ny, n, bx, by = case
+    s = _mk(case, batch=2, coarse_stencil="gmg5")
+    got = host(s.coarse_stencil())
+    ref = O.coarse_stencil_gmg5(nx // n, ny // n, n, bx, by)
+    np.testing.assert_array_equal(got, ref)
+    Rc = np.random.default_rng(120).standard_normal((2, ny // n, nx // n))
+    E = host(s.coarse_solve(dev(Rc)))
+    cs = O.CoarseSolver(O.coarse_matrix(ref, bx, by))
+    for b in range(2):
+        r = cs.solve(Rc[b])
+        np.testing.assert_allclose(E[b], r, rtol=0, atol=1e-12 * np.abs(r).max())

@@ -27,9 +27,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout():
-    # C layout: 6 int32, 2 double, 2 int32, 2 double, 5 int32 (+4 padding), 1 double
-    assert ctypes.sizeof(L.IsmConfig) == 96
-    assert L.IsmConfig.stall_drop.offset == 88
+    # C layout: 6 int32, 2 double, 2 int32, 2 double, 5 int32 (+4 padding), 1 double, 2 int32
+    assert ctypes.sizeof(L.IsmConfig) == 104
+    assert L.IsmConfig.stall_drop.offset == 88 and L.IsmConfig.coarse_stencil.offset == 96
     assert L.IsmConfig.lx.offset == 24 and L.IsmConfig.rtol.offset == 48
     assert ctypes.sizeof(L.IsmStats) == 56
 
@@ -70,6 +70,8 @@ def _create(**kw):
     (dict(nu=5, fused=1), L.ISM_ERR_UNSUPPORTED),
     (dict(stall_window=0), L.ISM_ERR_INVALID),
     (dict(stall_drop=1.0), L.ISM_ERR_INVALID),
+    (dict(coarse_stencil=2), L.ISM_ERR_INVALID),
+    (dict(reserved=1), L.ISM_ERR_INVALID),
 ])
 def test_invalid_configs_rejected_before_device(kw, code):
     got, h, lib = _create(**kw)
