@@ -59,6 +59,10 @@ extern "C" {
 #define ISM_COARSE_ISM 0  /* interpolated 9-point coarse stencil (Sec. 3.3, Eq. 5-7)            */
 #define ISM_COARSE_GMG5 1 /* 5-point stencil rediscretized at spacing n h: the aggressive-
                              coarsening GMG scheme the paper compares with (Sec. 4.3.2)         */
+#define ISM_COARSE_ACM 2  /* not two-level: additive correction multigrid with 2x2
+                             agglomeration down to spacing n h and V(0,1) cycles, the scheme the
+                             paper compares with (Sec. 3.2, Sec. 4, Sec. 4.3.1); FP64 only;
+                             ism_cycle is unsupported on such a handle                         */
 
 #define ISM_F64 0 /* element type selector of the stage entry points: double */
 #define ISM_F32 1 /*                                                  float  */
@@ -85,7 +89,7 @@ typedef struct {
                          and restriction); 0: one kernel per step                          */
   int32_t stall_window; /* an inner solve also stops when its residual fell by less than   */
   double stall_drop;    /* stall_drop (a fraction) over the last >= stall_window cycles     */
-  int32_t coarse_stencil; /* ISM_COARSE_ISM (default) or ISM_COARSE_GMG5                    */
+  int32_t coarse_stencil; /* ISM_COARSE_ISM (default), ISM_COARSE_GMG5 or ISM_COARSE_ACM    */
   int32_t reserved;       /* must be 0                                                      */
 } ism_config;
 

@@ -26,6 +26,7 @@ ISM_PREC_FP64 = 0
 ISM_PREC_MIXED = 1
 ISM_COARSE_ISM = 0
 ISM_COARSE_GMG5 = 1
+ISM_COARSE_ACM = 2
 ISM_F64 = 0
 ISM_F32 = 1
 KERNEL_CLASSES = {"cycle": 0, "smooth": 1, "restrict": 2, "prolong": 3, "coarse": 4, "outer": 5}

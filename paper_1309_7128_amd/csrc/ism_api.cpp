@@ -53,6 +53,11 @@ struct ism_ctx {
   double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
   void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
   double* h_scal = nullptr;   // pinned mirror of scal
+  // ACM hierarchy (coarse_stencil == ISM_COARSE_ACM): per level l = 1..L-1 the agglomerated
+  // right-hand side and two correction buffers, plus level-0 squared-residual partials
+  void* acm_mem = nullptr;
+  std::vector<double*> acm_r, acm_ea, acm_eb;
+  double* acm_psq = nullptr;
   std::string err;
   int64_t launches = 0, syncs = 0;
   // kernel timing (ism_profile): event pairs recorded around launches, resolved at syncs
@@ -147,8 +152,11 @@ int validate(const ism_config* cfg, std::string& why) {
   if (cfg->max_cycles < 1 || cfg->max_outer < 1 || cfg->check_every < 0)
     return why = "max_cycles and max_outer must be >= 1, check_every >= 0", ISM_ERR_INVALID;
   if (cfg->fused != 0 && cfg->fused != 1) return why = "fused must be 0 or 1", ISM_ERR_INVALID;
-  if (cfg->coarse_stencil != ISM_COARSE_ISM && cfg->coarse_stencil != ISM_COARSE_GMG5)
-    return why = "coarse_stencil must be ISM_COARSE_ISM or ISM_COARSE_GMG5", ISM_ERR_INVALID;
+  if (cfg->coarse_stencil != ISM_COARSE_ISM && cfg->coarse_stencil != ISM_COARSE_GMG5 &&
+      cfg->coarse_stencil != ISM_COARSE_ACM)
+    return why = "coarse_stencil must be ISM_COARSE_ISM, ISM_COARSE_GMG5 or ISM_COARSE_ACM", ISM_ERR_INVALID;
+  if (cfg->coarse_stencil == ISM_COARSE_ACM && cfg->precision != ISM_PREC_FP64)
+    return why = "the ACM scheme runs in FP64 only", ISM_ERR_UNSUPPORTED;
   if (cfg->reserved != 0) return why = "reserved must be 0", ISM_ERR_INVALID;
   if (cfg->stall_window < 1 || !(cfg->stall_drop >= 0.0) || !(cfg->stall_drop < 1.0))
     return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
@@ -280,27 +288,26 @@ struct Check {
   std::vector<double> res;
 };
 
-// Inner solve of A' e = rT from e = 0 in type T, until every grid's residual norm is below
-// its target, or the residual stagnates, or the cycle cap is reached.  rc holds R rT on entry.
-template <typename T>
-int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** e_out) {
-  const int B = c->g.batch;
-  T* cur = (T*)c->eA;
-  T* spare = (T*)c->eB;
-  const T* rhs = (const T*)c->rT;
+// Convergence bookkeeping of one inner solve: evaluates a check (the grid residual norms in
+// the ISQ slot) and schedules the next one.
+struct Monitor {
+  ism_ctx* c;
+  const std::vector<double>& target;
+  bool mixed;
   std::vector<Check> hist;
-  const bool mixed = sizeof(T) == 4;
-  int k = 0, next = 1;
-  auto last_time = std::chrono::steady_clock::now();
+  int next = 1;
+  std::chrono::steady_clock::time_point last_time = std::chrono::steady_clock::now();
   int last_cycle = 0;
-  for (;;) {
-    int rcode = run_cycle<T>(c, rhs, &cur, &spare, c->rc, c->p_sq, k == 0);
+
+  Monitor(ism_ctx* ctx, const std::vector<double>& tgt, bool is_mixed)
+      : c(ctx), target(tgt), mixed(is_mixed) {}
+
+  // After k cycles of this inner solve: < 0 error, 1 stop (target met, stagnation or cycle
+  // cap), 0 continue (next check scheduled in `next`).
+  int check(int k, int cycles) {
+    const int B = c->g.batch;
+    int rcode = read_scalars(c);
     if (rcode) return rcode;
-    ++k;
-    ++cycles;
-    if (k < next && cycles < c->cfg.max_cycles) continue;
-    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
-    if ((rcode = read_scalars(c))) return rcode;
     auto now = std::chrono::steady_clock::now();
     const double dt = std::chrono::duration<double>(now - last_time).count() / std::max(1, k - last_cycle);
     last_time = now;
@@ -314,7 +321,7 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
     }
     if (!finite) return set_err(c, ISM_ERR_NONFINITE, "non-finite residual in the inner iteration");
     hist.push_back(ck);
-    if (done || cycles >= c->cfg.max_cycles) break;
+    if (done || cycles >= c->cfg.max_cycles) return 1;
     // stagnation: the newest check against the latest one at least stall_window cycles older
     const Check* old = nullptr;
     for (auto it = hist.rbegin(); it != hist.rend(); ++it)
@@ -326,13 +333,14 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
       bool stalled = true;
       for (int b = 0; b < B; ++b)
         if (ck.res[b] > target[b] && ck.res[b] < (1.0 - c->cfg.stall_drop) * old->res[b]) stalled = false;
-      if (stalled) break;
+      if (stalled) return 1;
     }
-    // schedule the next check
     int gap;
     if (c->cfg.check_every > 0) {
       gap = c->cfg.check_every;
     } else {
+      // predict the cycle that meets every target from the rate since the previous check,
+      // at most doubling the cycle count per check
       gap = 1;
       if (hist.size() >= 2) {
         const Check& p = hist[hist.size() - 2];
@@ -352,8 +360,92 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
       gap = std::max(gap, 1);
     }
     next = k + gap;
+    return 0;
+  }
+};
+
+// Inner solve of A' e = rT from e = 0 in type T, until every grid's residual norm is below
+// its target, or the residual stagnates, or the cycle cap is reached.  rc holds R rT on entry.
+template <typename T>
+int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** e_out) {
+  T* cur = (T*)c->eA;
+  T* spare = (T*)c->eB;
+  const T* rhs = (const T*)c->rT;
+  Monitor mon(c, target, sizeof(T) == 4);
+  for (int k = 0;;) {
+    int rcode = run_cycle<T>(c, rhs, &cur, &spare, c->rc, c->p_sq, k == 0);
+    if (rcode) return rcode;
+    ++k;
+    ++cycles;
+    if (k < mon.next && cycles < c->cfg.max_cycles) continue;
+    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
+    rcode = mon.check(k, cycles);
+    if (rcode < 0) return rcode;
+    if (rcode == 1) break;
   }
   *e_out = cur;
+  return ISM_OK;
+}
+
+// Geometry of ACM level l (spacing 2^l h).
+Geo acm_level(const Geo& g, int l) {
+  Geo gl = g;
+  gl.nx = g.nx >> l;
+  gl.ny = g.ny >> l;
+  gl.plane = (long long)gl.nx * gl.ny;
+  return gl;
+}
+
+// Inner solve by additive correction multigrid V(0,1) cycles (the comparison scheme): 2x2
+// agglomeration of the residual down to spacing n h, exact solve of n times the 5-point
+// operator there, then on the way up the piecewise-constant correction and one red-black
+// sweep per level on 2^l A' e = r_l (Sec. 3.2, Sec. 4, Sec. 4.3.1).  FP64.  The level-0
+// agglomeration at the start of a cycle also yields the residual norm of the previous one.
+int acm_inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, double** e_out) {
+  const Geo& g = c->g;
+  const int L = g.log2n, B = g.batch;
+  hipStream_t s = c->stream;
+  double* e0 = (double*)c->eA;
+  double* sp0 = (double*)c->eB;
+  const double* rhs = (const double*)c->rT;
+  const long long count0 = (long long)(g.nx / 2) * (g.ny / 2);
+  Monitor mon(c, target, false);
+  for (int k = 0;;) {
+    double* r1 = L == 1 ? c->rc : c->acm_r[1];
+    LAUNCH(c, ism::launch_agglomerate(acm_level(g, 0), rhs, k == 0 ? nullptr : e0, 1.0, r1,
+                                      c->acm_psq, s));
+    if (k > 0 && (k >= mon.next || cycles >= c->cfg.max_cycles)) {
+      LAUNCH(c, ism::launch_finalize(c->acm_psq, int(count0), count0, B, ism::SUM, 1.0,
+                                     c->scal + size_t(ISQ) * B, 1, 0, s));
+      int rcode = mon.check(k, cycles);
+      if (rcode < 0) return rcode;
+      if (rcode == 1) break;
+    }
+    for (int l = 1; l < L; ++l)
+      LAUNCH(c, ism::launch_agglomerate(acm_level(g, l), c->acm_r[l], nullptr, 1.0,
+                                        l + 1 == L ? c->rc : c->acm_r[l + 1], nullptr, s));
+    hipEvent_t ev = prof_start(c);
+    int rcode = coarse_solve(c, c->rc, c->E);
+    if (rcode) return rcode;
+    prof_stop(c, ISM_KERNEL_COARSE, ev);
+    const double* above = c->E;
+    for (int l = L - 1; l >= 1; --l) {
+      LAUNCH(c, ism::launch_inject(acm_level(g, l), above, c->acm_ea[l], 1, s));
+      ev = prof_start(c);
+      LAUNCH(c, ism::launch_rbgs<double>(acm_level(g, l), c->acm_r[l], c->acm_ea[l], c->acm_eb[l], s,
+                                         std::ldexp(1.0, -l)));
+      prof_stop(c, ISM_KERNEL_SMOOTH, ev);
+      above = c->acm_eb[l];
+    }
+    LAUNCH(c, ism::launch_inject(acm_level(g, 0), above, e0, k == 0, s));
+    ev = prof_start(c);
+    LAUNCH(c, ism::launch_rbgs<double>(acm_level(g, 0), rhs, e0, sp0, s, 1.0));
+    prof_stop(c, ISM_KERNEL_SMOOTH, ev);
+    std::swap(e0, sp0);
+    ++k;
+    ++cycles;
+  }
+  *e_out = e0;
   return ISM_OK;
 }
 
@@ -415,7 +507,13 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
     }
     ++outer;
     T* e = nullptr;
-    if ((rcode = inner_solve<T>(c, target, cycles, &e))) return rcode;
+    if (c->cfg.coarse_stencil == ISM_COARSE_ACM) {
+      double* e64 = nullptr;
+      if ((rcode = acm_inner_solve(c, target, cycles, &e64))) return rcode;
+      e = (T*)e64;  // ACM handles are FP64 (T = double)
+    } else if ((rcode = inner_solve<T>(c, target, cycles, &e))) {
+      return rcode;
+    }
     LAUNCH(c, ism::launch_add_to<T>(g, x, e, s));
   }
   if (status >= 0) {
@@ -538,6 +636,32 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     return set_err(nullptr, ISM_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(he));
   }
 
+  if (cfg->coarse_stencil == ISM_COARSE_ACM) {
+    const int L = g.log2n;
+    size_t total = align(sizeof(double) * size_t(g.nx / 2) * (g.ny / 2) * g.batch);
+    for (int l = 1; l < L; ++l) total += 3 * align(sizeof(double) * size_t(g.nx >> l) * (g.ny >> l) * g.batch);
+    he = hipMalloc(&c->acm_mem, total);
+    if (he != hipSuccess) {
+      (void)hipHostFree(c->h_scal);
+      (void)hipFree(c->block);
+      delete c;
+      return set_err(nullptr, ISM_ERR_HIP, std::string("hipMalloc ACM levels: ") + hipGetErrorString(he));
+    }
+    char* q = (char*)c->acm_mem;
+    c->acm_psq = (double*)q;
+    q += align(sizeof(double) * size_t(g.nx / 2) * (g.ny / 2) * g.batch);
+    c->acm_r.assign(L + 1, nullptr);
+    c->acm_ea.assign(L + 1, nullptr);
+    c->acm_eb.assign(L + 1, nullptr);
+    for (int l = 1; l < L; ++l) {
+      const size_t sz = align(sizeof(double) * size_t(g.nx >> l) * (g.ny >> l) * g.batch);
+      c->acm_r[l] = (double*)q; q += sz;
+      c->acm_ea[l] = (double*)q; q += sz;
+      c->acm_eb[l] = (double*)q; q += sz;
+    }
+    c->bytes += total;
+  }
+
   // coarse tables (host, FP64), uploaded once
   std::vector<double> Vx, Vy, thx, thy;
   coarse_basis(g.ncx, g.per_x, Vx, thx);
@@ -547,8 +671,10 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     for (int k = 0; k < g.ncx; ++k) {
       const double kx = -2.0 * (1.0 - std::cos(thx[k])), mx = (3.0 + std::cos(thx[k])) / 4.0;
       const double ky = -2.0 * (1.0 - std::cos(thy[l])), my = (3.0 + std::cos(thy[l])) / 4.0;
-      // ISM: K_x (x) M_y + M_x (x) K_y; GMG5: K_x (x) I + I (x) K_y
-      const double lam = cfg->coarse_stencil == ISM_COARSE_GMG5 ? kx + ky : kx * my + mx * ky;
+      // ISM: K_x (x) M_y + M_x (x) K_y; GMG5: K_x (x) I + I (x) K_y; ACM: n times GMG5
+      const double lam = cfg->coarse_stencil == ISM_COARSE_GMG5  ? kx + ky
+                         : cfg->coarse_stencil == ISM_COARSE_ACM ? double(g.n) * (kx + ky)
+                                                                 : kx * my + mx * ky;
       inv[size_t(l) * g.ncx + k] = (l == 0 && k == 0) ? 0.0 : 1.0 / lam;
     }
   he = hipMemcpyAsync(c->Vx, Vx.data(), sizeof(double) * Vx.size(), hipMemcpyHostToDevice, c->stream);
@@ -559,6 +685,7 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   if (he == hipSuccess) he = hipMemsetAsync(c->scal, 0, scal, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   if (he != hipSuccess) {
+    if (c->acm_mem) (void)hipFree(c->acm_mem);
     (void)hipHostFree(c->h_scal);
     (void)hipFree(c->block);
     delete c;
@@ -573,6 +700,7 @@ int ism_destroy(ism_handle c) {
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->stage_tmp) (void)hipFree(c->stage_tmp);
+  if (c->acm_mem) (void)hipFree(c->acm_mem);
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   if (c->block) (void)hipFree(c->block);
   delete c;
@@ -708,6 +836,8 @@ int ism_coarse_solve(ism_handle c, const double* rc, double* E) {
 int ism_cycle(ism_handle c, int32_t dtype, const void* rhs, void* e, double* rc, int32_t zero_e,
               double* sumsq) {
   if (!c) return ISM_ERR_INVALID;
+  if (c->cfg.coarse_stencil == ISM_COARSE_ACM)
+    return set_err(c, ISM_ERR_UNSUPPORTED, "ism_cycle is the two-level cycle; an ACM handle has none");
   if (!rhs || !e || !rc) return set_err(c, ISM_ERR_INVALID, "bad arguments");
   if (dtype == ISM_F32) return cycle_impl<float>(c, (const float*)rhs, (float*)e, rc, zero_e, sumsq);
   if (dtype == ISM_F64) return cycle_impl<double>(c, (const double*)rhs, (double*)e, rc, zero_e, sumsq);

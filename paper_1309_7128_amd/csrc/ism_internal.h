@@ -30,8 +30,17 @@ struct Partials {
 // ---- launchers (ism_kernels.hip); every one enqueues on `s` and returns hipGetLastError()
 // One red-black sweep; e_in and e_out must not alias (workgroups read halos of their
 // neighbours' tiles).
+// The right-hand side is multiplied by rscale as it is read (a power of two on the ACM
+// levels, so the product is exact).
 template <typename T>
-hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* e_in, T* e_out, hipStream_t s);
+hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* e_in, T* e_out, hipStream_t s,
+                       T rscale = T(1));
+
+// ACM (FP64): out = 2x2 sums of (r - scale A'e) on the level grid g (e may be null) with
+// per-output sums of squares; ef (+)= piecewise-constant injection of the level above.
+hipError_t launch_agglomerate(const Geo& g, const double* r, const double* e, double scale,
+                              double* out, double* psq, hipStream_t s);
+hipError_t launch_inject(const Geo& g, const double* ec, double* ef, int assign, hipStream_t s);
 
 template <typename T>
 hipError_t launch_restrict(const Geo& g, const T* rhs, const T* e, double* rc, double* part_sumsq,

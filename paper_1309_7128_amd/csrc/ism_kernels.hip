@@ -110,7 +110,7 @@ __device__ __forceinline__ double bilinear(double q11, double q21, double q12, d
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rhs,
                                                  const T* __restrict__ ein,
-                                                 T* __restrict__ eout) {
+                                                 T* __restrict__ eout, T rscale) {
   constexpr int TX = 64, TY = 32;
   constexpr int LE = TX + 4, HE = TY + 4;
   constexpr int LR = TX + 2, HR = TY + 2;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rh
     int ly = t / LR, lx = t - ly * LR;
     int i = x0 + lx - 1, j = y0 + ly - 1;
     T v = T(0);
-    if (map_cell(g, i, j)) v = rb[(long long)j * g.nx + i];
+    if (map_cell(g, i, j)) v = rb[(long long)j * g.nx + i] * rscale;
     sr[t] = v;
   }
   __syncthreads();
@@ -814,6 +814,65 @@ __global__ __launch_bounds__(kBlock) void k_grad_adjoint(Geo g, const double* __
   }
 }
 
+// ----------------------------------------------------------------------------------------
+// Additive correction multigrid (the comparison scheme, Sec. 3.2 and Sec. 4), FP64.
+// ----------------------------------------------------------------------------------------
+
+// out = 2x2 sums of (r - scale * A'e) over the level grid g (e may be null: sums of r), and
+// per output cell the sum of the squared residuals of its 4 cells.
+__global__ __launch_bounds__(kBlock) void k_agglomerate(Geo g, const double* __restrict__ r,
+                                                        const double* __restrict__ e, double scale,
+                                                        double* __restrict__ out,
+                                                        double* __restrict__ psq) {
+  const int cx = g.nx / 2, cy = g.ny / 2;
+  const long long cpl = (long long)cx * cy, total = cpl * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / cpl;
+    const int rem = int(k - bi * cpl);
+    const int J = rem / cx, I = rem - J * cx;
+    const double* rb = r + bi * g.plane;
+    const double* eb = e ? e + bi * g.plane : nullptr;
+    double sum = 0.0, sq = 0.0;
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) {
+        const int i = 2 * I + di, j = 2 * J + dj;
+        double res = rb[(long long)j * g.nx + i];
+        if (eb) {
+          const bool hw = g.per_x || i > 0, he = g.per_x || i < g.nx - 1;
+          const bool hs = g.per_y || j > 0, hn = g.per_y || j < g.ny - 1;
+          const double* row = eb + (long long)j * g.nx;
+          const double c = row[i];
+          const double w = hw ? row[g.per_x ? imod(i - 1, g.nx) : i - 1] : 0.0;
+          const double ee = he ? row[g.per_x ? imod(i + 1, g.nx) : i + 1] : 0.0;
+          const double sv = hs ? eb[(long long)(g.per_y ? imod(j - 1, g.ny) : j - 1) * g.nx + i] : 0.0;
+          const double nv = hn ? eb[(long long)(g.per_y ? imod(j + 1, g.ny) : j + 1) * g.nx + i] : 0.0;
+          res = res - scale * lap5<double>(c, w, ee, sv, nv, hw, he, hs, hn);
+        }
+        sum += res;
+        sq += res * res;
+      }
+    out[k] = sum;
+    if (psq) psq[k] = sq;
+  }
+}
+
+// ef (+)= the value of the coarse cell that contains each fine cell (ACM's correction: the
+// coarse result is added without interpolation, Sec. 3.2).  g is the fine level.
+__global__ __launch_bounds__(kBlock) void k_inject(Geo g, const double* __restrict__ ec,
+                                                   double* __restrict__ ef, int assign) {
+  const int cx = g.nx / 2;
+  const long long cpl = (long long)cx * (g.ny / 2), total = g.plane * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / g.plane;
+    const int rem = int(k - bi * g.plane);
+    const int j = rem / g.nx, i = rem - j * g.nx;
+    const double v = ec[bi * cpl + (long long)(j >> 1) * cx + (i >> 1)];
+    ef[k] = assign ? v : ef[k] + v;
+  }
+}
+
 inline unsigned grid_stride_blocks(long long total) {
   long long b = (total + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -851,9 +910,23 @@ hipError_t cycle_dispatch2(const Geo& g, const T* rhs, const T* ein, T* eout, co
 // ---------------------------------------------------------------------------- launchers
 
 template <typename T>
-hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* ein, T* eout, hipStream_t s) {
+hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* ein, T* eout, hipStream_t s, T rscale) {
   dim3 grid((g.nx + 63) / 64, (g.ny + 31) / 32, g.batch);
-  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout);
+  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout, rscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_agglomerate(const Geo& g, const double* r, const double* e, double scale,
+                              double* out, double* psq, hipStream_t s) {
+  const long long total = (long long)(g.nx / 2) * (g.ny / 2) * g.batch;
+  hipLaunchKernelGGL(k_agglomerate, dim3(grid_stride_blocks(total)), dim3(kBlock), 0, s, g, r, e,
+                     scale, out, psq);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(const Geo& g, const double* ec, double* ef, int assign, hipStream_t s) {
+  const long long total = g.plane * g.batch;
+  hipLaunchKernelGGL(k_inject, dim3(grid_stride_blocks(total)), dim3(kBlock), 0, s, g, ec, ef, assign);
   return hipGetLastError();
 }
 
@@ -976,8 +1049,8 @@ hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv,
   return hipGetLastError();
 }
 
-template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t);
-template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t, float);
+template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t, double);
 template hipError_t launch_restrict<float>(const Geo&, const float*, const float*, double*, double*, hipStream_t);
 template hipError_t launch_restrict<double>(const Geo&, const double*, const double*, double*, double*, hipStream_t);
 template hipError_t launch_prolong<float>(const Geo&, const double*, float*, int, hipStream_t);

@@ -71,7 +71,8 @@ class Solver:
             cfg.stall_window = stall_window
         if stall_drop is not None:
             cfg.stall_drop = stall_drop
-        cfg.coarse_stencil = {"ism": L.ISM_COARSE_ISM, "gmg5": L.ISM_COARSE_GMG5}[coarse_stencil]
+        cfg.coarse_stencil = {"ism": L.ISM_COARSE_ISM, "gmg5": L.ISM_COARSE_GMG5,
+                              "acm": L.ISM_COARSE_ACM}[coarse_stencil]
         self.cfg = cfg
         self.nx, self.ny, self.batch = nx, ny, batch
         self.bc_x, self.bc_y = bc_x, bc_y

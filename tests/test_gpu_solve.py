@@ -216,3 +216,42 @@ def test_gmg5_vs_ism_cycle_counts_match_oracle(scheme):
     assert O.relative_residual(b, host(x).reshape(ny, nx), 1 / nx) <= 1e-10
     _, info = O.ism_solve(b, 1 / nx, 16, nu=2, rtol=1e-10, stencil=scheme)
     assert abs(st["cycles"] - info["cycles"]) <= 1
+
+
+@pytest.mark.parametrize("bx", [N, P])
+@pytest.mark.parametrize("n", [8, 16])
+def test_acm_matches_oracle(bx, n):
+    """ACM V(0,1) on the GPU against the oracle's (Sec. 3.2, Sec. 4.3.1): same cycle count,
+    same limit x*."""
+    announce("acm", bx, n)
+    nx, ny = 256, 128
+    rng = np.random.default_rng(230 + n)
+    b = rng.standard_normal((ny, nx))
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, precision="fp64", rtol=1e-10, check_every=1,
+               coarse_stencil="acm", lx=2.0)
+    x, st = s.solve(dev(b))
+    x = host(x).reshape(ny, nx)
+    assert st["status"] == 0
+    assert O.relative_residual(b, x, s.h, bx) <= 1e-10
+    _, info = O.acm_solve(b, s.h, n, bx, rtol=1e-10)
+    assert abs(st["cycles"] - info["cycles"]) <= 1
+    xs = O.exact_solve(b, s.h, bx)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_cavity2048_ism_vs_acm_counts(n):
+    """The workload's comparison: ISM and ACM to 1e-10 at 16h and 32h, counts reported."""
+    announce("cavity2048_ism_vs_acm", n)
+    w = inputs.WORKLOADS["cavity2048_fp64"]
+    u, v = inputs.workload_fields(w.name)
+    b = _rhs(u, v, w.h, N)
+    out = {}
+    for scheme in ("ism", "acm"):
+        s = solver(nx=w.nx, ny=w.ny, coarsen=n, precision="fp64", rtol=w.rtol, coarse_stencil=scheme,
+                   max_cycles=5000)
+        x, st = s.solve(dev(b))
+        out[scheme] = st
+        print(scheme, n, st, flush=True)
+        assert O.relative_residual(b, host(x).reshape(w.ny, w.nx), w.h) <= w.rtol
+    assert out["ism"]["cycles"] < out["acm"]["cycles"] or n == 16

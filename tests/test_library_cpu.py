@@ -70,7 +70,8 @@ def _create(**kw):
     (dict(nu=5, fused=1), L.ISM_ERR_UNSUPPORTED),
     (dict(stall_window=0), L.ISM_ERR_INVALID),
     (dict(stall_drop=1.0), L.ISM_ERR_INVALID),
-    (dict(coarse_stencil=2), L.ISM_ERR_INVALID),
+    (dict(coarse_stencil=3), L.ISM_ERR_INVALID),
+    (dict(coarse_stencil=2, precision=1), L.ISM_ERR_UNSUPPORTED),  # ACM is FP64 only
     (dict(reserved=1), L.ISM_ERR_INVALID),
 ])
 def test_invalid_configs_rejected_before_device(kw, code):
