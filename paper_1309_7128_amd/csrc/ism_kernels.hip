@@ -268,37 +268,51 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
 // ----------------------------------------------------------------------------------------
 // Fused two-level cycle kernel (temporal blocking of the red-black sweeps).
 //
-// A workgroup owns a 64 x 64 tile of fine cells.  It stages e with a halo of H = 2 NU + 1
+// A workgroup owns a 64 x TSY tile of fine cells (TSY = 64 for FP32, 32 for FP64 so that
+// three workgroups fit in a CU's LDS either way).  It stages e with a halo of H = 2 NU + 1
 // cells and rhs with a halo of 2 NU in LDS, adds the bilinear coarse correction to every
 // staged cell, then performs the 2 NU red/black half-steps on shrinking regions (half-step s
 // updates the tile grown by H - 1 - s rings), so that after the last half-step e is exact on
 // the tile plus one ring.  It then forms the residual on the tile, writes the tile of e and
 // the sums of the residual (and its square) over each n x n coarse tile it contains.
 // Redundant halo work replaces the NU extra round trips through HBM: per cycle the kernel
-// reads e and rhs once and writes e once.
+// reads e and rhs once and writes e once.  A red-black half-step reads only the other colour,
+// so a halo cell gets exactly the value its owner computes.
+// Workgroups are numbered so that the consecutive workgroups one XCD receives (the hardware
+// deals them out round-robin over the 8 XCDs) take neighbouring tiles, whose halos then
+// meet in that XCD's L2.
 // ----------------------------------------------------------------------------------------
-template <typename T, int NU, int LOG2N>
+template <typename T, int NU, int LOG2N, int TSY>
 __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
                                                   const T* __restrict__ ein,
                                                   T* __restrict__ eout,
                                                   const double* __restrict__ E,
                                                   double* __restrict__ rc,
-                                                  double* __restrict__ psq, int zero_e) {
-  constexpr int TS = 64;
+                                                  double* __restrict__ psq, int zero_e,
+                                                  int tiles_x, int tiles_y) {
+  constexpr int TSX = 64;
   constexpr int N = 1 << LOG2N;
   constexpr int H = 2 * NU + 1;
-  constexpr int LE = TS + 2 * H;
+  constexpr int LEX = TSX + 2 * H, LEY = TSY + 2 * H;
   constexpr int HR = 2 * NU;
-  constexpr int LR = TS + 2 * HR;
-  constexpr int CE = (TS + 2 * H) / N + 3;
-  constexpr int NBW = (16 >> LOG2N) > 0 ? (16 >> LOG2N) : 1;  // coarse bands per wave
-  __shared__ T se[LE * LE];
-  __shared__ T sr[LR * LR];
-  __shared__ double sE[CE * CE];
-  __shared__ double red1[4][NBW][16];
-  __shared__ double red2[4][NBW][16];
+  constexpr int LRX = TSX + 2 * HR, LRY = TSY + 2 * HR;
+  constexpr int CEX = LEX / N + 3, CEY = LEY / N + 3;
+  constexpr int RPW = TSY / 4;                 // tile rows per wave
+  constexpr int NBW = RPW >= N ? RPW / N : 1;  // coarse bands per wave
+  constexpr int WPB = N > RPW ? N / RPW : 1;   // waves per coarse band
+  constexpr int TPX = TSX / N, TPY = TSY / N;  // coarse tiles per workgroup tile
+  static_assert(TSY % 4 == 0 && N <= TSY, "a workgroup tile must hold whole coarse tiles");
+  __shared__ T se[LEY * LEX];
+  __shared__ T sr[LRY * LRX];
+  __shared__ double sE[CEY * CEX];
+  __shared__ double red1[4][NBW][TPX];
+  __shared__ double red2[4][NBW][TPX];
 
-  const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS;
+  const int nt = tiles_x * tiles_y;
+  int tid_tile = blockIdx.x;
+  if ((nt & 7) == 0) tid_tile = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
+  const int by = tid_tile / tiles_x, bx = tid_tile - by * tiles_x;
+  const int x0 = bx * TSX, y0 = by * TSY;
   const long long off = (long long)blockIdx.z * g.plane;
   const T* rb = rhs + off;
   const T* eb = ein + off;
@@ -308,8 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   // coarse values around the staged region, with the boundary rule applied at load time
   const int cI0 = floordiv(x0 - H - (N >> 1), N);
   const int cJ0 = floordiv(y0 - H - (N >> 1), N);
-  for (int t = threadIdx.x; t < CE * CE; t += kBlock) {
-    int cj = t / CE, ci = t - cj * CE;
+  for (int t = threadIdx.x; t < CEY * CEX; t += kBlock) {
+    int cj = t / CEX, ci = t - cj * CEX;
     int I = cI0 + ci, J = cJ0 + cj;
     I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
     J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
@@ -317,8 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   }
   __syncthreads();
 
-  for (int t = threadIdx.x; t < LE * LE; t += kBlock) {
-    int ly = t / LE, lx = t - ly * LE;
+  for (int t = threadIdx.x; t < LEY * LEX; t += kBlock) {
+    int ly = t / LEX, lx = t - ly * LEX;
     int gi = x0 + lx - H, gj = y0 + ly - H;
     int i = gi, j = gj;
     T v = T(0);
@@ -327,15 +341,15 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
       double X, Y;
       interp_coord(gi, N, ilo, X);
       interp_coord(gj, N, jlo, Y);
-      const double* q = sE + (jlo - cJ0) * CE + (ilo - cI0);
-      double p = bilinear(q[0], q[1], q[CE], q[CE + 1], X, Y);
+      const double* q = sE + (jlo - cJ0) * CEX + (ilo - cI0);
+      double p = bilinear(q[0], q[1], q[CEX], q[CEX + 1], X, Y);
       double base = zero_e ? 0.0 : double(eb[(long long)j * g.nx + i]);
       v = T(base + p);
     }
     se[t] = v;
   }
-  for (int t = threadIdx.x; t < LR * LR; t += kBlock) {
-    int ly = t / LR, lx = t - ly * LR;
+  for (int t = threadIdx.x; t < LRY * LRX; t += kBlock) {
+    int ly = t / LRX, lx = t - ly * LRX;
     int i = x0 + lx - HR, j = y0 + ly - HR;
     T v = T(0);
     if (map_cell(g, i, j)) v = rb[(long long)j * g.nx + i];
@@ -347,9 +361,9 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   for (int s = 0; s < 2 * NU; ++s) {
     const int R = H - 1 - s;  // rings beyond the tile updated in this half-step
     const int colour = s & 1;
-    const int L = TS + 2 * R;
-    const int HW = L / 2;
-    for (int t = threadIdx.x; t < L * HW; t += kBlock) {
+    const int LX = TSX + 2 * R, LY = TSY + 2 * R;
+    const int HW = LX / 2;    // cells of one colour per row
+    for (int t = threadIdx.x; t < LY * HW; t += kBlock) {
       int r = t / HW, k = t - r * HW;
       int ly = H - R + r;
       int gj = y0 + ly - H;
@@ -357,9 +371,9 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
       int gi = x0 + lx - H;
       int i = gi, j = gj;
       if (!map_cell(g, i, j)) continue;
-      int idx = ly * LE + lx;
-      T sum = ((se[idx - 1] + se[idx + 1]) + se[idx - LE]) + se[idx + LE];
-      se[idx] = (sum - sr[(ly - 1) * LR + (lx - 1)]) * inv_count<T>(g, i, j);
+      int idx = ly * LEX + lx;
+      T sum = ((se[idx - 1] + se[idx + 1]) + se[idx - LEX]) + se[idx + LEX];
+      se[idx] = (sum - sr[(ly - 1) * LRX + (lx - 1)]) * inv_count<T>(g, i, j);
     }
     __syncthreads();
   }
@@ -372,18 +386,18 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
 #pragma unroll
   for (int q = 0; q < NBW; ++q) acc[q] = acc2[q] = 0.0;
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    const int r = 16 * wave + rr;
+  for (int rr = 0; rr < RPW; ++rr) {
+    const int r = RPW * wave + rr;
     const int gj = y0 + r;
     if (gi < g.nx && gj < g.ny) {
       const bool hs = g.per_y || gj > 0, hn = g.per_y || gj < g.ny - 1;
-      const int idx = (r + H) * LE + (lane + H);
+      const int idx = (r + H) * LEX + (lane + H);
       T c = se[idx];
-      T res = sr[(r + HR) * LR + (lane + HR)] -
-              lap5<T>(c, se[idx - 1], se[idx + 1], se[idx - LE], se[idx + LE], hw, he, hs, hn);
+      T res = sr[(r + HR) * LRX + (lane + HR)] -
+              lap5<T>(c, se[idx - 1], se[idx + 1], se[idx - LEX], se[idx + LEX], hw, he, hs, hn);
       ob[(long long)gj * g.nx + gi] = c;
       double d = double(res);
-      const int q = (LOG2N >= 4) ? 0 : (rr >> LOG2N);
+      const int q = RPW >= N ? (rr >> LOG2N) : 0;
       acc[q] += d;
       acc2[q] += d * d;
     }
@@ -398,13 +412,14 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
     }
   }
   __syncthreads();
-  constexpr int TPS = TS / N;  // coarse tiles per tile side
-  if ((int)threadIdx.x < TPS * TPS) {
-    const int band = threadIdx.x / TPS, tc = threadIdx.x - band * TPS;
-    double a, b;
-    if (LOG2N == 5) {  // a band of 32 rows spans two waves
-      a = red1[2 * band][0][tc] + red1[2 * band + 1][0][tc];
-      b = red2[2 * band][0][tc] + red2[2 * band + 1][0][tc];
+  if ((int)threadIdx.x < TPX * TPY) {
+    const int band = threadIdx.x / TPX, tc = threadIdx.x - band * TPX;
+    double a = 0.0, b = 0.0;
+    if (WPB > 1) {  // a coarse band spans WPB waves: add them in wave order
+      for (int w = band * WPB; w < band * WPB + WPB; ++w) {
+        a += red1[w][0][tc];
+        b += red2[w][0][tc];
+      }
     } else {
       const int w = band / NBW, q = band - w * NBW;
       a = red1[w][q][tc];
@@ -887,9 +902,11 @@ inline dim3 strip_grid(const Geo& g) {
 template <typename T, int NU, int LOG2N>
 hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
                            double* rc, double* psq, int zero_e, hipStream_t s) {
-  dim3 grid((g.nx + 63) / 64, (g.ny + 63) / 64, g.batch);
-  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N>), grid, dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc,
-                     psq, zero_e);
+  constexpr int TSY = sizeof(T) == 4 ? 64 : 32;
+  const int tx = (g.nx + 63) / 64, ty = (g.ny + TSY - 1) / TSY;
+  dim3 grid(tx * ty, 1, g.batch);
+  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N, TSY>), grid, dim3(kBlock), 0, s, g, rhs, ein, eout, E,
+                     rc, psq, zero_e, tx, ty);
   return hipGetLastError();
 }
 
