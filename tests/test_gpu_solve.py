@@ -255,3 +255,17 @@ def test_cavity2048_ism_vs_acm_counts(n):
         print(scheme, n, st, flush=True)
         assert O.relative_residual(b, host(x).reshape(w.ny, w.nx), w.h) <= w.rtol
     assert out["ism"]["cycles"] < out["acm"]["cycles"] or n == 16
+
+
+def test_kernel_timer_counts_launches():
+    announce("profile")
+    nx = ny = 256
+    b = dev(np.random.default_rng(240).standard_normal((ny, nx)))
+    s = solver(nx=nx, ny=ny, coarsen=16, precision="mixed", rtol=1e-10)
+    s.profile(True)
+    x, st = s.solve(b)
+    prof = s.profile_read()
+    s.profile(False)
+    assert prof["cycle"][1] == st["cycles"] and prof["coarse"][1] == st["cycles"]
+    assert prof["outer"][1] == st["outer_iters"] + 1
+    assert prof["cycle"][0] > 0.0
