@@ -178,7 +178,9 @@ def main():
         s64.close()
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, b, last["cycles"], last["outer_iters"], args.nu)
+        mean_cycles = sum(st["cycles"] for st in stats) / len(stats)
+        mean_outer = sum(st["outer_iters"] for st in stats) / len(stats)
+        out["cpu_baseline"] = cpu_baseline(w, b, mean_cycles, mean_outer, args.nu)
 
     print(json.dumps(out), flush=True)
 
@@ -248,9 +250,9 @@ def cpu_baseline(w, b_dev, gpu_cycles, gpu_outer, nu):
             "kind": "oracle",
             "sample": f"one inner cycle ({t_cycle:.1f} s) and one outer residual ({t_outer:.1f} s) "
                       f"of the oracle's ISM iteration on grid 0 of the same input, single thread, "
-                      f"extrapolated to the GPU solve's {gpu_cycles} cycles and {gpu_outer} outer "
-                      f"steps per grid; oracle coarse factorization ({t_setup:.1f} s) excluded like "
-                      f"the library's setup"}
+                      f"extrapolated to the GPU solve's {gpu_cycles:g} cycles and {gpu_outer:g} outer "
+                      f"steps per solve and grid; oracle coarse factorization ({t_setup:.1f} s) "
+                      f"excluded like the library's setup"}
 
 
 if __name__ == "__main__":
