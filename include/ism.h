@@ -44,7 +44,8 @@ extern "C" {
 #define ISM_OK 0
 #define ISM_NOT_CONVERGED 1
 #define ISM_ERR_INVALID (-1)     /* null pointer, non-positive size, bad enum value       */
-#define ISM_ERR_UNSUPPORTED (-2) /* nx or ny not a multiple of coarsen, lx/nx != ly/ny   */
+#define ISM_ERR_UNSUPPORTED (-2) /* nx or ny not a multiple of coarsen, lx/nx != ly/ny,  
+                                    nx * ny >= 2^31                                      */
 #define ISM_ERR_HIP (-3)         /* a HIP runtime call failed; see ism_last_error        */
 #define ISM_ERR_NONFINITE (-4)   /* NaN or Inf met in b or during the iteration          */
 

@@ -238,22 +238,19 @@ def _interp_axis(nf, n, bc):
 def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN):
     """P E: bilinear interpolation of the coarse values to every fine cell centre.
 
-    Eq. 5 with origin at the south-west centre Q11 of the surrounding rectangle:
-    p = Q11 (1-x)(1-y) + Q21 x (1-y) + Q12 (1-x) y + Q22 x y in coordinates scaled by the
-    rectangle size; the same interpolation serves the coarse stencil and the prolongation
-    (Sec. 3.3).  Pinned by exactness on constants and bilinear fields, dyadic weights and
-    the coarse-stencil identities."""
+    Eq. 5 with origin at the south-west centre Q11 of the surrounding rectangle, in
+    coordinates scaled by the rectangle size: p = Q11 (1-x)(1-y) + Q21 x (1-y) + Q12 (1-x) y
+    + Q22 x y, evaluated in nested form, first along x on the lower and upper coarse rows,
+    then along y: p = (Q11 (1-x) + Q21 x)(1-y) + (Q12 (1-x) + Q22 x) y.  The same
+    interpolation serves the coarse stencil and the prolongation (Sec. 3.3).  Pinned by
+    exactness on constants and bilinear fields, dyadic weights and the coarse-stencil
+    identities."""
     ncy, ncx = E.shape
     ilo, ihi, tx = _interp_axis(ncx * n, n, bc_x)
     jlo, jhi, ty = _interp_axis(ncy * n, n, bc_y)
     E = np.asarray(E, dtype=np.float64)
-    q11 = E[np.ix_(jlo, ilo)]
-    q21 = E[np.ix_(jlo, ihi)]
-    q12 = E[np.ix_(jhi, ilo)]
-    q22 = E[np.ix_(jhi, ihi)]
-    X = tx[None, :]
-    Y = ty[:, None]
-    return q11 * (1 - X) * (1 - Y) + q21 * X * (1 - Y) + q12 * (1 - X) * Y + q22 * X * Y
+    ex = E[:, ilo] * (1 - tx)[None, :] + E[:, ihi] * tx[None, :]  # along x, every coarse row
+    return ex[jlo, :] * (1 - ty)[:, None] + ex[jhi, :] * ty[:, None]
 
 
 def inject_constant(E, n):

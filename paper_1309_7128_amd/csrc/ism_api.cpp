@@ -50,6 +50,7 @@ struct ism_ctx {
   double *rc = nullptr, *E = nullptr, *t1 = nullptr, *t2 = nullptr;
   double *p_sq = nullptr, *p_max = nullptr, *p_bsq = nullptr, *p_bmax = nullptr, *p_sum = nullptr;
   double* scal = nullptr;  // [kSlots][batch]
+  double* fin = nullptr;   // chunk results of the two-stage reductions
   double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
   void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
   double* h_scal = nullptr;   // pinned mirror of scal
@@ -169,8 +170,8 @@ int validate(const ism_config* cfg, std::string& why) {
   if (std::fabs(hx - hy) > 1e-12 * hx) return why = "cells must be square (lx/nx == ly/ny)", ISM_ERR_UNSUPPORTED;
   if (cfg->fused && cfg->nu > ism::fused_max_nu())
     return why = "the fused cycle kernel supports nu <= 4; use fused = 0", ISM_ERR_UNSUPPORTED;
-  const double cells = double(cfg->nx) * cfg->ny * cfg->batch;
-  if (cells > 4.0e10) return why = "grid too large", ISM_ERR_UNSUPPORTED;
+  if (double(cfg->nx) * cfg->ny >= 2147483648.0)
+    return why = "one grid must have fewer than 2^31 cells", ISM_ERR_UNSUPPORTED;
   return ISM_OK;
 }
 
@@ -238,7 +239,7 @@ int read_scalars(ism_ctx* c) {
 
 int finalize(ism_ctx* c, const double* part, ism::Reduce op, double scale, int slot) {
   LAUNCH(c, ism::launch_finalize(part, int(c->g.cplane), c->g.cplane, c->g.batch, op, scale,
-                                 c->scal + size_t(slot) * c->g.batch, 1, 0, c->stream));
+                                 c->scal + size_t(slot) * c->g.batch, 1, 0, c->fin, c->stream));
   return ISM_OK;
 }
 
@@ -416,7 +417,7 @@ int acm_inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, 
                                       c->acm_psq, s));
     if (k > 0 && (k >= mon.next || cycles >= c->cfg.max_cycles)) {
       LAUNCH(c, ism::launch_finalize(c->acm_psq, int(count0), count0, B, ism::SUM, 1.0,
-                                     c->scal + size_t(ISQ) * B, 1, 0, s));
+                                     c->scal + size_t(ISQ) * B, 1, 0, c->fin, s));
       int rcode = mon.check(k, cycles);
       if (rcode < 0) return rcode;
       if (rcode == 1) break;
@@ -607,9 +608,11 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   const size_t fine = align(size_t(g.plane) * g.batch * c->tsize);
   const size_t coarse = align(size_t(g.cplane) * g.batch * sizeof(double));
   const size_t scal = align(sizeof(double) * kSlots * g.batch);
+  const long long fin_count = std::max<long long>(g.cplane, (long long)(g.nx / 2) * (g.ny / 2));
+  const size_t fin = align(sizeof(double) * g.batch * size_t(fin_count / 4096 + 2));
   const size_t tabs = align(sizeof(double) * g.ncx * g.ncx) + align(sizeof(double) * g.ncy * g.ncy) +
                       align(sizeof(double) * g.cplane);
-  c->bytes = 3 * fine + 9 * coarse + scal + tabs;
+  c->bytes = 3 * fine + 9 * coarse + scal + fin + tabs;
   he = hipMalloc((void**)&c->block, c->bytes);
   if (he != hipSuccess) {
     delete c;
@@ -625,6 +628,7 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     p += coarse;
   }
   c->scal = (double*)p; p += scal;
+  c->fin = (double*)p; p += fin;
   c->Vx = (double*)p; p += align(sizeof(double) * g.ncx * g.ncx);
   c->Vy = (double*)p; p += align(sizeof(double) * g.ncy * g.ncy);
   c->invLam = (double*)p;
@@ -786,7 +790,7 @@ int cycle_impl(ism_ctx* c, const T* rhs, T* e, double* rc, int zero_e, double* s
                              hipMemcpyDeviceToDevice, c->stream));
   if (sumsq)
     LAUNCH(c, ism::launch_finalize(c->p_sq, int(c->g.cplane), c->g.cplane, c->g.batch, ism::SUM, 1.0,
-                                   sumsq, 1, 0, c->stream));
+                                   sumsq, 1, 0, c->fin, c->stream));
   return ISM_OK;
 }
 
@@ -814,7 +818,7 @@ int ism_restrict(ism_handle c, int32_t dtype, const void* rhs, const void* e, do
     return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
   if (sumsq)
     LAUNCH(c, ism::launch_finalize(c->p_sq, int(c->g.cplane), c->g.cplane, c->g.batch, ism::SUM, 1.0,
-                                   sumsq, 1, 0, c->stream));
+                                   sumsq, 1, 0, c->fin, c->stream));
   return ISM_OK;
 }
 

@@ -65,9 +65,11 @@ hipError_t launch_outer_residual(const Geo& g, const double* b, const double* x,
 
 hipError_t launch_tile_sum(const Geo& g, const double* x, double* part, hipStream_t s);
 
+// out[g * out_stride + slot] = scale * (sum or max of count partials of grid g); scratch
+// holds batch * ceil(count / 4096) doubles for the chunk results.
 hipError_t launch_finalize(const double* part, int count, long long part_stride, int batch,
                            Reduce op, double scale, double* out, int out_stride, int slot,
-                           hipStream_t s);
+                           double* scratch, hipStream_t s);
 
 template <typename T>
 hipError_t launch_add_to(const Geo& g, double* x, const T* e, hipStream_t s);

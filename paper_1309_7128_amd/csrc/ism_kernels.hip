@@ -93,14 +93,13 @@ __device__ __forceinline__ void interp_coord(int gi, int n, int& lo, double& t) 
   t = double(2 * k + 1) / double(2 * n);
 }
 
-// p = Q11 (1-X)(1-Y) + Q21 X (1-Y) + Q12 (1-X) Y + Q22 X Y, in this order (Eq. 5).
+// Eq. 5 evaluated in nested form: interpolate along x on the lower and the upper coarse row,
+// then along y, p = (Q11 (1-X) + Q21 X) (1-Y) + (Q12 (1-X) + Q22 X) Y, rounded in this order.
+__device__ __forceinline__ double lerp(double a, double b, double t) { return a * (1.0 - t) + b * t; }
+
 __device__ __forceinline__ double bilinear(double q11, double q21, double q12, double q22,
                                            double X, double Y) {
-  double a = q11 * (1.0 - X) * (1.0 - Y);
-  double b = q21 * X * (1.0 - Y);
-  double c = q12 * (1.0 - X) * Y;
-  double d = q22 * X * Y;
-  return ((a + b) + c) + d;
+  return lerp(lerp(q11, q21, X), lerp(q12, q22, X), Y);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -283,6 +282,176 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
 // meet in that XCD's L2.
 // ----------------------------------------------------------------------------------------
 template <typename T, int NU, int LOG2N, int TSY>
+struct CycleTile {
+  static constexpr int TSX = 64;
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int H = 2 * NU + 1;
+  static constexpr int LEX = TSX + 2 * H, LEY = TSY + 2 * H;
+  static constexpr int HR = 2 * NU;
+  static constexpr int LRX = TSX + 2 * HR, LRY = TSY + 2 * HR;
+  static constexpr int CEX = LEX / N + 3, CEY = LEY / N + 3;
+  static constexpr int RPW = TSY / 4;                 // tile rows per wave
+  static constexpr int NBW = RPW >= N ? RPW / N : 1;  // coarse bands per wave
+  static constexpr int WPB = N > RPW ? N / RPW : 1;   // waves per coarse band
+  static constexpr int TPX = TSX / N, TPY = TSY / N;  // coarse tiles per workgroup tile
+  static_assert(TSY % 4 == 0 && N <= TSY, "a workgroup tile must hold whole coarse tiles");
+
+  struct Shared {
+    T se[LEY * LEX];
+    T sr[LRY * LRX];
+    double sE[CEY * CEX];   // coarse values around the staged region
+    double sEx[CEY * LEX];  // the same, interpolated along x at every staged column
+    double rowY[LEY];       // y weight of every staged row ...
+    int rowJ[LEY];          // ... and its lower coarse row in sEx
+    double red1[4][NBW][TPX];
+    double red2[4][NBW][TPX];
+  };
+
+  // INTERIOR: the staged region lies inside the grid and touches no wall, so no cell needs
+  // wrapping, clamping or a reduced neighbour count.
+  template <bool INTERIOR>
+  static __device__ __forceinline__ void run(Shared& sh, const Geo& g, const T* __restrict__ rb,
+                                             const T* __restrict__ eb, T* __restrict__ ob,
+                                             const double* __restrict__ Eb, double* __restrict__ rc,
+                                             double* __restrict__ psq, int zero_e, int x0, int y0,
+                                             int bz) {
+    const int cI0 = floordiv(x0 - H - (N >> 1), N);
+    const int cJ0 = floordiv(y0 - H - (N >> 1), N);
+    for (int t = threadIdx.x; t < CEY * CEX; t += kBlock) {
+      int cj = t / CEX, ci = t - cj * CEX;
+      int I = cI0 + ci, J = cJ0 + cj;
+      if (!INTERIOR) {
+        I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
+        J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
+      }
+      sh.sE[t] = Eb[J * g.ncx + I];
+    }
+    for (int t = threadIdx.x; t < LEY; t += kBlock) {
+      int jlo;
+      double Y;
+      interp_coord(y0 + t - H, N, jlo, Y);
+      sh.rowY[t] = Y;
+      sh.rowJ[t] = (jlo - cJ0) * LEX;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < CEY * LEX; t += kBlock) {
+      int cj = t / LEX, lx = t - cj * LEX;
+      int ilo;
+      double X;
+      interp_coord(x0 + lx - H, N, ilo, X);
+      const double* q = sh.sE + cj * CEX + (ilo - cI0);
+      sh.sEx[t] = lerp(q[0], q[1], X);
+    }
+    __syncthreads();
+
+    // stage e + P E (the coarse correction) and rhs
+#pragma unroll 4
+    for (int t = threadIdx.x; t < LEY * LEX; t += kBlock) {
+      const int ly = t / LEX, lx = t - ly * LEX;
+      int i = x0 + lx - H, j = y0 + ly - H;
+      T v = T(0);
+      if (INTERIOR || map_cell(g, i, j)) {
+        const double* q = sh.sEx + sh.rowJ[ly] + lx;
+        const double p = lerp(q[0], q[LEX], sh.rowY[ly]);
+        const double base = zero_e ? 0.0 : double(eb[j * g.nx + i]);
+        v = T(base + p);
+      }
+      sh.se[t] = v;
+    }
+#pragma unroll 4
+    for (int t = threadIdx.x; t < LRY * LRX; t += kBlock) {
+      const int ly = t / LRX, lx = t - ly * LRX;
+      int i = x0 + lx - HR, j = y0 + ly - HR;
+      T v = T(0);
+      if (INTERIOR || map_cell(g, i, j)) v = rb[j * g.nx + i];
+      sh.sr[t] = v;
+    }
+    __syncthreads();
+
+    // 2 NU red/black half-steps on regions shrinking by one ring each
+#pragma unroll
+    for (int s = 0; s < 2 * NU; ++s) {
+      const int R = H - 1 - s;
+      const int colour = s & 1;
+      const int LX = TSX + 2 * R, LY = TSY + 2 * R;
+      const int HW = LX / 2;  // cells of one colour per row
+      for (int t = threadIdx.x; t < LY * HW; t += kBlock) {
+        const int r = t / HW, k = t - r * HW;
+        const int ly = H - R + r;
+        const int gj = y0 + ly - H;
+        const int lx = (H - R) + ((colour + R + gj) & 1) + 2 * k;
+        T inv = T(0.25);
+        if (!INTERIOR) {
+          int i = x0 + lx - H, j = gj;
+          if (!map_cell(g, i, j)) continue;
+          inv = inv_count<T>(g, i, j);
+        }
+        const int idx = ly * LEX + lx;
+        const T sum = ((sh.se[idx - 1] + sh.se[idx + 1]) + sh.se[idx - LEX]) + sh.se[idx + LEX];
+        sh.se[idx] = (sum - sh.sr[(ly - 1) * LRX + (lx - 1)]) * inv;
+      }
+      __syncthreads();
+    }
+
+    // residual on the tile, write-back, per-coarse-tile sums
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int gi = x0 + lane;
+    const bool hw = INTERIOR || g.per_x || gi > 0, he = INTERIOR || g.per_x || gi < g.nx - 1;
+    double acc[NBW], acc2[NBW];
+#pragma unroll
+    for (int q = 0; q < NBW; ++q) acc[q] = acc2[q] = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int r = RPW * wave + rr;
+      const int gj = y0 + r;
+      if (INTERIOR || (gi < g.nx && gj < g.ny)) {
+        const bool hs = INTERIOR || g.per_y || gj > 0, hn = INTERIOR || g.per_y || gj < g.ny - 1;
+        const int idx = (r + H) * LEX + (lane + H);
+        const T c = sh.se[idx];
+        const T res = sh.sr[(r + HR) * LRX + (lane + HR)] -
+                      lap5<T>(c, sh.se[idx - 1], sh.se[idx + 1], sh.se[idx - LEX], sh.se[idx + LEX],
+                              hw, he, hs, hn);
+        ob[gj * g.nx + gi] = c;
+        const double d = double(res);
+        const int q = RPW >= N ? (rr >> LOG2N) : 0;
+        acc[q] += d;
+        acc2[q] += d * d;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NBW; ++q) {
+      double a = wave_sum_group(acc[q], N);
+      double b = wave_sum_group(acc2[q], N);
+      if ((lane & (N - 1)) == 0) {
+        sh.red1[wave][q][lane >> LOG2N] = a;
+        sh.red2[wave][q][lane >> LOG2N] = b;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < TPX * TPY) {
+      const int band = threadIdx.x / TPX, tc = threadIdx.x - band * TPX;
+      double a = 0.0, b = 0.0;
+      if (WPB > 1) {  // a coarse band spans WPB waves: add them in wave order
+        for (int w = band * WPB; w < band * WPB + WPB; ++w) {
+          a += sh.red1[w][0][tc];
+          b += sh.red2[w][0][tc];
+        }
+      } else {
+        const int w = band / NBW, q = band - w * NBW;
+        a = sh.red1[w][q][tc];
+        b = sh.red2[w][q][tc];
+      }
+      const int I = (x0 >> LOG2N) + tc, J = (y0 >> LOG2N) + band;
+      if (INTERIOR || (I < g.ncx && J < g.ncy)) {
+        const long long o = (long long)bz * g.cplane + (long long)J * g.ncx + I;
+        rc[o] = a;
+        if (psq) psq[o] = b;
+      }
+    }
+  }
+};
+
+template <typename T, int NU, int LOG2N, int TSY>
 __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
                                                   const T* __restrict__ ein,
                                                   T* __restrict__ eout,
@@ -290,148 +459,28 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
                                                   double* __restrict__ rc,
                                                   double* __restrict__ psq, int zero_e,
                                                   int tiles_x, int tiles_y) {
-  constexpr int TSX = 64;
-  constexpr int N = 1 << LOG2N;
-  constexpr int H = 2 * NU + 1;
-  constexpr int LEX = TSX + 2 * H, LEY = TSY + 2 * H;
-  constexpr int HR = 2 * NU;
-  constexpr int LRX = TSX + 2 * HR, LRY = TSY + 2 * HR;
-  constexpr int CEX = LEX / N + 3, CEY = LEY / N + 3;
-  constexpr int RPW = TSY / 4;                 // tile rows per wave
-  constexpr int NBW = RPW >= N ? RPW / N : 1;  // coarse bands per wave
-  constexpr int WPB = N > RPW ? N / RPW : 1;   // waves per coarse band
-  constexpr int TPX = TSX / N, TPY = TSY / N;  // coarse tiles per workgroup tile
-  static_assert(TSY % 4 == 0 && N <= TSY, "a workgroup tile must hold whole coarse tiles");
-  __shared__ T se[LEY * LEX];
-  __shared__ T sr[LRY * LRX];
-  __shared__ double sE[CEY * CEX];
-  __shared__ double red1[4][NBW][TPX];
-  __shared__ double red2[4][NBW][TPX];
-
+  using CT = CycleTile<T, NU, LOG2N, TSY>;
+  __shared__ typename CT::Shared sh;
   const int nt = tiles_x * tiles_y;
-  int tid_tile = blockIdx.x;
-  if ((nt & 7) == 0) tid_tile = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
-  const int by = tid_tile / tiles_x, bx = tid_tile - by * tiles_x;
-  const int x0 = bx * TSX, y0 = by * TSY;
+  int tile = blockIdx.x;
+  if ((nt & 7) == 0) tile = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
+  const int by = tile / tiles_x, bx = tile - by * tiles_x;
+  const int x0 = bx * CT::TSX, y0 = by * TSY;
   const long long off = (long long)blockIdx.z * g.plane;
-  const T* rb = rhs + off;
-  const T* eb = ein + off;
-  T* ob = eout + off;
   const double* Eb = E + (long long)blockIdx.z * g.cplane;
-
-  // coarse values around the staged region, with the boundary rule applied at load time
-  const int cI0 = floordiv(x0 - H - (N >> 1), N);
-  const int cJ0 = floordiv(y0 - H - (N >> 1), N);
-  for (int t = threadIdx.x; t < CEY * CEX; t += kBlock) {
-    int cj = t / CEX, ci = t - cj * CEX;
-    int I = cI0 + ci, J = cJ0 + cj;
-    I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
-    J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
-    sE[t] = Eb[(long long)J * g.ncx + I];
-  }
-  __syncthreads();
-
-  for (int t = threadIdx.x; t < LEY * LEX; t += kBlock) {
-    int ly = t / LEX, lx = t - ly * LEX;
-    int gi = x0 + lx - H, gj = y0 + ly - H;
-    int i = gi, j = gj;
-    T v = T(0);
-    if (map_cell(g, i, j)) {
-      int ilo, jlo;
-      double X, Y;
-      interp_coord(gi, N, ilo, X);
-      interp_coord(gj, N, jlo, Y);
-      const double* q = sE + (jlo - cJ0) * CEX + (ilo - cI0);
-      double p = bilinear(q[0], q[1], q[CEX], q[CEX + 1], X, Y);
-      double base = zero_e ? 0.0 : double(eb[(long long)j * g.nx + i]);
-      v = T(base + p);
-    }
-    se[t] = v;
-  }
-  for (int t = threadIdx.x; t < LRY * LRX; t += kBlock) {
-    int ly = t / LRX, lx = t - ly * LRX;
-    int i = x0 + lx - HR, j = y0 + ly - HR;
-    T v = T(0);
-    if (map_cell(g, i, j)) v = rb[(long long)j * g.nx + i];
-    sr[t] = v;
-  }
-  __syncthreads();
-
-#pragma unroll
-  for (int s = 0; s < 2 * NU; ++s) {
-    const int R = H - 1 - s;  // rings beyond the tile updated in this half-step
-    const int colour = s & 1;
-    const int LX = TSX + 2 * R, LY = TSY + 2 * R;
-    const int HW = LX / 2;    // cells of one colour per row
-    for (int t = threadIdx.x; t < LY * HW; t += kBlock) {
-      int r = t / HW, k = t - r * HW;
-      int ly = H - R + r;
-      int gj = y0 + ly - H;
-      int lx = (H - R) + ((colour + R + gj) & 1) + 2 * k;
-      int gi = x0 + lx - H;
-      int i = gi, j = gj;
-      if (!map_cell(g, i, j)) continue;
-      int idx = ly * LEX + lx;
-      T sum = ((se[idx - 1] + se[idx + 1]) + se[idx - LEX]) + se[idx + LEX];
-      se[idx] = (sum - sr[(ly - 1) * LRX + (lx - 1)]) * inv_count<T>(g, i, j);
-    }
-    __syncthreads();
-  }
-
-  // residual on the tile, write-back, per-coarse-tile sums
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int gi = x0 + lane;
-  const bool hw = g.per_x || gi > 0, he = g.per_x || gi < g.nx - 1;
-  double acc[NBW], acc2[NBW];
-#pragma unroll
-  for (int q = 0; q < NBW; ++q) acc[q] = acc2[q] = 0.0;
-#pragma unroll
-  for (int rr = 0; rr < RPW; ++rr) {
-    const int r = RPW * wave + rr;
-    const int gj = y0 + r;
-    if (gi < g.nx && gj < g.ny) {
-      const bool hs = g.per_y || gj > 0, hn = g.per_y || gj < g.ny - 1;
-      const int idx = (r + H) * LEX + (lane + H);
-      T c = se[idx];
-      T res = sr[(r + HR) * LRX + (lane + HR)] -
-              lap5<T>(c, se[idx - 1], se[idx + 1], se[idx - LEX], se[idx + LEX], hw, he, hs, hn);
-      ob[(long long)gj * g.nx + gi] = c;
-      double d = double(res);
-      const int q = RPW >= N ? (rr >> LOG2N) : 0;
-      acc[q] += d;
-      acc2[q] += d * d;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < NBW; ++q) {
-    double a = wave_sum_group(acc[q], N);
-    double b = wave_sum_group(acc2[q], N);
-    if ((lane & (N - 1)) == 0) {
-      red1[wave][q][lane >> LOG2N] = a;
-      red2[wave][q][lane >> LOG2N] = b;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < TPX * TPY) {
-    const int band = threadIdx.x / TPX, tc = threadIdx.x - band * TPX;
-    double a = 0.0, b = 0.0;
-    if (WPB > 1) {  // a coarse band spans WPB waves: add them in wave order
-      for (int w = band * WPB; w < band * WPB + WPB; ++w) {
-        a += red1[w][0][tc];
-        b += red2[w][0][tc];
-      }
-    } else {
-      const int w = band / NBW, q = band - w * NBW;
-      a = red1[w][q][tc];
-      b = red2[w][q][tc];
-    }
-    const int I = (x0 >> LOG2N) + tc, J = (y0 >> LOG2N) + band;
-    if (I < g.ncx && J < g.ncy) {
-      const long long o = (long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I;
-      rc[o] = a;
-      if (psq) psq[o] = b;
-    }
-  }
+  // interior: every staged cell and its neighbours lie in the grid away from the walls, and
+  // every coarse value the staged cells interpolate from lies in the coarse grid unclamped
+  const int cI0 = floordiv(x0 - CT::H - (CT::N >> 1), CT::N);
+  const int cJ0 = floordiv(y0 - CT::H - (CT::N >> 1), CT::N);
+  const bool interior = x0 >= CT::H && x0 + CT::TSX + CT::H <= g.nx && y0 >= CT::H &&
+                        y0 + TSY + CT::H <= g.ny && cI0 >= 0 && cI0 + CT::CEX <= g.ncx &&
+                        cJ0 >= 0 && cJ0 + CT::CEY <= g.ncy;
+  if (interior)
+    CT::template run<true>(sh, g, rhs + off, ein + off, eout + off, Eb, rc, psq, zero_e, x0, y0,
+                           blockIdx.z);
+  else
+    CT::template run<false>(sh, g, rhs + off, ein + off, eout + off, Eb, rc, psq, zero_e, x0, y0,
+                            blockIdx.z);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -533,15 +582,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_sum(Geo g, const double* __rest
   }
 }
 
-// Second reduction stage: one workgroup per grid, fixed summation order (reproducible).
+// Second reduction stage: the partials of each grid are reduced in chunks of kChunk by
+// gridDim.x workgroups, in a fixed order (reproducible); a further pass (same kernel, one
+// workgroup per grid) reduces the chunk results when there is more than one chunk.
+constexpr int kChunk = 4096;
+
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ part, int count,
                                                      long long stride, int op, double scale,
                                                      double* __restrict__ out, int out_stride,
                                                      int slot) {
   __shared__ double sh[kBlock];
-  const double* p = part + (long long)blockIdx.x * stride;
+  const double* p = part + (long long)blockIdx.y * stride;
+  const int lo = blockIdx.x * kChunk, hi = min(count, lo + kChunk);
   double a = 0.0;
-  for (int i = threadIdx.x; i < count; i += kBlock) a = op == MAX ? fmax(a, p[i]) : a + p[i];
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) a = op == MAX ? fmax(a, p[i]) : a + p[i];
   sh[threadIdx.x] = a;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -551,7 +605,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride + slot] = sh[0] * scale;
+  if (threadIdx.x == 0) {
+    if (gridDim.x == 1) out[(long long)blockIdx.y * out_stride + slot] = sh[0] * scale;
+    else out[(long long)blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
+  }
 }
 
 template <typename T>
@@ -574,35 +631,41 @@ __global__ __launch_bounds__(kBlock) void k_sub_scalar(long long plane, int batc
 
 // ----------------------------------------------------------------------------------------
 // Small batched FP64 GEMM for the separable coarse solve: C = op(A) op(B) [.* S].
-// 32 x 32 output tile per workgroup, K staged through LDS in chunks of 32.
+// A 16 x 16 output tile per workgroup of one wave (so a 256 x 256 product spreads over 256
+// workgroups, one per CU), each lane computing a 2 x 2 block; K is staged through LDS in
+// chunks of 32.
 // ----------------------------------------------------------------------------------------
+constexpr int kGemmTile = 16, kGemmK = 32, kGemmThreads = 64;
+
 template <int TA, int TB>
-__global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const double* __restrict__ A,
-                                                 long long sA, int lda,
-                                                 const double* __restrict__ B, long long sB,
-                                                 int ldb, double* __restrict__ C, long long sC,
-                                                 int ldc, const double* __restrict__ S) {
-  constexpr int BT = 32;
-  __shared__ double As[BT][BT + 1];  // [k][m]
-  __shared__ double Bs[BT][BT + 1];  // [k][n]
+__global__ __launch_bounds__(kGemmThreads) void k_gemm(int M, int N, int K,
+                                                       const double* __restrict__ A, long long sA,
+                                                       int lda, const double* __restrict__ B,
+                                                       long long sB, int ldb,
+                                                       double* __restrict__ C, long long sC,
+                                                       int ldc, const double* __restrict__ S) {
+  __shared__ double As[kGemmK][kGemmTile + 1];  // [k][m]
+  __shared__ double Bs[kGemmK][kGemmTile + 1];  // [k][n]
   A += (long long)blockIdx.z * sA;
   B += (long long)blockIdx.z * sB;
   C += (long long)blockIdx.z * sC;
-  const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
-  const int tx = threadIdx.x & (BT - 1), ty = threadIdx.x / BT;  // ty in 0..7
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += BT) {
-    for (int t = threadIdx.x; t < BT * BT; t += kBlock) {
-      const int a = t / BT, c = t - a * BT;
-      {
-        const int m = TA ? c : a, k = TA ? a : c;
+  const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
+  const int tx = threadIdx.x & 7, ty = threadIdx.x >> 3;  // 8 x 8 lanes
+  double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+  for (int k0 = 0; k0 < K; k0 += kGemmK) {
+#pragma unroll
+    for (int t = threadIdx.x; t < kGemmTile * kGemmK; t += kGemmThreads) {
+      {  // A tile, coalesced along the contiguous index of the stored matrix
+        const int m = TA ? (t & (kGemmTile - 1)) : (t / kGemmK);
+        const int k = TA ? (t / kGemmTile) : (t & (kGemmK - 1));
         const int gm = m0 + m, gk = k0 + k;
         double v = 0.0;
         if (gm < M && gk < K) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
         As[k][m] = v;
       }
       {
-        const int k = TB ? c : a, nn = TB ? a : c;
+        const int nn = TB ? (t / kGemmK) : (t & (kGemmTile - 1));
+        const int k = TB ? (t & (kGemmK - 1)) : (t / kGemmTile);
         const int gk = k0 + k, gn = n0 + nn;
         double v = 0.0;
         if (gk < K && gn < N) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
@@ -611,22 +674,28 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
     }
     __syncthreads();
 #pragma unroll 8
-    for (int kk = 0; kk < BT; ++kk) {
-      const double bv = Bs[kk][tx];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = fma(As[kk][ty + 8 * q], bv, acc[q]);
+    for (int kk = 0; kk < kGemmK; ++kk) {
+      const double a0 = As[kk][ty], a1 = As[kk][ty + 8];
+      const double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 8];
+      c00 = fma(a0, b0, c00);
+      c01 = fma(a0, b1, c01);
+      c10 = fma(a1, b0, c10);
+      c11 = fma(a1, b1, c11);
     }
     __syncthreads();
   }
+  const double cv[2][2] = {{c00, c01}, {c10, c11}};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gm = m0 + ty + 8 * q, gn = n0 + tx;
-    if (gm < M && gn < N) {
-      double v = acc[q];
-      if (S) v *= S[(long long)gm * N + gn];
-      C[(long long)gm * ldc + gn] = v;
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int gm = m0 + ty + 8 * a, gn = n0 + tx + 8 * b;
+      if (gm < M && gn < N) {
+        double v = cv[a][b];
+        if (S) v *= S[(long long)gm * N + gn];
+        C[(long long)gm * ldc + gn] = v;
+      }
     }
-  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -992,9 +1061,17 @@ hipError_t launch_tile_sum(const Geo& g, const double* x, double* part, hipStrea
 
 hipError_t launch_finalize(const double* part, int count, long long part_stride, int batch,
                            Reduce op, double scale, double* out, int out_stride, int slot,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(kBlock), 0, s, part, count, part_stride, int(op),
-                     scale, out, out_stride, slot);
+                           double* scratch, hipStream_t s) {
+  const int chunks = (count + kChunk - 1) / kChunk;
+  if (chunks <= 1) {
+    hipLaunchKernelGGL(k_finalize, dim3(1, batch), dim3(kBlock), 0, s, part, count, part_stride,
+                       int(op), scale, out, out_stride, slot);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(chunks, batch), dim3(kBlock), 0, s, part, count, part_stride,
+                     int(op), 1.0, scratch, 0, 0);
+  hipLaunchKernelGGL(k_finalize, dim3(1, batch), dim3(kBlock), 0, s, scratch, chunks,
+                     (long long)chunks, int(op), scale, out, out_stride, slot);
   return hipGetLastError();
 }
 
@@ -1015,15 +1092,16 @@ hipError_t launch_sub_scalar(const Geo& g, double* x, const double* vals, int va
 hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long long sA, int lda,
                        int transB, const double* B, long long sB, int ldb, double* C, long long sC,
                        int ldc, const double* S, int batch, hipStream_t s) {
-  dim3 grid((N + 31) / 32, (M + 31) / 32, batch);
+  dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, batch);
+  dim3 block(kGemmThreads);
   if (!transA && !transB)
-    hipLaunchKernelGGL((k_gemm<0, 0>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+    hipLaunchKernelGGL((k_gemm<0, 0>), grid, block, 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
   else if (transA && !transB)
-    hipLaunchKernelGGL((k_gemm<1, 0>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+    hipLaunchKernelGGL((k_gemm<1, 0>), grid, block, 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
   else if (!transA && transB)
-    hipLaunchKernelGGL((k_gemm<0, 1>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+    hipLaunchKernelGGL((k_gemm<0, 1>), grid, block, 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
   else
-    hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(kBlock), 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
+    hipLaunchKernelGGL((k_gemm<1, 1>), grid, block, 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
   return hipGetLastError();
 }
 

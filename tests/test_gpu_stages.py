@@ -23,6 +23,11 @@ CASES = [
     (256, 192, 32, N, N),
     (64, 48, 4, P, N),
     (160, 96, 32, P, N),
+    # large enough for the fused kernel's interior fast path (tiles whose halo touches no
+    # wall and interpolates unclamped)
+    (320, 256, 32, N, N),
+    (320, 192, 16, P, N),
+    (384, 320, 8, N, N),
 ]
 DTYPES = [(torch.float64, np.float64), (torch.float32, np.float32)]
 
