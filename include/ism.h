@@ -168,9 +168,10 @@ int ism_prolong(ism_handle h, int32_t dtype, const double* E, void* e);
  * was created with ISM_COARSE_GMG5.  Exact up to FP64 rounding. */
 int ism_coarse_solve(ism_handle h, const double* rc, double* E);
 
-/* One two-level cycle on A' e = rhs: E = coarse solve of rc; e += P E; nsweeps red-black
+/* One two-level cycle on A' e = rhs: E = coarse solve of rc; e += P E; nu red-black
  * sweeps; rc = R (rhs - A' e) (rc is read and then overwritten).  With zero_e != 0 the
- * incoming e is taken as zero.  Uses the fused kernel if the handle was created fused. */
+ * incoming e is taken as zero.  Uses the fused kernel if the handle was created fused.
+ * rhs and e must be 16-byte aligned (ISM_ERR_INVALID otherwise). */
 int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
               int32_t zero_e, double* sumsq);
 

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -779,6 +780,8 @@ int smooth_impl(ism_ctx* c, const T* rhs, T* e, int nsweeps) {
 
 template <typename T>
 int cycle_impl(ism_ctx* c, const T* rhs, T* e, double* rc, int zero_e, double* sumsq) {
+  if ((reinterpret_cast<uintptr_t>(rhs) | reinterpret_cast<uintptr_t>(e)) % 16)
+    return set_err(c, ISM_ERR_INVALID, "rhs and e must be 16-byte aligned");
   T* tmp = (T*)scratch_fine(c);
   if (!tmp) return set_err(c, ISM_ERR_HIP, "hipMalloc of the stage scratch failed");
   T* cur = e;

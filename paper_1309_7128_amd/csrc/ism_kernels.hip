@@ -268,55 +268,115 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
 // Fused two-level cycle kernel (temporal blocking of the red-black sweeps).
 //
 // A workgroup owns a 64 x TSY tile of fine cells (TSY = 64 for FP32, 32 for FP64 so that
-// three workgroups fit in a CU's LDS either way).  It stages e with a halo of H = 2 NU + 1
-// cells and rhs with a halo of 2 NU in LDS, adds the bilinear coarse correction to every
-// staged cell, then performs the 2 NU red/black half-steps on shrinking regions (half-step s
-// updates the tile grown by H - 1 - s rings), so that after the last half-step e is exact on
-// the tile plus one ring.  It then forms the residual on the tile, writes the tile of e and
-// the sums of the residual (and its square) over each n x n coarse tile it contains.
-// Redundant halo work replaces the NU extra round trips through HBM: per cycle the kernel
-// reads e and rhs once and writes e once.  A red-black half-step reads only the other colour,
-// so a halo cell gets exactly the value its owner computes.
+// three workgroups fit in a CU's LDS either way).  It stages e on the tile grown by H = 2 NU + 1
+// rows and PADX columns (PADX >= H - 1 + VEC, a multiple of the 16-byte chunk of VEC cells),
+// and rhs on the cells a half-step may update, in LDS, adding the bilinear coarse correction
+// to every staged e.  Every global access is a 16-byte chunk and all of a lane's loads are in
+// flight together.  The 2 NU red/black half-steps then each update their colour on every
+// staged chunk that has all its neighbours staged; a lane keeps the same chunks throughout.
+// Values computed outside the ring H - 1 - s at half-step s come from stale neighbours, but
+// no later half-step inside its own ring reads them, so after the last half-step e is exact
+// on the tile plus one ring.  A red/black half-step reads only the other colour, so a halo
+// cell gets exactly the value its owner computes.  The kernel then forms the residual on the
+// tile, writes the tile of e and the sums of the residual (and its square) over each n x n
+// coarse tile it contains.  Per cycle it reads e and rhs once and writes e once.
 // Workgroups are numbered so that the consecutive workgroups one XCD receives (the hardware
 // deals them out round-robin over the 8 XCDs) take neighbouring tiles, whose halos then
 // meet in that XCD's L2.
 // ----------------------------------------------------------------------------------------
+template <typename T>
+struct Chunk;
+template <>
+struct Chunk<float> {
+  using type = float4;
+};
+template <>
+struct Chunk<double> {
+  using type = double2;
+};
+
+template <typename V>
+__device__ __forceinline__ V zero_chunk() {
+  V v;
+  for (int k = 0; k < int(sizeof(V) / sizeof(v.x)); ++k) (&v.x)[k] = 0;
+  return v;
+}
+
 template <typename T, int NU, int LOG2N, int TSY>
 struct CycleTile {
+  using V = typename Chunk<T>::type;
+  static constexpr int VEC = 16 / sizeof(T);  // cells per 16-byte chunk
   static constexpr int TSX = 64;
   static constexpr int N = 1 << LOG2N;
   static constexpr int H = 2 * NU + 1;
-  static constexpr int LEX = TSX + 2 * H, LEY = TSY + 2 * H;
-  static constexpr int HR = 2 * NU;
-  static constexpr int LRX = TSX + 2 * HR, LRY = TSY + 2 * HR;
+  static constexpr int PADX = ((H - 1 + VEC + VEC - 1) / VEC) * VEC;
+  static constexpr int LEX = TSX + 2 * PADX, LEY = TSY + 2 * H;  // staged e
+  static constexpr int CX = LEX / VEC;                           // chunks per staged row
+  static constexpr int LRX = LEX - 2 * VEC, LRY = LEY - 2;       // staged rhs
+  static constexpr int CRX = LRX / VEC;
+  static constexpr int NE = (LEY * CX + kBlock - 1) / kBlock;    // e chunks per lane
+  static constexpr int NRC = (LRY * CRX + kBlock - 1) / kBlock;  // rhs chunks (= updated chunks) per lane
   static constexpr int CEX = LEX / N + 3, CEY = LEY / N + 3;
-  static constexpr int RPW = TSY / 4;                 // tile rows per wave
+  static constexpr int RPW = TSY / 4;                 // tile rows per wave (residual)
   static constexpr int NBW = RPW >= N ? RPW / N : 1;  // coarse bands per wave
   static constexpr int WPB = N > RPW ? N / RPW : 1;   // waves per coarse band
   static constexpr int TPX = TSX / N, TPY = TSY / N;  // coarse tiles per workgroup tile
   static_assert(TSY % 4 == 0 && N <= TSY, "a workgroup tile must hold whole coarse tiles");
 
   struct Shared {
-    T se[LEY * LEX];
-    T sr[LRY * LRX];
+    V se[LEY * CX];
+    V sr[LRY * CRX];
     double sE[CEY * CEX];   // coarse values around the staged region
     double sEx[CEY * LEX];  // the same, interpolated along x at every staged column
     double rowY[LEY];       // y weight of every staged row ...
-    int rowJ[LEY];          // ... and its lower coarse row in sEx
+    int rowJ[LEY];          // ... and the offset of its lower coarse row in sEx
     double red1[4][NBW][TPX];
     double red2[4][NBW][TPX];
   };
 
-  // INTERIOR: the staged region lies inside the grid and touches no wall, so no cell needs
-  // wrapping, clamping or a reduced neighbour count.
+  // 1 / (number of existing neighbours) of a staged cell, 0 for a cell behind a wall (which
+  // then stays 0, as a missing neighbour contributes nothing)
+  static __device__ __forceinline__ T inv_at(const Geo& g, int i, int j) {
+    if (!map_cell(g, i, j)) return T(0);
+    return inv_count<T>(g, i, j);
+  }
+
+  // INTERIOR: the staged region lies inside the grid, touches no wall and interpolates from
+  // unclamped coarse values.
   template <bool INTERIOR>
   static __device__ __forceinline__ void run(Shared& sh, const Geo& g, const T* __restrict__ rb,
                                              const T* __restrict__ eb, T* __restrict__ ob,
                                              const double* __restrict__ Eb, double* __restrict__ rc,
                                              double* __restrict__ psq, int zero_e, int x0, int y0,
-                                             int bz) {
-    const int cI0 = floordiv(x0 - H - (N >> 1), N);
-    const int cJ0 = floordiv(y0 - H - (N >> 1), N);
+                                             int cI0, int cJ0, int bz) {
+    T* se = reinterpret_cast<T*>(sh.se);
+    const T* sr = reinterpret_cast<const T*>(sh.sr);
+    const int xs = x0 - PADX, ys = y0 - H;  // grid coordinates of staged cell (0, 0)
+
+    // issue every global load of this lane first
+    V ev[NE], rv[NRC];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+      const int q = threadIdx.x + m * kBlock;
+      ev[m] = zero_chunk<V>();
+      if (q < LEY * CX && !zero_e) {
+        const int ly = q / CX, c = q - ly * CX;
+        int i = xs + VEC * c, j = ys + ly;
+        if (INTERIOR || map_cell(g, i, j)) ev[m] = *reinterpret_cast<const V*>(eb + j * g.nx + i);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NRC; ++m) {
+      const int q = threadIdx.x + m * kBlock;
+      rv[m] = zero_chunk<V>();
+      if (q < LRY * CRX) {
+        const int ly = 1 + q / CRX, c = 1 + (q - (ly - 1) * CRX);
+        int i = xs + VEC * c, j = ys + ly;
+        if (INTERIOR || map_cell(g, i, j)) rv[m] = *reinterpret_cast<const V*>(rb + j * g.nx + i);
+      }
+    }
+
+    // coarse values around the staged region, with the boundary rule applied at load time
     for (int t = threadIdx.x; t < CEY * CEX; t += kBlock) {
       int cj = t / CEX, ci = t - cj * CEX;
       int I = cI0 + ci, J = cJ0 + cj;
@@ -329,7 +389,7 @@ struct CycleTile {
     for (int t = threadIdx.x; t < LEY; t += kBlock) {
       int jlo;
       double Y;
-      interp_coord(y0 + t - H, N, jlo, Y);
+      interp_coord(ys + t, N, jlo, Y);
       sh.rowY[t] = Y;
       sh.rowJ[t] = (jlo - cJ0) * LEX;
     }
@@ -338,57 +398,64 @@ struct CycleTile {
       int cj = t / LEX, lx = t - cj * LEX;
       int ilo;
       double X;
-      interp_coord(x0 + lx - H, N, ilo, X);
+      interp_coord(xs + lx, N, ilo, X);
       const double* q = sh.sE + cj * CEX + (ilo - cI0);
       sh.sEx[t] = lerp(q[0], q[1], X);
     }
     __syncthreads();
 
-    // stage e + P E (the coarse correction) and rhs
-#pragma unroll 4
-    for (int t = threadIdx.x; t < LEY * LEX; t += kBlock) {
-      const int ly = t / LEX, lx = t - ly * LEX;
-      int i = x0 + lx - H, j = y0 + ly - H;
-      T v = T(0);
-      if (INTERIOR || map_cell(g, i, j)) {
-        const double* q = sh.sEx + sh.rowJ[ly] + lx;
-        const double p = lerp(q[0], q[LEX], sh.rowY[ly]);
-        const double base = zero_e ? 0.0 : double(eb[j * g.nx + i]);
-        v = T(base + p);
+    // staged e = e + P E (cells behind a wall stay 0), staged rhs
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+      const int q = threadIdx.x + m * kBlock;
+      if (q < LEY * CX) {
+        const int ly = q / CX, c = q - ly * CX;
+        int i = xs + VEC * c, j = ys + ly;
+        V v = zero_chunk<V>();
+        if (INTERIOR || map_cell(g, i, j)) {
+          const double* p = sh.sEx + sh.rowJ[ly] + VEC * c;
+          const double Y = sh.rowY[ly];
+#pragma unroll
+          for (int k = 0; k < VEC; ++k)
+            (&v.x)[k] = T(double((&ev[m].x)[k]) + lerp(p[k], p[k + LEX], Y));
+        }
+        sh.se[q] = v;
       }
-      sh.se[t] = v;
     }
-#pragma unroll 4
-    for (int t = threadIdx.x; t < LRY * LRX; t += kBlock) {
-      const int ly = t / LRX, lx = t - ly * LRX;
-      int i = x0 + lx - HR, j = y0 + ly - HR;
-      T v = T(0);
-      if (INTERIOR || map_cell(g, i, j)) v = rb[j * g.nx + i];
-      sh.sr[t] = v;
+#pragma unroll
+    for (int m = 0; m < NRC; ++m) {
+      const int q = threadIdx.x + m * kBlock;
+      if (q < LRY * CRX) sh.sr[q] = rv[m];
     }
     __syncthreads();
 
-    // 2 NU red/black half-steps on regions shrinking by one ring each
+    // 2 NU red/black half-steps; a lane updates the same chunks (those it staged rhs for)
 #pragma unroll
     for (int s = 0; s < 2 * NU; ++s) {
-      const int R = H - 1 - s;
       const int colour = s & 1;
-      const int LX = TSX + 2 * R, LY = TSY + 2 * R;
-      const int HW = LX / 2;  // cells of one colour per row
-      for (int t = threadIdx.x; t < LY * HW; t += kBlock) {
-        const int r = t / HW, k = t - r * HW;
-        const int ly = H - R + r;
-        const int gj = y0 + ly - H;
-        const int lx = (H - R) + ((colour + R + gj) & 1) + 2 * k;
-        T inv = T(0.25);
-        if (!INTERIOR) {
-          int i = x0 + lx - H, j = gj;
-          if (!map_cell(g, i, j)) continue;
-          inv = inv_count<T>(g, i, j);
+#pragma unroll
+      for (int m = 0; m < NRC; ++m) {
+        const int q = threadIdx.x + m * kBlock;
+        if (q < LRY * CRX) {
+          const int ly = 1 + q / CRX, c = 1 + (q - (ly - 1) * CRX);
+          const int vi = ly * CX + c;
+          V cur = sh.se[vi];
+          const V up = sh.se[vi + CX], dn = sh.se[vi - CX];
+          const V rr = sh.sr[q];
+          const T left = se[VEC * vi - 1], right = se[VEC * vi + VEC];
+          const int k0 = (colour + ly + 1) & 1;  // first cell of this colour in the chunk
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) {
+            if ((k & 1) != k0) continue;
+            const T w = k == 0 ? left : (&cur.x)[k - 1];
+            const T e = k == VEC - 1 ? right : (&cur.x)[k + 1];
+            T inv = T(0.25);
+            if (!INTERIOR) inv = inv_at(g, xs + VEC * c + k, ys + ly);
+            const T sum = ((w + e) + (&dn.x)[k]) + (&up.x)[k];
+            (&cur.x)[k] = (sum - (&rr.x)[k]) * inv;
+          }
+          sh.se[vi] = cur;
         }
-        const int idx = ly * LEX + lx;
-        const T sum = ((sh.se[idx - 1] + sh.se[idx + 1]) + sh.se[idx - LEX]) + sh.se[idx + LEX];
-        sh.se[idx] = (sum - sh.sr[(ly - 1) * LRX + (lx - 1)]) * inv;
       }
       __syncthreads();
     }
@@ -406,11 +473,10 @@ struct CycleTile {
       const int gj = y0 + r;
       if (INTERIOR || (gi < g.nx && gj < g.ny)) {
         const bool hs = INTERIOR || g.per_y || gj > 0, hn = INTERIOR || g.per_y || gj < g.ny - 1;
-        const int idx = (r + H) * LEX + (lane + H);
-        const T c = sh.se[idx];
-        const T res = sh.sr[(r + HR) * LRX + (lane + HR)] -
-                      lap5<T>(c, sh.se[idx - 1], sh.se[idx + 1], sh.se[idx - LEX], sh.se[idx + LEX],
-                              hw, he, hs, hn);
+        const int idx = (r + H) * LEX + (lane + PADX);
+        const T c = se[idx];
+        const T res = sr[(r + H - 1) * LRX + (lane + PADX - VEC)] -
+                      lap5<T>(c, se[idx - 1], se[idx + 1], se[idx - LEX], se[idx + LEX], hw, he, hs, hn);
         ob[gj * g.nx + gi] = c;
         const double d = double(res);
         const int q = RPW >= N ? (rr >> LOG2N) : 0;
@@ -468,19 +534,19 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   const int x0 = bx * CT::TSX, y0 = by * TSY;
   const long long off = (long long)blockIdx.z * g.plane;
   const double* Eb = E + (long long)blockIdx.z * g.cplane;
-  // interior: every staged cell and its neighbours lie in the grid away from the walls, and
-  // every coarse value the staged cells interpolate from lies in the coarse grid unclamped
-  const int cI0 = floordiv(x0 - CT::H - (CT::N >> 1), CT::N);
+  const int cI0 = floordiv(x0 - CT::PADX - (CT::N >> 1), CT::N);
   const int cJ0 = floordiv(y0 - CT::H - (CT::N >> 1), CT::N);
-  const bool interior = x0 >= CT::H && x0 + CT::TSX + CT::H <= g.nx && y0 >= CT::H &&
-                        y0 + TSY + CT::H <= g.ny && cI0 >= 0 && cI0 + CT::CEX <= g.ncx &&
-                        cJ0 >= 0 && cJ0 + CT::CEY <= g.ncy;
+  // interior: every staged cell lies in the grid away from the walls, and every coarse value
+  // the staged cells interpolate from lies in the coarse grid unclamped
+  const bool interior = x0 - CT::PADX >= 1 && x0 + CT::TSX + CT::PADX + 1 <= g.nx &&
+                        y0 - CT::H >= 1 && y0 + TSY + CT::H + 1 <= g.ny && cI0 >= 0 &&
+                        cI0 + CT::CEX <= g.ncx && cJ0 >= 0 && cJ0 + CT::CEY <= g.ncy;
   if (interior)
     CT::template run<true>(sh, g, rhs + off, ein + off, eout + off, Eb, rc, psq, zero_e, x0, y0,
-                           blockIdx.z);
+                           cI0, cJ0, blockIdx.z);
   else
     CT::template run<false>(sh, g, rhs + off, ein + off, eout + off, Eb, rc, psq, zero_e, x0, y0,
-                            blockIdx.z);
+                            cI0, cJ0, blockIdx.z);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -631,36 +697,39 @@ __global__ __launch_bounds__(kBlock) void k_sub_scalar(long long plane, int batc
 
 // ----------------------------------------------------------------------------------------
 // Small batched FP64 GEMM for the separable coarse solve: C = op(A) op(B) [.* S].
-// A 16 x 16 output tile per workgroup of one wave (so a 256 x 256 product spreads over 256
-// workgroups, one per CU), each lane computing a 2 x 2 block; K is staged through LDS in
-// chunks of 32.
+// A 16 x 16 output tile per workgroup (a 256 x 256 product spreads over 256 workgroups, one
+// per CU).  The whole K panel of A and B (up to 256 deep per pass) is loaded in one batch so
+// that all loads are in flight together; the 4 waves then each accumulate a quarter of K
+// (a lane owns a 2 x 2 block) and the quarters are added in wave order through LDS.
 // ----------------------------------------------------------------------------------------
-constexpr int kGemmTile = 16, kGemmK = 32, kGemmThreads = 64;
+constexpr int kGemmTile = 16, kGemmK = 256;
 
 template <int TA, int TB>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm(int M, int N, int K,
-                                                       const double* __restrict__ A, long long sA,
-                                                       int lda, const double* __restrict__ B,
-                                                       long long sB, int ldb,
-                                                       double* __restrict__ C, long long sC,
-                                                       int ldc, const double* __restrict__ S) {
+__global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const double* __restrict__ A,
+                                                 long long sA, int lda,
+                                                 const double* __restrict__ B, long long sB,
+                                                 int ldb, double* __restrict__ C, long long sC,
+                                                 int ldc, const double* __restrict__ S) {
   __shared__ double As[kGemmK][kGemmTile + 1];  // [k][m]
   __shared__ double Bs[kGemmK][kGemmTile + 1];  // [k][n]
+  __shared__ double red[4][kGemmTile][kGemmTile + 1];
   A += (long long)blockIdx.z * sA;
   B += (long long)blockIdx.z * sB;
   C += (long long)blockIdx.z * sC;
   const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
-  const int tx = threadIdx.x & 7, ty = threadIdx.x >> 3;  // 8 x 8 lanes
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int tx = lane & 7, ty = lane >> 3;  // lane computes rows ty, ty+8 and cols tx, tx+8
   double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
   for (int k0 = 0; k0 < K; k0 += kGemmK) {
-#pragma unroll
-    for (int t = threadIdx.x; t < kGemmTile * kGemmK; t += kGemmThreads) {
-      {  // A tile, coalesced along the contiguous index of the stored matrix
+    const int kc = min(kGemmK, K - k0);
+#pragma unroll 4
+    for (int t = threadIdx.x; t < kGemmTile * kGemmK; t += kBlock) {
+      {  // A panel, coalesced along the contiguous index of the stored matrix
         const int m = TA ? (t & (kGemmTile - 1)) : (t / kGemmK);
         const int k = TA ? (t / kGemmTile) : (t & (kGemmK - 1));
         const int gm = m0 + m, gk = k0 + k;
         double v = 0.0;
-        if (gm < M && gk < K) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+        if (gm < M && k < kc) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
         As[k][m] = v;
       }
       {
@@ -668,13 +737,15 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(int M, int N, int K,
         const int k = TB ? (t & (kGemmK - 1)) : (t / kGemmTile);
         const int gk = k0 + k, gn = n0 + nn;
         double v = 0.0;
-        if (gk < K && gn < N) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
+        if (k < kc && gn < N) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
         Bs[k][nn] = v;
       }
     }
     __syncthreads();
+    const int q = (kc + 3) / 4;  // this wave's quarter of the panel
+    const int ka = wave * q, kb = min(kc, ka + q);
 #pragma unroll 8
-    for (int kk = 0; kk < kGemmK; ++kk) {
+    for (int kk = ka; kk < kb; ++kk) {
       const double a0 = As[kk][ty], a1 = As[kk][ty + 8];
       const double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 8];
       c00 = fma(a0, b0, c00);
@@ -684,18 +755,18 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(int M, int N, int K,
     }
     __syncthreads();
   }
-  const double cv[2][2] = {{c00, c01}, {c10, c11}};
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int gm = m0 + ty + 8 * a, gn = n0 + tx + 8 * b;
-      if (gm < M && gn < N) {
-        double v = cv[a][b];
-        if (S) v *= S[(long long)gm * N + gn];
-        C[(long long)gm * ldc + gn] = v;
-      }
-    }
+  red[wave][ty][tx] = c00;
+  red[wave][ty][tx + 8] = c01;
+  red[wave][ty + 8][tx] = c10;
+  red[wave][ty + 8][tx + 8] = c11;
+  __syncthreads();
+  const int m = threadIdx.x / kGemmTile, nn = threadIdx.x & (kGemmTile - 1);
+  const int gm = m0 + m, gn = n0 + nn;
+  if (gm < M && gn < N) {
+    double v = ((red[0][m][nn] + red[1][m][nn]) + red[2][m][nn]) + red[3][m][nn];
+    if (S) v *= S[(long long)gm * N + gn];
+    C[(long long)gm * ldc + gn] = v;
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1093,7 +1164,7 @@ hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long lo
                        int transB, const double* B, long long sB, int ldb, double* C, long long sC,
                        int ldc, const double* S, int batch, hipStream_t s) {
   dim3 grid((N + kGemmTile - 1) / kGemmTile, (M + kGemmTile - 1) / kGemmTile, batch);
-  dim3 block(kGemmThreads);
+  dim3 block(kBlock);
   if (!transA && !transB)
     hipLaunchKernelGGL((k_gemm<0, 0>), grid, block, 0, s, M, N, K, A, sA, lda, B, sB, ldb, C, sC, ldc, S);
   else if (transA && !transB)
