@@ -310,22 +310,26 @@ struct CycleTile {
   static constexpr int N = 1 << LOG2N;
   static constexpr int H = 2 * NU + 1;
   static constexpr int PADX = ((H - 1 + VEC + VEC - 1) / VEC) * VEC;
-  static constexpr int LEX = TSX + 2 * PADX, LEY = TSY + 2 * H;  // staged e
-  static constexpr int CX = LEX / VEC;                           // chunks per staged row
-  static constexpr int LRX = LEX - 2 * VEC, LRY = LEY - 2;       // staged rhs
-  static constexpr int CRX = LRX / VEC;
-  static constexpr int NE = (LEY * CX + kBlock - 1) / kBlock;    // e chunks per lane
-  static constexpr int NRC = (LRY * CRX + kBlock - 1) / kBlock;  // rhs chunks (= updated chunks) per lane
+  static constexpr int LEX = TSX + 2 * PADX, LEY = TSY + 2 * H;  // staged region
+  static constexpr int HX = LEX / 2;                             // cells per half-row
+  static constexpr int CX = LEX / VEC;                           // global chunks per staged row
+  static constexpr int HC = HX / VEC;                            // LDS chunks per half-row
+  static constexpr int NE = (LEY * CX + kBlock - 1) / kBlock;    // e chunks staged per lane
+  static constexpr int NRC = ((LEY - 2) * CX + kBlock - 1) / kBlock;  // rhs chunks per lane
+  static constexpr int NUC = ((LEY - 2) * HC + kBlock - 1) / kBlock;  // updated chunks per lane
   static constexpr int CEX = LEX / N + 3, CEY = LEY / N + 3;
   static constexpr int RPW = TSY / 4;                 // tile rows per wave (residual)
   static constexpr int NBW = RPW >= N ? RPW / N : 1;  // coarse bands per wave
   static constexpr int WPB = N > RPW ? N / RPW : 1;   // waves per coarse band
   static constexpr int TPX = TSX / N, TPY = TSY / N;  // coarse tiles per workgroup tile
   static_assert(TSY % 4 == 0 && N <= TSY, "a workgroup tile must hold whole coarse tiles");
+  static_assert(HX % VEC == 0, "half-rows must hold whole chunks");
 
+  // Staged rows are stored split by column parity: [even columns | odd columns], so that a
+  // red or black half-step works on contiguous chunks of one colour.
   struct Shared {
-    V se[LEY * CX];
-    V sr[LRY * CRX];
+    alignas(16) T se[LEY * LEX];        // e, rows 0 .. LEY-1
+    alignas(16) T sr[(LEY - 2) * LEX];  // rhs, rows 1 .. LEY-2
     double sE[CEY * CEX];   // coarse values around the staged region
     double sEx[CEY * LEX];  // the same, interpolated along x at every staged column
     double rowY[LEY];       // y weight of every staged row ...
@@ -333,6 +337,14 @@ struct CycleTile {
     double red1[4][NBW][TPX];
     double red2[4][NBW][TPX];
   };
+
+  static __device__ __forceinline__ int at(int ly, int lx) { return ly * LEX + (lx & 1) * HX + (lx >> 1); }
+
+  // a natural-order chunk of VEC cells (columns lx0 .. lx0+VEC-1) into the split row
+  static __device__ __forceinline__ void put(T* row, int lx0, const V& v) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) row[(k & 1) * HX + ((lx0 + k) >> 1)] = (&v.x)[k];
+  }
 
   // 1 / (number of existing neighbours) of a staged cell, 0 for a cell behind a wall (which
   // then stays 0, as a missing neighbour contributes nothing)
@@ -349,8 +361,6 @@ struct CycleTile {
                                              const double* __restrict__ Eb, double* __restrict__ rc,
                                              double* __restrict__ psq, int zero_e, int x0, int y0,
                                              int cI0, int cJ0, int bz) {
-    T* se = reinterpret_cast<T*>(sh.se);
-    const T* sr = reinterpret_cast<const T*>(sh.sr);
     const int xs = x0 - PADX, ys = y0 - H;  // grid coordinates of staged cell (0, 0)
 
     // issue every global load of this lane first
@@ -369,8 +379,8 @@ struct CycleTile {
     for (int m = 0; m < NRC; ++m) {
       const int q = threadIdx.x + m * kBlock;
       rv[m] = zero_chunk<V>();
-      if (q < LRY * CRX) {
-        const int ly = 1 + q / CRX, c = 1 + (q - (ly - 1) * CRX);
+      if (q < (LEY - 2) * CX) {
+        const int ly = 1 + q / CX, c = q - (ly - 1) * CX;
         int i = xs + VEC * c, j = ys + ly;
         if (INTERIOR || map_cell(g, i, j)) rv[m] = *reinterpret_cast<const V*>(rb + j * g.nx + i);
       }
@@ -419,42 +429,54 @@ struct CycleTile {
           for (int k = 0; k < VEC; ++k)
             (&v.x)[k] = T(double((&ev[m].x)[k]) + lerp(p[k], p[k + LEX], Y));
         }
-        sh.se[q] = v;
+        put(sh.se + ly * LEX, VEC * c, v);
       }
     }
 #pragma unroll
     for (int m = 0; m < NRC; ++m) {
       const int q = threadIdx.x + m * kBlock;
-      if (q < LRY * CRX) sh.sr[q] = rv[m];
+      if (q < (LEY - 2) * CX) {
+        const int r = q / CX, c = q - r * CX;
+        put(sh.sr + r * LEX, VEC * c, rv[m]);
+      }
     }
     __syncthreads();
 
-    // 2 NU red/black half-steps; a lane updates the same chunks (those it staged rhs for)
+    // 2 NU red/black half-steps: in rows 1 .. LEY-2 every chunk of the half-row holding the
+    // colour is updated.  Edge chunks read a neighbour from outside their row; the garbage
+    // they make spreads one column per half-step and never reaches the valid ring.
 #pragma unroll
     for (int s = 0; s < 2 * NU; ++s) {
       const int colour = s & 1;
 #pragma unroll
-      for (int m = 0; m < NRC; ++m) {
+      for (int m = 0; m < NUC; ++m) {
         const int q = threadIdx.x + m * kBlock;
-        if (q < LRY * CRX) {
-          const int ly = 1 + q / CRX, c = 1 + (q - (ly - 1) * CRX);
-          const int vi = ly * CX + c;
-          V cur = sh.se[vi];
-          const V up = sh.se[vi + CX], dn = sh.se[vi - CX];
-          const V rr = sh.sr[q];
-          const T left = se[VEC * vi - 1], right = se[VEC * vi + VEC];
-          const int k0 = (colour + ly + 1) & 1;  // first cell of this colour in the chunk
+        if (q < (LEY - 2) * HC) {
+          const int ly = 1 + q / HC, h = q - (ly - 1) * HC;
+          const int par = (colour + ly + 1) & 1;  // column parity of this colour in row ly
+          const int t0 = VEC * h;
+          const int xrow = ly * LEX + par * HX;        // this colour's half-row
+          const int orow = ly * LEX + (1 - par) * HX;  // the other colour's
+          const V on = *reinterpret_cast<const V*>(sh.se + orow + t0);
+          const T ox = sh.se[orow + (par ? t0 + VEC : t0 - 1)];
+          const V up = *reinterpret_cast<const V*>(sh.se + xrow + LEX + t0);
+          const V dn = *reinterpret_cast<const V*>(sh.se + xrow - LEX + t0);
+          const V rr = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + par * HX + t0);
+          V out;
 #pragma unroll
           for (int k = 0; k < VEC; ++k) {
-            if ((k & 1) != k0) continue;
-            const T w = k == 0 ? left : (&cur.x)[k - 1];
-            const T e = k == VEC - 1 ? right : (&cur.x)[k + 1];
+            // even cells (par 0) have their west neighbour one slot left in the odd half,
+            // odd cells (par 1) their east neighbour one slot right in the even half
+            const T lo = k == 0 ? ox : (&on.x)[k - 1];
+            const T hi = k == VEC - 1 ? ox : (&on.x)[k + 1];
+            const T w = par ? (&on.x)[k] : lo;
+            const T e = par ? hi : (&on.x)[k];
             T inv = T(0.25);
-            if (!INTERIOR) inv = inv_at(g, xs + VEC * c + k, ys + ly);
+            if (!INTERIOR) inv = inv_at(g, xs + 2 * (t0 + k) + par, ys + ly);
             const T sum = ((w + e) + (&dn.x)[k]) + (&up.x)[k];
-            (&cur.x)[k] = (sum - (&rr.x)[k]) * inv;
+            (&out.x)[k] = (sum - (&rr.x)[k]) * inv;
           }
-          sh.se[vi] = cur;
+          *reinterpret_cast<V*>(sh.se + xrow + t0) = out;
         }
       }
       __syncthreads();
@@ -463,6 +485,7 @@ struct CycleTile {
     // residual on the tile, write-back, per-coarse-tile sums
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int gi = x0 + lane;
+    const int lx = PADX + lane;
     const bool hw = INTERIOR || g.per_x || gi > 0, he = INTERIOR || g.per_x || gi < g.nx - 1;
     double acc[NBW], acc2[NBW];
 #pragma unroll
@@ -471,12 +494,13 @@ struct CycleTile {
     for (int rr = 0; rr < RPW; ++rr) {
       const int r = RPW * wave + rr;
       const int gj = y0 + r;
+      const int ly = r + H;
       if (INTERIOR || (gi < g.nx && gj < g.ny)) {
         const bool hs = INTERIOR || g.per_y || gj > 0, hn = INTERIOR || g.per_y || gj < g.ny - 1;
-        const int idx = (r + H) * LEX + (lane + PADX);
-        const T c = se[idx];
-        const T res = sr[(r + H - 1) * LRX + (lane + PADX - VEC)] -
-                      lap5<T>(c, se[idx - 1], se[idx + 1], se[idx - LEX], se[idx + LEX], hw, he, hs, hn);
+        const T c = sh.se[at(ly, lx)];
+        const T res = sh.sr[at(ly - 1, lx)] -
+                      lap5<T>(c, sh.se[at(ly, lx - 1)], sh.se[at(ly, lx + 1)], sh.se[at(ly - 1, lx)],
+                              sh.se[at(ly + 1, lx)], hw, he, hs, hn);
         ob[gj * g.nx + gi] = c;
         const double d = double(res);
         const int q = RPW >= N ? (rr >> LOG2N) : 0;
