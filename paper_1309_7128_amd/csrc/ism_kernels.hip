@@ -331,8 +331,9 @@ struct CycleTile {
     alignas(16) T se[LEY * LEX];        // e, rows 0 .. LEY-1
     alignas(16) T sr[(LEY - 2) * LEX];  // rhs, rows 1 .. LEY-2
     double sE[CEY * CEX];   // coarse values around the staged region
-    double sEx[CEY * LEX];  // the same, interpolated along x at every staged column
-    double rowY[LEY];       // y weight of every staged row ...
+    alignas(16) double sEx[CEY * LEX];  // the same, interpolated along x at every staged column
+    double rowY[LEY];       // y weight of every staged row, 1 minus it ...
+    double rowY1[LEY];
     int rowJ[LEY];          // ... and the offset of its lower coarse row in sEx
     double red1[4][NBW][TPX];
     double red2[4][NBW][TPX];
@@ -401,6 +402,7 @@ struct CycleTile {
       double Y;
       interp_coord(ys + t, N, jlo, Y);
       sh.rowY[t] = Y;
+      sh.rowY1[t] = 1.0 - Y;
       sh.rowJ[t] = (jlo - cJ0) * LEX;
     }
     __syncthreads();
@@ -423,11 +425,17 @@ struct CycleTile {
         int i = xs + VEC * c, j = ys + ly;
         V v = zero_chunk<V>();
         if (INTERIOR || map_cell(g, i, j)) {
-          const double* p = sh.sEx + sh.rowJ[ly] + VEC * c;
-          const double Y = sh.rowY[ly];
+          // the chunk's interpolated values on the bounding coarse rows, read as 16-byte
+          // vectors (contiguous across the wave), then the y weights: same rounding as lerp
+          const double2* plo = reinterpret_cast<const double2*>(sh.sEx + sh.rowJ[ly] + VEC * c);
+          const double2* phi = reinterpret_cast<const double2*>(sh.sEx + sh.rowJ[ly] + LEX + VEC * c);
+          const double Y = sh.rowY[ly], Y1 = sh.rowY1[ly];
 #pragma unroll
-          for (int k = 0; k < VEC; ++k)
-            (&v.x)[k] = T(double((&ev[m].x)[k]) + lerp(p[k], p[k + LEX], Y));
+          for (int k2 = 0; k2 < VEC / 2; ++k2) {
+            const double2 a = plo[k2], b = phi[k2];
+            (&v.x)[2 * k2] = T(double((&ev[m].x)[2 * k2]) + (a.x * Y1 + b.x * Y));
+            (&v.x)[2 * k2 + 1] = T(double((&ev[m].x)[2 * k2 + 1]) + (a.y * Y1 + b.y * Y));
+          }
         }
         put(sh.se + ly * LEX, VEC * c, v);
       }
@@ -441,6 +449,19 @@ struct CycleTile {
       }
     }
     __syncthreads();
+
+    // a lane updates the same chunks in every half-step: keep their rhs (both half-rows) in
+    // registers
+    V rh[NUC][2];
+#pragma unroll
+    for (int m = 0; m < NUC; ++m) {
+      const int q = threadIdx.x + m * kBlock;
+      if (q < (LEY - 2) * HC) {
+        const int ly = 1 + q / HC, h = q - (ly - 1) * HC;
+        rh[m][0] = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + VEC * h);
+        rh[m][1] = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + HX + VEC * h);
+      }
+    }
 
     // 2 NU red/black half-steps: in rows 1 .. LEY-2 every chunk of the half-row holding the
     // colour is updated.  Edge chunks read a neighbour from outside their row; the garbage
@@ -461,7 +482,7 @@ struct CycleTile {
           const T ox = sh.se[orow + (par ? t0 + VEC : t0 - 1)];
           const V up = *reinterpret_cast<const V*>(sh.se + xrow + LEX + t0);
           const V dn = *reinterpret_cast<const V*>(sh.se + xrow - LEX + t0);
-          const V rr = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + par * HX + t0);
+          const V rr = par ? rh[m][1] : rh[m][0];
           V out;
 #pragma unroll
           for (int k = 0; k < VEC; ++k) {
