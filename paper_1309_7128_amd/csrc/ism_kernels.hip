@@ -356,16 +356,14 @@ struct CycleTile {
 
   // INTERIOR: the staged region lies inside the grid, touches no wall and interpolates from
   // unclamped coarse values.
-  template <bool INTERIOR>
-  static __device__ __forceinline__ void run(Shared& sh, const Geo& g, const T* __restrict__ rb,
-                                             const T* __restrict__ eb, T* __restrict__ ob,
-                                             const double* __restrict__ Eb, double* __restrict__ rc,
-                                             double* __restrict__ psq, int zero_e, int x0, int y0,
-                                             int cI0, int cJ0, int bz) {
-    const int xs = x0 - PADX, ys = y0 - H;  // grid coordinates of staged cell (0, 0)
 
-    // issue every global load of this lane first
-    V ev[NE], rv[NRC];
+  // Issue every global load of a tile (e with its halo, rhs on the rows a half-step updates)
+  // into registers.
+  template <bool INTERIOR>
+  static __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ rb,
+                                              const T* __restrict__ eb, int zero_e, int x0, int y0,
+                                              V (&ev)[NE], V (&rv)[NRC]) {
+    const int xs = x0 - PADX, ys = y0 - H;
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
       const int q = threadIdx.x + m * kBlock;
@@ -386,7 +384,15 @@ struct CycleTile {
         if (INTERIOR || map_cell(g, i, j)) rv[m] = *reinterpret_cast<const V*>(rb + j * g.nx + i);
       }
     }
+  }
 
+  // Coarse tables of the tile, then e + P E and rhs from the registers into LDS.
+  template <bool INTERIOR>
+  static __device__ __forceinline__ void stage(Shared& sh, const Geo& g,
+                                               const double* __restrict__ Eb, int x0, int y0,
+                                               int cI0, int cJ0, const V (&ev)[NE],
+                                               const V (&rv)[NRC]) {
+    const int xs = x0 - PADX, ys = y0 - H;
     // coarse values around the staged region, with the boundary rule applied at load time
     for (int t = threadIdx.x; t < CEY * CEX; t += kBlock) {
       int cj = t / CEX, ci = t - cj * CEX;
@@ -449,7 +455,14 @@ struct CycleTile {
       }
     }
     __syncthreads();
+  }
 
+  // Red/black half-steps, residual, write-back of the tile and its coarse-tile sums.
+  template <bool INTERIOR>
+  static __device__ __forceinline__ void compute(Shared& sh, const Geo& g, T* __restrict__ ob,
+                                                 double* __restrict__ rc, double* __restrict__ psq,
+                                                 int x0, int y0, int bz) {
+    const int xs = x0 - PADX, ys = y0 - H;
     // a lane updates the same chunks in every half-step: keep their rhs (both half-rows) in
     // registers
     V rh[NUC][2];
@@ -466,7 +479,7 @@ struct CycleTile {
     // 2 NU red/black half-steps: in rows 1 .. LEY-2 every chunk of the half-row holding the
     // colour is updated.  Edge chunks read a neighbour from outside their row; the garbage
     // they make spreads one column per half-step and never reaches the valid ring.
-#pragma unroll
+#pragma unroll 1
     for (int s = 0; s < 2 * NU; ++s) {
       const int colour = s & 1;
 #pragma unroll
@@ -562,36 +575,115 @@ struct CycleTile {
   }
 };
 
+// Origin of tile (bx, by) and the coarse index of its first staged interpolation cell.
+template <typename CT>
+struct TileInfo {
+  int x0, y0, cI0, cJ0;
+  __device__ __forceinline__ TileInfo(int bx, int by, int tsy) {
+    x0 = bx * CT::TSX;
+    y0 = by * tsy;
+    cI0 = floordiv(x0 - CT::PADX - (CT::N >> 1), CT::N);
+    cJ0 = floordiv(y0 - CT::H - (CT::N >> 1), CT::N);
+  }
+};
+
+// Interior tiles (whose staged region lies inside the grid away from the walls and
+// interpolates from unclamped coarse values) form the rectangle [bx0, bx0+nbx) x
+// [by0, by0+nby) of tile indices.  This persistent kernel runs them: gridDim.x workgroups per
+// grid each walk a sequence of tiles, loading the next tile's e and rhs into registers while
+// they sweep the current one.  When possible the workgroups on one XCD (the hardware deals
+// workgroups out round-robin over the 8 XCDs) walk one contiguous band of tiles, so that
+// neighbouring tiles' halos meet in that XCD's L2.  Every workgroup leaves the loop after its
+// last tile; there is no inter-workgroup wait.
 template <typename T, int NU, int LOG2N, int TSY>
-__global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
-                                                  const T* __restrict__ ein,
-                                                  T* __restrict__ eout,
-                                                  const double* __restrict__ E,
-                                                  double* __restrict__ rc,
-                                                  double* __restrict__ psq, int zero_e,
-                                                  int tiles_x, int tiles_y) {
+__global__ __launch_bounds__(kBlock) void k_cycle_interior(Geo g, const T* __restrict__ rhs,
+                                                           const T* __restrict__ ein,
+                                                           T* __restrict__ eout,
+                                                           const double* __restrict__ E,
+                                                           double* __restrict__ rc,
+                                                           double* __restrict__ psq, int zero_e,
+                                                           int bx0, int by0, int nbx, int nby) {
   using CT = CycleTile<T, NU, LOG2N, TSY>;
+  using V = typename CT::V;
   __shared__ typename CT::Shared sh;
-  const int nt = tiles_x * tiles_y;
-  int tile = blockIdx.x;
-  if ((nt & 7) == 0) tile = (blockIdx.x & 7) * (nt >> 3) + (blockIdx.x >> 3);
-  const int by = tile / tiles_x, bx = tile - by * tiles_x;
-  const int x0 = bx * CT::TSX, y0 = by * TSY;
+  const int nt = nbx * nby;
+  const int G = gridDim.x, b = blockIdx.x;
+  const bool banded = (nt & 7) == 0 && (G & 7) == 0;
+  auto tile_at = [&](int it) {  // the it-th tile of this workgroup, nt when none is left
+    if (banded) {
+      const int local = (b >> 3) + it * (G >> 3);
+      return local < (nt >> 3) ? (b & 7) * (nt >> 3) + local : nt;
+    }
+    const int t = b + it * G;
+    return t < nt ? t : nt;
+  };
   const long long off = (long long)blockIdx.z * g.plane;
+  const T* rb = rhs + off;
+  const T* eb = ein + off;
+  T* ob = eout + off;
   const double* Eb = E + (long long)blockIdx.z * g.cplane;
-  const int cI0 = floordiv(x0 - CT::PADX - (CT::N >> 1), CT::N);
-  const int cJ0 = floordiv(y0 - CT::H - (CT::N >> 1), CT::N);
-  // interior: every staged cell lies in the grid away from the walls, and every coarse value
-  // the staged cells interpolate from lies in the coarse grid unclamped
-  const bool interior = x0 - CT::PADX >= 1 && x0 + CT::TSX + CT::PADX + 1 <= g.nx &&
-                        y0 - CT::H >= 1 && y0 + TSY + CT::H + 1 <= g.ny && cI0 >= 0 &&
-                        cI0 + CT::CEX <= g.ncx && cJ0 >= 0 && cJ0 + CT::CEY <= g.ncy;
-  if (interior)
-    CT::template run<true>(sh, g, rhs + off, ein + off, eout + off, Eb, rc, psq, zero_e, x0, y0,
-                           cI0, cJ0, blockIdx.z);
-  else
-    CT::template run<false>(sh, g, rhs + off, ein + off, eout + off, Eb, rc, psq, zero_e, x0, y0,
-                            cI0, cJ0, blockIdx.z);
+
+  V ev[CT::NE], rv[CT::NRC];
+  int t = tile_at(0);
+  if (t < nt) {
+    const int by = t / nbx;
+    TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
+    CT::template load<true>(g, rb, eb, zero_e, ti.x0, ti.y0, ev, rv);
+  }
+  for (int it = 0; t < nt; ++it) {
+    const int by = t / nbx;
+    const TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
+    const int tn = tile_at(it + 1);
+    __syncthreads();  // the previous tile is done with LDS
+    CT::template stage<true>(sh, g, Eb, ti.x0, ti.y0, ti.cI0, ti.cJ0, ev, rv);
+    if (tn < nt) {  // prefetch the next tile while this one is swept
+      const int byn = tn / nbx;
+      TileInfo<CT> tj(bx0 + tn - byn * nbx, by0 + byn, TSY);
+      CT::template load<true>(g, rb, eb, zero_e, tj.x0, tj.y0, ev, rv);
+    }
+    CT::template compute<true>(sh, g, ob, rc, psq, ti.x0, ti.y0, blockIdx.z);
+    t = tn;
+  }
+}
+
+// The tiles outside the interior rectangle (the frame next to the walls, or every tile of a
+// small grid): one workgroup per tile, with the boundary rules applied cell by cell.
+template <typename T, int NU, int LOG2N, int TSY>
+__global__ __launch_bounds__(kBlock) void k_cycle_edge(Geo g, const T* __restrict__ rhs,
+                                                       const T* __restrict__ ein,
+                                                       T* __restrict__ eout,
+                                                       const double* __restrict__ E,
+                                                       double* __restrict__ rc,
+                                                       double* __restrict__ psq, int zero_e,
+                                                       int tiles_x, int tiles_y, int bx0, int by0,
+                                                       int nbx, int nby) {
+  using CT = CycleTile<T, NU, LOG2N, TSY>;
+  using V = typename CT::V;
+  __shared__ typename CT::Shared sh;
+  // frame tile f: the rows below the rectangle, the rows above it, then the columns left and
+  // right of it in the rectangle's rows
+  int f = blockIdx.x, bx, by;
+  const int below = by0 * tiles_x, above = (tiles_y - by0 - nby) * tiles_x;
+  if (f < below) {
+    by = f / tiles_x;
+    bx = f - by * tiles_x;
+  } else if ((f -= below) < above) {
+    by = by0 + nby + f / tiles_x;
+    bx = f % tiles_x;
+  } else {
+    f -= above;
+    const int side = tiles_x - nbx;  // frame tiles per rectangle row
+    by = by0 + f / side;
+    const int k = f % side;
+    bx = k < bx0 ? k : k + nbx;
+  }
+  const long long off = (long long)blockIdx.z * g.plane;
+  const TileInfo<CT> ti(bx, by, TSY);
+  V ev[CT::NE], rv[CT::NRC];
+  CT::template load<false>(g, rhs + off, ein + off, zero_e, ti.x0, ti.y0, ev, rv);
+  CT::template stage<false>(sh, g, E + (long long)blockIdx.z * g.cplane, ti.x0, ti.y0, ti.cI0,
+                            ti.cJ0, ev, rv);
+  CT::template compute<false>(sh, g, eout + off, rc, psq, ti.x0, ti.y0, blockIdx.z);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1084,14 +1176,67 @@ inline dim3 strip_grid(const Geo& g) {
   return dim3((g.nx + kWave - 1) / kWave, g.ncy, g.batch);
 }
 
+// Resident workgroups of a kernel on the whole device (compute units x workgroups per CU).
+template <typename K>
+int resident_workgroups(K kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
+    return 0;
+  return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+// Host copy of the interior test of one tile axis: the staged span [o - pad, o + len + pad)
+// lies in [1, n - 1) and its interpolation reads coarse cells [c0, c0 + ce) inside [0, nc).
+inline bool axis_interior(int o, int len, int pad, int N, int ce, int n, int nc) {
+  const int s = o - pad - N / 2;
+  const int c0 = s >= 0 ? s / N : -((-s + N - 1) / N);
+  return o - pad >= 1 && o + len + pad + 1 <= n && c0 >= 0 && c0 + ce <= nc;
+}
+
 template <typename T, int NU, int LOG2N>
 hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
                            double* rc, double* psq, int zero_e, hipStream_t s) {
   constexpr int TSY = sizeof(T) == 4 ? 64 : 32;
+  using CT = CycleTile<T, NU, LOG2N, TSY>;
   const int tx = (g.nx + 63) / 64, ty = (g.ny + TSY - 1) / TSY;
-  dim3 grid(tx * ty, 1, g.batch);
-  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N, TSY>), grid, dim3(kBlock), 0, s, g, rhs, ein, eout, E,
-                     rc, psq, zero_e, tx, ty);
+  // the interior rectangle of tiles (the test is separable in x and y)
+  int bx0 = tx, bx1 = tx, by0 = ty, by1 = ty;
+  for (int b = 0; b < tx; ++b)
+    if (axis_interior(b * CT::TSX, CT::TSX, CT::PADX, CT::N, CT::CEX, g.nx, g.ncx)) {
+      bx0 = bx0 == tx ? b : bx0;
+      bx1 = b + 1;
+    }
+  for (int b = 0; b < ty; ++b)
+    if (axis_interior(b * TSY, TSY, CT::H, CT::N, CT::CEY, g.ny, g.ncy)) {
+      by0 = by0 == ty ? b : by0;
+      by1 = b + 1;
+    }
+  int nbx = bx1 - bx0, nby = by1 - by0;
+  if (nbx <= 0 || nby <= 0) {
+    bx0 = by0 = 0;
+    nbx = nby = 0;
+  }
+  const int nt = nbx * nby;
+  if (nt > 0) {
+    auto kernel = k_cycle_interior<T, NU, LOG2N, TSY>;
+    static int resident = 0;  // per kernel instantiation, computed on first use
+    if (resident == 0) resident = resident_workgroups(kernel);
+    int G = resident;
+    if (G <= 0) return hipErrorInvalidValue;
+    G = (G + g.batch - 1) / g.batch;  // workgroups per grid
+    if (G >= 8) G &= ~7;
+    G = G < nt ? G : nt;
+    hipLaunchKernelGGL(kernel, dim3(G, 1, g.batch), dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc,
+                       psq, zero_e, bx0, by0, nbx, nby);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  const int frame = tx * ty - nt;
+  if (frame > 0)
+    hipLaunchKernelGGL((k_cycle_edge<T, NU, LOG2N, TSY>), dim3(frame, 1, g.batch), dim3(kBlock), 0, s,
+                       g, rhs, ein, eout, E, rc, psq, zero_e, tx, ty, bx0, by0, nbx, nby);
   return hipGetLastError();
 }
 
