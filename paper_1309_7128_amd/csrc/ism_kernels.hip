@@ -362,11 +362,11 @@ struct CycleTile {
   template <bool INTERIOR>
   static __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ rb,
                                               const T* __restrict__ eb, int zero_e, int x0, int y0,
-                                              V (&ev)[NE], V (&rv)[NRC]) {
+                                              V (&ev)[NE], V (&rv)[NRC], int tid) {
     const int xs = x0 - PADX, ys = y0 - H;
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-      const int q = threadIdx.x + m * kBlock;
+      const int q = tid + m * kBlock;
       ev[m] = zero_chunk<V>();
       if (q < LEY * CX && !zero_e) {
         const int ly = q / CX, c = q - ly * CX;
@@ -376,7 +376,7 @@ struct CycleTile {
     }
 #pragma unroll
     for (int m = 0; m < NRC; ++m) {
-      const int q = threadIdx.x + m * kBlock;
+      const int q = tid + m * kBlock;
       rv[m] = zero_chunk<V>();
       if (q < (LEY - 2) * CX) {
         const int ly = 1 + q / CX, c = q - (ly - 1) * CX;
@@ -391,10 +391,10 @@ struct CycleTile {
   static __device__ __forceinline__ void stage(Shared& sh, const Geo& g,
                                                const double* __restrict__ Eb, int x0, int y0,
                                                int cI0, int cJ0, const V (&ev)[NE],
-                                               const V (&rv)[NRC]) {
+                                               const V (&rv)[NRC], int tid) {
     const int xs = x0 - PADX, ys = y0 - H;
     // coarse values around the staged region, with the boundary rule applied at load time
-    for (int t = threadIdx.x; t < CEY * CEX; t += kBlock) {
+    for (int t = tid; t < CEY * CEX; t += kBlock) {
       int cj = t / CEX, ci = t - cj * CEX;
       int I = cI0 + ci, J = cJ0 + cj;
       if (!INTERIOR) {
@@ -403,7 +403,7 @@ struct CycleTile {
       }
       sh.sE[t] = Eb[J * g.ncx + I];
     }
-    for (int t = threadIdx.x; t < LEY; t += kBlock) {
+    for (int t = tid; t < LEY; t += kBlock) {
       int jlo;
       double Y;
       interp_coord(ys + t, N, jlo, Y);
@@ -412,7 +412,7 @@ struct CycleTile {
       sh.rowJ[t] = (jlo - cJ0) * LEX;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < CEY * LEX; t += kBlock) {
+    for (int t = tid; t < CEY * LEX; t += kBlock) {
       int cj = t / LEX, lx = t - cj * LEX;
       int ilo;
       double X;
@@ -425,7 +425,7 @@ struct CycleTile {
     // staged e = e + P E (cells behind a wall stay 0), staged rhs
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-      const int q = threadIdx.x + m * kBlock;
+      const int q = tid + m * kBlock;
       if (q < LEY * CX) {
         const int ly = q / CX, c = q - ly * CX;
         int i = xs + VEC * c, j = ys + ly;
@@ -448,7 +448,7 @@ struct CycleTile {
     }
 #pragma unroll
     for (int m = 0; m < NRC; ++m) {
-      const int q = threadIdx.x + m * kBlock;
+      const int q = tid + m * kBlock;
       if (q < (LEY - 2) * CX) {
         const int r = q / CX, c = q - r * CX;
         put(sh.sr + r * LEX, VEC * c, rv[m]);
@@ -461,20 +461,8 @@ struct CycleTile {
   template <bool INTERIOR>
   static __device__ __forceinline__ void compute(Shared& sh, const Geo& g, T* __restrict__ ob,
                                                  double* __restrict__ rc, double* __restrict__ psq,
-                                                 int x0, int y0, int bz) {
+                                                 int x0, int y0, int bz, int tid) {
     const int xs = x0 - PADX, ys = y0 - H;
-    // a lane updates the same chunks in every half-step: keep their rhs (both half-rows) in
-    // registers
-    V rh[NUC][2];
-#pragma unroll
-    for (int m = 0; m < NUC; ++m) {
-      const int q = threadIdx.x + m * kBlock;
-      if (q < (LEY - 2) * HC) {
-        const int ly = 1 + q / HC, h = q - (ly - 1) * HC;
-        rh[m][0] = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + VEC * h);
-        rh[m][1] = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + HX + VEC * h);
-      }
-    }
 
     // 2 NU red/black half-steps: in rows 1 .. LEY-2 every chunk of the half-row holding the
     // colour is updated.  Edge chunks read a neighbour from outside their row; the garbage
@@ -484,7 +472,7 @@ struct CycleTile {
       const int colour = s & 1;
 #pragma unroll
       for (int m = 0; m < NUC; ++m) {
-        const int q = threadIdx.x + m * kBlock;
+        const int q = tid + m * kBlock;
         if (q < (LEY - 2) * HC) {
           const int ly = 1 + q / HC, h = q - (ly - 1) * HC;
           const int par = (colour + ly + 1) & 1;  // column parity of this colour in row ly
@@ -495,7 +483,7 @@ struct CycleTile {
           const T ox = sh.se[orow + (par ? t0 + VEC : t0 - 1)];
           const V up = *reinterpret_cast<const V*>(sh.se + xrow + LEX + t0);
           const V dn = *reinterpret_cast<const V*>(sh.se + xrow - LEX + t0);
-          const V rr = par ? rh[m][1] : rh[m][0];
+          const V rr = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + par * HX + t0);
           V out;
 #pragma unroll
           for (int k = 0; k < VEC; ++k) {
@@ -517,7 +505,7 @@ struct CycleTile {
     }
 
     // residual on the tile, write-back, per-coarse-tile sums
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
     const int gi = x0 + lane;
     const int lx = PADX + lane;
     const bool hw = INTERIOR || g.per_x || gi > 0, he = INTERIOR || g.per_x || gi < g.nx - 1;
@@ -552,8 +540,8 @@ struct CycleTile {
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < TPX * TPY) {
-      const int band = threadIdx.x / TPX, tc = threadIdx.x - band * TPX;
+    if ((int)tid < TPX * TPY) {
+      const int band = tid / TPX, tc = tid - band * TPX;
       double a = 0.0, b = 0.0;
       if (WPB > 1) {  // a coarse band spans WPB waves: add them in wave order
         for (int w = band * WPB; w < band * WPB + WPB; ++w) {
@@ -628,20 +616,26 @@ __global__ __launch_bounds__(kBlock) void k_cycle_interior(Geo g, const T* __res
   if (t < nt) {
     const int by = t / nbx;
     TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
-    CT::template load<true>(g, rb, eb, zero_e, ti.x0, ti.y0, ev, rv);
+    CT::template load<true>(g, rb, eb, zero_e, ti.x0, ti.y0, ev, rv, threadIdx.x);
   }
   for (int it = 0; t < nt; ++it) {
+    // the lane index is re-read each iteration (opaque to the compiler) so that the per-chunk
+    // index arithmetic is recomputed per tile instead of being hoisted out of the tile loop
+    // into registers for the kernel's lifetime
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int by = t / nbx;
     const TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
     const int tn = tile_at(it + 1);
     __syncthreads();  // the previous tile is done with LDS
-    CT::template stage<true>(sh, g, Eb, ti.x0, ti.y0, ti.cI0, ti.cJ0, ev, rv);
+    CT::template stage<true>(sh, g, Eb, ti.x0, ti.y0, ti.cI0, ti.cJ0, ev, rv, tid);
     if (tn < nt) {  // prefetch the next tile while this one is swept
       const int byn = tn / nbx;
       TileInfo<CT> tj(bx0 + tn - byn * nbx, by0 + byn, TSY);
-      CT::template load<true>(g, rb, eb, zero_e, tj.x0, tj.y0, ev, rv);
+      CT::template load<true>(g, rb, eb, zero_e, tj.x0, tj.y0, ev, rv, tid);
     }
-    CT::template compute<true>(sh, g, ob, rc, psq, ti.x0, ti.y0, blockIdx.z);
+    asm volatile("" : "+v"(tid));
+    CT::template compute<true>(sh, g, ob, rc, psq, ti.x0, ti.y0, blockIdx.z, tid);
     t = tn;
   }
 }
@@ -680,10 +674,10 @@ __global__ __launch_bounds__(kBlock) void k_cycle_edge(Geo g, const T* __restric
   const long long off = (long long)blockIdx.z * g.plane;
   const TileInfo<CT> ti(bx, by, TSY);
   V ev[CT::NE], rv[CT::NRC];
-  CT::template load<false>(g, rhs + off, ein + off, zero_e, ti.x0, ti.y0, ev, rv);
+  CT::template load<false>(g, rhs + off, ein + off, zero_e, ti.x0, ti.y0, ev, rv, threadIdx.x);
   CT::template stage<false>(sh, g, E + (long long)blockIdx.z * g.cplane, ti.x0, ti.y0, ti.cI0,
-                            ti.cJ0, ev, rv);
-  CT::template compute<false>(sh, g, eout + off, rc, psq, ti.x0, ti.y0, blockIdx.z);
+                            ti.cJ0, ev, rv, threadIdx.x);
+  CT::template compute<false>(sh, g, eout + off, rc, psq, ti.x0, ti.y0, blockIdx.z, threadIdx.x);
 }
 
 // ----------------------------------------------------------------------------------------
