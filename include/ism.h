@@ -78,7 +78,8 @@ typedef struct {
                          nx and ny must be multiples of it                                  */
   double lx, ly;      /* domain size; lx/nx must equal ly/ny (square cells)                 */
   int32_t precision;  /* ISM_PREC_*                                                         */
-  int32_t nu;         /* red-black sweeps per cycle after the coarse correction (>= 1)      */
+  int32_t nu;         /* red-black sweeps per cycle after the coarse correction (>= 1);
+                         ISM_COARSE_ACM cycles always take one sweep per level             */
   double rtol;        /* stop when ||b~ - A x||_2 <= rtol ||b~||_2 for every grid            */
   double inner_rtol;  /* mixed form: an inner FP32 solve stops once its residual fell by
                          this factor (or stagnated)                                         */
@@ -98,7 +99,7 @@ typedef struct {
   int32_t status;      /* return code of the solve                                          */
   int32_t outer_iters; /* FP64 defect-correction steps taken                                */
   int32_t cycles;      /* two-level cycles (coarse solve + prolongation + nu sweeps)        */
-  int32_t sweeps;      /* red-black sweeps = cycles * nu                                    */
+  int32_t sweeps;      /* fine-grid red-black sweeps: cycles * nu (cycles for ACM)          */
   int64_t launches;    /* kernels launched                                                  */
   int64_t host_syncs;  /* device-to-host reads the host waited for                          */
   double rel_res_l2;   /* max over the batch of ||b~ - A x||_2 / ||b~||_2 (FP64, difference
@@ -108,7 +109,7 @@ typedef struct {
 } ism_stats;
 
 /* Fill cfg with defaults for an nx x ny grid of unit cell size 1/nx (unit square), Neumann
- * walls, coarsen 16, FP64, nu 2, rtol 1e-10, inner_rtol 1e-3, adaptive checks, fused,
+ * walls, coarsen 16, FP64, nu 4, rtol 1e-10, inner_rtol 1e-3, adaptive checks, fused,
  * stall_window 8, stall_drop 0.02. */
 int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch);
 

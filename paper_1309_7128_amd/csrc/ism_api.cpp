@@ -530,7 +530,7 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
     st->status = status;
     st->outer_iters = outer;
     st->cycles = cycles;
-    st->sweeps = cycles * c->cfg.nu;
+    st->sweeps = cycles * (c->cfg.coarse_stencil == ISM_COARSE_ACM ? 1 : c->cfg.nu);
     st->launches = c->launches;
     st->host_syncs = c->syncs;
     st->rel_res_l2 = rel_l2;
@@ -559,7 +559,7 @@ int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch) {
   cfg->lx = 1.0;
   cfg->ly = nx > 0 ? double(ny) / double(nx) : 1.0;
   cfg->precision = ISM_PREC_FP64;
-  cfg->nu = 2;
+  cfg->nu = 4;
   cfg->rtol = 1e-10;
   cfg->inner_rtol = 1e-3;
   cfg->max_cycles = 100000;

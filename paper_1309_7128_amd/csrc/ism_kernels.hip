@@ -619,11 +619,11 @@ __global__ __launch_bounds__(kBlock) void k_cycle_interior(Geo g, const T* __res
     CT::template load<true>(g, rb, eb, zero_e, ti.x0, ti.y0, ev, rv, threadIdx.x);
   }
   for (int it = 0; t < nt; ++it) {
-    // the lane index is re-read each iteration (opaque to the compiler) so that the per-chunk
-    // index arithmetic is recomputed per tile instead of being hoisted out of the tile loop
-    // into registers for the kernel's lifetime
+    // with few sweeps (where three workgroups fit a CU's LDS) the lane index is re-read each
+    // iteration, opaque to the compiler, so that the per-chunk index arithmetic is recomputed
+    // per tile instead of being hoisted out of the tile loop into registers
     int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
+    if (NU <= 2) asm volatile("" : "+v"(tid));
     const int by = t / nbx;
     const TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
     const int tn = tile_at(it + 1);
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(kBlock) void k_cycle_interior(Geo g, const T* __res
       TileInfo<CT> tj(bx0 + tn - byn * nbx, by0 + byn, TSY);
       CT::template load<true>(g, rb, eb, zero_e, tj.x0, tj.y0, ev, rv, tid);
     }
-    asm volatile("" : "+v"(tid));
+    if (NU <= 2) asm volatile("" : "+v"(tid));
     CT::template compute<true>(sh, g, ob, rc, psq, ti.x0, ti.y0, blockIdx.z, tid);
     t = tn;
   }
@@ -1221,7 +1221,9 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
     if (G <= 0) return hipErrorInvalidValue;
     G = (G + g.batch - 1) / g.batch;  // workgroups per grid
     if (G >= 8) G &= ~7;
-    G = G < nt ? G : nt;
+    // with few sweeps per cycle one tile per workgroup (more workgroups in flight) measured
+    // faster than the persistent walk; with more sweeps the prefetch pays
+    G = (NU <= 2 || G > nt) ? nt : G;
     hipLaunchKernelGGL(kernel, dim3(G, 1, g.batch), dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc,
                        psq, zero_e, bx0, by0, nbx, nby);
     hipError_t err = hipGetLastError();

@@ -44,7 +44,7 @@ class Solver:
     nx x ny grid of square cells (size lx / nx), for `batch` independent grids."""
 
     def __init__(self, nx, ny, batch=1, bc_x="neumann", bc_y="neumann", coarsen=16, lx=1.0,
-                 ly=None, precision="fp64", nu=2, rtol=1e-10, inner_rtol=1e-3,
+                 ly=None, precision="fp64", nu=4, rtol=1e-10, inner_rtol=1e-3,
                  max_cycles=100000, max_outer=50, check_every=0, fused=True, device=None,
                  raise_not_converged=False, stall_window=None, stall_drop=None,
                  coarse_stencil="ism"):

@@ -31,7 +31,7 @@ def test_cavity256_fp64_matches_oracle_iteration(fused):
     u, v = inputs.workload_fields(w.name)
     b = _rhs(u, v, w.h, N)
     s = solver(nx=w.nx, ny=w.ny, coarsen=w.coarsen, precision="fp64", rtol=w.rtol, check_every=1,
-               fused=fused)
+               fused=fused, nu=2)
     x, st = s.solve(dev(b))
     x = host(x).reshape(w.ny, w.nx)
     assert st["status"] == 0
@@ -69,9 +69,9 @@ def test_mixed_outer_steps_match_oracle_emulation():
     nx = ny = 256
     rng = np.random.default_rng(210)
     b = rng.standard_normal((ny, nx))
-    s = solver(nx=nx, ny=ny, coarsen=16, precision="mixed", rtol=1e-10, check_every=1)
+    s = solver(nx=nx, ny=ny, coarsen=16, precision="mixed", rtol=1e-10, check_every=1, nu=2)
     x, st = s.solve(dev(b))
-    xo, info = O.ism_solve_mixed(b, 1 / nx, 16, rtol=1e-10)
+    xo, info = O.ism_solve_mixed(b, 1 / nx, 16, nu=2, rtol=1e-10)
     assert abs(st["outer_iters"] - info["outer"]) <= 1
     assert O.relative_residual(b, host(x).reshape(ny, nx), 1 / nx) <= 1e-10
 
@@ -211,7 +211,7 @@ def test_gmg5_vs_ism_cycle_counts_match_oracle(scheme):
     rng = np.random.default_rng(220)
     b = rng.standard_normal((ny, nx))
     s = solver(nx=nx, ny=ny, coarsen=16, precision="fp64", rtol=1e-10, check_every=1,
-               coarse_stencil=scheme)
+               coarse_stencil=scheme, nu=2)
     x, st = s.solve(dev(b))
     assert O.relative_residual(b, host(x).reshape(ny, nx), 1 / nx) <= 1e-10
     _, info = O.ism_solve(b, 1 / nx, 16, nu=2, rtol=1e-10, stencil=scheme)
@@ -241,20 +241,26 @@ def test_acm_matches_oracle(bx, n):
 
 @pytest.mark.parametrize("n", [16, 32])
 def test_cavity2048_ism_vs_acm_counts(n):
-    """The workload's comparison: ISM and ACM to 1e-10 at 16h and 32h, counts reported."""
+    """The workload's comparison: ISM and ACM to 1e-10 at 16h and 32h, counts reported.  The
+    paper's claim for the two-level scheme is fewer synchronisations (kernel calls) than the
+    multilevel ACM cycle (Sec. 4.3, Sec. 5); the cycle counts themselves may go either way
+    (ACM smooths on every level, ISM on the fine grid only)."""
     announce("cavity2048_ism_vs_acm", n)
     w = inputs.WORKLOADS["cavity2048_fp64"]
     u, v = inputs.workload_fields(w.name)
     b = _rhs(u, v, w.h, N)
     out = {}
+    s_nu = 4
     for scheme in ("ism", "acm"):
         s = solver(nx=w.nx, ny=w.ny, coarsen=n, precision="fp64", rtol=w.rtol, coarse_stencil=scheme,
-                   max_cycles=5000)
+                   max_cycles=5000, nu=s_nu)
         x, st = s.solve(dev(b))
         out[scheme] = st
         print(scheme, n, st, flush=True)
         assert O.relative_residual(b, host(x).reshape(w.ny, w.nx), w.h) <= w.rtol
-    assert out["ism"]["cycles"] < out["acm"]["cycles"] or n == 16
+    assert out["ism"]["launches"] < out["acm"]["launches"]
+    assert out["acm"]["sweeps"] == out["acm"]["cycles"]
+    assert out["ism"]["sweeps"] == out["ism"]["cycles"] * s_nu
 
 
 def test_kernel_timer_counts_launches():

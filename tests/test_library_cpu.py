@@ -38,7 +38,7 @@ def test_config_defaults():
     lib = L.load()
     cfg = L.IsmConfig()
     assert lib.ism_config_init(ctypes.byref(cfg), 256, 128, 2) == 0
-    assert (cfg.nx, cfg.ny, cfg.batch, cfg.coarsen, cfg.nu) == (256, 128, 2, 16, 2)
+    assert (cfg.nx, cfg.ny, cfg.batch, cfg.coarsen, cfg.nu) == (256, 128, 2, 16, 4)
     assert cfg.lx == 1.0 and cfg.ly == 0.5 and cfg.rtol == 1e-10 and cfg.fused == 1
     assert lib.ism_config_init(None, 1, 1, 1) == L.ISM_ERR_INVALID
 
