@@ -134,7 +134,7 @@ def main():
         achieved = alg / launches / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": f"k_cycle<{'float' if w.precision == 'mixed' else 'double'},{args.nu},"
+                    "kernel": f"k_cycle<{'float' if w.precision == 'mixed' else 'double'}, {args.nu}, "
                               f"{w.coarsen.bit_length() - 1}>",
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
                     "bytes_per_launch": int(alg / launches)}

@@ -19,10 +19,13 @@ ARCH = os.environ.get("ISM_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: expressions round exactly as written (fused multiply-adds only where a
 # kernel calls fma explicitly), so the fine-grid kernels reproduce a plain evaluation.
-# The packed-FP32 feature is disabled for the device code.
+# The packed-FP32 feature is disabled for the device code.  The fused cycle kernel's row
+# pipeline must unroll completely (its register ring is addressed by the unrolled phase), which
+# exceeds the default size limit for pragma-directed unrolling.
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-Wall", "-Wno-unused-result",
 ]
 

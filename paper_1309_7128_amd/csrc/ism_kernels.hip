@@ -265,419 +265,361 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
 }
 
 // ----------------------------------------------------------------------------------------
-// Fused two-level cycle kernel (temporal blocking of the red-black sweeps).
+// Fused two-level cycle kernel: row-pipelined temporal blocking in registers.
 //
-// A workgroup owns a 64 x TSY tile of fine cells (TSY = 64 for FP32, 32 for FP64 so that
-// three workgroups fit in a CU's LDS either way).  It stages e on the tile grown by H = 2 NU + 1
-// rows and PADX columns (PADX >= H - 1 + VEC, a multiple of the 16-byte chunk of VEC cells),
-// and rhs on the cells a half-step may update, in LDS, adding the bilinear coarse correction
-// to every staged e.  Every global access is a 16-byte chunk and all of a lane's loads are in
-// flight together.  The 2 NU red/black half-steps then each update their colour on every
-// staged chunk that has all its neighbours staged; a lane keeps the same chunks throughout.
-// Values computed outside the ring H - 1 - s at half-step s come from stale neighbours, but
-// no later half-step inside its own ring reads them, so after the last half-step e is exact
-// on the tile plus one ring.  A red/black half-step reads only the other colour, so a halo
-// cell gets exactly the value its owner computes.  The kernel then forms the residual on the
-// tile, writes the tile of e and the sums of the residual (and its square) over each n x n
-// coarse tile it contains.  Per cycle it reads e and rhs once and writes e once.
-// Workgroups are numbered so that the consecutive workgroups one XCD receives (the hardware
-// deals them out round-robin over the 8 XCDs) take neighbouring tiles, whose halos then
-// meet in that XCD's L2.
+// One wave owns a strip of LW = 64 CPL columns (CPL consecutive cells per lane) and a run of
+// L output rows, and walks up the strip one row at a time holding a ring of P rows of e and
+// rhs in registers.  When row t enters it receives the bilinear coarse correction (Eq. 5).
+// Then half-step k = 1 .. 2 NU (odd k red, even k black) updates its colour on row t - k:
+// at that moment row t - k + 1 has just had half-step k - 1 and row t - k - 1 still waits
+// for half-step k + 1, so every cell sees exactly the neighbours the k-th half-step of a
+// whole-grid sweep would give it.  Row t - 2 NU - 1 is then final: its residual is formed,
+// summed over the n x n coarse tiles, and the row is written out.  East and west neighbours
+// across lanes come from DPP wavefront shifts, so the half-steps touch neither LDS nor
+// memory.  The strip's PX >= 2 NU + 1 outer columns on each side and its first H rows absorb
+// the stale values its edges inject (they spread one cell per half-step); the VW = LW - 2 PX
+// valid columns start on a coarse tile boundary.  Per cycle e and rhs are read once (plus
+// halos) and e is written once.
 // ----------------------------------------------------------------------------------------
+constexpr int stream_pad(int h, int n, int cpl, int lw) {
+  int px = (h + cpl - 1) / cpl * cpl;
+  while ((lw - 2 * px) % n != 0) px += cpl;
+  return px;
+}
+
+template <typename T, int NU, int LOG2N>
+struct Stream {
+  static constexpr int CPL = 4;           // cells per lane
+  static constexpr int LW = kWave * CPL;  // columns per strip
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int H = 2 * NU + 1;    // reach of one cycle (2 NU half-steps + residual)
+  static constexpr int PX = stream_pad(H, N, CPL, LW);
+  static constexpr int VW = LW - 2 * PX;  // valid columns per strip
+  static constexpr int P = 2 * NU + 4;    // ring rows (2 NU + 3 live), an even number
+  static constexpr int L = N >= 8 ? 128 : 64;  // output rows per unit (half that by a wall)
+  // coarse rows and columns one walk interpolates from, at most (staged in LDS per wave)
+  static constexpr int NR = (L + 2 * H - 1) / N + 3;
+  static constexpr int NC = LW / N + 3;
+  static_assert(N >= CPL && VW >= N && VW % N == 0 && PX % CPL == 0, "strip geometry");
+  static_assert(P % 2 == 0, "an even ring keeps each slot's row parity fixed");
+};
+
+
 template <typename T>
-struct Chunk;
+struct Vec16;
 template <>
-struct Chunk<float> {
+struct Vec16<float> {
   using type = float4;
 };
 template <>
-struct Chunk<double> {
+struct Vec16<double> {
   using type = double2;
 };
 
-template <typename V>
-__device__ __forceinline__ V zero_chunk() {
-  V v;
-  for (int k = 0; k < int(sizeof(V) / sizeof(v.x)); ++k) (&v.x)[k] = 0;
-  return v;
-}
-
-template <typename T, int NU, int LOG2N, int TSY>
-struct CycleTile {
-  using V = typename Chunk<T>::type;
-  static constexpr int VEC = 16 / sizeof(T);  // cells per 16-byte chunk
-  static constexpr int TSX = 64;
-  static constexpr int N = 1 << LOG2N;
-  static constexpr int H = 2 * NU + 1;
-  static constexpr int PADX = ((H - 1 + VEC + VEC - 1) / VEC) * VEC;
-  static constexpr int LEX = TSX + 2 * PADX, LEY = TSY + 2 * H;  // staged region
-  static constexpr int HX = LEX / 2;                             // cells per half-row
-  static constexpr int CX = LEX / VEC;                           // global chunks per staged row
-  static constexpr int HC = HX / VEC;                            // LDS chunks per half-row
-  static constexpr int NE = (LEY * CX + kBlock - 1) / kBlock;    // e chunks staged per lane
-  static constexpr int NRC = ((LEY - 2) * CX + kBlock - 1) / kBlock;  // rhs chunks per lane
-  static constexpr int NUC = ((LEY - 2) * HC + kBlock - 1) / kBlock;  // updated chunks per lane
-  static constexpr int CEX = LEX / N + 3, CEY = LEY / N + 3;
-  static constexpr int RPW = TSY / 4;                 // tile rows per wave (residual)
-  static constexpr int NBW = RPW >= N ? RPW / N : 1;  // coarse bands per wave
-  static constexpr int WPB = N > RPW ? N / RPW : 1;   // waves per coarse band
-  static constexpr int TPX = TSX / N, TPY = TSY / N;  // coarse tiles per workgroup tile
-  static_assert(TSY % 4 == 0 && N <= TSY, "a workgroup tile must hold whole coarse tiles");
-  static_assert(HX % VEC == 0, "half-rows must hold whole chunks");
-
-  // Staged rows are stored split by column parity: [even columns | odd columns], so that a
-  // red or black half-step works on contiguous chunks of one colour.
-  struct Shared {
-    alignas(16) T se[LEY * LEX];        // e, rows 0 .. LEY-1
-    alignas(16) T sr[(LEY - 2) * LEX];  // rhs, rows 1 .. LEY-2
-    double sE[CEY * CEX];   // coarse values around the staged region
-    alignas(16) double sEx[CEY * LEX];  // the same, interpolated along x at every staged column
-    double rowY[LEY];       // y weight of every staged row, 1 minus it ...
-    double rowY1[LEY];
-    int rowJ[LEY];          // ... and the offset of its lower coarse row in sEx
-    double red1[4][NBW][TPX];
-    double red2[4][NBW][TPX];
-  };
-
-  static __device__ __forceinline__ int at(int ly, int lx) { return ly * LEX + (lx & 1) * HX + (lx >> 1); }
-
-  // a natural-order chunk of VEC cells (columns lx0 .. lx0+VEC-1) into the split row
-  static __device__ __forceinline__ void put(T* row, int lx0, const V& v) {
+template <typename T, int C>
+__device__ __forceinline__ void load_cells(const T* __restrict__ p, T (&v)[C]) {
+  using V = typename Vec16<T>::type;
+  constexpr int K = 16 / sizeof(T);
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) row[(k & 1) * HX + ((lx0 + k) >> 1)] = (&v.x)[k];
-  }
-
-  // 1 / (number of existing neighbours) of a staged cell, 0 for a cell behind a wall (which
-  // then stays 0, as a missing neighbour contributes nothing)
-  static __device__ __forceinline__ T inv_at(const Geo& g, int i, int j) {
-    if (!map_cell(g, i, j)) return T(0);
-    return inv_count<T>(g, i, j);
-  }
-
-  // INTERIOR: the staged region lies inside the grid, touches no wall and interpolates from
-  // unclamped coarse values.
-
-  // Issue every global load of a tile (e with its halo, rhs on the rows a half-step updates)
-  // into registers.
-  template <bool INTERIOR>
-  static __device__ __forceinline__ void load(const Geo& g, const T* __restrict__ rb,
-                                              const T* __restrict__ eb, int zero_e, int x0, int y0,
-                                              V (&ev)[NE], V (&rv)[NRC], int tid) {
-    const int xs = x0 - PADX, ys = y0 - H;
+  for (int q = 0; q < C / K; ++q) {
+    const V x = reinterpret_cast<const V*>(p)[q];
 #pragma unroll
-    for (int m = 0; m < NE; ++m) {
-      const int q = tid + m * kBlock;
-      ev[m] = zero_chunk<V>();
-      if (q < LEY * CX && !zero_e) {
-        const int ly = q / CX, c = q - ly * CX;
-        int i = xs + VEC * c, j = ys + ly;
-        if (INTERIOR || map_cell(g, i, j)) ev[m] = *reinterpret_cast<const V*>(eb + j * g.nx + i);
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < NRC; ++m) {
-      const int q = tid + m * kBlock;
-      rv[m] = zero_chunk<V>();
-      if (q < (LEY - 2) * CX) {
-        const int ly = 1 + q / CX, c = q - (ly - 1) * CX;
-        int i = xs + VEC * c, j = ys + ly;
-        if (INTERIOR || map_cell(g, i, j)) rv[m] = *reinterpret_cast<const V*>(rb + j * g.nx + i);
-      }
-    }
-  }
-
-  // Coarse tables of the tile, then e + P E and rhs from the registers into LDS.
-  template <bool INTERIOR>
-  static __device__ __forceinline__ void stage(Shared& sh, const Geo& g,
-                                               const double* __restrict__ Eb, int x0, int y0,
-                                               int cI0, int cJ0, const V (&ev)[NE],
-                                               const V (&rv)[NRC], int tid) {
-    const int xs = x0 - PADX, ys = y0 - H;
-    // coarse values around the staged region, with the boundary rule applied at load time
-    for (int t = tid; t < CEY * CEX; t += kBlock) {
-      int cj = t / CEX, ci = t - cj * CEX;
-      int I = cI0 + ci, J = cJ0 + cj;
-      if (!INTERIOR) {
-        I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
-        J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
-      }
-      sh.sE[t] = Eb[J * g.ncx + I];
-    }
-    for (int t = tid; t < LEY; t += kBlock) {
-      int jlo;
-      double Y;
-      interp_coord(ys + t, N, jlo, Y);
-      sh.rowY[t] = Y;
-      sh.rowY1[t] = 1.0 - Y;
-      sh.rowJ[t] = (jlo - cJ0) * LEX;
-    }
-    __syncthreads();
-    for (int t = tid; t < CEY * LEX; t += kBlock) {
-      int cj = t / LEX, lx = t - cj * LEX;
-      int ilo;
-      double X;
-      interp_coord(xs + lx, N, ilo, X);
-      const double* q = sh.sE + cj * CEX + (ilo - cI0);
-      sh.sEx[t] = lerp(q[0], q[1], X);
-    }
-    __syncthreads();
-
-    // staged e = e + P E (cells behind a wall stay 0), staged rhs
-#pragma unroll
-    for (int m = 0; m < NE; ++m) {
-      const int q = tid + m * kBlock;
-      if (q < LEY * CX) {
-        const int ly = q / CX, c = q - ly * CX;
-        int i = xs + VEC * c, j = ys + ly;
-        V v = zero_chunk<V>();
-        if (INTERIOR || map_cell(g, i, j)) {
-          // the chunk's interpolated values on the bounding coarse rows, read as 16-byte
-          // vectors (contiguous across the wave), then the y weights: same rounding as lerp
-          const double2* plo = reinterpret_cast<const double2*>(sh.sEx + sh.rowJ[ly] + VEC * c);
-          const double2* phi = reinterpret_cast<const double2*>(sh.sEx + sh.rowJ[ly] + LEX + VEC * c);
-          const double Y = sh.rowY[ly], Y1 = sh.rowY1[ly];
-#pragma unroll
-          for (int k2 = 0; k2 < VEC / 2; ++k2) {
-            const double2 a = plo[k2], b = phi[k2];
-            (&v.x)[2 * k2] = T(double((&ev[m].x)[2 * k2]) + (a.x * Y1 + b.x * Y));
-            (&v.x)[2 * k2 + 1] = T(double((&ev[m].x)[2 * k2 + 1]) + (a.y * Y1 + b.y * Y));
-          }
-        }
-        put(sh.se + ly * LEX, VEC * c, v);
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < NRC; ++m) {
-      const int q = tid + m * kBlock;
-      if (q < (LEY - 2) * CX) {
-        const int r = q / CX, c = q - r * CX;
-        put(sh.sr + r * LEX, VEC * c, rv[m]);
-      }
-    }
-    __syncthreads();
-  }
-
-  // Red/black half-steps, residual, write-back of the tile and its coarse-tile sums.
-  template <bool INTERIOR>
-  static __device__ __forceinline__ void compute(Shared& sh, const Geo& g, T* __restrict__ ob,
-                                                 double* __restrict__ rc, double* __restrict__ psq,
-                                                 int x0, int y0, int bz, int tid) {
-    const int xs = x0 - PADX, ys = y0 - H;
-
-    // 2 NU red/black half-steps: in rows 1 .. LEY-2 every chunk of the half-row holding the
-    // colour is updated.  Edge chunks read a neighbour from outside their row; the garbage
-    // they make spreads one column per half-step and never reaches the valid ring.
-#pragma unroll 1
-    for (int s = 0; s < 2 * NU; ++s) {
-      const int colour = s & 1;
-#pragma unroll
-      for (int m = 0; m < NUC; ++m) {
-        const int q = tid + m * kBlock;
-        if (q < (LEY - 2) * HC) {
-          const int ly = 1 + q / HC, h = q - (ly - 1) * HC;
-          const int par = (colour + ly + 1) & 1;  // column parity of this colour in row ly
-          const int t0 = VEC * h;
-          const int xrow = ly * LEX + par * HX;        // this colour's half-row
-          const int orow = ly * LEX + (1 - par) * HX;  // the other colour's
-          const V on = *reinterpret_cast<const V*>(sh.se + orow + t0);
-          const T ox = sh.se[orow + (par ? t0 + VEC : t0 - 1)];
-          const V up = *reinterpret_cast<const V*>(sh.se + xrow + LEX + t0);
-          const V dn = *reinterpret_cast<const V*>(sh.se + xrow - LEX + t0);
-          const V rr = *reinterpret_cast<const V*>(sh.sr + (ly - 1) * LEX + par * HX + t0);
-          V out;
-#pragma unroll
-          for (int k = 0; k < VEC; ++k) {
-            // even cells (par 0) have their west neighbour one slot left in the odd half,
-            // odd cells (par 1) their east neighbour one slot right in the even half
-            const T lo = k == 0 ? ox : (&on.x)[k - 1];
-            const T hi = k == VEC - 1 ? ox : (&on.x)[k + 1];
-            const T w = par ? (&on.x)[k] : lo;
-            const T e = par ? hi : (&on.x)[k];
-            T inv = T(0.25);
-            if (!INTERIOR) inv = inv_at(g, xs + 2 * (t0 + k) + par, ys + ly);
-            const T sum = ((w + e) + (&dn.x)[k]) + (&up.x)[k];
-            (&out.x)[k] = (sum - (&rr.x)[k]) * inv;
-          }
-          *reinterpret_cast<V*>(sh.se + xrow + t0) = out;
-        }
-      }
-      __syncthreads();
-    }
-
-    // residual on the tile, write-back, per-coarse-tile sums
-    const int lane = tid & (kWave - 1), wave = tid / kWave;
-    const int gi = x0 + lane;
-    const int lx = PADX + lane;
-    const bool hw = INTERIOR || g.per_x || gi > 0, he = INTERIOR || g.per_x || gi < g.nx - 1;
-    double acc[NBW], acc2[NBW];
-#pragma unroll
-    for (int q = 0; q < NBW; ++q) acc[q] = acc2[q] = 0.0;
-#pragma unroll
-    for (int rr = 0; rr < RPW; ++rr) {
-      const int r = RPW * wave + rr;
-      const int gj = y0 + r;
-      const int ly = r + H;
-      if (INTERIOR || (gi < g.nx && gj < g.ny)) {
-        const bool hs = INTERIOR || g.per_y || gj > 0, hn = INTERIOR || g.per_y || gj < g.ny - 1;
-        const T c = sh.se[at(ly, lx)];
-        const T res = sh.sr[at(ly - 1, lx)] -
-                      lap5<T>(c, sh.se[at(ly, lx - 1)], sh.se[at(ly, lx + 1)], sh.se[at(ly - 1, lx)],
-                              sh.se[at(ly + 1, lx)], hw, he, hs, hn);
-        ob[gj * g.nx + gi] = c;
-        const double d = double(res);
-        const int q = RPW >= N ? (rr >> LOG2N) : 0;
-        acc[q] += d;
-        acc2[q] += d * d;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NBW; ++q) {
-      double a = wave_sum_group(acc[q], N);
-      double b = wave_sum_group(acc2[q], N);
-      if ((lane & (N - 1)) == 0) {
-        sh.red1[wave][q][lane >> LOG2N] = a;
-        sh.red2[wave][q][lane >> LOG2N] = b;
-      }
-    }
-    __syncthreads();
-    if ((int)tid < TPX * TPY) {
-      const int band = tid / TPX, tc = tid - band * TPX;
-      double a = 0.0, b = 0.0;
-      if (WPB > 1) {  // a coarse band spans WPB waves: add them in wave order
-        for (int w = band * WPB; w < band * WPB + WPB; ++w) {
-          a += sh.red1[w][0][tc];
-          b += sh.red2[w][0][tc];
-        }
-      } else {
-        const int w = band / NBW, q = band - w * NBW;
-        a = sh.red1[w][q][tc];
-        b = sh.red2[w][q][tc];
-      }
-      const int I = (x0 >> LOG2N) + tc, J = (y0 >> LOG2N) + band;
-      if (INTERIOR || (I < g.ncx && J < g.ncy)) {
-        const long long o = (long long)bz * g.cplane + (long long)J * g.ncx + I;
-        rc[o] = a;
-        if (psq) psq[o] = b;
-      }
-    }
-  }
-};
-
-// Origin of tile (bx, by) and the coarse index of its first staged interpolation cell.
-template <typename CT>
-struct TileInfo {
-  int x0, y0, cI0, cJ0;
-  __device__ __forceinline__ TileInfo(int bx, int by, int tsy) {
-    x0 = bx * CT::TSX;
-    y0 = by * tsy;
-    cI0 = floordiv(x0 - CT::PADX - (CT::N >> 1), CT::N);
-    cJ0 = floordiv(y0 - CT::H - (CT::N >> 1), CT::N);
-  }
-};
-
-// Interior tiles (whose staged region lies inside the grid away from the walls and
-// interpolates from unclamped coarse values) form the rectangle [bx0, bx0+nbx) x
-// [by0, by0+nby) of tile indices.  This persistent kernel runs them: gridDim.x workgroups per
-// grid each walk a sequence of tiles, loading the next tile's e and rhs into registers while
-// they sweep the current one.  When possible the workgroups on one XCD (the hardware deals
-// workgroups out round-robin over the 8 XCDs) walk one contiguous band of tiles, so that
-// neighbouring tiles' halos meet in that XCD's L2.  Every workgroup leaves the loop after its
-// last tile; there is no inter-workgroup wait.
-template <typename T, int NU, int LOG2N, int TSY>
-__global__ __launch_bounds__(kBlock) void k_cycle_interior(Geo g, const T* __restrict__ rhs,
-                                                           const T* __restrict__ ein,
-                                                           T* __restrict__ eout,
-                                                           const double* __restrict__ E,
-                                                           double* __restrict__ rc,
-                                                           double* __restrict__ psq, int zero_e,
-                                                           int bx0, int by0, int nbx, int nby) {
-  using CT = CycleTile<T, NU, LOG2N, TSY>;
-  using V = typename CT::V;
-  __shared__ typename CT::Shared sh;
-  const int nt = nbx * nby;
-  const int G = gridDim.x, b = blockIdx.x;
-  const bool banded = (nt & 7) == 0 && (G & 7) == 0;
-  auto tile_at = [&](int it) {  // the it-th tile of this workgroup, nt when none is left
-    if (banded) {
-      const int local = (b >> 3) + it * (G >> 3);
-      return local < (nt >> 3) ? (b & 7) * (nt >> 3) + local : nt;
-    }
-    const int t = b + it * G;
-    return t < nt ? t : nt;
-  };
-  const long long off = (long long)blockIdx.z * g.plane;
-  const T* rb = rhs + off;
-  const T* eb = ein + off;
-  T* ob = eout + off;
-  const double* Eb = E + (long long)blockIdx.z * g.cplane;
-
-  V ev[CT::NE], rv[CT::NRC];
-  int t = tile_at(0);
-  if (t < nt) {
-    const int by = t / nbx;
-    TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
-    CT::template load<true>(g, rb, eb, zero_e, ti.x0, ti.y0, ev, rv, threadIdx.x);
-  }
-  for (int it = 0; t < nt; ++it) {
-    // with few sweeps (where three workgroups fit a CU's LDS) the lane index is re-read each
-    // iteration, opaque to the compiler, so that the per-chunk index arithmetic is recomputed
-    // per tile instead of being hoisted out of the tile loop into registers
-    int tid = threadIdx.x;
-    if (NU <= 2) asm volatile("" : "+v"(tid));
-    const int by = t / nbx;
-    const TileInfo<CT> ti(bx0 + t - by * nbx, by0 + by, TSY);
-    const int tn = tile_at(it + 1);
-    __syncthreads();  // the previous tile is done with LDS
-    CT::template stage<true>(sh, g, Eb, ti.x0, ti.y0, ti.cI0, ti.cJ0, ev, rv, tid);
-    if (tn < nt) {  // prefetch the next tile while this one is swept
-      const int byn = tn / nbx;
-      TileInfo<CT> tj(bx0 + tn - byn * nbx, by0 + byn, TSY);
-      CT::template load<true>(g, rb, eb, zero_e, tj.x0, tj.y0, ev, rv, tid);
-    }
-    if (NU <= 2) asm volatile("" : "+v"(tid));
-    CT::template compute<true>(sh, g, ob, rc, psq, ti.x0, ti.y0, blockIdx.z, tid);
-    t = tn;
+    for (int k = 0; k < K; ++k) v[q * K + k] = (&x.x)[k];
   }
 }
 
-// The tiles outside the interior rectangle (the frame next to the walls, or every tile of a
-// small grid): one workgroup per tile, with the boundary rules applied cell by cell.
-template <typename T, int NU, int LOG2N, int TSY>
-__global__ __launch_bounds__(kBlock) void k_cycle_edge(Geo g, const T* __restrict__ rhs,
-                                                       const T* __restrict__ ein,
-                                                       T* __restrict__ eout,
-                                                       const double* __restrict__ E,
-                                                       double* __restrict__ rc,
-                                                       double* __restrict__ psq, int zero_e,
-                                                       int tiles_x, int tiles_y, int bx0, int by0,
-                                                       int nbx, int nby) {
-  using CT = CycleTile<T, NU, LOG2N, TSY>;
-  using V = typename CT::V;
-  __shared__ typename CT::Shared sh;
-  // frame tile f: the rows below the rectangle, the rows above it, then the columns left and
-  // right of it in the rectangle's rows
-  int f = blockIdx.x, bx, by;
-  const int below = by0 * tiles_x, above = (tiles_y - by0 - nby) * tiles_x;
-  if (f < below) {
-    by = f / tiles_x;
-    bx = f - by * tiles_x;
-  } else if ((f -= below) < above) {
-    by = by0 + nby + f / tiles_x;
-    bx = f % tiles_x;
-  } else {
-    f -= above;
-    const int side = tiles_x - nbx;  // frame tiles per rectangle row
-    by = by0 + f / side;
-    const int k = f % side;
-    bx = k < bx0 ? k : k + nbx;
+template <typename T, int C>
+__device__ __forceinline__ void store_cells(T* __restrict__ p, const T (&v)[C]) {
+  using V = typename Vec16<T>::type;
+  constexpr int K = 16 / sizeof(T);
+#pragma unroll
+  for (int q = 0; q < C / K; ++q) {
+    V x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) (&x.x)[k] = v[q * K + k];
+    reinterpret_cast<V*>(p)[q] = x;
   }
+}
+
+// A value known to be the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffll)));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((long long)lo | ((long long)hi << 32));
+}
+
+// The value of lane l - 1 (wave_shr:1) or lane l + 1 (wave_shl:1); lanes without a source
+// get 0.
+constexpr int kDppFromLeft = 0x138, kDppFromRight = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, 0xf, 0xf, false));
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)lo | ((long long)hi << 32));
+}
+
+// One wave's walk up its strip: output rows y0 .. y0 + min(L, ny - y0) - 1 of the strip whose
+// first read column is xs.  EDGE: the strip reads columns behind a wall (x not periodic),
+// handled lane by lane; otherwise every column it reads exists (possibly wrapped).
+template <typename T, int NU, int LOG2N, bool EDGE>
+__device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ rb,
+                                           const T* __restrict__ eb, T* __restrict__ ob,
+                                           const double* __restrict__ Eb, double* __restrict__ rc,
+                                           double* __restrict__ psq, double* __restrict__ sE,
+                                           long long coff, int zero_e, int xs, int y0, int L) {
+  using S = Stream<T, NU, LOG2N>;
+  constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
+  constexpr int G = N / CPL;  // lanes per coarse tile
+  constexpr double inv2n = 1.0 / double(2 * N);
+  constexpr T third = T(1) / T(3);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ys = y0 - H;
+  const int yend = y0 + min(L, g.ny - y0) + H;  // rows ys .. yend - 1 are read
+
+  // this lane's first column (unwrapped), the column it is read from, whether it exists
+  const int cu = xs + CPL * lane;
+  bool col_in = true;
+  int cw = cu;
+  if (g.per_x) {
+    cw = imod(cu, g.nx);
+  } else if (EDGE) {
+    col_in = cu >= 0 && cu < g.nx;
+    cw = col_in ? cu : 0;
+  }
+  const bool lane_out = lane >= PX / CPL && lane < (PX + VW) / CPL && cu < g.nx;
+  // EDGE: 1 / (existing neighbours) of each cell on rows with both y-neighbours (ia) and
+  // with one (ib); 0 for cells behind a wall
+  T ia[CPL], ib[CPL];
+#pragma unroll
+  for (int p = 0; p < CPL; ++p) {
+    const int mxp = 2 - (cu + p == 0) - (cu + p == g.nx - 1);
+    ia[p] = !col_in ? T(0) : (mxp == 2 ? T(0.25) : third);
+    ib[p] = !col_in ? T(0) : (mxp == 2 ? third : T(0.5));
+  }
+
+  // The coarse values the walk interpolates from (Eq. 5, boundary rule applied), staged in
+  // this wave's LDS block: rows crow(ys) .. crow(yend - 1) + 1, columns from the lower
+  // neighbour of the strip's first column on.  Only this wave reads them.
+  auto crow = [](int t) { return (t - N / 2) >> LOG2N; };  // lower coarse row of fine row t
+  const int J0 = crow(ys), I0 = (xs - N / 2) >> LOG2N;
+  {
+    const int nr = crow(yend - 1) + 2 - J0;
+    for (int i = lane; i < nr * S::NC; i += kWave) {
+      const int rr = i / S::NC, c = i - rr * S::NC;
+      int J = J0 + rr, I = I0 + c;
+      J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
+      I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
+      sE[i] = Eb[(long long)J * g.ncx + I];
+    }
+    // the block is written and read by this wave only: order its writes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // For n >= 8 all of a lane's cells lie between the same two coarse centres; for n = 4 its
+  // first and last two cells lie between consecutive pairs.
+  constexpr int NEC = N >= 8 ? 2 : 3;
+  const int crel = ((cu - N / 2) >> LOG2N) - I0;
+  // coarse row J interpolated along x at the lane's cells
+  auto interp_x = [&](int J, double (&out)[CPL]) {
+    const double* q = sE + (J - J0) * S::NC + crel;
+    double v[NEC];
+#pragma unroll
+    for (int k = 0; k < NEC; ++k) v[k] = q[k];
+    int c0 = cu;
+    asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
+#pragma unroll
+    for (int p = 0; p < CPL; ++p) {
+      const double X = double(2 * ((c0 + p - N / 2) & (N - 1)) + 1) * inv2n;
+      const int k = N >= 8 ? 0 : (p >> 1);
+      out[p] = lerp(v[k], v[k + 1], X);
+    }
+  };
+
+  // The ring: e and rhs of rows t - P + 1 .. t in slot (row - ys) mod P, and per slot the
+  // row's y-neighbour class: the inverse neighbour count for cells with both x-neighbours (0
+  // behind a wall and for rows not read yet, which the half-steps then leave at 0) and the
+  // number of existing y-neighbours.
+  T e[P][CPL], r[P][CPL];
+  T invs[P];
+  int mys[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    invs[q] = T(0);
+    mys[q] = 0;
+#pragma unroll
+    for (int p = 0; p < CPL; ++p) e[q][p] = r[q][p] = T(0);
+  }
+  int jc = J0;
+  double xlo[CPL], xhi[CPL];
+  interp_x(jc, xlo);
+  interp_x(jc + 1, xhi);
+  // the next row to read, wrapped or clamped into the grid
+  int jn = g.per_y ? imod(ys, g.ny) : min(max(ys, 0), g.ny - 1);
+  // Rows are read two ahead into landing registers of their parity and enter the ring when
+  // used, so that no ring register is the target of a load in flight (a copy or reuse of
+  // one would stall on it).  e is read even when it is ignored, so that every row issues the
+  // same loads and the memory-counter waits stay exact.
+  T le[2][CPL], lr[2][CPL];
+  auto fetch = [&](int t, int par) {
+    const long long a = (long long)jn * g.nx + cw;
+    load_cells(eb + a, le[par]);
+    load_cells(rb + a, lr[par]);
+    jn = g.per_y ? (jn + 1 == g.ny ? 0 : jn + 1) : min(max(t + 1, 0), g.ny - 1);
+  };
+  fetch(ys, 1);  // ys is odd
+  fetch(ys + 1, 0);
+  double acc = 0.0, acc2 = 0.0;
+
+  for (int tb = ys; tb < yend; tb += P) {
+#pragma unroll
+    for (int ph = 0; ph < P; ++ph) {
+      const int t = tb + ph;
+      if (t < yend) {
+        // ys is odd (y0 even, H odd) and P even, so the parity of t is fixed per slot
+        const int tpar = (1 + ph) & 1;
+
+        // row t enters: e = (zero_e ? 0 : e) + P E; cells behind a wall hold 0
+        {
+          if (crow(t) != jc) {  // next pair of coarse rows
+            jc = crow(t);
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) xlo[p] = xhi[p];
+            interp_x(jc + 1, xhi);
+          }
+          const int k = (t - N / 2) & (N - 1);
+          const double Y = double(2 * k + 1) * inv2n, Y1 = 1.0 - Y;
+#pragma unroll
+          for (int p = 0; p < CPL; ++p) {
+            const T e0 = zero_e ? T(0) : le[tpar][p];
+            e[ph][p] = T(double(e0) + (xlo[p] * Y1 + xhi[p] * Y));
+            r[ph][p] = lr[tpar][p];
+          }
+          const bool row_in = g.per_y || (t >= 0 && t < g.ny);
+          if (!row_in) {
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
+          }
+          if (EDGE && !col_in) {
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
+          }
+          const int my = !row_in ? 0 : (g.per_y ? 2 : 2 - (t == 0) - (t == g.ny - 1));
+          invs[ph] = uniform(my == 2 ? T(0.25) : (my == 1 ? third : T(0)));
+          mys[ph] = my;
+        }
+
+        // half-step k (odd red, even black) on row t - k
+#pragma unroll
+        for (int k = 1; k <= 2 * NU; ++k) {
+          const int sc = (ph - k + P) % P, sb = (ph - k - 1 + P) % P, sa = (ph - k + 1 + P) % P;
+          const int colour = (k - 1) & 1;          // 0 red, 1 black
+          const int p0 = (colour + tpar + k) & 1;  // the lane's cells p with (p + row) & 1 == colour
+#pragma unroll
+          for (int p = 0; p < CPL; ++p) {
+            if ((p & 1) != p0) continue;
+            const T w = p > 0 ? e[sc][p - 1] : lane_shift<kDppFromLeft>(e[sc][CPL - 1]);
+            const T ea = p < CPL - 1 ? e[sc][p + 1] : lane_shift<kDppFromRight>(e[sc][0]);
+            const T sum = ((w + ea) + e[sb][p]) + e[sa][p];
+            T inv = invs[sc];
+            if (EDGE) inv = mys[sc] == 2 ? ia[p] : (mys[sc] == 1 ? ib[p] : T(0));
+            e[sc][p] = (sum - r[sc][p]) * inv;
+          }
+        }
+
+        // row o = t - H is final: residual, write-back, coarse-tile sums
+        const int o = t - H;
+        if (o >= y0) {
+          const int so = (ph - H + P) % P, sb = (ph - H - 1 + P) % P, sa = (ph - H + 1 + P) % P;
+          const bool hs = g.per_y || o > 0, hn = g.per_y || o < g.ny - 1;
+#pragma unroll
+          for (int p = 0; p < CPL; ++p) {
+            const T c = e[so][p];
+            const T w = p > 0 ? e[so][p - 1] : lane_shift<kDppFromLeft>(e[so][CPL - 1]);
+            const T ea = p < CPL - 1 ? e[so][p + 1] : lane_shift<kDppFromRight>(e[so][0]);
+            const bool hw = !EDGE || cu + p > 0, he = !EDGE || cu + p < g.nx - 1;
+            const T res = r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn);
+            const double d = double(res);
+            acc += d;
+            acc2 += d * d;
+          }
+          if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
+          if (((o - y0) & (N - 1)) == N - 1) {
+            double a = acc, q = acc2;
+#pragma unroll
+            for (int k = 1; k < G; k <<= 1) {
+              a += __shfl_down(a, k, kWave);
+              q += __shfl_down(q, k, kWave);
+            }
+            if (lane_out && ((lane - PX / CPL) & (G - 1)) == 0) {
+              const long long oc = coff + (long long)(o >> LOG2N) * g.ncx + (cu >> LOG2N);
+              rc[oc] = a;
+              if (psq) psq[oc] = q;
+            }
+            acc = acc2 = 0.0;
+          }
+        }
+
+        // row t + 2 (same parity as t)
+        fetch(t + 2, tpar);
+      }
+    }
+  }
+}
+
+// One launch covers every strip.  Units (a strip and a chunk of rows) are numbered
+// strip-fastest.  The first blocks take the strips that touch a wall (strip 0 and strips
+// efirst + 1, efirst + 2, ...) in chunks of Le rows; the others take strips first,
+// first + 1, ... in chunks of L rows, dealt out so that each XCD (the hardware deals
+// workgroups out round-robin over the 8 XCDs) runs one contiguous band of units.
+template <typename T, int NU, int LOG2N>
+__global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
+                                                  const T* __restrict__ ein,
+                                                  T* __restrict__ eout,
+                                                  const double* __restrict__ E,
+                                                  double* __restrict__ rc,
+                                                  double* __restrict__ psq, int zero_e,
+                                                  int L, int nchunk, int nstrip, int first,
+                                                  int Le, int nchunk_e, int nstrip_e, int efirst,
+                                                  int nblk_e) {
+  using S = Stream<T, NU, LOG2N>;
+  constexpr int WPB = kBlock / kWave;
+  __shared__ double sE[WPB][S::NR * S::NC];
   const long long off = (long long)blockIdx.z * g.plane;
-  const TileInfo<CT> ti(bx, by, TSY);
-  V ev[CT::NE], rv[CT::NRC];
-  CT::template load<false>(g, rhs + off, ein + off, zero_e, ti.x0, ti.y0, ev, rv, threadIdx.x);
-  CT::template stage<false>(sh, g, E + (long long)blockIdx.z * g.cplane, ti.x0, ti.y0, ti.cI0,
-                            ti.cJ0, ev, rv, threadIdx.x);
-  CT::template compute<false>(sh, g, eout + off, rc, psq, ti.x0, ti.y0, blockIdx.z, threadIdx.x);
+  const long long coff = (long long)blockIdx.z * g.cplane;
+  const double* Eb = E + coff;
+  // the wave index, made visibly wave-uniform so that everything derived from it (strip,
+  // rows, the walk's row bookkeeping) lives in scalar registers and scalar branches
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+  const int b = blockIdx.x;
+  if (b < nblk_e) {
+    const int u = b * WPB + w;
+    if (u >= nstrip_e * nchunk_e) return;
+    const int chunk = u / nstrip_e, sl = u - chunk * nstrip_e;
+    const int strip = sl == 0 ? 0 : efirst + sl;
+    cycle_walk<T, NU, LOG2N, true>(g, rhs + off, ein + off, eout + off, Eb, rc, psq, sE[w], coff,
+                                   zero_e, strip * S::VW - S::PX, chunk * Le, Le);
+    return;
+  }
+  int bi = b - nblk_e;
+  const int nbi = gridDim.x - nblk_e;
+  if ((nbi & 7) == 0) bi = (bi & 7) * (nbi >> 3) + (bi >> 3);
+  const int u = bi * WPB + w;
+  if (u >= nstrip * nchunk) return;
+  const int chunk = u / nstrip, sl = u - chunk * nstrip;
+  cycle_walk<T, NU, LOG2N, false>(g, rhs + off, ein + off, eout + off, Eb, rc, psq, sE[w], coff,
+                                  zero_e, (first + sl) * S::VW - S::PX, chunk * L, L);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1170,69 +1112,34 @@ inline dim3 strip_grid(const Geo& g) {
   return dim3((g.nx + kWave - 1) / kWave, g.ncy, g.batch);
 }
 
-// Resident workgroups of a kernel on the whole device (compute units x workgroups per CU).
-template <typename K>
-int resident_workgroups(K kernel) {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
-    return 0;
-  return cus * (per_cu > 0 ? per_cu : 1);
-}
-
-// Host copy of the interior test of one tile axis: the staged span [o - pad, o + len + pad)
-// lies in [1, n - 1) and its interpolation reads coarse cells [c0, c0 + ce) inside [0, nc).
-inline bool axis_interior(int o, int len, int pad, int N, int ce, int n, int nc) {
-  const int s = o - pad - N / 2;
-  const int c0 = s >= 0 ? s / N : -((-s + N - 1) / N);
-  return o - pad >= 1 && o + len + pad + 1 <= n && c0 >= 0 && c0 + ce <= nc;
-}
-
 template <typename T, int NU, int LOG2N>
 hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
                            double* rc, double* psq, int zero_e, hipStream_t s) {
-  constexpr int TSY = sizeof(T) == 4 ? 64 : 32;
-  using CT = CycleTile<T, NU, LOG2N, TSY>;
-  const int tx = (g.nx + 63) / 64, ty = (g.ny + TSY - 1) / TSY;
-  // the interior rectangle of tiles (the test is separable in x and y)
-  int bx0 = tx, bx1 = tx, by0 = ty, by1 = ty;
-  for (int b = 0; b < tx; ++b)
-    if (axis_interior(b * CT::TSX, CT::TSX, CT::PADX, CT::N, CT::CEX, g.nx, g.ncx)) {
-      bx0 = bx0 == tx ? b : bx0;
-      bx1 = b + 1;
-    }
-  for (int b = 0; b < ty; ++b)
-    if (axis_interior(b * TSY, TSY, CT::H, CT::N, CT::CEY, g.ny, g.ncy)) {
-      by0 = by0 == ty ? b : by0;
-      by1 = b + 1;
-    }
-  int nbx = bx1 - bx0, nby = by1 - by0;
-  if (nbx <= 0 || nby <= 0) {
-    bx0 = by0 = 0;
-    nbx = nby = 0;
+  using S = Stream<T, NU, LOG2N>;
+  constexpr int WPB = kBlock / kWave;
+  // wall strips walk half as far: their rows cost more (per-cell neighbour counts) and they
+  // run beside the others
+  const int L = S::L, Le = S::L / 2;
+  const int ns = (g.nx + S::VW - 1) / S::VW;
+  // strips whose columns all exist: every strip of a periodic axis, else strips 1 .. kmax
+  // with (k + 1) VW + PX <= nx; the others (strip 0 and those after kmax) touch a wall
+  int first = 0, ni = ns, ne = 0, efirst = 0;
+  if (!g.per_x) {
+    const int kmax = g.nx >= S::PX ? (g.nx - S::PX) / S::VW - 1 : -1;
+    first = 1;
+    ni = kmax > 0 ? kmax : 0;
+    efirst = ni;
+    ne = ns - ni;
   }
-  const int nt = nbx * nby;
-  if (nt > 0) {
-    auto kernel = k_cycle_interior<T, NU, LOG2N, TSY>;
-    static int resident = 0;  // per kernel instantiation, computed on first use
-    if (resident == 0) resident = resident_workgroups(kernel);
-    int G = resident;
-    if (G <= 0) return hipErrorInvalidValue;
-    G = (G + g.batch - 1) / g.batch;  // workgroups per grid
-    if (G >= 8) G &= ~7;
-    // with few sweeps per cycle one tile per workgroup (more workgroups in flight) measured
-    // faster than the persistent walk; with more sweeps the prefetch pays
-    G = (NU <= 2 || G > nt) ? nt : G;
-    hipLaunchKernelGGL(kernel, dim3(G, 1, g.batch), dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc,
-                       psq, zero_e, bx0, by0, nbx, nby);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-  }
-  const int frame = tx * ty - nt;
-  if (frame > 0)
-    hipLaunchKernelGGL((k_cycle_edge<T, NU, LOG2N, TSY>), dim3(frame, 1, g.batch), dim3(kBlock), 0, s,
-                       g, rhs, ein, eout, E, rc, psq, zero_e, tx, ty, bx0, by0, nbx, nby);
+  const int nchunk = (g.ny + L - 1) / L, nchunk_e = (g.ny + Le - 1) / Le;
+  // wall blocks padded to a multiple of 8 so that the XCD of a block (its index mod 8) is
+  // known to the band mapping of the others
+  const int nblk_e = ne > 0 ? ((ne * nchunk_e + WPB - 1) / WPB + 7) / 8 * 8 : 0;
+  const int nblk_i = (ni * nchunk + WPB - 1) / WPB;
+  if (nblk_e + nblk_i == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N>), dim3(nblk_e + nblk_i, 1, g.batch), dim3(kBlock), 0, s,
+                     g, rhs, ein, eout, E, rc, psq, zero_e, L, nchunk, ni, first, Le, nchunk_e, ne,
+                     efirst, nblk_e);
   return hipGetLastError();
 }
 
