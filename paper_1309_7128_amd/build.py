@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libism.so")
-SOURCES = ["ism_kernels.hip", "ism_api.cpp"]
+SOURCES = ["ism_kernels.hip", "ism_cycle_f32.hip", "ism_cycle_f64.hip", "ism_api.cpp"]
 ARCH = os.environ.get("ISM_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: expressions round exactly as written (fused multiply-adds only where a
@@ -39,15 +39,18 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Compile every source and link libism.so; returns the library path."""
-    objs = []
-    for src in SOURCES:
+    objs, procs = [], []
+    for src in SOURCES:  # the translation units compile in parallel
         obj = os.path.join(CSRC, src + ".o")
         cmd = [hipcc(), f"--offload-arch={ARCH}", *FLAGS, "-I", INCLUDE, "-I", CSRC,
                "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, proc in procs:
+        if proc.wait() != 0:
+            raise subprocess.CalledProcessError(proc.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

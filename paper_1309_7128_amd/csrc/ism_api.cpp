@@ -169,8 +169,13 @@ int validate(const ism_config* cfg, std::string& why) {
   if (cfg->nx < 2 || cfg->ny < 2) return why = "the grid needs at least 2 cells per axis", ISM_ERR_UNSUPPORTED;
   const double hx = cfg->lx / cfg->nx, hy = cfg->ly / cfg->ny;
   if (std::fabs(hx - hy) > 1e-12 * hx) return why = "cells must be square (lx/nx == ly/ny)", ISM_ERR_UNSUPPORTED;
-  if (cfg->fused && cfg->nu > ism::fused_max_nu())
-    return why = "the fused cycle kernel supports nu <= 4; use fused = 0", ISM_ERR_UNSUPPORTED;
+  if (cfg->fused && cfg->coarse_stencil != ISM_COARSE_ACM) {
+    const int maxnu = cfg->precision == ISM_PREC_FP64 ? ism::fused_max_nu<double>()
+                                                        : ism::fused_max_nu<float>();
+    if (cfg->nu > maxnu)
+      return why = "the fused cycle kernel supports nu <= " + std::to_string(maxnu) +
+                   " in this precision; use fused = 0", ISM_ERR_UNSUPPORTED;
+  }
   if (double(cfg->nx) * cfg->ny >= 2147483648.0)
     return why = "one grid must have fewer than 2^31 cells", ISM_ERR_UNSUPPORTED;
   return ISM_OK;
@@ -782,6 +787,8 @@ template <typename T>
 int cycle_impl(ism_ctx* c, const T* rhs, T* e, double* rc, int zero_e, double* sumsq) {
   if ((reinterpret_cast<uintptr_t>(rhs) | reinterpret_cast<uintptr_t>(e)) % 16)
     return set_err(c, ISM_ERR_INVALID, "rhs and e must be 16-byte aligned");
+  if (c->cfg.fused && c->cfg.nu > ism::fused_max_nu<T>())
+    return set_err(c, ISM_ERR_UNSUPPORTED, "nu exceeds the fused kernel's limit for this dtype");
   T* tmp = (T*)scratch_fine(c);
   if (!tmp) return set_err(c, ISM_ERR_HIP, "hipMalloc of the stage scratch failed");
   T* cur = e;

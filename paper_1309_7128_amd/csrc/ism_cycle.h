@@ -1,0 +1,532 @@
+// The fused two-level cycle kernel of the ISM solver (prolongation, red-black sweeps,
+// residual and restriction in one pass over the grid), as templates; ism_cycle_f32.hip and
+// ism_cycle_f64.hip instantiate them for the two fine-grid types.
+#pragma once
+
+#include "ism_device.h"
+
+namespace ism {
+namespace {
+
+// ----------------------------------------------------------------------------------------
+// Fused two-level cycle kernel: row-pipelined temporal blocking in registers.
+//
+// One wave owns a strip of LW = 64 CPL columns (CPL consecutive cells per lane) and a run of
+// L output rows, and walks up the strip one row at a time holding a ring of P rows of e and
+// rhs in registers.  When row t enters it receives the bilinear coarse correction (Eq. 5).
+// Then half-step k = 1 .. 2 NU (odd k red, even k black) updates its colour on row t - k:
+// at that moment row t - k + 1 has just had half-step k - 1 and row t - k - 1 still waits
+// for half-step k + 1, so every cell sees exactly the neighbours the k-th half-step of a
+// whole-grid sweep would give it.  Row t - 2 NU - 1 is then final: its residual is formed,
+// summed over the n x n coarse tiles, and the row is written out.  East and west neighbours
+// across lanes come from DPP wavefront shifts, so the half-steps touch neither LDS nor
+// memory.  The strip's PX >= 2 NU + 1 outer columns on each side and its first H rows absorb
+// the stale values its edges inject (they spread one cell per half-step); the VW = LW - 2 PX
+// valid columns start on a coarse tile boundary.  Per cycle e and rhs are read once (plus
+// halos) and e is written once.
+// ----------------------------------------------------------------------------------------
+constexpr int stream_pad(int h, int n, int cpl, int lw) {
+  int px = (h + cpl - 1) / cpl * cpl;
+  while ((lw - 2 * px) % n != 0) px += cpl;
+  return px;
+}
+
+template <typename T, int NU, int LOG2N>
+struct Stream {
+  static constexpr int CPL = 4;           // cells per lane
+  static constexpr int LW = kWave * CPL;  // columns per strip
+  static constexpr int N = 1 << LOG2N;
+  static constexpr int H = 2 * NU + 1;    // reach of one cycle (2 NU half-steps + residual)
+  static constexpr int PX = stream_pad(H, N, CPL, LW);
+  static constexpr int VW = LW - 2 * PX;  // valid columns per strip
+  // rows read ahead, through a per-wave LDS ring of DL slots (16-byte chunks per lane of e
+  // and rhs in each)
+  static constexpr int C16 = CPL * int(sizeof(T)) / 16;
+  static constexpr int DL = sizeof(T) == 4 ? 4 : 3;
+  static constexpr int SLOT = 2 * C16 * kWave * 16;  // bytes per ring slot
+  // register ring rows: 2 NU + 3 live, even (fixed row parity per slot)
+  static constexpr int P = 2 * NU + 4;
+  static constexpr int L = N >= 8 ? 128 : 64;  // output rows per unit (half that by a wall)
+  // coarse rows and columns one walk interpolates from, at most (staged in LDS per wave)
+  static constexpr int NR = (L + 2 * H - 1) / N + 3;
+  static constexpr int NC = LW / N + 3;
+  static_assert(N >= CPL && VW >= N && VW % N == 0 && PX % CPL == 0, "strip geometry");
+  static_assert(P % 2 == 0 && P >= 2 * NU + 3, "ring length");
+};
+
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void load_cells(const T* __restrict__ p, T (&v)[C]) {
+  using V = typename Vec16<T>::type;
+  constexpr int K = 16 / sizeof(T);
+#pragma unroll
+  for (int q = 0; q < C / K; ++q) {
+    const V x = reinterpret_cast<const V*>(p)[q];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[q * K + k] = (&x.x)[k];
+  }
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void store_cells(T* __restrict__ p, const T (&v)[C]) {
+  using V = typename Vec16<T>::type;
+  constexpr int K = 16 / sizeof(T);
+#pragma unroll
+  for (int q = 0; q < C / K; ++q) {
+    V x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) (&x.x)[k] = v[q * K + k];
+    reinterpret_cast<V*>(p)[q] = x;
+  }
+}
+
+// A value known to be the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffll)));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((long long)lo | ((long long)hi << 32));
+}
+
+// The value of lane l - 1 (wave_shr:1) or lane l + 1 (wave_shl:1); lanes without a source
+// get 0.
+constexpr int kDppFromLeft = 0x138, kDppFromRight = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, 0xf, 0xf, false));
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)lo | ((long long)hi << 32));
+}
+
+// LDS byte offset of a pointer into __shared__ memory.
+typedef __attribute__((address_space(3))) char LdsChar;
+typedef unsigned Vec4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned lds_offset(const void* p) {
+  return (unsigned)(uintptr_t)(const LdsChar*)p;
+}
+
+// 16 bytes per lane from global memory into LDS: lane i's bytes at g land at LDS byte offset
+// lds + 16 i (an LDS-DMA load, M0 holding the base; lds must be wave-uniform).  Issued as
+// inline assembly so that the compiler, which otherwise waits for every such load in flight
+// before any LDS read, leaves the waits to the caller.  The LDS it writes is touched only by
+// these statements and lds_take (volatile, so kept in program order), and the global memory
+// it reads is not written by the kernel, so no memory clobber is needed.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma16(const void* g, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "s"(lds) : "m0");
+}
+#pragma clang diagnostic pop
+
+// Wait until at most NV vector-memory operations are outstanding, then read K 16-byte chunks
+// per lane from LDS at a, a + 1024, ... and wait for them.
+template <int NV, int K>
+__device__ __forceinline__ void lds_take(unsigned a, Vec4u (&v)[K]) {
+  static_assert(K == 2 || K == 4, "two or four chunks");
+  if constexpr (K == 2) {
+    asm volatile(
+        "s_waitcnt vmcnt(%3)\n\tds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:1024\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1])
+        : "v"(a), "n"(NV));
+  } else {
+    asm volatile(
+        "s_waitcnt vmcnt(%5)\n\tds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
+        "ds_read_b128 %2, %4 offset:2048\n\tds_read_b128 %3, %4 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3])
+        : "v"(a), "n"(NV));
+  }
+}
+
+// The CPL cells of one array held in 16-byte chunks c0, c0 + 1, ...
+template <typename T, int CPL, int K>
+__device__ __forceinline__ void unpack_cells(const Vec4u (&v)[K], int c0, T (&out)[CPL]) {
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int p = 0; p < CPL; ++p) out[p] = __uint_as_float(v[c0 + p / 4][p % 4]);
+  } else {
+#pragma unroll
+    for (int p = 0; p < CPL; ++p) {
+      const Vec4u& c = v[c0 + p / 2];
+      out[p] = __hiloint2double(int(c[2 * (p % 2) + 1]), int(c[2 * (p % 2)]));
+    }
+  }
+}
+
+// One wave's walk up its strip: output rows y0 .. y0 + min(L, ny - y0) - 1 of the strip whose
+// first read column is xs.  EDGE: the strip reads columns behind a wall (x not periodic),
+// handled lane by lane; otherwise every column it reads exists (possibly wrapped).
+template <typename T, int NU, int LOG2N, bool EDGE>
+__device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ rb,
+                                           const T* __restrict__ eb, T* __restrict__ ob,
+                                           const double* __restrict__ Eb, double* __restrict__ rc,
+                                           double* __restrict__ psq, double* __restrict__ sE,
+                                           double2* __restrict__ sX, Vec4u* __restrict__ sR,
+                                           long long coff, int zero_e, int xs, int y0, int L) {
+  using S = Stream<T, NU, LOG2N>;
+  constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
+  constexpr int G = N / CPL;  // lanes per coarse tile
+  constexpr double inv2n = 1.0 / double(2 * N);
+  constexpr T third = T(1) / T(3);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ys = y0 - H;
+  const int yend = y0 + min(L, g.ny - y0) + H;  // rows ys .. yend - 1 are read
+
+  // this lane's first column (unwrapped), the column it is read from, whether it exists
+  const int cu = xs + CPL * lane;
+  bool col_in = true;
+  int cw = cu;
+  if (g.per_x) {
+    cw = imod(cu, g.nx);
+  } else if (EDGE) {
+    col_in = cu >= 0 && cu < g.nx;
+    cw = col_in ? cu : 0;
+  }
+  const bool lane_out = lane >= PX / CPL && lane < (PX + VW) / CPL && cu < g.nx;
+
+  // The coarse values the walk interpolates from (Eq. 5, boundary rule applied), staged in
+  // this wave's LDS block: rows crow(ys) .. crow(yend - 1) + 1, columns from the lower
+  // neighbour of the strip's first column on.  Only this wave reads them.
+  auto crow = [](int t) { return (t - N / 2) >> LOG2N; };  // lower coarse row of fine row t
+  const int J0 = crow(ys), I0 = (xs - N / 2) >> LOG2N;
+  {
+    const int nr = crow(yend - 1) + 2 - J0;
+    for (int i = lane; i < nr * S::NC; i += kWave) {
+      const int rr = i / S::NC, c = i - rr * S::NC;
+      int J = J0 + rr, I = I0 + c;
+      J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
+      I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
+      sE[i] = Eb[(long long)J * g.ncx + I];
+    }
+    // the block is written and read by this wave only: order its writes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // For n >= 8 all of a lane's cells lie between the same two coarse centres; for n = 4 its
+  // first and last two cells lie between consecutive pairs.
+  constexpr int NEC = N >= 8 ? 2 : 3;
+  const int crel = ((cu - N / 2) >> LOG2N) - I0;
+  // coarse row J interpolated along x at the lane's cells
+  auto interp_x = [&](int J, double (&out)[CPL]) {
+    const double* q = sE + (J - J0) * S::NC + crel;
+    double v[NEC];
+#pragma unroll
+    for (int k = 0; k < NEC; ++k) v[k] = q[k];
+    int c0 = cu;
+    asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
+#pragma unroll
+    for (int p = 0; p < CPL; ++p) {
+      const double X = double(2 * ((c0 + p - N / 2) & (N - 1)) + 1) * inv2n;
+      const int k = N >= 8 ? 0 : (p >> 1);
+      out[p] = lerp(v[k], v[k + 1], X);
+    }
+  };
+
+  // The ring: e and rhs of rows t - P + 1 .. t in slot (row - ys) mod P, and per slot the
+  // row's y-neighbour class: the inverse neighbour count for cells with both x-neighbours (0
+  // behind a wall and for rows not read yet, which the half-steps then leave at 0) and the
+  // number of existing y-neighbours.
+  T e[P][CPL], r[P][CPL];
+  T invs[P];
+  int mys[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    invs[q] = T(0);
+    mys[q] = 0;
+#pragma unroll
+    for (int p = 0; p < CPL; ++p) e[q][p] = r[q][p] = T(0);
+  }
+  // Coarse rows J interpolated along x at the lane's cells, kept in LDS buffer J & 1 (each
+  // lane reads back only what it wrote): [buffer][cell pair][lane].
+  auto put_x = [&](int J) {
+    double v[CPL];
+    interp_x(J, v);
+    double2* d = sX + (J & 1) * (CPL / 2) * kWave + lane;
+#pragma unroll
+    for (int q = 0; q < CPL / 2; ++q) d[q * kWave] = make_double2(v[2 * q], v[2 * q + 1]);
+  };
+  int jc = J0;
+  put_x(jc);
+  put_x(jc + 1);
+  // the next row to read, wrapped or clamped into the grid
+  int jn = g.per_y ? imod(ys, g.ny) : min(max(ys, 0), g.ny - 1);
+  // Rows are read DL ahead by LDS-DMA into this wave's LDS ring (slot (row - ys) mod DL:
+  // the C16 chunks of e, then those of rhs) and enter the register ring when used.  Every row
+  // issues the same 2 C16 loads (e is read even when it is ignored), so when row t enters,
+  // the loads of rows t + 1 .. t + DL - 1 at most may still be outstanding besides stores:
+  // waiting until no more than that many operations are outstanding guarantees row t landed.
+  constexpr int DL = S::DL, C16 = S::C16;
+  constexpr int NWAIT = 2 * C16 * (DL - 1);
+  const unsigned ring0 = lds_offset(sR);
+  int qs = 0;  // LDS slot of the next row to enter
+  auto fetch = [&](int t, int slot) {
+    const long long a = (long long)jn * g.nx + cw;
+    const unsigned base = ring0 + unsigned(slot) * S::SLOT;
+#pragma unroll
+    for (int c = 0; c < C16; ++c) {
+      dma16(eb + a + c * (16 / int(sizeof(T))), base + c * 1024);
+      dma16(rb + a + c * (16 / int(sizeof(T))), base + (C16 + c) * 1024);
+    }
+    jn = g.per_y ? (jn + 1 == g.ny ? 0 : jn + 1) : min(max(t + 1, 0), g.ny - 1);
+  };
+#pragma unroll
+  for (int q = 0; q < DL; ++q) fetch(ys + q, q);
+  double acc = 0.0, acc2 = 0.0;
+
+  for (int tb = ys; tb < yend; tb += P) {
+#pragma unroll
+    for (int ph = 0; ph < P; ++ph) {
+      const int t = tb + ph;
+      if (t < yend) {
+        // ys is odd (y0 even, H odd) and P even, so the parity of t is fixed per slot
+        const int tpar = (1 + ph) & 1;
+        // EDGE: the lane's first column, opaque so that the per-cell wall arithmetic below is
+        // redone each row rather than held in registers for the walk
+        int cx = cu;
+        if (EDGE) asm volatile("" : "+v"(cx));
+
+        // row t enters: e = (zero_e ? 0 : e) + P E; cells behind a wall hold 0
+        {
+          if (crow(t) != jc) {  // next pair of coarse rows
+            jc = crow(t);
+            put_x(jc + 1);
+          }
+          double xlo[CPL], xhi[CPL];
+          {
+            const double2* a = sX + (jc & 1) * (CPL / 2) * kWave + lane;
+            const double2* b = sX + ((jc + 1) & 1) * (CPL / 2) * kWave + lane;
+#pragma unroll
+            for (int q = 0; q < CPL / 2; ++q) {
+              const double2 u = a[q * kWave], w = b[q * kWave];
+              xlo[2 * q] = u.x;
+              xlo[2 * q + 1] = u.y;
+              xhi[2 * q] = w.x;
+              xhi[2 * q + 1] = w.y;
+            }
+          }
+          const int k = (t - N / 2) & (N - 1);
+          const double Y = double(2 * k + 1) * inv2n, Y1 = 1.0 - Y;
+          {
+            Vec4u v[2 * C16];
+            lds_take<NWAIT>(ring0 + unsigned(qs) * S::SLOT + 16u * unsigned(lane), v);
+            T le[CPL];
+            unpack_cells<T, CPL>(v, 0, le);
+            unpack_cells<T, CPL>(v, C16, r[ph]);
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) {
+              const T e0 = zero_e ? T(0) : le[p];
+              e[ph][p] = T(double(e0) + (xlo[p] * Y1 + xhi[p] * Y));
+            }
+          }
+          const bool row_in = g.per_y || (t >= 0 && t < g.ny);
+          if (!row_in) {
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
+          }
+          if (EDGE && !col_in) {
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
+          }
+          const int my = !row_in ? 0 : (g.per_y ? 2 : 2 - (t == 0) - (t == g.ny - 1));
+          invs[ph] = uniform(my == 2 ? T(0.25) : (my == 1 ? third : T(0)));
+          mys[ph] = my;
+        }
+
+        // half-step k (odd red, even black) on row t - k
+#pragma unroll
+        for (int k = 1; k <= 2 * NU; ++k) {
+          const int sc = (ph - k + P) % P, sb = (ph - k - 1 + P) % P, sa = (ph - k + 1 + P) % P;
+          const int colour = (k - 1) & 1;          // 0 red, 1 black
+          const int p0 = (colour + tpar + k) & 1;  // the lane's cells p with (p + row) & 1 == colour
+#pragma unroll
+          for (int p = 0; p < CPL; ++p) {
+            if ((p & 1) != p0) continue;
+            const T w = p > 0 ? e[sc][p - 1] : lane_shift<kDppFromLeft>(e[sc][CPL - 1]);
+            const T ea = p < CPL - 1 ? e[sc][p + 1] : lane_shift<kDppFromRight>(e[sc][0]);
+            const T sum = ((w + ea) + e[sb][p]) + e[sa][p];
+            T inv = invs[sc];
+            if (EDGE) {
+              // 1 / (existing neighbours): 1, 1/2 or 1/4 as a power of two, 1/3 for three;
+              // 0 behind a wall (the cell then stays 0)
+              const int i = cx + p;
+              const int m = (i > 0) + (i < g.nx - 1) + mys[sc];
+              const T pw = T(__builtin_ldexpf(1.0f, -(m >> 1)));
+              inv = m == 3 ? third : pw;
+              inv = (unsigned(i) < unsigned(g.nx) && mys[sc] > 0) ? inv : T(0);
+            }
+            e[sc][p] = (sum - r[sc][p]) * inv;
+          }
+        }
+
+        // row o = t - H is final: residual, write-back, coarse-tile sums
+        const int o = t - H;
+        if (o >= y0) {
+          const int so = (ph - H + P) % P, sb = (ph - H - 1 + P) % P, sa = (ph - H + 1 + P) % P;
+          const bool hs = g.per_y || o > 0, hn = g.per_y || o < g.ny - 1;
+#pragma unroll
+          for (int p = 0; p < CPL; ++p) {
+            const T c = e[so][p];
+            const T w = p > 0 ? e[so][p - 1] : lane_shift<kDppFromLeft>(e[so][CPL - 1]);
+            const T ea = p < CPL - 1 ? e[so][p + 1] : lane_shift<kDppFromRight>(e[so][0]);
+            const bool hw = !EDGE || cx + p > 0, he = !EDGE || cx + p < g.nx - 1;
+            const T res = r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn);
+            const double d = double(res);
+            acc += d;
+            acc2 += d * d;
+          }
+          if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
+          if (((o - y0) & (N - 1)) == N - 1) {
+            double a = acc, q = acc2;
+#pragma unroll
+            for (int k = 1; k < G; k <<= 1) {
+              a += __shfl_down(a, k, kWave);
+              q += __shfl_down(q, k, kWave);
+            }
+            if (lane_out && ((lane - PX / CPL) & (G - 1)) == 0) {
+              const long long oc = coff + (long long)(o >> LOG2N) * g.ncx + (cu >> LOG2N);
+              rc[oc] = a;
+              if (psq) psq[oc] = q;
+            }
+            acc = acc2 = 0.0;
+          }
+        }
+
+        // row t + DL into the LDS slot row t just left
+        fetch(t + DL, qs);
+        qs = qs + 1 == DL ? 0 : qs + 1;
+      }
+    }
+  }
+  // the loads of rows past the end are still in flight into LDS: wait for them
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// One launch covers every strip.  Units (a strip and a chunk of rows) are numbered
+// strip-fastest.  The first nblk_e workgroups take the strips that touch a wall (strip 0 and
+// strips efirst + 1, efirst + 2, ...) in chunks of Le rows; the others take strips first,
+// first + 1, ... in chunks of L rows, dealt out so that each XCD (the hardware deals
+// workgroups out round-robin over the 8 XCDs) runs one contiguous band of units.
+template <typename T, int NU, int LOG2N>
+__global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
+                                                  const T* __restrict__ ein,
+                                                  T* __restrict__ eout,
+                                                  const double* __restrict__ E,
+                                                  double* __restrict__ rc,
+                                                  double* __restrict__ psq, int zero_e,
+                                                  int L, int nchunk, int nstrip, int first,
+                                                  int Le, int nchunk_e, int nstrip_e, int efirst,
+                                                  int nblk_e) {
+  using S = Stream<T, NU, LOG2N>;
+  constexpr int WPB = kBlock / kWave;
+  __shared__ double sE[WPB][S::NR * S::NC];
+  __shared__ double2 sX[WPB][2 * (S::CPL / 2) * kWave];
+  __shared__ Vec4u sR[WPB][S::DL * S::SLOT / 16];
+  const long long off = (long long)blockIdx.z * g.plane;
+  const long long coff = (long long)blockIdx.z * g.cplane;
+  // the wave index, made visibly wave-uniform so that everything derived from it (strip,
+  // rows, the walk's row bookkeeping) lives in scalar registers and scalar branches
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+  const int b = blockIdx.x;
+  if (b < nblk_e) {
+    const int u = b * WPB + w;
+    if (u >= nstrip_e * nchunk_e) return;
+    const int chunk = u / nstrip_e, sl = u - chunk * nstrip_e;
+    const int strip = sl == 0 ? 0 : efirst + sl;
+    cycle_walk<T, NU, LOG2N, true>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq, sE[w],
+                                   sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
+                                   chunk * Le, Le);
+    return;
+  }
+  int bi = b - nblk_e;
+  const int nbi = gridDim.x - nblk_e;
+  if ((nbi & 7) == 0) bi = (bi & 7) * (nbi >> 3) + (bi >> 3);
+  const int u = bi * WPB + w;
+  if (u >= nstrip * nchunk) return;
+  const int chunk = u / nstrip, sl = u - chunk * nstrip;
+  cycle_walk<T, NU, LOG2N, false>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq, sE[w],
+                                  sX[w], sR[w], coff, zero_e, (first + sl) * S::VW - S::PX,
+                                  chunk * L, L);
+}
+
+template <typename T, int NU, int LOG2N>
+hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                           double* rc, double* psq, int zero_e, hipStream_t s) {
+  using S = Stream<T, NU, LOG2N>;
+  constexpr int WPB = kBlock / kWave;
+  // wall strips walk half as far: their rows cost more (per-cell neighbour counts) and they
+  // run beside the others
+  const int L = S::L, Le = S::L / 2;
+  const int ns = (g.nx + S::VW - 1) / S::VW;
+  // strips whose columns all exist: every strip of a periodic axis, else strips 1 .. kmax
+  // with (k + 1) VW + PX <= nx; the others (strip 0 and those after kmax) touch a wall
+  int first = 0, ni = ns, ne = 0, efirst = 0;
+  if (!g.per_x) {
+    const int kmax = g.nx >= S::PX ? (g.nx - S::PX) / S::VW - 1 : -1;
+    first = 1;
+    ni = kmax > 0 ? kmax : 0;
+    efirst = ni;
+    ne = ns - ni;
+  }
+  const int nchunk = (g.ny + L - 1) / L, nchunk_e = (g.ny + Le - 1) / Le;
+  // wall blocks padded to a multiple of 8 so that the XCD of a block (its index mod 8) is
+  // known to the band mapping of the others
+  const int nblk_e = ne > 0 ? ((ne * nchunk_e + WPB - 1) / WPB + 7) / 8 * 8 : 0;
+  const int nblk_i = (ni * nchunk + WPB - 1) / WPB;
+  if (nblk_e + nblk_i == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N>), dim3(nblk_e + nblk_i, 1, g.batch), dim3(kBlock), 0, s,
+                     g, rhs, ein, eout, E, rc, psq, zero_e, L, nchunk, ni, first, Le, nchunk_e, ne,
+                     efirst, nblk_e);
+  return hipGetLastError();
+}
+
+template <typename T, int NU>
+hipError_t cycle_dispatch2(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                           double* rc, double* psq, int zero_e, hipStream_t s) {
+  switch (g.log2n) {
+    case 2: return cycle_dispatch3<T, NU, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 3: return cycle_dispatch3<T, NU, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 4: return cycle_dispatch3<T, NU, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 5: return cycle_dispatch3<T, NU, 5>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// Every sweep count 1 .. MAXNU of the fused kernel for fine type T.
+template <typename T, int MAXNU>
+hipError_t launch_cycle_upto(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                             double* rc, double* psq, int nu, int zero_e, hipStream_t s) {
+  if constexpr (MAXNU == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (nu == MAXNU) return cycle_dispatch2<T, MAXNU>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    return launch_cycle_upto<T, MAXNU - 1>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s);
+  }
+}
+
+}  // namespace ism

@@ -1,0 +1,18 @@
+// The fused cycle kernel for FP32 fine grids, nu = 1 .. 5.
+#include "ism_cycle.h"
+
+namespace ism {
+
+template <>
+hipError_t launch_cycle_fused<float>(const Geo& g, const float* rhs, const float* ein, float* eout,
+                                  const double* E, double* rc, double* psq, int nu, int zero_e,
+                                  hipStream_t s) {
+  return launch_cycle_upto<float, 5>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s);
+}
+
+template <>
+int fused_max_nu<float>() {
+  return 5;
+}
+
+}  // namespace ism

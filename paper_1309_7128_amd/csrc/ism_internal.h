@@ -50,13 +50,24 @@ template <typename T>
 hipError_t launch_prolong(const Geo& g, const double* E, T* e, int assign, hipStream_t s);
 
 // One fused cycle: e = (zero_e ? 0 : e) + P E, nu red-black sweeps on A'e = rhs, then
-// rc = R (rhs - A'e) and per-tile sums of squares.  Tile TXxTY of fine cells per workgroup.
-// e_in and e_out must not alias.
+// rc = R (rhs - A'e) and per-coarse-tile sums of squares (ism_cycle_f32.hip and
+// ism_cycle_f64.hip).  e_in and e_out must not alias.  nu <= fused_max_nu<T>().
 template <typename T>
 hipError_t launch_cycle_fused(const Geo& g, const T* rhs, const T* e_in, T* e_out,
                               const double* E, double* rc, double* part_sumsq, int nu,
                               int zero_e, hipStream_t s);
+template <typename T>
 int fused_max_nu();
+template <>
+hipError_t launch_cycle_fused<float>(const Geo&, const float*, const float*, float*,
+                                     const double*, double*, double*, int, int, hipStream_t);
+template <>
+hipError_t launch_cycle_fused<double>(const Geo&, const double*, const double*, double*,
+                                      const double*, double*, double*, int, int, hipStream_t);
+template <>
+int fused_max_nu<float>();
+template <>
+int fused_max_nu<double>();
 
 template <typename T>
 hipError_t launch_outer_residual(const Geo& g, const double* b, const double* x,

@@ -6,101 +6,13 @@
 // [batch][ny][nx]; a wave covers 64 consecutive cells of a row so every global access is a
 // full 256 B (FP32) or 512 B (FP64) row segment.
 //
-// Arithmetic conventions (shared by every kernel so that a cell value never depends on the
-// kernel that produced it):
-//  * A'e (the 5-point Laplacian times h^2) in difference form,
-//    ((e_W - e_C) + (e_E - e_C)) + (e_S - e_C)) + (e_N - e_C), a wall neighbour's term being
-//    absent (Sec. 2.3 stencil, Sec. 4.1 walls).
-//  * Red-black Gauss-Seidel (Sec. 3.1): red is (i + j) even; a cell is set to
-//    (((e_W + e_E) + e_S) + e_N - rhs_C) * (1 / m_C), m_C its number of existing neighbours
-//    and a missing neighbour contributing 0.
-//  * Bilinear prolongation (Eq. 5) evaluated in FP64 and added to the fine value in FP64,
-//    then rounded to the fine type.
-// The library is compiled with -ffp-contract=off so these expressions round exactly as
-// written; products that are meant to fuse (the coarse transforms) call fma explicitly.
+// The arithmetic conventions all kernels share are stated in ism_device.h; the fused cycle
+// kernel lives in ism_cycle.h.
 
-#include <hip/hip_runtime.h>
-
-#include "ism_internal.h"
+#include "ism_device.h"
 
 namespace ism {
 namespace {
-
-constexpr int kWave = 64;
-constexpr int kBlock = 256;
-
-__device__ __forceinline__ int imod(int i, int n) {
-  int r = i % n;
-  return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ int floordiv(int a, int n) {
-  return a >= 0 ? a / n : -((-a + n - 1) / n);
-}
-
-// Map an unwrapped cell coordinate onto the grid: wraps periodic axes, rejects cells behind
-// a wall.
-__device__ __forceinline__ bool map_cell(const Geo& g, int& i, int& j) {
-  if (g.per_x) {
-    i = imod(i, g.nx);
-  } else if (i < 0 || i >= g.nx) {
-    return false;
-  }
-  if (g.per_y) {
-    j = imod(j, g.ny);
-  } else if (j < 0 || j >= g.ny) {
-    return false;
-  }
-  return true;
-}
-
-template <typename T>
-__device__ __forceinline__ T inv_count(const Geo& g, int i, int j) {
-  int m = 4;
-  if (!g.per_x) m -= (i == 0) + (i == g.nx - 1);
-  if (!g.per_y) m -= (j == 0) + (j == g.ny - 1);
-  constexpr T third = T(1) / T(3);
-  return m == 4 ? T(0.25) : (m == 3 ? third : (m == 2 ? T(0.5) : T(1)));
-}
-
-// A'e at a cell from its four neighbours, difference form; absent terms skipped.
-template <typename T>
-__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, bool hw, bool he, bool hs, bool hn) {
-  T dw = hw ? T(w - c) : T(0);
-  T de = he ? T(e - c) : T(0);
-  T ds = hs ? T(s - c) : T(0);
-  T dn = hn ? T(n - c) : T(0);
-  return ((dw + de) + ds) + dn;
-}
-
-__device__ __forceinline__ double wave_sum_group(double v, int group) {
-  for (int off = 1; off < group; off <<= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max_group(double v, int group) {
-  for (int off = 1; off < group; off <<= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-  return v;
-}
-
-// Interpolation coordinate along one axis (Eq. 5): fine index -> lower coarse index
-// (unwrapped, may be -1 or the last+1) and the offset t = (2k+1)/(2n) of the fine centre
-// from the lower coarse centre, in units of the rectangle size n.
-__device__ __forceinline__ void interp_coord(int gi, int n, int& lo, double& t) {
-  int s = gi - (n >> 1);
-  lo = floordiv(s, n);
-  int k = s - lo * n;
-  t = double(2 * k + 1) / double(2 * n);
-}
-
-// Eq. 5 evaluated in nested form: interpolate along x on the lower and the upper coarse row,
-// then along y, p = (Q11 (1-X) + Q21 X) (1-Y) + (Q12 (1-X) + Q22 X) Y, rounded in this order.
-__device__ __forceinline__ double lerp(double a, double b, double t) { return a * (1.0 - t) + b * t; }
-
-__device__ __forceinline__ double bilinear(double q11, double q21, double q12, double q22,
-                                           double X, double Y) {
-  return lerp(lerp(q11, q21, X), lerp(q12, q22, X), Y);
-}
 
 // ----------------------------------------------------------------------------------------
 // One red-black sweep (red on the tile plus one ring, black on the tile), LDS-staged.
@@ -265,364 +177,6 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
 }
 
 // ----------------------------------------------------------------------------------------
-// Fused two-level cycle kernel: row-pipelined temporal blocking in registers.
-//
-// One wave owns a strip of LW = 64 CPL columns (CPL consecutive cells per lane) and a run of
-// L output rows, and walks up the strip one row at a time holding a ring of P rows of e and
-// rhs in registers.  When row t enters it receives the bilinear coarse correction (Eq. 5).
-// Then half-step k = 1 .. 2 NU (odd k red, even k black) updates its colour on row t - k:
-// at that moment row t - k + 1 has just had half-step k - 1 and row t - k - 1 still waits
-// for half-step k + 1, so every cell sees exactly the neighbours the k-th half-step of a
-// whole-grid sweep would give it.  Row t - 2 NU - 1 is then final: its residual is formed,
-// summed over the n x n coarse tiles, and the row is written out.  East and west neighbours
-// across lanes come from DPP wavefront shifts, so the half-steps touch neither LDS nor
-// memory.  The strip's PX >= 2 NU + 1 outer columns on each side and its first H rows absorb
-// the stale values its edges inject (they spread one cell per half-step); the VW = LW - 2 PX
-// valid columns start on a coarse tile boundary.  Per cycle e and rhs are read once (plus
-// halos) and e is written once.
-// ----------------------------------------------------------------------------------------
-constexpr int stream_pad(int h, int n, int cpl, int lw) {
-  int px = (h + cpl - 1) / cpl * cpl;
-  while ((lw - 2 * px) % n != 0) px += cpl;
-  return px;
-}
-
-template <typename T, int NU, int LOG2N>
-struct Stream {
-  static constexpr int CPL = 4;           // cells per lane
-  static constexpr int LW = kWave * CPL;  // columns per strip
-  static constexpr int N = 1 << LOG2N;
-  static constexpr int H = 2 * NU + 1;    // reach of one cycle (2 NU half-steps + residual)
-  static constexpr int PX = stream_pad(H, N, CPL, LW);
-  static constexpr int VW = LW - 2 * PX;  // valid columns per strip
-  static constexpr int P = 2 * NU + 4;    // ring rows (2 NU + 3 live), an even number
-  static constexpr int L = N >= 8 ? 128 : 64;  // output rows per unit (half that by a wall)
-  // coarse rows and columns one walk interpolates from, at most (staged in LDS per wave)
-  static constexpr int NR = (L + 2 * H - 1) / N + 3;
-  static constexpr int NC = LW / N + 3;
-  static_assert(N >= CPL && VW >= N && VW % N == 0 && PX % CPL == 0, "strip geometry");
-  static_assert(P % 2 == 0, "an even ring keeps each slot's row parity fixed");
-};
-
-
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<float> {
-  using type = float4;
-};
-template <>
-struct Vec16<double> {
-  using type = double2;
-};
-
-template <typename T, int C>
-__device__ __forceinline__ void load_cells(const T* __restrict__ p, T (&v)[C]) {
-  using V = typename Vec16<T>::type;
-  constexpr int K = 16 / sizeof(T);
-#pragma unroll
-  for (int q = 0; q < C / K; ++q) {
-    const V x = reinterpret_cast<const V*>(p)[q];
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[q * K + k] = (&x.x)[k];
-  }
-}
-
-template <typename T, int C>
-__device__ __forceinline__ void store_cells(T* __restrict__ p, const T (&v)[C]) {
-  using V = typename Vec16<T>::type;
-  constexpr int K = 16 / sizeof(T);
-#pragma unroll
-  for (int q = 0; q < C / K; ++q) {
-    V x;
-#pragma unroll
-    for (int k = 0; k < K; ++k) (&x.x)[k] = v[q * K + k];
-    reinterpret_cast<V*>(p)[q] = x;
-  }
-}
-
-// A value known to be the same in every lane, moved to a scalar register.
-__device__ __forceinline__ float uniform(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ double uniform(double v) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b & 0xffffffffll)));
-  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
-  return __longlong_as_double((long long)lo | ((long long)hi << 32));
-}
-
-// The value of lane l - 1 (wave_shr:1) or lane l + 1 (wave_shl:1); lanes without a source
-// get 0.
-constexpr int kDppFromLeft = 0x138, kDppFromRight = 0x130;
-
-template <int CTRL>
-__device__ __forceinline__ float lane_shift(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double lane_shift(double v) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(b & 0xffffffffll), CTRL, 0xf, 0xf, false));
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double((long long)lo | ((long long)hi << 32));
-}
-
-// One wave's walk up its strip: output rows y0 .. y0 + min(L, ny - y0) - 1 of the strip whose
-// first read column is xs.  EDGE: the strip reads columns behind a wall (x not periodic),
-// handled lane by lane; otherwise every column it reads exists (possibly wrapped).
-template <typename T, int NU, int LOG2N, bool EDGE>
-__device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ rb,
-                                           const T* __restrict__ eb, T* __restrict__ ob,
-                                           const double* __restrict__ Eb, double* __restrict__ rc,
-                                           double* __restrict__ psq, double* __restrict__ sE,
-                                           long long coff, int zero_e, int xs, int y0, int L) {
-  using S = Stream<T, NU, LOG2N>;
-  constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
-  constexpr int G = N / CPL;  // lanes per coarse tile
-  constexpr double inv2n = 1.0 / double(2 * N);
-  constexpr T third = T(1) / T(3);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int ys = y0 - H;
-  const int yend = y0 + min(L, g.ny - y0) + H;  // rows ys .. yend - 1 are read
-
-  // this lane's first column (unwrapped), the column it is read from, whether it exists
-  const int cu = xs + CPL * lane;
-  bool col_in = true;
-  int cw = cu;
-  if (g.per_x) {
-    cw = imod(cu, g.nx);
-  } else if (EDGE) {
-    col_in = cu >= 0 && cu < g.nx;
-    cw = col_in ? cu : 0;
-  }
-  const bool lane_out = lane >= PX / CPL && lane < (PX + VW) / CPL && cu < g.nx;
-  // EDGE: 1 / (existing neighbours) of each cell on rows with both y-neighbours (ia) and
-  // with one (ib); 0 for cells behind a wall
-  T ia[CPL], ib[CPL];
-#pragma unroll
-  for (int p = 0; p < CPL; ++p) {
-    const int mxp = 2 - (cu + p == 0) - (cu + p == g.nx - 1);
-    ia[p] = !col_in ? T(0) : (mxp == 2 ? T(0.25) : third);
-    ib[p] = !col_in ? T(0) : (mxp == 2 ? third : T(0.5));
-  }
-
-  // The coarse values the walk interpolates from (Eq. 5, boundary rule applied), staged in
-  // this wave's LDS block: rows crow(ys) .. crow(yend - 1) + 1, columns from the lower
-  // neighbour of the strip's first column on.  Only this wave reads them.
-  auto crow = [](int t) { return (t - N / 2) >> LOG2N; };  // lower coarse row of fine row t
-  const int J0 = crow(ys), I0 = (xs - N / 2) >> LOG2N;
-  {
-    const int nr = crow(yend - 1) + 2 - J0;
-    for (int i = lane; i < nr * S::NC; i += kWave) {
-      const int rr = i / S::NC, c = i - rr * S::NC;
-      int J = J0 + rr, I = I0 + c;
-      J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
-      I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
-      sE[i] = Eb[(long long)J * g.ncx + I];
-    }
-    // the block is written and read by this wave only: order its writes before the reads
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  // For n >= 8 all of a lane's cells lie between the same two coarse centres; for n = 4 its
-  // first and last two cells lie between consecutive pairs.
-  constexpr int NEC = N >= 8 ? 2 : 3;
-  const int crel = ((cu - N / 2) >> LOG2N) - I0;
-  // coarse row J interpolated along x at the lane's cells
-  auto interp_x = [&](int J, double (&out)[CPL]) {
-    const double* q = sE + (J - J0) * S::NC + crel;
-    double v[NEC];
-#pragma unroll
-    for (int k = 0; k < NEC; ++k) v[k] = q[k];
-    int c0 = cu;
-    asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
-#pragma unroll
-    for (int p = 0; p < CPL; ++p) {
-      const double X = double(2 * ((c0 + p - N / 2) & (N - 1)) + 1) * inv2n;
-      const int k = N >= 8 ? 0 : (p >> 1);
-      out[p] = lerp(v[k], v[k + 1], X);
-    }
-  };
-
-  // The ring: e and rhs of rows t - P + 1 .. t in slot (row - ys) mod P, and per slot the
-  // row's y-neighbour class: the inverse neighbour count for cells with both x-neighbours (0
-  // behind a wall and for rows not read yet, which the half-steps then leave at 0) and the
-  // number of existing y-neighbours.
-  T e[P][CPL], r[P][CPL];
-  T invs[P];
-  int mys[P];
-#pragma unroll
-  for (int q = 0; q < P; ++q) {
-    invs[q] = T(0);
-    mys[q] = 0;
-#pragma unroll
-    for (int p = 0; p < CPL; ++p) e[q][p] = r[q][p] = T(0);
-  }
-  int jc = J0;
-  double xlo[CPL], xhi[CPL];
-  interp_x(jc, xlo);
-  interp_x(jc + 1, xhi);
-  // the next row to read, wrapped or clamped into the grid
-  int jn = g.per_y ? imod(ys, g.ny) : min(max(ys, 0), g.ny - 1);
-  // Rows are read two ahead into landing registers of their parity and enter the ring when
-  // used, so that no ring register is the target of a load in flight (a copy or reuse of
-  // one would stall on it).  e is read even when it is ignored, so that every row issues the
-  // same loads and the memory-counter waits stay exact.
-  T le[2][CPL], lr[2][CPL];
-  auto fetch = [&](int t, int par) {
-    const long long a = (long long)jn * g.nx + cw;
-    load_cells(eb + a, le[par]);
-    load_cells(rb + a, lr[par]);
-    jn = g.per_y ? (jn + 1 == g.ny ? 0 : jn + 1) : min(max(t + 1, 0), g.ny - 1);
-  };
-  fetch(ys, 1);  // ys is odd
-  fetch(ys + 1, 0);
-  double acc = 0.0, acc2 = 0.0;
-
-  for (int tb = ys; tb < yend; tb += P) {
-#pragma unroll
-    for (int ph = 0; ph < P; ++ph) {
-      const int t = tb + ph;
-      if (t < yend) {
-        // ys is odd (y0 even, H odd) and P even, so the parity of t is fixed per slot
-        const int tpar = (1 + ph) & 1;
-
-        // row t enters: e = (zero_e ? 0 : e) + P E; cells behind a wall hold 0
-        {
-          if (crow(t) != jc) {  // next pair of coarse rows
-            jc = crow(t);
-#pragma unroll
-            for (int p = 0; p < CPL; ++p) xlo[p] = xhi[p];
-            interp_x(jc + 1, xhi);
-          }
-          const int k = (t - N / 2) & (N - 1);
-          const double Y = double(2 * k + 1) * inv2n, Y1 = 1.0 - Y;
-#pragma unroll
-          for (int p = 0; p < CPL; ++p) {
-            const T e0 = zero_e ? T(0) : le[tpar][p];
-            e[ph][p] = T(double(e0) + (xlo[p] * Y1 + xhi[p] * Y));
-            r[ph][p] = lr[tpar][p];
-          }
-          const bool row_in = g.per_y || (t >= 0 && t < g.ny);
-          if (!row_in) {
-#pragma unroll
-            for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
-          }
-          if (EDGE && !col_in) {
-#pragma unroll
-            for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
-          }
-          const int my = !row_in ? 0 : (g.per_y ? 2 : 2 - (t == 0) - (t == g.ny - 1));
-          invs[ph] = uniform(my == 2 ? T(0.25) : (my == 1 ? third : T(0)));
-          mys[ph] = my;
-        }
-
-        // half-step k (odd red, even black) on row t - k
-#pragma unroll
-        for (int k = 1; k <= 2 * NU; ++k) {
-          const int sc = (ph - k + P) % P, sb = (ph - k - 1 + P) % P, sa = (ph - k + 1 + P) % P;
-          const int colour = (k - 1) & 1;          // 0 red, 1 black
-          const int p0 = (colour + tpar + k) & 1;  // the lane's cells p with (p + row) & 1 == colour
-#pragma unroll
-          for (int p = 0; p < CPL; ++p) {
-            if ((p & 1) != p0) continue;
-            const T w = p > 0 ? e[sc][p - 1] : lane_shift<kDppFromLeft>(e[sc][CPL - 1]);
-            const T ea = p < CPL - 1 ? e[sc][p + 1] : lane_shift<kDppFromRight>(e[sc][0]);
-            const T sum = ((w + ea) + e[sb][p]) + e[sa][p];
-            T inv = invs[sc];
-            if (EDGE) inv = mys[sc] == 2 ? ia[p] : (mys[sc] == 1 ? ib[p] : T(0));
-            e[sc][p] = (sum - r[sc][p]) * inv;
-          }
-        }
-
-        // row o = t - H is final: residual, write-back, coarse-tile sums
-        const int o = t - H;
-        if (o >= y0) {
-          const int so = (ph - H + P) % P, sb = (ph - H - 1 + P) % P, sa = (ph - H + 1 + P) % P;
-          const bool hs = g.per_y || o > 0, hn = g.per_y || o < g.ny - 1;
-#pragma unroll
-          for (int p = 0; p < CPL; ++p) {
-            const T c = e[so][p];
-            const T w = p > 0 ? e[so][p - 1] : lane_shift<kDppFromLeft>(e[so][CPL - 1]);
-            const T ea = p < CPL - 1 ? e[so][p + 1] : lane_shift<kDppFromRight>(e[so][0]);
-            const bool hw = !EDGE || cu + p > 0, he = !EDGE || cu + p < g.nx - 1;
-            const T res = r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn);
-            const double d = double(res);
-            acc += d;
-            acc2 += d * d;
-          }
-          if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
-          if (((o - y0) & (N - 1)) == N - 1) {
-            double a = acc, q = acc2;
-#pragma unroll
-            for (int k = 1; k < G; k <<= 1) {
-              a += __shfl_down(a, k, kWave);
-              q += __shfl_down(q, k, kWave);
-            }
-            if (lane_out && ((lane - PX / CPL) & (G - 1)) == 0) {
-              const long long oc = coff + (long long)(o >> LOG2N) * g.ncx + (cu >> LOG2N);
-              rc[oc] = a;
-              if (psq) psq[oc] = q;
-            }
-            acc = acc2 = 0.0;
-          }
-        }
-
-        // row t + 2 (same parity as t)
-        fetch(t + 2, tpar);
-      }
-    }
-  }
-}
-
-// One launch covers every strip.  Units (a strip and a chunk of rows) are numbered
-// strip-fastest.  The first blocks take the strips that touch a wall (strip 0 and strips
-// efirst + 1, efirst + 2, ...) in chunks of Le rows; the others take strips first,
-// first + 1, ... in chunks of L rows, dealt out so that each XCD (the hardware deals
-// workgroups out round-robin over the 8 XCDs) runs one contiguous band of units.
-template <typename T, int NU, int LOG2N>
-__global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
-                                                  const T* __restrict__ ein,
-                                                  T* __restrict__ eout,
-                                                  const double* __restrict__ E,
-                                                  double* __restrict__ rc,
-                                                  double* __restrict__ psq, int zero_e,
-                                                  int L, int nchunk, int nstrip, int first,
-                                                  int Le, int nchunk_e, int nstrip_e, int efirst,
-                                                  int nblk_e) {
-  using S = Stream<T, NU, LOG2N>;
-  constexpr int WPB = kBlock / kWave;
-  __shared__ double sE[WPB][S::NR * S::NC];
-  const long long off = (long long)blockIdx.z * g.plane;
-  const long long coff = (long long)blockIdx.z * g.cplane;
-  const double* Eb = E + coff;
-  // the wave index, made visibly wave-uniform so that everything derived from it (strip,
-  // rows, the walk's row bookkeeping) lives in scalar registers and scalar branches
-  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
-  const int b = blockIdx.x;
-  if (b < nblk_e) {
-    const int u = b * WPB + w;
-    if (u >= nstrip_e * nchunk_e) return;
-    const int chunk = u / nstrip_e, sl = u - chunk * nstrip_e;
-    const int strip = sl == 0 ? 0 : efirst + sl;
-    cycle_walk<T, NU, LOG2N, true>(g, rhs + off, ein + off, eout + off, Eb, rc, psq, sE[w], coff,
-                                   zero_e, strip * S::VW - S::PX, chunk * Le, Le);
-    return;
-  }
-  int bi = b - nblk_e;
-  const int nbi = gridDim.x - nblk_e;
-  if ((nbi & 7) == 0) bi = (bi & 7) * (nbi >> 3) + (bi >> 3);
-  const int u = bi * WPB + w;
-  if (u >= nstrip * nchunk) return;
-  const int chunk = u / nstrip, sl = u - chunk * nstrip;
-  cycle_walk<T, NU, LOG2N, false>(g, rhs + off, ein + off, eout + off, Eb, rc, psq, sE[w], coff,
-                                  zero_e, (first + sl) * S::VW - S::PX, chunk * L, L);
-}
-
-// ----------------------------------------------------------------------------------------
 // Outer FP64 residual: r = h^2 (b - mean b) - A'x, written as T, with per-tile sums of r
 // (the first coarse right-hand side), sum of r^2, max |r| and, on request, the same two for
 // the right-hand side.  Same workgroup layout as k_restrict.
@@ -772,8 +326,9 @@ __global__ __launch_bounds__(kBlock) void k_sub_scalar(long long plane, int batc
 // Small batched FP64 GEMM for the separable coarse solve: C = op(A) op(B) [.* S].
 // A 16 x 16 output tile per workgroup (a 256 x 256 product spreads over 256 workgroups, one
 // per CU).  The whole K panel of A and B (up to 256 deep per pass) is loaded in one batch so
-// that all loads are in flight together; the 4 waves then each accumulate a quarter of K
-// (a lane owns a 2 x 2 block) and the quarters are added in wave order through LDS.
+// that all loads are in flight together; the 4 waves then each accumulate a quarter of K on
+// the matrix cores (V_MFMA_F64_16X16X4F64: a 16 x 4 by 4 x 16 product per instruction) and
+// the quarters are added in wave order through LDS.
 // ----------------------------------------------------------------------------------------
 constexpr int kGemmTile = 16, kGemmK = 256;
 
@@ -791,8 +346,12 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
   C += (long long)blockIdx.z * sC;
   const int m0 = blockIdx.y * kGemmTile, n0 = blockIdx.x * kGemmTile;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int tx = lane & 7, ty = lane >> 3;  // lane computes rows ty, ty+8 and cols tx, tx+8
-  double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+  // MFMA operands: lane l holds A[row l % 16][k l / 16] and B[k l / 16][col l % 16] of a
+  // 4-deep step; the 16 x 16 result lies in lane l's four values r as row l / 16 + 4 r,
+  // column l % 16
+  const int li = lane & 15, lk = lane >> 4;
+  typedef double Vec4d __attribute__((ext_vector_type(4)));
+  Vec4d acc = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += kGemmK) {
     const int kc = min(kGemmK, K - k0);
 #pragma unroll 4
@@ -815,23 +374,15 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
       }
     }
     __syncthreads();
-    const int q = (kc + 3) / 4;  // this wave's quarter of the panel
-    const int ka = wave * q, kb = min(kc, ka + q);
-#pragma unroll 8
-    for (int kk = ka; kk < kb; ++kk) {
-      const double a0 = As[kk][ty], a1 = As[kk][ty + 8];
-      const double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 8];
-      c00 = fma(a0, b0, c00);
-      c01 = fma(a0, b1, c01);
-      c10 = fma(a1, b0, c10);
-      c11 = fma(a1, b1, c11);
-    }
+    // this wave's quarter of the panel, in steps of 4 (rows past kc hold zeros)
+    const int q = (kc + 15) / 16 * 4;
+    const int ka = wave * q;
+    for (int kk = ka; kk < ka + q; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[kk + lk][li], Bs[kk + lk][li], acc, 0, 0, 0);
     __syncthreads();
   }
-  red[wave][ty][tx] = c00;
-  red[wave][ty][tx + 8] = c01;
-  red[wave][ty + 8][tx] = c10;
-  red[wave][ty + 8][tx + 8] = c11;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave][lk + 4 * r][li] = acc[r];
   __syncthreads();
   const int m = threadIdx.x / kGemmTile, nn = threadIdx.x & (kGemmTile - 1);
   const int gm = m0 + m, gn = n0 + nn;
@@ -1112,49 +663,6 @@ inline dim3 strip_grid(const Geo& g) {
   return dim3((g.nx + kWave - 1) / kWave, g.ncy, g.batch);
 }
 
-template <typename T, int NU, int LOG2N>
-hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
-                           double* rc, double* psq, int zero_e, hipStream_t s) {
-  using S = Stream<T, NU, LOG2N>;
-  constexpr int WPB = kBlock / kWave;
-  // wall strips walk half as far: their rows cost more (per-cell neighbour counts) and they
-  // run beside the others
-  const int L = S::L, Le = S::L / 2;
-  const int ns = (g.nx + S::VW - 1) / S::VW;
-  // strips whose columns all exist: every strip of a periodic axis, else strips 1 .. kmax
-  // with (k + 1) VW + PX <= nx; the others (strip 0 and those after kmax) touch a wall
-  int first = 0, ni = ns, ne = 0, efirst = 0;
-  if (!g.per_x) {
-    const int kmax = g.nx >= S::PX ? (g.nx - S::PX) / S::VW - 1 : -1;
-    first = 1;
-    ni = kmax > 0 ? kmax : 0;
-    efirst = ni;
-    ne = ns - ni;
-  }
-  const int nchunk = (g.ny + L - 1) / L, nchunk_e = (g.ny + Le - 1) / Le;
-  // wall blocks padded to a multiple of 8 so that the XCD of a block (its index mod 8) is
-  // known to the band mapping of the others
-  const int nblk_e = ne > 0 ? ((ne * nchunk_e + WPB - 1) / WPB + 7) / 8 * 8 : 0;
-  const int nblk_i = (ni * nchunk + WPB - 1) / WPB;
-  if (nblk_e + nblk_i == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N>), dim3(nblk_e + nblk_i, 1, g.batch), dim3(kBlock), 0, s,
-                     g, rhs, ein, eout, E, rc, psq, zero_e, L, nchunk, ni, first, Le, nchunk_e, ne,
-                     efirst, nblk_e);
-  return hipGetLastError();
-}
-
-template <typename T, int NU>
-hipError_t cycle_dispatch2(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
-                           double* rc, double* psq, int zero_e, hipStream_t s) {
-  switch (g.log2n) {
-    case 2: return cycle_dispatch3<T, NU, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 3: return cycle_dispatch3<T, NU, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 4: return cycle_dispatch3<T, NU, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 5: return cycle_dispatch3<T, NU, 5>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------- launchers
@@ -1192,21 +700,6 @@ hipError_t launch_prolong(const Geo& g, const double* E, T* e, int assign, hipSt
   dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.batch);
   hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, s, g, E, e, assign);
   return hipGetLastError();
-}
-
-int fused_max_nu() { return 4; }
-
-template <typename T>
-hipError_t launch_cycle_fused(const Geo& g, const T* rhs, const T* ein, T* eout,
-                              const double* E, double* rc, double* psq, int nu, int zero_e,
-                              hipStream_t s) {
-  switch (nu) {
-    case 1: return cycle_dispatch2<T, 1>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 2: return cycle_dispatch2<T, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 3: return cycle_dispatch2<T, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 4: return cycle_dispatch2<T, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 template <typename T>
@@ -1314,10 +807,6 @@ template hipError_t launch_restrict<float>(const Geo&, const float*, const float
 template hipError_t launch_restrict<double>(const Geo&, const double*, const double*, double*, double*, hipStream_t);
 template hipError_t launch_prolong<float>(const Geo&, const double*, float*, int, hipStream_t);
 template hipError_t launch_prolong<double>(const Geo&, const double*, double*, int, hipStream_t);
-template hipError_t launch_cycle_fused<float>(const Geo&, const float*, const float*, float*,
-                                              const double*, double*, double*, int, int, hipStream_t);
-template hipError_t launch_cycle_fused<double>(const Geo&, const double*, const double*, double*,
-                                               const double*, double*, double*, int, int, hipStream_t);
 template hipError_t launch_outer_residual<float>(const Geo&, const double*, const double*,
                                                  const double*, double, float*, double*, Partials,
                                                  hipStream_t);
