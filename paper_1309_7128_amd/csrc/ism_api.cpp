@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <utility>
 #include <vector>
@@ -25,6 +26,10 @@ namespace {
 
 // Slots of the per-grid device scalars; the array is slot-major, [kSlots][batch].
 enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, kSlots };
+
+// Adaptive convergence checks in flight at once (pinned read-back slots) and the number of
+// cycles the host enqueues past a check before it waits for that check's result.
+constexpr int kChecks = 8, kLag = 2;
 
 thread_local std::string g_create_error;
 
@@ -54,7 +59,9 @@ struct ism_ctx {
   double* fin = nullptr;   // chunk results of the two-stage reductions
   double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
   void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
-  double* h_scal = nullptr;   // pinned mirror of scal
+  double* h_scal = nullptr;   // pinned mirror of scal, then kChecks slots of B check norms
+  double* h_chk = nullptr;    // = h_scal + kSlots * batch
+  std::vector<hipEvent_t> chk_ev;  // one per check slot (created on first use)
   // ACM hierarchy (coarse_stencil == ISM_COARSE_ACM): per level l = 1..L-1 the agglomerated
   // right-hand side and two correction buffers, plus level-0 squared-residual partials
   void* acm_mem = nullptr;
@@ -309,12 +316,18 @@ struct Monitor {
   Monitor(ism_ctx* ctx, const std::vector<double>& tgt, bool is_mixed)
       : c(ctx), target(tgt), mixed(is_mixed) {}
 
-  // After k cycles of this inner solve: < 0 error, 1 stop (target met, stagnation or cycle
-  // cap), 0 continue (next check scheduled in `next`).
+  // After k cycles of this inner solve (the squared grid residual norms read back now):
+  // < 0 error, 1 stop (target met, stagnation or cycle cap), 0 continue (next check
+  // scheduled in `next`).
   int check(int k, int cycles) {
-    const int B = c->g.batch;
     int rcode = read_scalars(c);
     if (rcode) return rcode;
+    return evaluate(k, cycles, c->h_scal + size_t(ISQ) * c->g.batch);
+  }
+
+  // The same decision from squared norms sq[batch] taken after cycle k.
+  int evaluate(int k, int cycles, const double* sq) {
+    const int B = c->g.batch;
     auto now = std::chrono::steady_clock::now();
     const double dt = std::chrono::duration<double>(now - last_time).count() / std::max(1, k - last_cycle);
     last_time = now;
@@ -322,7 +335,7 @@ struct Monitor {
     Check ck{k, std::vector<double>(B)};
     bool done = true, finite = true;
     for (int b = 0; b < B; ++b) {
-      ck.res[b] = std::sqrt(c->h_scal[size_t(ISQ) * B + b]);
+      ck.res[b] = std::sqrt(sq[b]);
       finite = finite && std::isfinite(ck.res[b]);
       done = done && ck.res[b] <= target[b];
     }
@@ -373,22 +386,84 @@ struct Monitor {
 
 // Inner solve of A' e = rT from e = 0 in type T, until every grid's residual norm is below
 // its target, or the residual stagnates, or the cycle cap is reached.  rc holds R rT on entry.
+//
+// With a fixed check interval every check stops the stream and is evaluated at once.  With
+// adaptive checks the stream never waits on the host: a check's norms are copied to a pinned
+// slot behind an event and the host keeps enqueuing cycles, evaluating each check once its
+// event has completed (and waiting for it only after kLag more cycles).  A stop decision
+// then lands at most kLag cycles late; the cycles already enqueued only reduce the residual
+// further and are counted.  The squared-residual partials are formed only by the cycles a
+// check reads.
 template <typename T>
 int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** e_out) {
   T* cur = (T*)c->eA;
   T* spare = (T*)c->eB;
   const T* rhs = (const T*)c->rT;
+  const int B = c->g.batch;
   Monitor mon(c, target, sizeof(T) == 4);
+  if (c->cfg.check_every > 0) {
+    for (int k = 0;;) {
+      const bool due = k + 1 >= mon.next || cycles + 1 >= c->cfg.max_cycles;
+      int rcode = run_cycle<T>(c, rhs, &cur, &spare, c->rc, due ? c->p_sq : nullptr, k == 0);
+      if (rcode) return rcode;
+      ++k;
+      ++cycles;
+      if (!due) continue;
+      if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
+      rcode = mon.check(k, cycles);
+      if (rcode < 0) return rcode;
+      if (rcode == 1) break;
+    }
+    *e_out = cur;
+    return ISM_OK;
+  }
+  while (c->chk_ev.size() < size_t(kChecks)) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->chk_ev.push_back(e);
+  }
+  struct Pending {
+    int k, cycles, slot;
+  };
+  std::deque<Pending> pend;
+  int slot = 0, gap = 1, sched = 1;  // next check after cycle `sched`
   for (int k = 0;;) {
-    int rcode = run_cycle<T>(c, rhs, &cur, &spare, c->rc, c->p_sq, k == 0);
+    const bool due = k + 1 >= sched || cycles + 1 >= c->cfg.max_cycles;
+    int rcode = run_cycle<T>(c, rhs, &cur, &spare, c->rc, due ? c->p_sq : nullptr, k == 0);
     if (rcode) return rcode;
     ++k;
     ++cycles;
-    if (k < mon.next && cycles < c->cfg.max_cycles) continue;
-    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
-    rcode = mon.check(k, cycles);
-    if (rcode < 0) return rcode;
-    if (rcode == 1) break;
+    if (due) {
+      if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
+      HIPCHK(c, hipMemcpyAsync(c->h_chk + size_t(slot) * B, c->scal + size_t(ISQ) * B,
+                               sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipEventRecord(c->chk_ev[slot], c->stream));
+      pend.push_back({k, cycles, slot});
+      slot = (slot + 1) % kChecks;
+      sched = k + gap;  // provisional, until this check's own evaluation reschedules
+    }
+    bool stop = false;
+    while (!pend.empty()) {
+      const Pending p = pend.front();
+      const hipError_t q = hipEventQuery(c->chk_ev[p.slot]);
+      if (q == hipErrorNotReady) {
+        if (k - p.k < kLag && cycles < c->cfg.max_cycles) break;
+        HIPCHK(c, hipEventSynchronize(c->chk_ev[p.slot]));
+      } else if (q != hipSuccess) {
+        return set_err(c, ISM_ERR_HIP, std::string("check event: ") + hipGetErrorString(q));
+      }
+      pend.pop_front();
+      c->syncs++;
+      rcode = mon.evaluate(p.k, p.cycles, c->h_chk + size_t(p.slot) * B);
+      if (rcode < 0) return rcode;
+      if (rcode == 1) {
+        stop = true;
+        break;
+      }
+      gap = std::max(1, mon.next - p.k);
+      sched = std::max(mon.next, k + 1);
+    }
+    if (stop) break;
   }
   *e_out = cur;
   return ISM_OK;
@@ -639,7 +714,9 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   c->Vy = (double*)p; p += align(sizeof(double) * g.ncy * g.ncy);
   c->invLam = (double*)p;
 
-  he = hipHostMalloc((void**)&c->h_scal, sizeof(double) * kSlots * g.batch, hipHostMallocDefault);
+  he = hipHostMalloc((void**)&c->h_scal, sizeof(double) * (kSlots + kChecks) * g.batch,
+                     hipHostMallocDefault);
+  c->h_chk = c->h_scal + size_t(kSlots) * g.batch;
   if (he != hipSuccess) {
     (void)hipFree(c->block);
     delete c;
@@ -709,6 +786,7 @@ int ism_destroy(ism_handle c) {
   if (!c) return ISM_OK;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->chk_ev) (void)hipEventDestroy(e);
   if (c->stage_tmp) (void)hipFree(c->stage_tmp);
   if (c->acm_mem) (void)hipFree(c->acm_mem);
   if (c->h_scal) (void)hipHostFree(c->h_scal);

@@ -387,24 +387,28 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
         if (o >= y0) {
           const int so = (ph - H + P) % P, sb = (ph - H - 1 + P) % P, sa = (ph - H + 1 + P) % P;
           const bool hs = g.per_y || o > 0, hn = g.per_y || o < g.ny - 1;
+          double d[CPL];
 #pragma unroll
           for (int p = 0; p < CPL; ++p) {
             const T c = e[so][p];
             const T w = p > 0 ? e[so][p - 1] : lane_shift<kDppFromLeft>(e[so][CPL - 1]);
             const T ea = p < CPL - 1 ? e[so][p + 1] : lane_shift<kDppFromRight>(e[so][0]);
             const bool hw = !EDGE || cx + p > 0, he = !EDGE || cx + p < g.nx - 1;
-            const T res = r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn);
-            const double d = double(res);
-            acc += d;
-            acc2 += d * d;
+            d[p] = double(r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn));
+            acc += d[p];
+          }
+          if (psq) {  // squared sums only when a convergence check reads them
+#pragma unroll
+            for (int p = 0; p < CPL; ++p) acc2 += d[p] * d[p];
           }
           if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
           if (((o - y0) & (N - 1)) == N - 1) {
             double a = acc, q = acc2;
 #pragma unroll
-            for (int k = 1; k < G; k <<= 1) {
-              a += __shfl_down(a, k, kWave);
-              q += __shfl_down(q, k, kWave);
+            for (int k = 1; k < G; k <<= 1) a += __shfl_down(a, k, kWave);
+            if (psq) {
+#pragma unroll
+              for (int k = 1; k < G; k <<= 1) q += __shfl_down(q, k, kWave);
             }
             if (lane_out && ((lane - PX / CPL) & (G - 1)) == 0) {
               const long long oc = coff + (long long)(o >> LOG2N) * g.ncx + (cu >> LOG2N);

@@ -352,26 +352,35 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
   const int li = lane & 15, lk = lane >> 4;
   typedef double Vec4d __attribute__((ext_vector_type(4)));
   Vec4d acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int PER = kGemmTile * kGemmK / kBlock;  // panel elements per thread and operand
   for (int k0 = 0; k0 < K; k0 += kGemmK) {
     const int kc = min(kGemmK, K - k0);
-#pragma unroll 4
-    for (int t = threadIdx.x; t < kGemmTile * kGemmK; t += kBlock) {
-      {  // A panel, coalesced along the contiguous index of the stored matrix
+    // every load of both panels is issued before any is stored, so that one memory latency
+    // covers the whole panel; loads are coalesced along the contiguous index of the matrix
+    double ra[PER], rb[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * kBlock;
+      {
         const int m = TA ? (t & (kGemmTile - 1)) : (t / kGemmK);
         const int k = TA ? (t / kGemmTile) : (t & (kGemmK - 1));
         const int gm = m0 + m, gk = k0 + k;
-        double v = 0.0;
-        if (gm < M && k < kc) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
-        As[k][m] = v;
+        ra[i] = (gm < M && k < kc) ? (TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk])
+                                   : 0.0;
       }
       {
         const int nn = TB ? (t / kGemmK) : (t & (kGemmTile - 1));
         const int k = TB ? (t & (kGemmK - 1)) : (t / kGemmTile);
         const int gk = k0 + k, gn = n0 + nn;
-        double v = 0.0;
-        if (k < kc && gn < N) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
-        Bs[k][nn] = v;
+        rb[i] = (k < kc && gn < N) ? (TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn])
+                                   : 0.0;
       }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * kBlock;
+      As[TA ? (t / kGemmTile) : (t & (kGemmK - 1))][TA ? (t & (kGemmTile - 1)) : (t / kGemmK)] = ra[i];
+      Bs[TB ? (t & (kGemmK - 1)) : (t / kGemmTile)][TB ? (t / kGemmK) : (t & (kGemmTile - 1))] = rb[i];
     }
     __syncthreads();
     // this wave's quarter of the panel, in steps of 4 (rows past kc hold zeros)
