@@ -24,6 +24,33 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 CYCLE_BYTES = {"mixed": (12, 8), "fp64": (24, 16)}  # per cell: (e read + rhs read + e write, first cycle)
+# hardware-counter record of the fused cycle's HBM traffic (rocprofv3 --pmc, calibrated with
+# a plain copy); used while the kernel sources it was taken on are unchanged
+PROFILE_RECORD = os.path.join(ROOT, "profiles", "k_cycle_cavity8192_mixed.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_7128_amd", "csrc", f)
+                  for f in ("ism_cycle.h", "ism_device.h")]
+
+
+def measured_traffic(workload, nu):
+    """HBM bytes per cycle launch from the counter record, or None if there is no record for
+    this workload and sweep count or the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(PROFILE_RECORD).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(f, "rb").read())
+    except OSError:
+        return None
+    for m in re.finditer(r"^traffic-record: (.*)$", text, re.M):
+        kv = dict(item.split("=", 1) for item in m.group(1).split())
+        if kv.get("workload") == workload and int(kv.get("nu", -1)) == nu and \
+                kv.get("source_sha256") == h.hexdigest():
+            return int((float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                        float(kv["write_kib"]) * float(kv["write_scale"])) * 1024)
+    return None
 
 
 def parse():
@@ -135,7 +162,8 @@ def main():
         avg_s = prof["cycle"][0] * 1e-3 / launches
         achieved = alg / launches / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(w.name, args.nu),
                     "kernel": f"k_cycle<{'float' if w.precision == 'mixed' else 'double'}, {args.nu}, "
                               f"{w.coarsen.bit_length() - 1}>",
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
@@ -241,17 +269,19 @@ def cpu_baseline(w, b_dev, gpu_cycles, gpu_outer, nu):
         rT = r.astype(ft)
         Rc = O.restrict_sum(r, n)
         e = np.zeros_like(rT)
+        n_cyc = 3
         t0 = time.perf_counter()
-        E = cs.solve(Rc)
-        e = (e.astype(np.float64) + O.prolong_bilinear(E, n, bx, by)).astype(ft)
-        e = O.red_black_gs(e, rT, bx, by, sweeps=nu)
-        res = rT - O.laplacian(e, bx, by)
-        Rc = O.restrict_sum(res.astype(np.float64), n)
-        t_cycle = time.perf_counter() - t0
+        for _ in range(n_cyc):
+            E = cs.solve(Rc)
+            e = (e.astype(np.float64) + O.prolong_bilinear(E, n, bx, by)).astype(ft)
+            e = O.red_black_gs(e, rT, bx, by, sweeps=nu)
+            res = rT - O.laplacian(e, bx, by)
+            Rc = O.restrict_sum(res.astype(np.float64), n)
+        t_cycle = (time.perf_counter() - t0) / n_cyc
     total = (gpu_cycles * t_cycle + (gpu_outer + 1) * t_outer) * w.batch
     return {"value": round(w.nx * w.ny * w.batch / total / 1e6, 5), "unit": "Mdof/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one inner cycle ({t_cycle:.1f} s) and one outer residual ({t_outer:.1f} s) "
+            "sample": f"three inner cycles ({t_cycle:.1f} s each) and one outer residual ({t_outer:.1f} s) "
                       f"of the oracle's ISM iteration on grid 0 of the same input, single thread, "
                       f"extrapolated to the GPU solve's {gpu_cycles:g} cycles and {gpu_outer:g} outer "
                       f"steps per solve and grid; oracle coarse factorization ({t_setup:.1f} s) "
