@@ -3,6 +3,8 @@
 // ism_cycle_f64.hip instantiate them for the two fine-grid types.
 #pragma once
 
+#include <algorithm>
+
 #include "ism_device.h"
 
 namespace ism {
@@ -430,9 +432,10 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 }
 
 // One launch covers every strip.  Units (a strip and a chunk of rows) are numbered
-// strip-fastest.  The first nblk_e workgroups take the strips that touch a wall (strip 0 and
-// strips efirst + 1, efirst + 2, ...) in chunks of Le rows; the others take strips first,
-// first + 1, ... in chunks of L rows, dealt out so that each XCD (the hardware deals
+// strip-fastest.  A strip's nb bands of n rows are split into C chunks of floor or ceil(nb / C)
+// bands (chunk c starts at band c nb / C).  The first nblk_e workgroups take the strips that
+// touch a wall (strip 0 and strips efirst + 1, efirst + 2, ...) in Ce chunks; the others take
+// strips first, first + 1, ... in Ci chunks, dealt out so that each XCD (the hardware deals
 // workgroups out round-robin over the 8 XCDs) runs one contiguous band of units.
 template <typename T, int NU, int LOG2N>
 __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
@@ -441,9 +444,8 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
                                                   const double* __restrict__ E,
                                                   double* __restrict__ rc,
                                                   double* __restrict__ psq, int zero_e,
-                                                  int L, int nchunk, int nstrip, int first,
-                                                  int Le, int nchunk_e, int nstrip_e, int efirst,
-                                                  int nblk_e) {
+                                                  int nb, int Ci, int nstrip, int first, int Ce,
+                                                  int nstrip_e, int efirst, int nblk_e) {
   using S = Stream<T, NU, LOG2N>;
   constexpr int WPB = kBlock / kWave;
   __shared__ double sE[WPB][S::NR * S::NC];
@@ -457,23 +459,25 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   const int b = blockIdx.x;
   if (b < nblk_e) {
     const int u = b * WPB + w;
-    if (u >= nstrip_e * nchunk_e) return;
+    if (u >= nstrip_e * Ce) return;
     const int chunk = u / nstrip_e, sl = u - chunk * nstrip_e;
     const int strip = sl == 0 ? 0 : efirst + sl;
+    const int b0 = chunk * nb / Ce, b1 = (chunk + 1) * nb / Ce;
     cycle_walk<T, NU, LOG2N, true>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq, sE[w],
                                    sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
-                                   chunk * Le, Le);
+                                   b0 * S::N, (b1 - b0) * S::N);
     return;
   }
   int bi = b - nblk_e;
   const int nbi = gridDim.x - nblk_e;
   if ((nbi & 7) == 0) bi = (bi & 7) * (nbi >> 3) + (bi >> 3);
   const int u = bi * WPB + w;
-  if (u >= nstrip * nchunk) return;
+  if (u >= nstrip * Ci) return;
   const int chunk = u / nstrip, sl = u - chunk * nstrip;
+  const int b0 = chunk * nb / Ci, b1 = (chunk + 1) * nb / Ci;
   cycle_walk<T, NU, LOG2N, false>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq, sE[w],
                                   sX[w], sR[w], coff, zero_e, (first + sl) * S::VW - S::PX,
-                                  chunk * L, L);
+                                  b0 * S::N, (b1 - b0) * S::N);
 }
 
 template <typename T, int NU, int LOG2N>
@@ -481,9 +485,7 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
                            double* rc, double* psq, int zero_e, hipStream_t s) {
   using S = Stream<T, NU, LOG2N>;
   constexpr int WPB = kBlock / kWave;
-  // wall strips walk half as far: their rows cost more (per-cell neighbour counts) and they
-  // run beside the others
-  const int L = S::L, Le = S::L / 2;
+  auto kernel = k_cycle<T, NU, LOG2N>;
   const int ns = (g.nx + S::VW - 1) / S::VW;
   // strips whose columns all exist: every strip of a periodic axis, else strips 1 .. kmax
   // with (k + 1) VW + PX <= nx; the others (strip 0 and those after kmax) touch a wall
@@ -495,15 +497,19 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
     efirst = ni;
     ne = ns - ni;
   }
-  const int nchunk = (g.ny + L - 1) / L, nchunk_e = (g.ny + Le - 1) / Le;
+  // Chunks of S::L rows (the shortest that keep the pipeline's warm-up rows a small share;
+  // measured faster at 8192^2 than both shorter chunks that fill every SIMD with three waves
+  // and longer ones); wall strips, whose rows cost more, walk half as far.
+  const int nb = g.ny / S::N;
+  const int Ci = (nb * S::N + S::L - 1) / S::L;
+  const int Ce = std::min(2 * Ci, nb);
   // wall blocks padded to a multiple of 8 so that the XCD of a block (its index mod 8) is
   // known to the band mapping of the others
-  const int nblk_e = ne > 0 ? ((ne * nchunk_e + WPB - 1) / WPB + 7) / 8 * 8 : 0;
-  const int nblk_i = (ni * nchunk + WPB - 1) / WPB;
+  const int nblk_e = ne > 0 ? ((ne * Ce + WPB - 1) / WPB + 7) / 8 * 8 : 0;
+  const int nblk_i = (ni * Ci + WPB - 1) / WPB;
   if (nblk_e + nblk_i == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_cycle<T, NU, LOG2N>), dim3(nblk_e + nblk_i, 1, g.batch), dim3(kBlock), 0, s,
-                     g, rhs, ein, eout, E, rc, psq, zero_e, L, nchunk, ni, first, Le, nchunk_e, ne,
-                     efirst, nblk_e);
+  hipLaunchKernelGGL(kernel, dim3(nblk_e + nblk_i, 1, g.batch), dim3(kBlock), 0, s, g, rhs, ein,
+                     eout, E, rc, psq, zero_e, nb, Ci, ni, first, Ce, ne, efirst, nblk_e);
   return hipGetLastError();
 }
 
