@@ -15,10 +15,13 @@ Conventions
   0-based, i along x.  Batches are handled by the caller, one grid at a time.
 * ``laplacian`` is A' = h^2 A, the 5-point cell-centred Laplacian in difference form,
   (A'p)_C = (p_W - p_C) + (p_E - p_C) + (p_S - p_C) + (p_N - p_C), summed in that order.
-  A wall neighbour (the "symmetric" boundary condition of Sec. 4.1, read as a homogeneous
-  Neumann wall) contributes no term; a periodic axis wraps.
-* The pressure equation of Eq. 4 is solved as A x = b~ with b~ = b - mean(b); the solution
-  returned is the zero-mean one (the constants span the null space on these grids).
+  A periodic axis wraps.  Each face of a non-periodic axis is a wall of one of the two
+  kinds Sec. 4.1 names besides periodic: "symmetric" (read as a homogeneous Neumann wall:
+  the neighbour behind it contributes no term) or Dirichlet (zero pressure on the wall,
+  read as the mirror ghost p_ghost = -p_C, so its term is (-p_C) - p_C).
+* The pressure equation of Eq. 4 is solved as A x = b~.  Without a Dirichlet face the
+  constants span the null space: then b~ = b - mean(b) and the solution returned is the
+  zero-mean one.  With a Dirichlet face A is nonsingular and b~ = b.
 * Coarse grid: tiles of n x n fine cells (Sec. 4: one work-group per coarse cell), coarse
   cell (J, I) covers rows nJ..nJ+n-1 and columns nI..nI+n-1; its centre is the tile centre
   (Fig. 1).
@@ -36,6 +39,23 @@ import scipy.sparse.linalg
 
 NEUMANN = "neumann"
 PERIODIC = "periodic"
+DIRICHLET = "dirichlet"                  # both faces of the axis
+NEUMANN_DIRICHLET = "neumann-dirichlet"  # low face (west / south) Neumann, high face Dirichlet
+DIRICHLET_NEUMANN = "dirichlet-neumann"  # low face Dirichlet, high face Neumann
+
+_FACES = {NEUMANN: ("N", "N"), DIRICHLET: ("D", "D"), NEUMANN_DIRICHLET: ("N", "D"),
+          DIRICHLET_NEUMANN: ("D", "N"), PERIODIC: None}
+
+
+def faces(bc):
+    """(low face, high face) of an axis, each "N" (no-flux wall) or "D" (zero-pressure
+    wall); None for a periodic axis."""
+    return _FACES[bc]
+
+
+def singular(bc_x, bc_y):
+    """True when A has the constants in its null space: no face is a Dirichlet wall."""
+    return all(f is None or "D" not in f for f in (faces(bc_x), faces(bc_y)))
 
 
 # --------------------------------------------------------------------------------------
@@ -43,65 +63,63 @@ PERIODIC = "periodic"
 # --------------------------------------------------------------------------------------
 
 def _neighbours(p, bc_x, bc_y):
-    """Values of the W, E, S, N neighbour of every cell and whether that neighbour exists.
+    """Values of the W, E, S, N neighbour of every cell, whether that neighbour exists, and
+    whether the face towards it is a Dirichlet wall.
 
     A missing neighbour (behind a wall) has value 0 and ``present`` False."""
     zero = np.zeros((), dtype=p.dtype)
     out = {}
-    if bc_x == PERIODIC:
-        allp = np.ones(p.shape, dtype=bool)
-        out["W"] = (np.roll(p, 1, axis=1), allp)
-        out["E"] = (np.roll(p, -1, axis=1), allp)
-    else:
-        w = np.full_like(p, zero)
-        w[:, 1:] = p[:, :-1]
-        pw = np.zeros(p.shape, dtype=bool)
-        pw[:, 1:] = True
-        e = np.full_like(p, zero)
-        e[:, :-1] = p[:, 1:]
-        pe = np.zeros(p.shape, dtype=bool)
-        pe[:, :-1] = True
-        out["W"] = (w, pw)
-        out["E"] = (e, pe)
-    if bc_y == PERIODIC:
-        allp = np.ones(p.shape, dtype=bool)
-        out["S"] = (np.roll(p, 1, axis=0), allp)
-        out["N"] = (np.roll(p, -1, axis=0), allp)
-    else:
-        s = np.full_like(p, zero)
-        s[1:, :] = p[:-1, :]
-        ps = np.zeros(p.shape, dtype=bool)
-        ps[1:, :] = True
-        nn = np.full_like(p, zero)
-        nn[:-1, :] = p[1:, :]
-        pn = np.zeros(p.shape, dtype=bool)
-        pn[:-1, :] = True
-        out["S"] = (s, ps)
-        out["N"] = (nn, pn)
+    for axis, bc, (lo_key, hi_key) in ((1, bc_x, ("W", "E")), (0, bc_y, ("S", "N"))):
+        f = faces(bc)
+        if f is None:
+            allp = np.ones(p.shape, dtype=bool)
+            none = np.zeros(p.shape, dtype=bool)
+            out[lo_key] = (np.roll(p, 1, axis=axis), allp, none)
+            out[hi_key] = (np.roll(p, -1, axis=axis), allp, none)
+            continue
+        lo = np.full_like(p, zero)
+        hi = np.full_like(p, zero)
+        plo = np.zeros(p.shape, dtype=bool)
+        phi = np.zeros(p.shape, dtype=bool)
+        dlo = np.zeros(p.shape, dtype=bool)
+        dhi = np.zeros(p.shape, dtype=bool)
+        if axis == 1:
+            lo[:, 1:], plo[:, 1:], dlo[:, 0] = p[:, :-1], True, f[0] == "D"
+            hi[:, :-1], phi[:, :-1], dhi[:, -1] = p[:, 1:], True, f[1] == "D"
+        else:
+            lo[1:, :], plo[1:, :], dlo[0, :] = p[:-1, :], True, f[0] == "D"
+            hi[:-1, :], phi[:-1, :], dhi[-1, :] = p[1:, :], True, f[1] == "D"
+        out[lo_key] = (lo, plo, dlo)
+        out[hi_key] = (hi, phi, dhi)
     return out
 
 
 def laplacian(p, bc_x=NEUMANN, bc_y=NEUMANN):
-    """A'p: sum over existing neighbours of (p_nb - p_C), in the order W, E, S, N.
+    """A'p: the sum of (p_nb - p_C) over the four faces, in the order W, E, S, N.
 
     Sec. 2.3 (five-point Laplacian) and Sec. 3.3 (its finite-volume reading: a sum of face
-    fluxes; a wall face carries none).  Pinned by the closed-form eigenpairs of the
-    discrete Laplacian and by an independently assembled dense matrix."""
+    fluxes).  A Neumann wall face carries no flux; a Dirichlet wall face carries
+    (-p_C) - p_C, its ghost being the mirror -p_C (Sec. 4.1 lists Dirichlet walls).  Pinned
+    by the closed-form eigenpairs of the discrete Laplacian and by an independently
+    assembled dense matrix."""
     nb = _neighbours(p, bc_x, bc_y)
     zero = np.zeros((), dtype=p.dtype)
-    d = {k: np.where(pres, val - p, zero) for k, (val, pres) in nb.items()}
+    d = {k: np.where(pres, val - p, np.where(dw, (-p) - p, zero))
+         for k, (val, pres, dw) in nb.items()}
     return ((d["W"] + d["E"]) + d["S"]) + d["N"]
 
 
 def neighbour_count(nx, ny, bc_x=NEUMANN, bc_y=NEUMANN):
-    """m_C, the number of existing neighbours of each cell (the magnitude of A's diagonal)."""
+    """m_C, the magnitude of A's diagonal: 4, less one for each Neumann wall face of the
+    cell, plus one for each Dirichlet wall face (its ghost -p_C adds a second -p_C)."""
     m = np.full((ny, nx), 4, dtype=np.int64)
-    if bc_x != PERIODIC:
-        m[:, 0] -= 1
-        m[:, -1] -= 1
-    if bc_y != PERIODIC:
-        m[0, :] -= 1
-        m[-1, :] -= 1
+    for bc, lo, hi in ((bc_x, (slice(None), 0), (slice(None), -1)),
+                       (bc_y, (0, slice(None)), (-1, slice(None)))):
+        f = faces(bc)
+        if f is None:
+            continue
+        m[lo] += 1 if f[0] == "D" else -1
+        m[hi] += 1 if f[1] == "D" else -1
     return m
 
 
@@ -110,7 +128,8 @@ def red_black_gs(p, rhs, bc_x=NEUMANN, bc_y=NEUMANN, sweeps=1):
 
     A sweep updates the red cells ((i + j) even) and then the black cells.  A cell is set
     so that its own equation holds: p_C = (sum of existing neighbour values - rhs_C) / m_C,
-    with the neighbour values summed in the order W, E, S, N and the division taken as a
+    with the neighbour values summed in the order W, E, S, N (a neighbour behind a wall
+    counting 0), m_C the diagonal of ``neighbour_count`` and the division taken as a
     product with 1/m_C rounded to the working precision.  No over-relaxation factor is
     given in the paper; this is plain Gauss-Seidel.  Pinned by a cell-by-cell sequential
     sweep in red-black order on tiny grids and by the fixed point being the exact
@@ -149,20 +168,32 @@ def div(u, v, h, bc_x=NEUMANN):
 
 
 def grad(p, h, bc_x=NEUMANN, bc_y=NEUMANN):
-    """G p on the faces: (p_C - p_{west or south neighbour}) / h; zero on wall faces.
+    """G p on the faces: (p_C - p_{west or south neighbour}) / h.
 
-    A wall face carries no pressure gradient, which is what makes D G equal to the
-    cell-centred Laplacian with homogeneous Neumann walls.  Pinned by D G = A."""
+    A Neumann wall face carries no pressure gradient; on a Dirichlet wall face the missing
+    neighbour is the mirror ghost -p, so the face gets (p - (-p)) / h on the west or south
+    wall and ((-p) - p) / h on the east or north wall.  This is what makes D G equal to
+    the cell-centred Laplacian with the same walls.  Pinned by D G = A."""
     ny, nx = p.shape
     if bc_x == PERIODIC:
         gu = (p - np.roll(p, 1, axis=1)) / h
     else:
+        fx = faces(bc_x)
         gu = np.zeros((ny, nx + 1), dtype=p.dtype)
         gu[:, 1:nx] = (p[:, 1:] - p[:, :-1]) / h
+        if fx[0] == "D":
+            gu[:, 0] = (p[:, 0] - (-p[:, 0])) / h
+        if fx[1] == "D":
+            gu[:, nx] = ((-p[:, -1]) - p[:, -1]) / h
     gv = np.zeros((ny + 1, nx), dtype=p.dtype)
     if bc_y == PERIODIC:
         raise NotImplementedError("v faces are stored with ny+1 rows; periodic y is not used")
+    fy = faces(bc_y)
     gv[1:ny, :] = (p[1:, :] - p[:-1, :]) / h
+    if fy[0] == "D":
+        gv[0, :] = (p[0, :] - (-p[0, :])) / h
+    if fy[1] == "D":
+        gv[ny, :] = ((-p[-1, :]) - p[-1, :]) / h
     return gu, gv
 
 
@@ -185,18 +216,29 @@ def div_adjoint(lam, h, bc_x=NEUMANN):
     return gu, gv
 
 
-def grad_adjoint(gu, gv, h, bc_x=NEUMANN):
-    """G^T w, the transpose of ``grad``.  Pinned by <G p, w> = <p, G^T w>."""
+def grad_adjoint(gu, gv, h, bc_x=NEUMANN, bc_y=NEUMANN):
+    """G^T w, the transpose of ``grad`` (a Dirichlet wall face adds twice its value to the
+    cell next to it, with the sign of its gradient).  Pinned by <G p, w> = <p, G^T w>."""
     ny = gv.shape[0] - 1
     nx = gv.shape[1]
     out = np.zeros((ny, nx), dtype=gv.dtype)
     if bc_x == PERIODIC:
         out += gu - np.roll(gu, -1, axis=1)
     else:
+        fx = faces(bc_x)
         out[:, 1:] += gu[:, 1:nx]
         out[:, :-1] -= gu[:, 1:nx]
+        if fx[0] == "D":
+            out[:, 0] += 2.0 * gu[:, 0]
+        if fx[1] == "D":
+            out[:, -1] -= 2.0 * gu[:, nx]
+    fy = faces(bc_y)
     out[1:, :] += gv[1:ny, :]
     out[:-1, :] -= gv[1:ny, :]
+    if fy[0] == "D":
+        out[0, :] += 2.0 * gv[0, :]
+    if fy[1] == "D":
+        out[-1, :] -= 2.0 * gv[ny, :]
     return out / h
 
 
@@ -215,24 +257,34 @@ def restrict_sum(r, n):
 
 
 def _interp_axis(nf, n, bc):
-    """For every fine index along one axis: lower and upper coarse centre and the weight
-    of the upper one (Eq. 5 coordinates divided by the rectangle size).
+    """For every fine index along one axis: lower and upper coarse centre, the weight of
+    the upper one (Eq. 5 coordinates divided by the rectangle size) and the sign each
+    centre value is taken with.
 
     The coarse centre I sits at fine coordinate n (I + 1/2); fine centre i sits at i + 1/2.
-    Between a wall and the first centre the rule is constant extrapolation (the interpolant
-    is held at the value of the nearest centre), so the rectangle is clamped."""
+    Between a wall and the first centre the rectangle reaches a ghost centre, the mirror
+    image of the first one: an equal value behind a Neumann wall (the interpolant is held
+    constant, zero normal slope) and the negated value behind a Dirichlet wall (the
+    interpolant falls linearly to zero on the wall)."""
     nc = nf // n
     pos = (np.arange(nf) + 0.5) / n - 0.5
     lo = np.floor(pos).astype(np.int64)
     t = pos - lo
     hi = lo + 1
+    s_lo = np.ones(nf)
+    s_hi = np.ones(nf)
     if bc == PERIODIC:
         lo %= nc
         hi %= nc
     else:
+        f = faces(bc)
+        if f[0] == "D":
+            s_lo[lo < 0] = -1.0
+        if f[1] == "D":
+            s_hi[hi > nc - 1] = -1.0
         lo = np.clip(lo, 0, nc - 1)
         hi = np.clip(hi, 0, nc - 1)
-    return lo, hi, t
+    return lo, hi, t, s_lo, s_hi
 
 
 def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN):
@@ -246,11 +298,12 @@ def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN):
     exactness on constants and bilinear fields, dyadic weights and the coarse-stencil
     identities."""
     ncy, ncx = E.shape
-    ilo, ihi, tx = _interp_axis(ncx * n, n, bc_x)
-    jlo, jhi, ty = _interp_axis(ncy * n, n, bc_y)
+    ilo, ihi, tx, sxl, sxh = _interp_axis(ncx * n, n, bc_x)
+    jlo, jhi, ty, syl, syh = _interp_axis(ncy * n, n, bc_y)
     E = np.asarray(E, dtype=np.float64)
-    ex = E[:, ilo] * (1 - tx)[None, :] + E[:, ihi] * tx[None, :]  # along x, every coarse row
-    return ex[jlo, :] * (1 - ty)[:, None] + ex[jhi, :] * ty[:, None]
+    # along x, every coarse row (a ghost centre's value negated exactly by its sign)
+    ex = (E[:, ilo] * sxl[None, :]) * (1 - tx)[None, :] + (E[:, ihi] * sxh[None, :]) * tx[None, :]
+    return (ex[jlo, :] * syl[:, None]) * (1 - ty)[:, None] + (ex[jhi, :] * syh[:, None]) * ty[:, None]
 
 
 def inject_constant(E, n):
@@ -264,20 +317,37 @@ def inject_constant(E, n):
 # --------------------------------------------------------------------------------------
 
 def _fold(C, ncx, ncy, bc_x, bc_y):
-    """Move the coefficient of an off-grid neighbour of a Neumann axis onto the unknown the
-    clamped interpolation actually used (the cell itself at a wall)."""
+    """Move the coefficient of an off-grid (ghost) neighbour behind a wall onto the cell
+    whose mirror image it is: added for a Neumann wall (equal ghost), subtracted for a
+    Dirichlet wall (negated ghost)."""
     C = C.copy()
-    if bc_x != PERIODIC:
-        C[:, 0, :, 1] += C[:, 0, :, 0]
+    fx, fy = faces(bc_x), faces(bc_y)
+    if fx is not None:
+        sw, se = (-1.0 if f == "D" else 1.0 for f in fx)
+        C[:, 0, :, 1] += sw * C[:, 0, :, 0]
         C[:, 0, :, 0] = 0.0
-        C[:, -1, :, 1] += C[:, -1, :, 2]
+        C[:, -1, :, 1] += se * C[:, -1, :, 2]
         C[:, -1, :, 2] = 0.0
-    if bc_y != PERIODIC:
-        C[0, :, 1, :] += C[0, :, 0, :]
+    if fy is not None:
+        ss, sn = (-1.0 if f == "D" else 1.0 for f in fy)
+        C[0, :, 1, :] += ss * C[0, :, 0, :]
         C[0, :, 0, :] = 0.0
-        C[-1, :, 1, :] += C[-1, :, 2, :]
+        C[-1, :, 1, :] += sn * C[-1, :, 2, :]
         C[-1, :, 2, :] = 0.0
     return C
+
+
+def _open_faces(ncx, ncy, bc_x, bc_y):
+    """Masks over the coarse cells: which of the E, W, N, S faces carry a flux (interior
+    faces, periodic wraps and Dirichlet walls; a Neumann wall carries none)."""
+    J, I = np.indices((ncy, ncx))
+    fx, fy = faces(bc_x), faces(bc_y)
+    per_x, per_y = fx is None, fy is None
+    east = (I < ncx - 1) | per_x | (not per_x and fx[1] == "D")
+    west = (I > 0) | per_x | (not per_x and fx[0] == "D")
+    north = (J < ncy - 1) | per_y | (not per_y and fy[1] == "D")
+    south = (J > 0) | per_y | (not per_y and fy[0] == "D")
+    return east, west, north, south
 
 
 def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
@@ -289,7 +359,10 @@ def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
     On a face between centres I and I+1 in x, Eq. 6 gives for the fine row whose centre has
     scaled offset y from the lower centre Q11:
         dp/dx = ((Q21 - Q11)(1 - y) + (Q22 - Q12) y) / n      (in fine-cell units),
-    and Eq. 7 the same with x and y exchanged.  A wall face carries no flux.
+    and Eq. 7 the same with x and y exchanged.  A Neumann wall face carries no flux.  A
+    Dirichlet wall face carries the Eq. 6 flux towards the negated ghost centre: the
+    interpolant is linear through zero on the wall, so that flux equals the fine one,
+    (-p) - p of the wall cell.
 
     Returns C with shape (ncy, ncx, 3, 3): C[J, I, dj+1, di+1] multiplies the unknown at
     (J+dj, I+di) (wrapped on a periodic axis).  Pinned by the brute-force product R A' P,
@@ -303,10 +376,7 @@ def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
         # val is an array over (J, I) or a scalar; the stencil entry gets it where mask holds
         C[:, :, dj + 1, di + 1] += np.where(mask, val, 0.0)
 
-    east_open = (I < ncx - 1) | (bc_x == PERIODIC)
-    west_open = (I > 0) | (bc_x == PERIODIC)
-    north_open = (J < ncy - 1) | (bc_y == PERIODIC)
-    south_open = (J > 0) | (bc_y == PERIODIC)
+    east_open, west_open, north_open, south_open = _open_faces(ncx, ncy, bc_x, bc_y)
     for k in range(n):
         # fine row nJ + k: lower interpolation centre J-1 (k < n/2) or J (k >= n/2)
         lo_off = -1 if k < half else 0
@@ -337,18 +407,13 @@ def coarse_stencil_acm(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
     times the 5-point stencil (Sec. 4: summing fine equations gives a 5-point stencil).
     Pinned by the brute-force product R A' P0."""
     C = np.zeros((ncy, ncx, 3, 3))
-    J, I = np.indices((ncy, ncx))
-    opens = {
-        (0, 1): (I < ncx - 1) | (bc_x == PERIODIC),
-        (0, -1): (I > 0) | (bc_x == PERIODIC),
-        (1, 0): (J < ncy - 1) | (bc_y == PERIODIC),
-        (-1, 0): (J > 0) | (bc_y == PERIODIC),
-    }
+    east, west, north, south = _open_faces(ncx, ncy, bc_x, bc_y)
+    opens = {(0, 1): east, (0, -1): west, (1, 0): north, (-1, 0): south}
     for (dj, di), mask in opens.items():
         for _ in range(n):  # one flux per fine face on the coarse face
             C[:, :, dj + 1, di + 1] += np.where(mask, 1.0, 0.0)
             C[:, :, 1, 1] -= np.where(mask, 1.0, 0.0)
-    return C
+    return _fold(C, ncx, ncy, bc_x, bc_y)
 
 
 def coarse_stencil_gmg5(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
@@ -383,25 +448,37 @@ def coarse_matrix(C, bc_x=NEUMANN, bc_y=NEUMANN):
 
 
 class CoarseSolver:
-    """Exact zero-mean solve of A_c E = R_c (the limit of the paper's coarse iterations to a
+    """Exact solve of A_c E = R_c (the limit of the paper's coarse iterations to a
     vanishing tolerance; a direct solve on the coarsest grid, Sec. 3.2).
 
-    The singular system is bordered with the constraint sum(E) = 0 and factorized once by
-    sparse LU (a library primitive).  The bordered solve returns the E that satisfies
-    A_c E = R_c - mean(R_c), the same projection as dropping the constant mode.  The
+    When the constants span the null space of A_c (no Dirichlet wall; detected from the
+    row sums, or given), the system is bordered with the constraint sum(E) = 0, and the
+    bordered solve returns the zero-mean E that satisfies A_c E = R_c - mean(R_c), the same
+    projection as dropping the constant mode.  Otherwise A_c is nonsingular and is solved
+    as it is.  Either system is factorized once by sparse LU (a library primitive).  The
     paper's host-side Gauss-Seidel to a tolerance is `gauss_seidel`."""
 
-    def __init__(self, Ac):
+    def __init__(self, Ac, singular=None):
         N = Ac.shape[0]
-        ones = np.ones((N, 1))
-        K = scipy.sparse.bmat([[Ac, ones], [ones.T, None]], format="csc")
+        Ac = scipy.sparse.csr_matrix(Ac)
+        if singular is None:
+            singular = bool(np.allclose(np.asarray(Ac.sum(axis=1)).ravel(), 0.0, atol=1e-12))
         self.N = N
-        self.Ac = Ac.tocsr()
+        self.Ac = Ac
+        self.singular = singular
+        if singular:
+            ones = np.ones((N, 1))
+            K = scipy.sparse.bmat([[Ac, ones], [ones.T, None]], format="csc")
+        else:
+            K = Ac.tocsc()
         self.lu = scipy.sparse.linalg.splu(K)
 
     def solve(self, Rc):
         shape = Rc.shape
-        rhs = np.concatenate([np.asarray(Rc, dtype=np.float64).ravel(), [0.0]])
+        rhs = np.asarray(Rc, dtype=np.float64).ravel()
+        if not self.singular:
+            return self.lu.solve(rhs).reshape(shape)
+        rhs = np.concatenate([rhs, [0.0]])
         return self.lu.solve(rhs)[: self.N].reshape(shape)
 
     def gauss_seidel(self, Rc, E0=None, tol_c=1e-6, max_iter=100000):
@@ -411,7 +488,8 @@ class CoarseSolver:
         unpinned (an option of the oracle, not used by the library)."""
         A = self.Ac
         b = np.asarray(Rc, dtype=np.float64).ravel()
-        b = b - b.mean()
+        if self.singular:
+            b = b - b.mean()
         E = np.zeros_like(b) if E0 is None else np.asarray(E0, dtype=np.float64).ravel().copy()
         L = scipy.sparse.tril(A, format="csr")
         U = A - L
@@ -419,56 +497,86 @@ class CoarseSolver:
         while np.max(np.abs(b - A @ E)) >= tol_c and it < max_iter:
             E = scipy.sparse.linalg.spsolve_triangular(L, b - U @ E, lower=True)
             it += 1
-        return E.reshape(Rc.shape) - E.mean(), it
+        return E.reshape(Rc.shape) - (E.mean() if self.singular else 0.0), it
 
 
 # --------------------------------------------------------------------------------------
 # The exact discrete solution x* (what every solver must converge to)
 # --------------------------------------------------------------------------------------
 
+# The real trigonometric basis that diagonalizes the three-point operator along a walled
+# axis, by its (low, high) faces: the mirror ghost of each wall fixes the cell-centred
+# modes cos or sin(theta (i + 1/2)) and the allowed angles theta.
+_TRANSFORM = {("N", "N"): ("dct", 2), ("D", "D"): ("dst", 2), ("N", "D"): ("dct", 4),
+              ("D", "N"): ("dst", 4)}
+
+
 def laplacian_eigenvalues(nf, bc):
-    """Eigenvalues of the 1D three-point operator with the given boundary condition, in the
-    order of the DCT-II (Neumann) or FFT (periodic) basis: -4 sin^2(pi k / (2 nf)) and
-    -4 sin^2(pi k / nf) respectively."""
+    """Eigenvalues -4 sin^2(theta_k / 2) of the 1D three-point operator with the given
+    boundary condition, in the order of its basis: theta_k = pi k / nf (Neumann walls,
+    DCT-II), pi (k + 1) / nf (Dirichlet walls, DST-II), pi (k + 1/2) / nf (one wall of each
+    kind, DCT-IV / DST-IV) and 2 pi k / nf (periodic, FFT order)."""
     k = np.arange(nf)
-    if bc == PERIODIC:
-        return -4.0 * np.sin(np.pi * k / nf) ** 2
-    return -4.0 * np.sin(np.pi * k / (2.0 * nf)) ** 2
+    f = faces(bc)
+    if f is None:
+        theta = 2.0 * np.pi * k / nf
+    elif f == ("N", "N"):
+        theta = np.pi * k / nf
+    elif f == ("D", "D"):
+        theta = np.pi * (k + 1.0) / nf
+    else:
+        theta = np.pi * (k + 0.5) / nf
+    return -4.0 * np.sin(theta / 2.0) ** 2
 
 
 def _spectral_solve(f, bc_x, bc_y):
-    """Zero-mean solution of A'x = f by diagonalizing A' (DCT-II on Neumann axes, FFT on
-    periodic ones)."""
+    """Solution of A'x = f by diagonalizing A' (the real transform of ``_TRANSFORM`` on
+    walled axes, the FFT on periodic ones); the zero-mean one when A' is singular."""
     ny, nx = f.shape
     lam = laplacian_eigenvalues(ny, bc_y)[:, None] + laplacian_eigenvalues(nx, bc_x)[None, :]
-    lam[0, 0] = 1.0
-    if bc_x == PERIODIC and bc_y == PERIODIC:
-        fh = np.fft.fft2(f)
-        fh /= lam
+    sing = singular(bc_x, bc_y)
+    if sing:
+        lam[0, 0] = 1.0
+    axes = ((0, faces(bc_y)), (1, faces(bc_x)))
+    fh = np.asarray(f, dtype=np.float64)
+    for axis, fc in axes:
+        if fc is not None:
+            kind, typ = _TRANSFORM[fc]
+            fh = getattr(scipy.fft, kind)(fh, type=typ, norm="ortho", axis=axis)
+    for axis, fc in axes:
+        if fc is None:
+            fh = np.fft.fft(fh, axis=axis)
+    fh = fh / lam
+    if sing:
         fh[0, 0] = 0.0
-        return np.fft.ifft2(fh).real
-    if bc_x == PERIODIC:
-        fh = np.fft.fft(scipy.fft.dct(f, type=2, norm="ortho", axis=0), axis=1)
-        fh /= lam
-        fh[0, 0] = 0.0
-        return scipy.fft.idct(np.fft.ifft(fh, axis=1).real, type=2, norm="ortho", axis=0)
-    fh = scipy.fft.dctn(f, type=2, norm="ortho")
-    fh /= lam
-    fh[0, 0] = 0.0
-    return scipy.fft.idctn(fh, type=2, norm="ortho")
+    for axis, fc in axes:
+        if fc is None:
+            fh = np.fft.ifft(fh, axis=axis)
+    fh = np.real(fh)
+    for axis, fc in axes:
+        if fc is not None:
+            kind, typ = _TRANSFORM[fc]
+            fh = getattr(scipy.fft, "i" + kind)(fh, type=typ, norm="ortho", axis=axis)
+    return fh
+
+
+def _project(b, bc_x, bc_y):
+    """b~: b less its mean when A is singular (the compatibility condition), else b."""
+    b = np.asarray(b, dtype=np.float64)
+    return b - b.mean() if singular(bc_x, bc_y) else b
 
 
 def exact_solve(b, h, bc_x=NEUMANN, bc_y=NEUMANN, refine=2):
-    """x*: the zero-mean solution of A x = b - mean(b), by spectral diagonalization followed
-    by `refine` steps of FP64 iterative refinement with the difference-form residual.
+    """x*: the solution of A x = b~ (zero-mean when A is singular), by spectral
+    diagonalization followed by `refine` steps of FP64 iterative refinement with the
+    difference-form residual.
 
     Pinned by dense direct solves on small grids and by its residual."""
-    b = np.asarray(b, dtype=np.float64)
-    bp = h * h * (b - b.mean())
+    bp = h * h * _project(b, bc_x, bc_y)
     x = _spectral_solve(bp, bc_x, bc_y)
     for _ in range(refine):
         x = x + _spectral_solve(bp - laplacian(x, bc_x, bc_y), bc_x, bc_y)
-    return x - x.mean()
+    return _project(x, bc_x, bc_y)
 
 
 def dense_laplacian(nx, ny, bc_x=NEUMANN, bc_y=NEUMANN):
@@ -487,28 +595,32 @@ def dense_laplacian(nx, ny, bc_x=NEUMANN, bc_y=NEUMANN):
                 if 0 <= ii < nx and 0 <= jj < ny:
                     A[c, jj * nx + ii] += 1.0
                     A[c, c] -= 1.0
+                else:  # behind a wall: the ghost is +p_C (Neumann) or -p_C (Dirichlet)
+                    fc = faces(bc_x) if di else faces(bc_y)
+                    if fc[0 if (di < 0 or dj < 0) else 1] == "D":
+                        A[c, c] -= 2.0
     return A
 
 
 def dense_solve(b, h, bc_x=NEUMANN, bc_y=NEUMANN):
-    """x* on a tiny grid by a dense solve of the system bordered with sum(x) = 0."""
+    """x* on a tiny grid by a dense solve (of the system bordered with sum(x) = 0 when A is
+    singular)."""
     ny, nx = b.shape
     A = dense_laplacian(nx, ny, bc_x, bc_y)
     N = nx * ny
+    rhs = (h * h * _project(b, bc_x, bc_y)).ravel()
+    if not singular(bc_x, bc_y):
+        return np.linalg.solve(A, rhs).reshape(ny, nx)
     K = np.zeros((N + 1, N + 1))
     K[:N, :N] = A
     K[:N, N] = 1.0
     K[N, :N] = 1.0
-    rhs = np.zeros(N + 1)
-    bb = np.asarray(b, dtype=np.float64)
-    rhs[:N] = (h * h * (bb - bb.mean())).ravel()
-    return np.linalg.solve(K, rhs)[:N].reshape(ny, nx)
+    return np.linalg.solve(K, np.concatenate([rhs, [0.0]]))[:N].reshape(ny, nx)
 
 
 def relative_residual(b, x, h, bc_x=NEUMANN, bc_y=NEUMANN):
-    """||b~ - A x||_2 / ||b~||_2 with b~ = b - mean(b), residual in difference form (FP64)."""
-    b = np.asarray(b, dtype=np.float64)
-    bp = h * h * (b - b.mean())
+    """||b~ - A x||_2 / ||b~||_2, residual in difference form (FP64)."""
+    bp = h * h * _project(b, bc_x, bc_y)
     r = bp - laplacian(np.asarray(x, dtype=np.float64), bc_x, bc_y)
     return float(np.linalg.norm(r) / np.linalg.norm(bp))
 
@@ -540,10 +652,11 @@ def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
     ||b~ - A x|| <= rtol ||b~||.  stencil="acm" or "gmg5" swaps the coarse operator (and,
     for ACM, the prolongation) for the comparison schemes.
 
-    Returns (x, info) with x zero-mean and info = dict(cycles, sweeps, history)."""
+    Returns (x, info) with x zero-mean (when A is singular) and
+    info = dict(cycles, sweeps, history)."""
     b = np.asarray(b, dtype=np.float64)
     ny, nx = b.shape
-    bp = h * h * (b - b.mean())
+    bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     ncx, ncy = nx // n, ny // n
     cs = CoarseSolver(coarse_matrix(_stencil(stencil, ncx, ncy, n, bc_x, bc_y), bc_x, bc_y))
@@ -562,7 +675,7 @@ def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
         r = bp - laplacian(x, bc_x, bc_y)
         cycles += 1
         hist.append(float(np.linalg.norm(r) / bnorm))
-    return x - x.mean(), dict(cycles=cycles, sweeps=cycles * nu, history=hist)
+    return _project(x, bc_x, bc_y), dict(cycles=cycles, sweeps=cycles * nu, history=hist)
 
 
 def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
@@ -580,7 +693,7 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
     max_inner.  Then x += e in FP64.  Returns (x, info)."""
     b = np.asarray(b, dtype=np.float64)
     ny, nx = b.shape
-    bp = h * h * (b - b.mean())
+    bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     ncx, ncy = nx // n, ny // n
     cs = CoarseSolver(coarse_matrix(coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y), bc_x, bc_y))
@@ -613,8 +726,8 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
                     and inner_hist[-1] > (1.0 - stall_drop) * inner_hist[-1 - stall_window]):
                 break
         x = x + e.astype(np.float64)
-    return x - x.mean(), dict(cycles=cycles, sweeps=cycles * nu, outer=outer,
-                              history=outer_hist)
+    return _project(x, bc_x, bc_y), dict(cycles=cycles, sweeps=cycles * nu, outer=outer,
+                                         history=outer_hist)
 
 
 # --------------------------------------------------------------------------------------
@@ -635,7 +748,7 @@ def acm_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, rtol=1e-10, x0=None, max_cycl
     b = np.asarray(b, dtype=np.float64)
     ny, nx = b.shape
     L = int(round(math.log2(n)))
-    bp = h * h * (b - b.mean())
+    bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     cs = CoarseSolver(coarse_matrix(coarse_stencil_acm(nx // n, ny // n, n, bc_x, bc_y),
                                     bc_x, bc_y))
@@ -657,8 +770,8 @@ def acm_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, rtol=1e-10, x0=None, max_cycl
         cycles += 1
         hist.append(float(np.linalg.norm(bp - laplacian(x, bc_x, bc_y)) / bnorm))
     launches = cycles * (3 * L + 1)
-    return x - x.mean(), dict(cycles=cycles, sweeps=cycles, launches=launches, history=hist,
-                              levels=L)
+    return _project(x, bc_x, bc_y), dict(cycles=cycles, sweeps=cycles, launches=launches,
+                                         history=hist, levels=L)
 
 
 # --------------------------------------------------------------------------------------
@@ -686,7 +799,7 @@ def transfer_matrices(nx, ny, n, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
 
 def two_grid_matrix(nx, ny, n, nu, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
     """Error propagation of one cycle, T = S^nu (I - P A_c^+ R A'), on the zero-mean
-    subspace (tiny grids).  S is the red-black sweep applied to errors (zero right-hand
+    subspace when A is singular (tiny grids).  S is the red-black sweep applied to errors (zero right-hand
     side)."""
     R, P, A = transfer_matrices(nx, ny, n, bc_x, bc_y, kind)
     C = _stencil(kind, nx // n, ny // n, n, bc_x, bc_y)
@@ -695,6 +808,8 @@ def two_grid_matrix(nx, ny, n, nu, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
     S = _columns(lambda f: red_black_gs(f, np.zeros_like(f), bc_x, bc_y, 1), N, (ny, nx))
     K = np.eye(N) - P @ np.linalg.pinv(Ac) @ R @ A
     T = np.linalg.matrix_power(S, nu) @ K
+    if not singular(bc_x, bc_y):
+        return T
     Pi = np.eye(N) - np.ones((N, N)) / N
     return Pi @ T @ Pi
 

@@ -14,17 +14,33 @@ import pytest
 
 from oracle import ism_oracle as O
 
-N, P = O.NEUMANN, O.PERIODIC
+N, P, D = O.NEUMANN, O.PERIODIC, O.DIRICHLET
+ND, DN = O.NEUMANN_DIRICHLET, O.DIRICHLET_NEUMANN
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-BCS = [(N, N), (P, N)]
+# (bc_x, bc_y): Neumann walls, a periodic axis, and zero-pressure (Dirichlet) walls on both
+# faces of an axis or on one face only
+BCS = [(N, N), (P, N), (D, D), (N, ND), (DN, N), (P, D)]
+
+
+def _theta(nf, k, bc):
+    """Angle of the k-th 1D mode, derived by hand from the mirror ghosts: cos(theta (c+1/2))
+    needs theta nf = pi k for two Neumann walls; sin(theta (c+1/2)) needs theta nf = pi (k+1)
+    for two Dirichlet walls; one wall of each kind needs theta nf = pi (k + 1/2)."""
+    f = {N: "NN", D: "DD", ND: "ND", DN: "DN"}.get(bc)
+    if bc == P:
+        return 2.0 * np.pi * k / nf
+    return np.pi * {"NN": k, "DD": k + 1, "ND": k + 0.5, "DN": k + 0.5}[f] / nf
 
 
 def _mode(nf, k, bc, coord):
-    """1D eigenvector of the three-point operator: DCT-II cosine (walls) or a Fourier
-    cosine (periodic), sampled at cell centres."""
+    """1D eigenvector of the three-point operator sampled at cell centres: a Fourier cosine
+    (periodic), a cosine (Neumann low face) or a sine (Dirichlet low face)."""
+    th = _theta(nf, k, bc)
     if bc == P:
-        return np.cos(2.0 * np.pi * k * coord / nf)
-    return np.cos(np.pi * k * (coord + 0.5) / nf)
+        return np.cos(th * coord)
+    if bc in (D, DN):
+        return np.sin(th * (coord + 0.5))
+    return np.cos(th * (coord + 0.5))
 
 
 # ---------------------------------------------------------------- fine operator
@@ -36,9 +52,10 @@ def test_laplacian_eigenpairs(bcx, bcy, k, l):
     nx, ny = 12, 10
     j, i = np.indices((ny, nx))
     v = _mode(nx, k, bcx, i) * _mode(ny, l, bcy, j)
-    lam_x = -4 * math.sin(math.pi * k / nx) ** 2 if bcx == P else -4 * math.sin(math.pi * k / (2 * nx)) ** 2
-    lam_y = -4 * math.sin(math.pi * l / (2 * ny)) ** 2
+    lam_x = -4 * math.sin(_theta(nx, k, bcx) / 2) ** 2
+    lam_y = -4 * math.sin(_theta(ny, l, bcy) / 2) ** 2
     np.testing.assert_allclose(O.laplacian(v, bcx, bcy), (lam_x + lam_y) * v, atol=1e-13)
+    np.testing.assert_allclose(O.laplacian_eigenvalues(nx, bcx)[k], lam_x, atol=1e-14)
 
 
 @pytest.mark.parametrize("bcx,bcy", BCS)
@@ -48,8 +65,11 @@ def test_laplacian_matches_dense_assembly(bcx, bcy):
     x = np.random.default_rng(0).standard_normal((ny, nx))
     np.testing.assert_allclose(O.laplacian(x, bcx, bcy).ravel(), A @ x.ravel(), atol=1e-13)
     assert np.allclose(A, A.T)                       # symmetric
-    np.testing.assert_allclose(A.sum(axis=1), 0.0)   # constants in the null space
-    assert np.linalg.matrix_rank(A) == nx * ny - 1   # and nothing else
+    if O.singular(bcx, bcy):
+        np.testing.assert_allclose(A.sum(axis=1), 0.0)   # constants in the null space
+        assert np.linalg.matrix_rank(A) == nx * ny - 1   # and nothing else
+    else:
+        assert np.linalg.eigvalsh(A).max() < -1e-3      # negative definite
 
 
 def test_laplacian_float32_stays_float32():
@@ -69,7 +89,8 @@ def test_exact_solve_matches_dense(bcx, bcy, nx, ny):
     xd = O.dense_solve(b, h, bcx, bcy)
     xs = O.exact_solve(b, h, bcx, bcy)
     np.testing.assert_allclose(xs, xd, atol=1e-12 * np.abs(xd).max())
-    assert abs(xs.mean()) < 1e-15 * np.abs(xs).max() * nx
+    if O.singular(bcx, bcy):
+        assert abs(xs.mean()) < 1e-15 * np.abs(xs).max() * nx
 
 
 @pytest.mark.parametrize("bcx,bcy", BCS)
@@ -99,6 +120,13 @@ def _sequential_rbgs(p, rhs, bcx, bcy):
                     if 0 <= ii < nx and 0 <= jj < ny:
                         s += p[jj, ii]
                         m += 1
+                    else:
+                        # behind a wall: the equation's ghost is +p (Neumann: no term) or
+                        # -p (Dirichlet: the term -p - p, i.e. 2 on the diagonal)
+                        bc = bcx if di else bcy
+                        low = di < 0 or dj < 0
+                        dirichlet = bc == D or (bc == ND and not low) or (bc == DN and low)
+                        m += 2 if dirichlet else 0
                 p[j, i] = (s - rhs[j, i]) * (1.0 / m)
     return p
 
@@ -118,7 +146,7 @@ def test_rbgs_fixed_point_is_exact_solution(bcx, bcy):
     b = np.random.default_rng(5).standard_normal((32, 32))
     h = 1 / 32
     x = O.exact_solve(b, h, bcx, bcy)
-    bp = h * h * (b - b.mean())
+    bp = h * h * (b - b.mean()) if O.singular(bcx, bcy) else h * h * b
     np.testing.assert_allclose(O.red_black_gs(x, bp, bcx, bcy, 3), x, atol=1e-13 * np.abs(x).max())
 
 
@@ -140,7 +168,18 @@ def test_restrict_conserves_and_matches_loops():
 def test_prolong_exact_on_constants_and_bilinear(n, bcx, bcy):
     ncx, ncy = 5, 4
     Ec = np.full((ncy, ncx), 2.5)
-    np.testing.assert_array_equal(O.prolong_bilinear(Ec, n, bcx, bcy), 2.5)
+    pc = O.prolong_bilinear(Ec, n, bcx, bcy)
+    # constants are reproduced except within half a tile of a Dirichlet wall, where the
+    # interpolant falls linearly to zero on the wall: 2.5 (2k+1)/n at the k-th cell from it
+    jc, ic = np.indices(pc.shape)
+    ref = np.full(pc.shape, 2.5)
+    for bc, c, nf in ((bcx, ic, ncx * n), (bcy, jc, ncy * n)):
+        f = O.faces(bc)
+        if f is not None and f[0] == "D":
+            ref = np.where(c < n // 2, ref * (2 * c + 1) / n, ref)
+        if f is not None and f[1] == "D":
+            ref = np.where(c >= nf - n // 2, ref * (2 * (nf - 1 - c) + 1) / n, ref)
+    np.testing.assert_array_equal(pc, ref)
     # bilinear field sampled at coarse centres, compared on fine cells strictly between
     # centres (away from the wall/wrap rectangles)
     a, bx, cy, d = 0.3, -1.7, 0.9, 0.25
@@ -155,7 +194,7 @@ def test_prolong_exact_on_constants_and_bilinear(n, bcx, bcy):
 
 def test_prolong_weights_are_dyadic():
     for n in (4, 8, 16, 32):
-        lo, hi, t = O._interp_axis(3 * n, n, N)
+        lo, hi, t, _, _ = O._interp_axis(3 * n, n, N)
         assert np.all((2 * n * t) % 2 == 1)  # t = (2k+1)/(2n)
 
 
@@ -183,7 +222,8 @@ def test_coarse_stencil_equals_RAP(n, nc, bcx, bcy, kind):
     Ac = O.coarse_matrix(C, bcx, bcy).toarray()
     np.testing.assert_allclose(Ac, _brute_coarse(ncx * n, ncy * n, n, bcx, bcy, kind), atol=1e-12)
     np.testing.assert_allclose(Ac, Ac.T, atol=1e-14)        # symmetric
-    np.testing.assert_allclose(Ac.sum(axis=0), 0.0, atol=1e-13)  # conservative
+    if O.singular(bcx, bcy):
+        np.testing.assert_allclose(Ac.sum(axis=0), 0.0, atol=1e-13)  # conservative
 
 
 @pytest.mark.parametrize("n", [4, 8, 16, 32])
@@ -208,9 +248,14 @@ def test_ism_coarse_matrix_is_K_M_kron(bcx, bcy):
         if bc == P:
             K[0, -1] = K[-1, 0] = 1
             M[0, -1] = M[-1, 0] = 1 / 8
-        else:  # wall: one-sided difference, constant extrapolation of the interpolant
-            K[0, 0] = K[-1, -1] = -1
-            M[0, 0] = M[-1, -1] = 7 / 8
+            return K, M
+        # Neumann wall: one-sided difference, constant extrapolation of the interpolant.
+        # Dirichlet wall (derived by hand): the wall flux is twice the first cell's value,
+        # which the interpolant through zero makes 2 E / n, so K gets -3; the tile sum of
+        # the interpolant loses n/8 against the interior, so M gets 5/8.
+        for end, f in zip((0, -1), O.faces(bc)):
+            K[end, end] = -1 if f == "N" else -3
+            M[end, end] = 7 / 8 if f == "N" else 5 / 8
         return K, M
 
     Kx, Mx = KM(ncx, bcx)
@@ -226,8 +271,8 @@ def test_ism_coarse_eigenvalues(bcx, bcy):
     Ac = O.coarse_matrix(O.coarse_stencil_ism(ncx, ncy, 16, bcx, bcy), bcx, bcy)
     J, I = np.indices((ncy, ncx))
     for k, l in [(0, 1), (1, 0), (2, 3), (4, 5)]:
-        th_k = (2 if bcx == P else 1) * np.pi * k / ncx
-        th_l = np.pi * l / ncy
+        th_k = _theta(ncx, k, bcx)
+        th_l = _theta(ncy, l, bcy)
         v = _mode(ncx, k, bcx, I) * _mode(ncy, l, bcy, J)
         lam = -(np.sin(th_k / 2) ** 2 * (3 + np.cos(th_l)) + np.sin(th_l / 2) ** 2 * (3 + np.cos(th_k)))
         np.testing.assert_allclose(Ac @ v.ravel(), lam * v.ravel(), atol=1e-13)
@@ -238,6 +283,10 @@ def test_acm_coarse_is_n_times_five_point():
         C = O.coarse_stencil_acm(5, 4, n)
         np.testing.assert_allclose(C[1, 2], n * np.array([[0, 1, 0], [1, -4, 1], [0, 1, 0]]))
         np.testing.assert_allclose(C[0, 0], n * np.array([[0, 0, 0], [0, -2, 1], [0, 1, 0]]))
+        # a Dirichlet wall face carries n fine fluxes -2 E_C
+        C = O.coarse_stencil_acm(5, 4, n, D, D)
+        np.testing.assert_allclose(C[0, 0], n * np.array([[0, 0, 0], [0, -6, 1], [0, 1, 0]]))
+        np.testing.assert_allclose(C[1, 2], n * np.array([[0, 1, 0], [1, -4, 1], [0, 1, 0]]))
 
 
 # ---------------------------------------------------------------- coarse solve
@@ -259,19 +308,39 @@ def test_coarse_solve_residual_and_modes():
     np.testing.assert_allclose(cs.solve(v), v / lam, atol=1e-12)
 
 
+def test_coarse_solve_dirichlet_nonsingular():
+    # with zero-pressure walls the coarse system is solved as it is (no projection) and a
+    # product of sine / quarter-wave modes comes back divided by its eigenvalue
+    ncx, ncy = 12, 10
+    for bcx, bcy in ((D, D), (N, ND), (DN, P)):
+        Ac = O.coarse_matrix(O.coarse_stencil_ism(ncx, ncy, 16, bcx, bcy), bcx, bcy)
+        cs = O.CoarseSolver(Ac)
+        assert not cs.singular
+        Rc = np.random.default_rng(7).standard_normal((ncy, ncx))
+        E = cs.solve(Rc)
+        assert np.linalg.norm(Ac @ E.ravel() - Rc.ravel()) < 1e-13 * np.linalg.norm(Rc)
+        J, I = np.indices((ncy, ncx))
+        v = _mode(ncx, 3, bcx, I) * _mode(ncy, 2, bcy, J)
+        th_k, th_l = _theta(ncx, 3, bcx), _theta(ncy, 2, bcy)
+        lam = -(np.sin(th_k / 2) ** 2 * (3 + np.cos(th_l)) + np.sin(th_l / 2) ** 2 * (3 + np.cos(th_k)))
+        np.testing.assert_allclose(cs.solve(v), v / lam, atol=1e-12)
+
+
 # ---------------------------------------------------------------- coarse correction
 
 
 @pytest.mark.parametrize("kind", ["ism", "acm"])
-def test_coarse_correction_exact_for_interpolated_fields(kind):
-    # if b' = A' P E0, a single coarse correction from x = 0 returns P E0 (up to a constant):
-    # the coarse solution approximates the fine discrete one (Sec. 3.2, Sec. 4.3.1)
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (D, ND)])
+def test_coarse_correction_exact_for_interpolated_fields(kind, bcx, bcy):
+    # if b' = A' P E0, a single coarse correction from x = 0 returns P E0 (up to a constant
+    # when A is singular): the coarse solution approximates the fine discrete one
+    # (Sec. 3.2, Sec. 4.3.1)
     n, ncx, ncy = 8, 5, 4
     E0 = np.random.default_rng(8).standard_normal((ncy, ncx))
-    bp = O.laplacian(O._prolong(kind, E0, n, N, N))
-    cs = O.CoarseSolver(O.coarse_matrix(O._stencil(kind, ncx, ncy, n, N, N)))
-    x = O._prolong(kind, cs.solve(O.restrict_sum(bp, n)), n, N, N)
-    ref = O._prolong(kind, E0 - E0.mean(), n, N, N)
+    bp = O.laplacian(O._prolong(kind, E0, n, bcx, bcy), bcx, bcy)
+    cs = O.CoarseSolver(O.coarse_matrix(O._stencil(kind, ncx, ncy, n, bcx, bcy), bcx, bcy))
+    x = O._prolong(kind, cs.solve(O.restrict_sum(bp, n)), n, bcx, bcy)
+    ref = O._prolong(kind, E0 - E0.mean() if cs.singular else E0, n, bcx, bcy)
     np.testing.assert_allclose(x, ref, atol=1e-13)
 
 
@@ -315,7 +384,8 @@ def test_ism_solve_reaches_exact_solution(bcx, bcy, n):
     assert O.relative_residual(b, x, h, bcx, bcy) <= 1e-10
     xs = O.exact_solve(b, h, bcx, bcy)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-6
-    assert abs(x.mean()) < 1e-14 * np.abs(x).max() * nx
+    if O.singular(bcx, bcy):
+        assert abs(x.mean()) < 1e-14 * np.abs(x).max() * nx
     assert info["history"][-2] > 1e-10  # it stopped at the first cycle that met rtol
 
 
@@ -329,37 +399,41 @@ def test_ism_counts_grid_independent():
     assert abs(h_cycles[0] - h_cycles[1]) <= 0.15 * max(h_cycles)
 
 
-@pytest.mark.parametrize("n,nu", [(4, 1), (4, 2), (8, 2)])
-def test_measured_rate_matches_two_grid_matrix(n, nu):
+@pytest.mark.parametrize("n,nu,bcx,bcy", [(4, 1, N, N), (4, 2, N, N), (8, 2, N, N),
+                                           (4, 2, D, D), (8, 2, N, ND)])
+def test_measured_rate_matches_two_grid_matrix(n, nu, bcx, bcy):
     nf = 32
-    T = O.two_grid_matrix(nf, nf, n, nu)
+    T = O.two_grid_matrix(nf, nf, n, nu, bcx, bcy)
     rho = np.max(np.abs(np.linalg.eigvals(T)))
     b = np.random.default_rng(11).standard_normal((nf, nf))
-    _, info = O.ism_solve(b, 1 / nf, n, nu=nu, rtol=1e-13, max_cycles=400)
+    _, info = O.ism_solve(b, 1 / nf, n, bcx, bcy, nu=nu, rtol=1e-13, max_cycles=400)
     hist = np.array(info["history"])
     tail = hist[hist > 1e-12][-20:]
     rate = (tail[-1] / tail[0]) ** (1.0 / (len(tail) - 1))
     assert abs(rate - rho) < 0.03 * rho
 
 
-def test_mixed_precision_oracle_reaches_tolerance():
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND)])
+def test_mixed_precision_oracle_reaches_tolerance(bcx, bcy):
     nf = 128
     h = 1 / nf
     b = np.random.default_rng(12).standard_normal((nf, nf))
-    x, info = O.ism_solve_mixed(b, h, 16, nu=2, rtol=1e-10)
-    assert O.relative_residual(b, x, h) <= 1e-10
+    x, info = O.ism_solve_mixed(b, h, 16, bcx, bcy, nu=2, rtol=1e-10)
+    assert O.relative_residual(b, x, h, bcx, bcy) <= 1e-10
     assert 2 <= info["outer"] <= 6
-    xs = O.exact_solve(b, h)
+    xs = O.exact_solve(b, h, bcx, bcy)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-6
 
 
-@pytest.mark.parametrize("n", [4, 8])
-def test_acm_solve_reaches_exact_solution(n):
+@pytest.mark.parametrize("n,bcx,bcy", [(4, N, N), (8, N, N), (8, D, DN)])
+def test_acm_solve_reaches_exact_solution(n, bcx, bcy):
     nf = 64
     h = 1 / nf
     b = np.random.default_rng(13).standard_normal((nf, nf))
-    x, info = O.acm_solve(b, h, n, rtol=1e-10)
-    assert O.relative_residual(b, x, h) <= 1e-10
+    x, info = O.acm_solve(b, h, n, bcx, bcy, rtol=1e-10)
+    assert O.relative_residual(b, x, h, bcx, bcy) <= 1e-10
+    xs = O.exact_solve(b, h, bcx, bcy)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-6
     assert info["levels"] == int(math.log2(n))
 
 
@@ -382,12 +456,28 @@ def test_coarse_gauss_seidel_option():
 # ---------------------------------------------------------------- MAC operators
 
 
-@pytest.mark.parametrize("bcx", [N, P])
-def test_div_grad_is_laplacian(bcx):
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, N), (D, D), (ND, DN), (P, ND)])
+def test_div_grad_is_laplacian(bcx, bcy):
     nx, ny, h = 12, 10, 0.1
     p = np.random.default_rng(16).standard_normal((ny, nx))
-    gu, gv = O.grad(p, h, bcx, N)
-    np.testing.assert_allclose(O.div(gu, gv, h, bcx), O.laplacian(p, bcx, N) / h**2, atol=1e-10)
+    gu, gv = O.grad(p, h, bcx, bcy)
+    np.testing.assert_allclose(O.div(gu, gv, h, bcx), O.laplacian(p, bcx, bcy) / h**2, atol=1e-10)
+    # G is zero on Neumann wall faces only
+    if bcx == N:
+        assert not gu[:, 0].any() and not gu[:, -1].any()
+    if bcy == D:
+        assert gv[0, :].all() and gv[-1, :].all()
+
+
+@pytest.mark.parametrize("bcx,bcy", [(D, ND)])
+def test_grad_adjoint_dirichlet(bcx, bcy):
+    nx, ny, h = 9, 7, 0.3
+    rng = np.random.default_rng(19)
+    u, v = rng.standard_normal((ny, nx + 1)), rng.standard_normal((ny + 1, nx))
+    p = rng.standard_normal((ny, nx))
+    gu, gv = O.grad(p, h, bcx, bcy)
+    lhs = np.sum(gu * u) + np.sum(gv * v)
+    assert abs(lhs - np.sum(p * O.grad_adjoint(u, v, h, bcx, bcy))) < 1e-11
 
 
 @pytest.mark.parametrize("bcx", [N, P])
