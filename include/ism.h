@@ -11,10 +11,12 @@
  *
  * Problem.  The pressure equation of the projection step (Sec. 2.2, Eq. 4) on a cell-centred
  * nx x ny grid with square cells of size h = lx/nx = ly/ny, discretized with the 5-point
- * Laplacian (Sec. 2.3): A x = b~, with (A x)_C = sum over existing neighbours of
- * (x_nb - x_C) / h^2 and b~ = b - mean(b).  Walls are the paper's "symmetric" condition
- * read as homogeneous Neumann (no flux through the wall face); an axis can instead be
- * periodic (Sec. 4.1 lists both).  The returned x is the zero-mean solution.
+ * Laplacian (Sec. 2.3): A x = b~, with (A x)_C = sum over the four faces of
+ * (x_nb - x_C) / h^2.  An axis is periodic or has a wall on each face, of one of the kinds
+ * Sec. 4.1 lists: "symmetric", read as homogeneous Neumann (no flux through the wall face),
+ * or Dirichlet (zero pressure on the wall face, read as the mirror ghost x_nb = -x_C).
+ * Without a Dirichlet face the constants span the null space of A: then b~ = b - mean(b)
+ * and the returned x is the zero-mean solution.  With one, A is nonsingular and b~ = b.
  *
  * Conventions for every entry point.
  *  - All array arguments are DEVICE pointers (HIP global memory), C-contiguous row-major
@@ -51,6 +53,12 @@ extern "C" {
 
 #define ISM_BC_NEUMANN 0  /* wall: no flux across the boundary face ("symmetric", Sec. 4.1) */
 #define ISM_BC_PERIODIC 1 /* the axis wraps (Sec. 4.1)                                       */
+#define ISM_BC_DIRICHLET 2 /* zero-pressure walls on both faces of the axis (Sec. 4.1)       */
+#define ISM_BC_NEUMANN_DIRICHLET 3 /* Neumann wall on the low face (west / south), zero-
+                                      pressure wall on the high face (east / north), e.g. an
+                                      outlet at the top of a channel                         */
+#define ISM_BC_DIRICHLET_NEUMANN 4 /* zero-pressure wall on the low face, Neumann on the
+                                      high face                                              */
 
 #define ISM_PREC_FP64 0  /* every fine-grid operation in FP64                                */
 #define ISM_PREC_MIXED 1 /* FP32 smoothing, restriction and prolongation inside an FP64
@@ -124,20 +132,22 @@ int ism_destroy(ism_handle h);
 /* Bytes of device memory the handle holds. */
 int ism_workspace_bytes(ism_handle h, size_t* bytes);
 
-/* Solve A x = b - mean(b) for every grid of the batch (Sec. 3.4 sparse two-level cycle,
- * Sec. 4.3.1 cycling: coarse correction first, then nu fine sweeps, repeated).  b: FP64
+/* Solve A x = b~ for every grid of the batch (Sec. 3.4 sparse two-level cycle, Sec. 4.3.1
+ * cycling: coarse correction first, then nu fine sweeps, repeated).  b: FP64
  * [batch][ny][nx], read only.  x: FP64 [batch][ny][nx], initial guess on entry (warm start),
- * zero-mean solution on return.  st may be NULL. */
+ * solution on return (the zero-mean one when A is singular).  st may be NULL. */
 int ism_solve(ism_handle h, const double* b, double* x, ism_stats* st);
 
-/* Adjoint solve A^T lam = g - mean(g).  A is symmetric for these boundary conditions, so
+/* Adjoint solve A^T lam = g~.  A is symmetric for these boundary conditions, so
  * this is the same solve; it exists so that a differentiable projection names its
  * backward pass.  Same layouts and ownership as ism_solve. */
 int ism_solve_adjoint(ism_handle h, const double* g, double* lam, ism_stats* st);
 
 /* Staggered-grid operators of the projection step (Sec. 2.2, Sec. 2.3), FP64:
  *   ism_div:          b = D[u; v],  b_C = ((u_e - u_w) + (v_n - v_s)) / h
- *   ism_grad:         [gu; gv] = G p, gradient on faces, zero on wall faces, so D G = A
+ *   ism_grad:         [gu; gv] = G p, gradient on faces: zero on Neumann wall faces,
+ *                     (p_C - (-p_C)) / h or ((-p_C) - p_C) / h on a west/south or
+ *                     east/north Dirichlet wall face, so D G = A
  *   ism_div_adjoint:  [gu; gv] = D^T lam
  *   ism_grad_adjoint: p = G^T [gu; gv]
  * Layouts as above; outputs are overwritten. */
@@ -160,13 +170,16 @@ int ism_smooth(ism_handle h, int32_t dtype, const void* rhs, void* e, int32_t ns
 int ism_restrict(ism_handle h, int32_t dtype, const void* rhs, const void* e, double* rc,
                  double* sumsq);
 
-/* e += P E: bilinear interpolation of the coarse values to the fine cell centres (Eq. 5),
- * constant extrapolation between a wall and the first coarse centre. */
+/* e += P E: bilinear interpolation of the coarse values to the fine cell centres (Eq. 5).
+ * Between a wall and the first coarse centre the interpolation reaches the mirror image of
+ * that centre: the same value behind a Neumann wall (constant extrapolation), the negated
+ * value behind a Dirichlet wall (linear to zero on the wall). */
 int ism_prolong(ism_handle h, int32_t dtype, const double* E, void* e);
 
-/* E = zero-mean solution of A_c E = rc - mean(rc) on each grid's coarse grid, where A_c is
- * the interpolated 9-point stencil (Sec. 3.3, Eq. 6-7), or the 5-point one when the handle
- * was created with ISM_COARSE_GMG5.  Exact up to FP64 rounding. */
+/* E = solution of A_c E = rc on each grid's coarse grid (without a Dirichlet face: the
+ * zero-mean solution of A_c E = rc - mean(rc)), where A_c is the interpolated 9-point
+ * stencil (Sec. 3.3, Eq. 6-7), or the 5-point one when the handle was created with
+ * ISM_COARSE_GMG5.  Exact up to FP64 rounding. */
 int ism_coarse_solve(ism_handle h, const double* rc, double* E);
 
 /* One two-level cycle on A' e = rhs: E = coarse solve of rc; e += P E; nu red-black
@@ -179,12 +192,12 @@ int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
 /* The coarse stencil assembled on the device (ISM: from the face sums of Eq. 6-7; GMG5:
  * the 5-point stencil with one-sided wall rows):
  * coef is FP64 [ny/n][nx/n][9]; entry 3*(dj+1) + (di+1) multiplies the unknown at
- * (J+dj, I+di) (wrapped on a periodic axis; a wall contribution is folded onto the unknown
- * the clamped interpolation uses). */
+ * (J+dj, I+di) (wrapped on a periodic axis; the coefficient of a ghost behind a wall is
+ * folded onto the unknown it mirrors, with a minus sign behind a Dirichlet wall). */
 int ism_coarse_stencil(ism_handle h, double* coef);
 
-/* r = h^2 (b - mean(b)) - A' x in FP64 for every grid (the outer defect-correction
- * residual, difference form). */
+/* r = h^2 b~ - A' x in FP64 for every grid (the outer defect-correction residual,
+ * difference form). */
 int ism_outer_residual(ism_handle h, const double* b, const double* x, double* r);
 
 /* ---- Kernel timing.  While enabled, the handle brackets every launch of the kernel classes

@@ -22,6 +22,9 @@ ISM_ERR_NONFINITE = -4
 
 ISM_BC_NEUMANN = 0
 ISM_BC_PERIODIC = 1
+ISM_BC_DIRICHLET = 2
+ISM_BC_NEUMANN_DIRICHLET = 3
+ISM_BC_DIRICHLET_NEUMANN = 4
 ISM_PREC_FP64 = 0
 ISM_PREC_MIXED = 1
 ISM_COARSE_ISM = 0

@@ -1,9 +1,10 @@
 """Differentiable pressure projection on the staggered grid.
 
-Forward: u_new = u - G p with p the zero-mean solution of A p = D u - mean(D u) (the
-projection step of Goda's scheme, Sec. 2.2, Eq. 4, with p standing for minus the pressure
-change).  Backward: the pressure solve is linear and A is symmetric, so its vector-Jacobian
-product is D^T applied to the solution of the adjoint system A lam = g - mean(g); the
+Forward: u_new = u - G p with p the solution of A p = D u (the projection step of Goda's
+scheme, Sec. 2.2, Eq. 4, with p standing for minus the pressure change).  Without a
+Dirichlet wall A is singular: then D u - mean(D u) is solved for the zero-mean p.
+Backward: the pressure solve is linear and A is symmetric, so its vector-Jacobian product is
+D^T applied to the solution of the adjoint system (A lam = g, with the same projection); the
 gradient's own vector-Jacobian product is G^T.  Both run in the library's HIP kernels.
 """
 from __future__ import annotations
@@ -14,7 +15,7 @@ from .solver import Solver
 
 
 class PressureSolve(torch.autograd.Function):
-    """p = A^+ (D u - mean(D u)) for face velocities (u, v)."""
+    """p = A^+ D u (with D u - mean(D u) when A is singular) for face velocities (u, v)."""
 
     @staticmethod
     def forward(ctx, u, v, solver: Solver):
@@ -32,7 +33,7 @@ class PressureSolve(torch.autograd.Function):
 
 
 class MacGrad(torch.autograd.Function):
-    """(gu, gv) = G p, the face gradient (zero on wall faces)."""
+    """(gu, gv) = G p, the face gradient (zero on Neumann wall faces)."""
 
     @staticmethod
     def forward(ctx, p, solver: Solver):

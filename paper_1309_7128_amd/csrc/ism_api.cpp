@@ -46,6 +46,7 @@ struct ism_ctx {
   hipStream_t stream = nullptr;
   Geo g{};
   double h = 0.0, h2 = 0.0;
+  bool singular = true;  // no Dirichlet face: the constants span the null space of A
   size_t tsize = 8;  // bytes per element of the inner fine arrays
   // device memory (one allocation)
   char* block = nullptr;
@@ -147,9 +148,9 @@ int validate(const ism_config* cfg, std::string& why) {
   if (!cfg) return why = "config is NULL", ISM_ERR_INVALID;
   if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->batch <= 0)
     return why = "nx, ny and batch must be positive", ISM_ERR_INVALID;
-  if ((cfg->bc_x != ISM_BC_NEUMANN && cfg->bc_x != ISM_BC_PERIODIC) ||
-      (cfg->bc_y != ISM_BC_NEUMANN && cfg->bc_y != ISM_BC_PERIODIC))
-    return why = "bc_x/bc_y must be ISM_BC_NEUMANN or ISM_BC_PERIODIC", ISM_ERR_INVALID;
+  auto bc_ok = [](int bc) { return bc >= ISM_BC_NEUMANN && bc <= ISM_BC_DIRICHLET_NEUMANN; };
+  if (!bc_ok(cfg->bc_x) || !bc_ok(cfg->bc_y))
+    return why = "bc_x/bc_y must be one of the ISM_BC_* values", ISM_ERR_INVALID;
   if (cfg->precision != ISM_PREC_FP64 && cfg->precision != ISM_PREC_MIXED)
     return why = "precision must be ISM_PREC_FP64 or ISM_PREC_MIXED", ISM_ERR_INVALID;
   if (!(cfg->lx > 0.0) || !(cfg->ly > 0.0) || !std::isfinite(cfg->lx) || !std::isfinite(cfg->ly))
@@ -188,19 +189,34 @@ int validate(const ism_config* cfg, std::string& why) {
   return ISM_OK;
 }
 
-// 1D eigenbasis of the coarse factors K = [1 -2 1] and M = [1 6 1]/8 with the boundary rule
-// of the axis (Neumann: one-sided K, M end entry 7/8; periodic: circulant).  Columns of V are
-// orthonormal eigenvectors; theta is the angle whose cosine gives the eigenvalues
-// lambda_K = -2 (1 - cos theta) and lambda_M = (3 + cos theta) / 4.
-void coarse_basis(int nc, bool periodic, std::vector<double>& V, std::vector<double>& theta) {
+// 1D eigenbasis of the coarse factors K = [1 -2 1] and M = [1 6 1]/8 = I + K/8 with the
+// boundary rule of the axis: periodic, circulant; at a Neumann end K = -1 and M = 7/8; at a
+// Dirichlet end K = -3 and M = 5/8.  Columns of V are orthonormal eigenvectors; theta is the
+// angle whose cosine gives the eigenvalues lambda_K = -2 (1 - cos theta) and
+// lambda_M = (3 + cos theta) / 4.  The mirror ghost of each end fixes the modes: cos or
+// sin(theta (I + 1/2)) for a Neumann or Dirichlet low end, with theta nc = pi k (two Neumann
+// ends), pi (k + 1) (two Dirichlet ends) or pi (k + 1/2) (one of each).
+void coarse_basis(int nc, int bc, std::vector<double>& V, std::vector<double>& theta) {
   V.assign(size_t(nc) * nc, 0.0);
   theta.assign(nc, 0.0);
   const double pi = 3.14159265358979323846;
-  if (!periodic) {
+  if (bc != ISM_BC_PERIODIC) {
+    const bool sine = bc == ISM_BC_DIRICHLET || bc == ISM_BC_DIRICHLET_NEUMANN;
     for (int k = 0; k < nc; ++k) {
-      const double sc = std::sqrt((k == 0 ? 1.0 : 2.0) / nc);
-      theta[k] = pi * k / nc;
-      for (int I = 0; I < nc; ++I) V[size_t(I) * nc + k] = sc * std::cos(pi * k * (I + 0.5) / nc);
+      double sc = std::sqrt(2.0 / nc), kk = k;
+      if (bc == ISM_BC_NEUMANN) {
+        if (k == 0) sc = std::sqrt(1.0 / nc);
+      } else if (bc == ISM_BC_DIRICHLET) {
+        kk = k + 1;
+        if (k == nc - 1) sc = std::sqrt(1.0 / nc);
+      } else {
+        kk = k + 0.5;
+      }
+      theta[k] = pi * kk / nc;
+      for (int I = 0; I < nc; ++I) {
+        const double a = pi * kk * (I + 0.5) / nc;
+        V[size_t(I) * nc + k] = sc * (sine ? std::sin(a) : std::cos(a));
+      }
     }
     return;
   }
@@ -531,6 +547,18 @@ int acm_inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, 
   return ISM_OK;
 }
 
+// The MEAN_B slots: the mean of each right-hand side when A is singular (the compatibility
+// projection b~ = b - mean b), else 0.
+int mean_of_b(ism_ctx* c, const double* b) {
+  if (!c->singular) {
+    HIPCHK(c, hipMemsetAsync(c->scal + size_t(MEAN_B) * c->g.batch, 0, sizeof(double) * c->g.batch,
+                             c->stream));
+    return ISM_OK;
+  }
+  LAUNCH(c, ism::launch_tile_sum(c->g, b, c->p_sum, c->stream));
+  return finalize(c, c->p_sum, ism::SUM, 1.0 / double(c->g.plane), MEAN_B);
+}
+
 template <typename T>
 int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -540,8 +568,7 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   const int B = g.batch;
   hipStream_t s = c->stream;
   int rcode;
-  LAUNCH(c, ism::launch_tile_sum(g, b, c->p_sum, s));
-  if ((rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(g.plane), MEAN_B))) return rcode;
+  if ((rcode = mean_of_b(c, b))) return rcode;
 
   std::vector<double> bnorm(B, 0.0), bmax(B, 0.0), den(B, 1.0), target(B);
   int cycles = 0, outer = 0, status = ISM_OK;
@@ -598,7 +625,7 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
     }
     LAUNCH(c, ism::launch_add_to<T>(g, x, e, s));
   }
-  if (status >= 0) {
+  if (status >= 0 && c->singular) {
     LAUNCH(c, ism::launch_tile_sum(g, x, c->p_sum, s));
     if ((rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(g.plane), MEAN_X))) return rcode;
     LAUNCH(c, ism::launch_sub_scalar(g, x, c->scal + size_t(MEAN_X) * B, 1, 0, s));
@@ -673,6 +700,11 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   g.ncy = g.ny / g.n;
   g.per_x = cfg->bc_x == ISM_BC_PERIODIC;
   g.per_y = cfg->bc_y == ISM_BC_PERIODIC;
+  auto dir_lo = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_DIRICHLET_NEUMANN; };
+  auto dir_hi = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_NEUMANN_DIRICHLET; };
+  g.dmask = (dir_lo(cfg->bc_x) ? 1 : 0) | (dir_hi(cfg->bc_x) ? 2 : 0) |
+            (dir_lo(cfg->bc_y) ? 4 : 0) | (dir_hi(cfg->bc_y) ? 8 : 0);
+  c->singular = g.dmask == 0;
   g.plane = (long long)g.nx * g.ny;
   g.cplane = (long long)g.ncx * g.ncy;
   c->h = cfg->lx / cfg->nx;
@@ -751,8 +783,8 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
 
   // coarse tables (host, FP64), uploaded once
   std::vector<double> Vx, Vy, thx, thy;
-  coarse_basis(g.ncx, g.per_x, Vx, thx);
-  coarse_basis(g.ncy, g.per_y, Vy, thy);
+  coarse_basis(g.ncx, cfg->bc_x, Vx, thx);
+  coarse_basis(g.ncy, cfg->bc_y, Vy, thy);
   std::vector<double> inv(size_t(g.cplane));
   for (int l = 0; l < g.ncy; ++l)
     for (int k = 0; k < g.ncx; ++k) {
@@ -762,7 +794,8 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
       const double lam = cfg->coarse_stencil == ISM_COARSE_GMG5  ? kx + ky
                          : cfg->coarse_stencil == ISM_COARSE_ACM ? double(g.n) * (kx + ky)
                                                                  : kx * my + mx * ky;
-      inv[size_t(l) * g.ncx + k] = (l == 0 && k == 0) ? 0.0 : 1.0 / lam;
+      // the constant mode is dropped only when A is singular (no Dirichlet face)
+      inv[size_t(l) * g.ncx + k] = (c->singular && l == 0 && k == 0) ? 0.0 : 1.0 / lam;
     }
   he = hipMemcpyAsync(c->Vx, Vx.data(), sizeof(double) * Vx.size(), hipMemcpyHostToDevice, c->stream);
   if (he == hipSuccess)
@@ -946,8 +979,7 @@ int ism_coarse_stencil(ism_handle c, double* coef) {
 int ism_outer_residual(ism_handle c, const double* b, const double* x, double* r) {
   if (!c) return ISM_ERR_INVALID;
   if (!b || !x || !r) return set_err(c, ISM_ERR_INVALID, "bad arguments");
-  LAUNCH(c, ism::launch_tile_sum(c->g, b, c->p_sum, c->stream));
-  int rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(c->g.plane), MEAN_B);
+  int rcode = mean_of_b(c, b);
   if (rcode) return rcode;
   Partials p{nullptr, nullptr, nullptr, nullptr};
   LAUNCH(c, ism::launch_outer_residual<double>(c->g, b, x, c->scal + size_t(MEAN_B) * c->g.batch, c->h2,

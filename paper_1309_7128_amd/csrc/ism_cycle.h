@@ -192,8 +192,18 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
   constexpr int G = N / CPL;  // lanes per coarse tile
   constexpr double inv2n = 1.0 / double(2 * N);
-  constexpr T third = T(1) / T(3);
   const int lane = threadIdx.x & (kWave - 1);
+  // Inverse diagonals, uniform over the walk.  The diagonal is 4, less one per Neumann wall
+  // face, plus one per Dirichlet wall face (its ghost -e counts twice).  y part of the first
+  // and last row (2 on a periodic axis), x part of the west and east wall cells; then
+  // 1 / diagonal for the first, middle and last row of an interior cell (ic*) and of the
+  // wall cells (iw*, ie*).
+  const int mys = g.per_y ? 2 : ((g.dmask & kDirS) ? 3 : 1);
+  const int myn = g.per_y ? 2 : ((g.dmask & kDirN) ? 3 : 1);
+  const int mxw = (g.dmask & kDirW) ? 3 : 1, mxe = (g.dmask & kDirE) ? 3 : 1;
+  const T icS = inv_diag<T>(2 + mys), icN = inv_diag<T>(2 + myn);
+  const T iwS = inv_diag<T>(mxw + mys), iwM = inv_diag<T>(mxw + 2), iwN = inv_diag<T>(mxw + myn);
+  const T ieS = inv_diag<T>(mxe + mys), ieM = inv_diag<T>(mxe + 2), ieN = inv_diag<T>(mxe + myn);
   const int ys = y0 - H;
   const int yend = y0 + min(L, g.ny - y0) + H;  // rows ys .. yend - 1 are read
 
@@ -219,9 +229,13 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
     for (int i = lane; i < nr * S::NC; i += kWave) {
       const int rr = i / S::NC, c = i - rr * S::NC;
       int J = J0 + rr, I = I0 + c;
-      J = g.per_y ? imod(J, g.ncy) : min(max(J, 0), g.ncy - 1);
-      I = g.per_x ? imod(I, g.ncx) : min(max(I, 0), g.ncx - 1);
-      sE[i] = Eb[(long long)J * g.ncx + I];
+      // a ghost centre behind a wall mirrors the first one, negated behind a Dirichlet wall
+      double sg = 1.0;
+      if (g.per_y) J = imod(J, g.ncy);
+      else sg = ghost_clamp(J, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
+      if (g.per_x) I = imod(I, g.ncx);
+      else sg *= ghost_clamp(I, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
+      sE[i] = sg * Eb[(long long)J * g.ncx + I];
     }
     // the block is written and read by this wave only: order its writes before the reads
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -249,16 +263,14 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   };
 
   // The ring: e and rhs of rows t - P + 1 .. t in slot (row - ys) mod P, and per slot the
-  // row's y-neighbour class: the inverse neighbour count for cells with both x-neighbours (0
-  // behind a wall and for rows not read yet, which the half-steps then leave at 0) and the
-  // number of existing y-neighbours.
+  // row's inverse diagonals (uniform): for cells with both x-neighbours, and (EDGE) for the
+  // west and east wall cells; 0 for rows off the grid and rows not read yet, which the
+  // half-steps then leave at 0.
   T e[P][CPL], r[P][CPL];
-  T invs[P];
-  int mys[P];
+  T invs[P], iws[P], ies[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) {
-    invs[q] = T(0);
-    mys[q] = 0;
+    invs[q] = iws[q] = ies[q] = T(0);
 #pragma unroll
     for (int p = 0; p < CPL; ++p) e[q][p] = r[q][p] = T(0);
   }
@@ -353,9 +365,12 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 #pragma unroll
             for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
           }
-          const int my = !row_in ? 0 : (g.per_y ? 2 : 2 - (t == 0) - (t == g.ny - 1));
-          invs[ph] = uniform(my == 2 ? T(0.25) : (my == 1 ? third : T(0)));
-          mys[ph] = my;
+          const bool first = !g.per_y && t == 0, last = !g.per_y && t == g.ny - 1;
+          invs[ph] = uniform(!row_in ? T(0) : (first ? icS : (last ? icN : T(0.25))));
+          if (EDGE) {  // the wall cells of the row
+            iws[ph] = uniform(!row_in ? T(0) : (first ? iwS : (last ? iwN : iwM)));
+            ies[ph] = uniform(!row_in ? T(0) : (first ? ieS : (last ? ieN : ieM)));
+          }
         }
 
         // half-step k (odd red, even black) on row t - k
@@ -372,13 +387,12 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             const T sum = ((w + ea) + e[sb][p]) + e[sa][p];
             T inv = invs[sc];
             if (EDGE) {
-              // 1 / (existing neighbours): 1, 1/2 or 1/4 as a power of two, 1/3 for three;
-              // 0 behind a wall (the cell then stays 0)
+              // 1 / diagonal: the row's interior value, the row's wall-cell value at the wall
+              // column, or 0 behind a wall (the cell then stays 0)
               const int i = cx + p;
-              const int m = (i > 0) + (i < g.nx - 1) + mys[sc];
-              const T pw = T(__builtin_ldexpf(1.0f, -(m >> 1)));
-              inv = m == 3 ? third : pw;
-              inv = (unsigned(i) < unsigned(g.nx) && mys[sc] > 0) ? inv : T(0);
+              inv = i == 0 ? iws[sc] : inv;
+              inv = i == g.nx - 1 ? ies[sc] : inv;
+              inv = unsigned(i) < unsigned(g.nx) ? inv : T(0);
             }
             e[sc][p] = (sum - r[sc][p]) * inv;
           }
@@ -389,6 +403,7 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
         if (o >= y0) {
           const int so = (ph - H + P) % P, sb = (ph - H - 1 + P) % P, sa = (ph - H + 1 + P) % P;
           const bool hs = g.per_y || o > 0, hn = g.per_y || o < g.ny - 1;
+          const bool ds = !hs && (g.dmask & kDirS), dn = !hn && (g.dmask & kDirN);
           double d[CPL];
 #pragma unroll
           for (int p = 0; p < CPL; ++p) {
@@ -396,7 +411,10 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             const T w = p > 0 ? e[so][p - 1] : lane_shift<kDppFromLeft>(e[so][CPL - 1]);
             const T ea = p < CPL - 1 ? e[so][p + 1] : lane_shift<kDppFromRight>(e[so][0]);
             const bool hw = !EDGE || cx + p > 0, he = !EDGE || cx + p < g.nx - 1;
-            d[p] = double(r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn));
+            const bool dw = EDGE && cx + p == 0 && (g.dmask & kDirW);
+            const bool de = EDGE && cx + p == g.nx - 1 && (g.dmask & kDirE);
+            d[p] = double(r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn, dw,
+                                             de, ds, dn));
             acc += d[p];
           }
           if (psq) {  // squared sums only when a convergence check reads them

@@ -4,11 +4,15 @@
 // Arithmetic conventions (shared by every kernel so that a cell value never depends on the
 // kernel that produced it):
 //  * A'e (the 5-point Laplacian times h^2) in difference form,
-//    ((e_W - e_C) + (e_E - e_C)) + (e_S - e_C)) + (e_N - e_C), a wall neighbour's term being
-//    absent (Sec. 2.3 stencil, Sec. 4.1 walls).
+//    ((e_W - e_C) + (e_E - e_C)) + (e_S - e_C)) + (e_N - e_C) (Sec. 2.3 stencil).  Behind
+//    a Neumann wall the term is absent; behind a Dirichlet wall the neighbour is the mirror
+//    ghost -e_C and the term is (-e_C) - e_C (Sec. 4.1 lists both wall kinds).
 //  * Red-black Gauss-Seidel (Sec. 3.1): red is (i + j) even; a cell is set to
-//    (((e_W + e_E) + e_S) + e_N - rhs_C) * (1 / m_C), m_C its number of existing neighbours
-//    and a missing neighbour contributing 0.
+//    (((e_W + e_E) + e_S) + e_N - rhs_C) * (1 / m_C), a missing neighbour contributing 0 and
+//    m_C the diagonal: 4, less one per Neumann wall face, plus one per Dirichlet wall face.
+//  * Bilinear interpolation (Eq. 5) reaches a ghost coarse centre behind a wall: the
+//    mirror image of the first centre, with the same value (Neumann) or the negated value
+//    (Dirichlet).
 //  * Bilinear prolongation (Eq. 5) evaluated in FP64 and added to the fine value in FP64,
 //    then rounded to the fine type.
 // The library is compiled with -ffp-contract=off so these expressions round exactly as
@@ -50,23 +54,77 @@ __device__ __forceinline__ bool map_cell(const Geo& g, int& i, int& j) {
   return true;
 }
 
-template <typename T>
-__device__ __forceinline__ T inv_count(const Geo& g, int i, int j) {
-  int m = 4;
-  if (!g.per_x) m -= (i == 0) + (i == g.nx - 1);
-  if (!g.per_y) m -= (j == 0) + (j == g.ny - 1);
-  constexpr T third = T(1) / T(3);
-  return m == 4 ? T(0.25) : (m == 3 ? third : (m == 2 ? T(0.5) : T(1)));
+enum : int { kDirW = 1, kDirE = 2, kDirS = 4, kDirN = 8 };
+
+// The wall faces of a cell: whether each neighbour exists (h*) and, where it does not,
+// whether the face is a Dirichlet wall (d*).
+struct CellFaces {
+  bool hw, he, hs, hn, dw, de, ds, dn;
+};
+
+__device__ __forceinline__ CellFaces cell_faces(const Geo& g, int i, int j) {
+  CellFaces f;
+  f.hw = g.per_x || i > 0;
+  f.he = g.per_x || i < g.nx - 1;
+  f.hs = g.per_y || j > 0;
+  f.hn = g.per_y || j < g.ny - 1;
+  f.dw = !f.hw && (g.dmask & kDirW);
+  f.de = !f.he && (g.dmask & kDirE);
+  f.ds = !f.hs && (g.dmask & kDirS);
+  f.dn = !f.hn && (g.dmask & kDirN);
+  return f;
 }
 
-// A'e at a cell from its four neighbours, difference form; absent terms skipped.
+// 1 / m for a diagonal m in 1 .. 6, each constant rounded once to T.
 template <typename T>
-__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, bool hw, bool he, bool hs, bool hn) {
-  T dw = hw ? T(w - c) : T(0);
-  T de = he ? T(e - c) : T(0);
-  T ds = hs ? T(s - c) : T(0);
-  T dn = hn ? T(n - c) : T(0);
-  return ((dw + de) + ds) + dn;
+__device__ __forceinline__ T inv_diag(int m) {
+  constexpr T third = T(1) / T(3), fifth = T(1) / T(5), sixth = T(1) / T(6);
+  return m == 4 ? T(0.25)
+                : (m == 3 ? third
+                          : (m == 5 ? fifth : (m == 2 ? T(0.5) : (m == 6 ? sixth : T(1)))));
+}
+
+template <typename T>
+__device__ __forceinline__ T inv_count(const Geo& g, int i, int j) {
+  const CellFaces f = cell_faces(g, i, j);
+  const int m = 4 - (!f.hw && !f.dw) - (!f.he && !f.de) - (!f.hs && !f.ds) - (!f.hn && !f.dn) +
+                f.dw + f.de + f.ds + f.dn;
+  return inv_diag<T>(m);
+}
+
+// One face term of A'e: the difference to an existing neighbour, (-c) - c across a
+// Dirichlet wall, nothing across a Neumann wall.
+template <typename T>
+__device__ __forceinline__ T face_term(T c, T v, bool has, bool dir) {
+  return has ? T(v - c) : (dir ? T(T(-c) - c) : T(0));
+}
+
+// A'e at a cell from its four neighbours, difference form.
+template <typename T>
+__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, bool hw, bool he, bool hs, bool hn,
+                                  bool dw = false, bool de = false, bool ds = false,
+                                  bool dn = false) {
+  return ((face_term(c, w, hw, dw) + face_term(c, e, he, de)) + face_term(c, s, hs, ds)) +
+         face_term(c, n, hn, dn);
+}
+
+template <typename T>
+__device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, const CellFaces& f) {
+  return lap5<T>(c, w, e, s, n, f.hw, f.he, f.hs, f.hn, f.dw, f.de, f.ds, f.dn);
+}
+
+// Coarse index I of a non-periodic axis clamped into 0 .. nc - 1, and the sign of the
+// value there: -1 for the ghost behind a Dirichlet wall (lo_dir / hi_dir).
+__device__ __forceinline__ double ghost_clamp(int& I, int nc, bool lo_dir, bool hi_dir) {
+  if (I < 0) {
+    I = 0;
+    return lo_dir ? -1.0 : 1.0;
+  }
+  if (I > nc - 1) {
+    I = nc - 1;
+    return hi_dir ? -1.0 : 1.0;
+  }
+  return 1.0;
 }
 
 __device__ __forceinline__ double wave_sum_group(double v, int group) {

@@ -12,6 +12,8 @@ struct Geo {
   int nx, ny, batch;   // fine grid and number of independent grids
   int n, ncx, ncy;     // tile edge and coarse grid
   int per_x, per_y;    // 1 if the axis is periodic
+  int dmask;           // Dirichlet wall faces: bit 0 west, 1 east, 2 south, 3 north (others
+                       // of a non-periodic axis are Neumann walls)
   int log2n;           // log2 of the tile edge
   long long plane;     // nx * ny
   long long cplane;    // ncx * ncy

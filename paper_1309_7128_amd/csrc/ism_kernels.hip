@@ -104,19 +104,18 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geo g, const T* __restrict_
   if (i < g.nx) {
     const int iw = g.per_x ? imod(i - 1, g.nx) : i - 1;
     const int ie = g.per_x ? imod(i + 1, g.nx) : i + 1;
-    const bool hw = g.per_x || i > 0, he = g.per_x || i < g.nx - 1;
     for (int r = wave; r < g.n; r += 4) {
       const int j = J * g.n + r;
       const int js = g.per_y ? imod(j - 1, g.ny) : j - 1;
       const int jn = g.per_y ? imod(j + 1, g.ny) : j + 1;
-      const bool hs = g.per_y || j > 0, hn = g.per_y || j < g.ny - 1;
+      const CellFaces f = cell_faces(g, i, j);
       const T* row = eb + (long long)j * g.nx;
       T c = row[i];
-      T w = hw ? row[iw] : T(0);
-      T ee = he ? row[ie] : T(0);
-      T s = hs ? eb[(long long)js * g.nx + i] : T(0);
-      T nn = hn ? eb[(long long)jn * g.nx + i] : T(0);
-      T res = rb[(long long)j * g.nx + i] - lap5<T>(c, w, ee, s, nn, hw, he, hs, hn);
+      T w = f.hw ? row[iw] : T(0);
+      T ee = f.he ? row[ie] : T(0);
+      T s = f.hs ? eb[(long long)js * g.nx + i] : T(0);
+      T nn = f.hn ? eb[(long long)jn * g.nx + i] : T(0);
+      T res = rb[(long long)j * g.nx + i] - lap5<T>(c, w, ee, s, nn, f);
       double d = double(res);
       acc += d;
       acc2 += d * d;
@@ -156,22 +155,25 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
   interp_coord(i, g.n, ilo, X);
   interp_coord(j, g.n, jlo, Y);
   int ihi = ilo + 1, jhi = jlo + 1;
+  double sil = 1.0, sih = 1.0, sjl = 1.0, sjh = 1.0;  // -1 at a ghost behind a Dirichlet wall
   if (g.per_x) {
     ilo = imod(ilo, g.ncx);
     ihi = imod(ihi, g.ncx);
   } else {
-    ilo = max(ilo, 0);
-    ihi = min(ihi, g.ncx - 1);
+    sil = ghost_clamp(ilo, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
+    sih = ghost_clamp(ihi, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
   }
   if (g.per_y) {
     jlo = imod(jlo, g.ncy);
     jhi = imod(jhi, g.ncy);
   } else {
-    jlo = max(jlo, 0);
-    jhi = min(jhi, g.ncy - 1);
+    sjl = ghost_clamp(jlo, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
+    sjh = ghost_clamp(jhi, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
   }
-  const double p = bilinear(Eb[jlo * g.ncx + ilo], Eb[jlo * g.ncx + ihi], Eb[jhi * g.ncx + ilo],
-                            Eb[jhi * g.ncx + ihi], X, Y);
+  // the signs multiply exactly, so negating a corner value commutes with the rounding
+  const double p = bilinear(sjl * sil * Eb[jlo * g.ncx + ilo], sjl * sih * Eb[jlo * g.ncx + ihi],
+                            sjh * sil * Eb[jhi * g.ncx + ilo], sjh * sih * Eb[jhi * g.ncx + ihi],
+                            X, Y);
   T* ec = e + (long long)blockIdx.z * g.plane + (long long)j * g.nx + i;
   *ec = assign ? T(p) : T(double(*ec) + p);
 }
@@ -200,20 +202,19 @@ __global__ __launch_bounds__(kBlock) void k_outer_residual(Geo g, const double* 
   if (i < g.nx) {
     const int iw = g.per_x ? imod(i - 1, g.nx) : i - 1;
     const int ie = g.per_x ? imod(i + 1, g.nx) : i + 1;
-    const bool hw = g.per_x || i > 0, he = g.per_x || i < g.nx - 1;
     for (int r = wave; r < g.n; r += 4) {
       const int j = J * g.n + r;
       const int js = g.per_y ? imod(j - 1, g.ny) : j - 1;
       const int jn = g.per_y ? imod(j + 1, g.ny) : j + 1;
-      const bool hs = g.per_y || j > 0, hn = g.per_y || j < g.ny - 1;
+      const CellFaces f = cell_faces(g, i, j);
       const double* row = xb + (long long)j * g.nx;
       double c = row[i];
-      double w = hw ? row[iw] : 0.0;
-      double ee = he ? row[ie] : 0.0;
-      double s = hs ? xb[(long long)js * g.nx + i] : 0.0;
-      double nn = hn ? xb[(long long)jn * g.nx + i] : 0.0;
+      double w = f.hw ? row[iw] : 0.0;
+      double ee = f.he ? row[ie] : 0.0;
+      double s = f.hs ? xb[(long long)js * g.nx + i] : 0.0;
+      double nn = f.hn ? xb[(long long)jn * g.nx + i] : 0.0;
       double bp = h2 * (bb[(long long)j * g.nx + i] - mb);
-      double res = bp - lap5<double>(c, w, ee, s, nn, hw, he, hs, hn);
+      double res = bp - lap5<double>(c, w, ee, s, nn, f);
       if (rT) rT[off + (long long)j * g.nx + i] = T(res);
       acc += res;
       acc2 += res * res;
@@ -405,8 +406,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
 // ----------------------------------------------------------------------------------------
 // Coarse 9-point stencil from the face sums of Eq. 6 (x faces) and Eq. 7 (y faces): for
 // each fine face on a coarse face, the outward derivative of the bilinear interpolant of
-// the coarse unknowns; walls carry no flux and the clamped interpolation folds an
-// off-grid neighbour onto the cell itself.  One thread per coarse cell.
+// the coarse unknowns.  A Neumann wall carries no flux; a Dirichlet wall carries the flux
+// towards the negated ghost centre.  An off-grid (ghost) neighbour is folded onto the cell
+// it mirrors, added (Neumann) or subtracted (Dirichlet).  One thread per coarse cell.
 // ----------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
                                                             double* __restrict__ coef) {
@@ -417,9 +419,11 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) c[a][b] = 0.0;
   const int n = g.n, half = n / 2;
-  const bool openE = g.per_x || I < g.ncx - 1, openW = g.per_x || I > 0;
-  const bool openN = g.per_y || J < g.ncy - 1, openS = g.per_y || J > 0;
-  if (gmg5) {  // unit 5-point stencil at the coarse spacing, no flux through a wall
+  const bool openE = g.per_x || I < g.ncx - 1 || (g.dmask & kDirE);
+  const bool openW = g.per_x || I > 0 || (g.dmask & kDirW);
+  const bool openN = g.per_y || J < g.ncy - 1 || (g.dmask & kDirN);
+  const bool openS = g.per_y || J > 0 || (g.dmask & kDirS);
+  if (gmg5) {  // unit 5-point stencil at the coarse spacing
     if (openE) c[1][2] += 1.0, c[1][1] -= 1.0;
     if (openW) c[1][0] += 1.0, c[1][1] -= 1.0;
     if (openN) c[2][1] += 1.0, c[1][1] -= 1.0;
@@ -459,26 +463,28 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
     }
   }
   if (!g.per_x) {
+    const double sw = (g.dmask & kDirW) ? -1.0 : 1.0, se = (g.dmask & kDirE) ? -1.0 : 1.0;
     if (I == 0)
       for (int a = 0; a < 3; ++a) {
-        c[a][1] += c[a][0];
+        c[a][1] += sw * c[a][0];
         c[a][0] = 0.0;
       }
     if (I == g.ncx - 1)
       for (int a = 0; a < 3; ++a) {
-        c[a][1] += c[a][2];
+        c[a][1] += se * c[a][2];
         c[a][2] = 0.0;
       }
   }
   if (!g.per_y) {
+    const double ss = (g.dmask & kDirS) ? -1.0 : 1.0, sn = (g.dmask & kDirN) ? -1.0 : 1.0;
     if (J == 0)
       for (int b = 0; b < 3; ++b) {
-        c[1][b] += c[0][b];
+        c[1][b] += ss * c[0][b];
         c[0][b] = 0.0;
       }
     if (J == g.ncy - 1)
       for (int b = 0; b < 3; ++b) {
-        c[1][b] += c[2][b];
+        c[1][b] += sn * c[2][b];
         c[2][b] = 0.0;
       }
   }
@@ -521,7 +527,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_u(Geo g, const double* __restri
     const double* pr = p + bi * g.plane + (long long)j * g.nx;
     double val;
     if (g.per_x) val = (pr[f] - pr[f == 0 ? g.nx - 1 : f - 1]) / h;
-    else val = (f == 0 || f == g.nx) ? 0.0 : (pr[f] - pr[f - 1]) / h;
+    else if (f == 0) val = (g.dmask & kDirW) ? (pr[0] - (-pr[0])) / h : 0.0;  // ghost -p
+    else if (f == g.nx) val = (g.dmask & kDirE) ? ((-pr[g.nx - 1]) - pr[g.nx - 1]) / h : 0.0;
+    else val = (pr[f] - pr[f - 1]) / h;
     gu[k] = val;
   }
 }
@@ -535,8 +543,17 @@ __global__ __launch_bounds__(kBlock) void k_grad_v(Geo g, const double* __restri
     const int rem = int(k - bi * per);
     const int f = rem / g.nx, i = rem - f * g.nx;
     const double* pb = p + bi * g.plane;
-    gv[k] = (f == 0 || f == g.ny) ? 0.0
-                                  : (pb[(long long)f * g.nx + i] - pb[(long long)(f - 1) * g.nx + i]) / h;
+    double val;
+    if (f == 0) {
+      const double q = pb[i];
+      val = (g.dmask & kDirS) ? (q - (-q)) / h : 0.0;
+    } else if (f == g.ny) {
+      const double q = pb[(long long)(g.ny - 1) * g.nx + i];
+      val = (g.dmask & kDirN) ? ((-q) - q) / h : 0.0;
+    } else {
+      val = (pb[(long long)f * g.nx + i] - pb[(long long)(f - 1) * g.nx + i]) / h;
+    }
+    gv[k] = val;
   }
 }
 
@@ -595,9 +612,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_adjoint(Geo g, const double* __
     } else {
       if (i >= 1) t += ur[i];
       if (i <= g.nx - 2) t -= ur[i + 1];
+      // a Dirichlet wall face's gradient is +-2 p / h of the cell next to it
+      if (i == 0 && (g.dmask & kDirW)) t += 2.0 * ur[0];
+      if (i == g.nx - 1 && (g.dmask & kDirE)) t -= 2.0 * ur[g.nx];
     }
     if (j >= 1) t += vb[(long long)j * g.nx + i];
     if (j <= g.ny - 2) t -= vb[(long long)(j + 1) * g.nx + i];
+    if (j == 0 && (g.dmask & kDirS)) t += 2.0 * vb[i];
+    if (j == g.ny - 1 && (g.dmask & kDirN)) t -= 2.0 * vb[(long long)g.ny * g.nx + i];
     p[k] = t / h;
   }
 }
@@ -627,15 +649,14 @@ __global__ __launch_bounds__(kBlock) void k_agglomerate(Geo g, const double* __r
         const int i = 2 * I + di, j = 2 * J + dj;
         double res = rb[(long long)j * g.nx + i];
         if (eb) {
-          const bool hw = g.per_x || i > 0, he = g.per_x || i < g.nx - 1;
-          const bool hs = g.per_y || j > 0, hn = g.per_y || j < g.ny - 1;
+          const CellFaces fc = cell_faces(g, i, j);
           const double* row = eb + (long long)j * g.nx;
           const double c = row[i];
-          const double w = hw ? row[g.per_x ? imod(i - 1, g.nx) : i - 1] : 0.0;
-          const double ee = he ? row[g.per_x ? imod(i + 1, g.nx) : i + 1] : 0.0;
-          const double sv = hs ? eb[(long long)(g.per_y ? imod(j - 1, g.ny) : j - 1) * g.nx + i] : 0.0;
-          const double nv = hn ? eb[(long long)(g.per_y ? imod(j + 1, g.ny) : j + 1) * g.nx + i] : 0.0;
-          res = res - scale * lap5<double>(c, w, ee, sv, nv, hw, he, hs, hn);
+          const double w = fc.hw ? row[g.per_x ? imod(i - 1, g.nx) : i - 1] : 0.0;
+          const double ee = fc.he ? row[g.per_x ? imod(i + 1, g.nx) : i + 1] : 0.0;
+          const double sv = fc.hs ? eb[(long long)(g.per_y ? imod(j - 1, g.ny) : j - 1) * g.nx + i] : 0.0;
+          const double nv = fc.hn ? eb[(long long)(g.per_y ? imod(j + 1, g.ny) : j + 1) * g.nx + i] : 0.0;
+          res = res - scale * lap5<double>(c, w, ee, sv, nv, fc);
         }
         sum += res;
         sq += res * res;

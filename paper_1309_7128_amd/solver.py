@@ -13,7 +13,9 @@ import torch
 
 from . import _lib as L
 
-_BC = {"neumann": L.ISM_BC_NEUMANN, "periodic": L.ISM_BC_PERIODIC}
+_BC = {"neumann": L.ISM_BC_NEUMANN, "periodic": L.ISM_BC_PERIODIC,
+       "dirichlet": L.ISM_BC_DIRICHLET, "neumann-dirichlet": L.ISM_BC_NEUMANN_DIRICHLET,
+       "dirichlet-neumann": L.ISM_BC_DIRICHLET_NEUMANN}
 _PREC = {"fp64": L.ISM_PREC_FP64, "mixed": L.ISM_PREC_MIXED}
 
 
@@ -40,8 +42,11 @@ def _check(code, handle=None, lib=None):
 class Solver:
     """One handle of the ISM pressure solver for a fixed grid (C ABI: ism_create).
 
-    The solve is A x = b - mean(b) with A the cell-centred 5-point Laplacian of an
-    nx x ny grid of square cells (size lx / nx), for `batch` independent grids."""
+    The solve is A x = b~ with A the cell-centred 5-point Laplacian of an nx x ny grid of
+    square cells (size lx / nx), for `batch` independent grids.  bc_x / bc_y: "neumann",
+    "periodic", "dirichlet" (zero pressure on both faces), "neumann-dirichlet" or
+    "dirichlet-neumann" (low face first).  Without a Dirichlet face b~ = b - mean(b) and x
+    is the zero-mean solution; with one, b~ = b."""
 
     def __init__(self, nx, ny, batch=1, bc_x="neumann", bc_y="neumann", coarsen=16, lx=1.0,
                  ly=None, precision="fp64", nu=4, rtol=1e-10, inner_rtol=1e-3,

@@ -10,14 +10,16 @@ from paper_1309_7128_amd import inputs
 from tests.gpu_util import announce, dev, host, solver
 
 pytestmark = pytest.mark.gpu
-N = O.NEUMANN
+N, P, D = O.NEUMANN, O.PERIODIC, O.DIRICHLET
+ND = O.NEUMANN_DIRICHLET
 
 
-def _oracle_grad(w_u, w_v, h, exact):
-    """d/du sum(w . (u - G A^+ Pi D u)) = w - D^T A^+ Pi G^T w (A, A^+ symmetric)."""
-    g = O.grad_adjoint(w_u, w_v, h)
+def _oracle_grad(w_u, w_v, h, exact, bx=N, by=N):
+    """d/du sum(w . (u - G A^+ Pi D u)) = w - D^T A^+ Pi G^T w (A, A^+ symmetric; Pi is the
+    mean removal when A is singular, else the identity)."""
+    g = O.grad_adjoint(w_u, w_v, h, bx, by)
     lam = exact(g)
-    du, dv = O.div_adjoint(lam, h)
+    du, dv = O.div_adjoint(lam, h, bx)
     return w_u - du, w_v - dv
 
 
@@ -54,6 +56,45 @@ def test_fd_and_dense_adjoint_64():
     for _ in range(32):
         du, dv = dirs.standard_normal(u0.shape), dirs.standard_normal(v0.shape)
         fd = (L(u0 + eps * du, v0 + eps * dv) - L(u0 - eps * du, v0 - eps * dv)) / (2 * eps)
+        an = np.sum(gu * du) + np.sum(gv * dv)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.sqrt(np.sum(du**2) + np.sum(dv**2)) * scale), (fd, an)
+
+
+def test_fd_and_dense_adjoint_dirichlet_64():
+    """The same gradient checks with zero-pressure walls (periodic x, Neumann bottom,
+    Dirichlet top): the wall faces of the top carry the gradient 2 p / h."""
+    announce("fd64_dirichlet")
+    from paper_1309_7128_amd.autograd import project
+
+    nx = ny = 64
+    s = solver(nx=nx, ny=ny, coarsen=16, precision="fp64", rtol=1e-12, bc_x=P, bc_y=ND)
+    h = s.h
+    rng = np.random.default_rng(10)
+    u0, v0 = rng.uniform(-1, 1, s.u_shape[1:]), rng.uniform(-1, 1, s.v_shape[1:])
+    wu, wv = rng.standard_normal(u0.shape), rng.standard_normal(v0.shape)
+    u = dev(u0).requires_grad_(True)
+    v = dev(v0).requires_grad_(True)
+    un, vn, p = project(u, v, s)
+    # exactly divergence-free: with a Dirichlet face there is no mean to leave behind
+    bn = O.div(host(un).reshape(u0.shape), host(vn).reshape(v0.shape), h, P)
+    assert np.abs(bn).max() <= 1e-9 * np.abs(O.div(u0, v0, h, P)).max()
+    loss = (dev(wu) * un).sum() + (dev(wv) * vn).sum()
+    loss.backward()
+    gu, gv = host(u.grad), host(v.grad)
+    ru, rv = _oracle_grad(wu, wv, h, lambda g: O.dense_solve(g, h, P, ND), P, ND)
+    scale = np.sqrt(np.sum(ru**2) + np.sum(rv**2))
+    err = np.sqrt(np.sum((gu - ru) ** 2) + np.sum((gv - rv) ** 2)) / scale
+    assert err < 1e-6, err
+
+    def L(uu, vv):
+        with torch.no_grad():
+            a, c, _ = project(dev(uu), dev(vv), s)
+            return float((dev(wu) * a).sum() + (dev(wv) * c).sum())
+
+    dirs = np.random.default_rng(11)
+    for _ in range(8):
+        du, dv = dirs.standard_normal(u0.shape), dirs.standard_normal(v0.shape)
+        fd = (L(u0 + 1e-3 * du, v0 + 1e-3 * dv) - L(u0 - 1e-3 * du, v0 - 1e-3 * dv)) / 2e-3
         an = np.sum(gu * du) + np.sum(gv * dv)
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.sqrt(np.sum(du**2) + np.sum(dv**2)) * scale), (fd, an)
 

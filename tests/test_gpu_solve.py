@@ -17,7 +17,8 @@ from paper_1309_7128_amd import inputs
 from tests.gpu_util import announce, dev, host, solver
 
 pytestmark = pytest.mark.gpu
-N, P = O.NEUMANN, O.PERIODIC
+N, P, D = O.NEUMANN, O.PERIODIC, O.DIRICHLET
+ND, DN = O.NEUMANN_DIRICHLET, O.DIRICHLET_NEUMANN
 
 
 def _rhs(u, v, h, bx):
@@ -62,6 +63,48 @@ def test_small_solves_reach_exact_solution(bx, prec, n):
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
     if prec == "mixed":
         assert st["outer_iters"] >= 2
+
+
+@pytest.mark.parametrize("bx,by", [(D, D), (P, ND), (ND, DN), (N, D)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [8, 32])
+def test_dirichlet_solves_reach_exact_solution(bx, by, prec, n):
+    """Zero-pressure walls (Sec. 4.1): A is nonsingular, b is taken as it is and x is not
+    projected; the FP64 form takes the oracle's cycle count."""
+    announce("dirichlet_solve", bx, by, prec, n)
+    nx, ny = 256, 192
+    rng = np.random.default_rng(300 + n)
+    b = rng.standard_normal((ny, nx)) + 0.5  # a nonzero mean must survive
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, bc_y=by, precision=prec, rtol=1e-10, lx=2.0,
+               check_every=1 if prec == "fp64" else 0, nu=2)
+    x, st = s.solve(dev(b))
+    x = host(x).reshape(ny, nx)
+    assert st["status"] == 0
+    assert O.relative_residual(b, x, s.h, bx, by) <= 1e-10
+    xs = O.exact_solve(b, s.h, bx, by)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
+    assert abs(x.mean()) > 1e-3 * np.abs(x).max()  # not zero-mean
+    if prec == "fp64":
+        _, info = O.ism_solve(b, s.h, n, bx, by, nu=2, rtol=1e-10)
+        assert abs(st["cycles"] - info["cycles"]) <= 1
+
+
+def test_dirichlet_outlet_2048_mixed():
+    """A channel-like grid with a zero-pressure top: periodic x, Neumann bottom, Dirichlet
+    top, 2048 x 2048 at 32h, mixed precision to 1e-10, in the benchmark's launch form."""
+    announce("outlet2048")
+    nx = ny = 2048
+    u, v = inputs.smooth64(31, nx, ny)
+    s = solver(nx=nx, ny=ny, coarsen=32, bc_x=P, bc_y=ND, precision="mixed", rtol=1e-10, nu=5)
+    u = u[:, :nx]  # periodic in x: nx faces per row
+    b = O.div(u, v, s.h, P)
+    x, st = s.solve(dev(b))
+    print(st, flush=True)
+    assert st["status"] == 0
+    rel = O.relative_residual(b, host(x).reshape(ny, nx), s.h, P, ND)
+    assert rel <= 1e-10
+    xs = O.exact_solve(b, s.h, P, ND, refine=1)
+    assert np.linalg.norm(host(x).reshape(ny, nx) - xs) / np.linalg.norm(xs) < 1e-6
 
 
 def test_mixed_outer_steps_match_oracle_emulation():
@@ -218,24 +261,24 @@ def test_gmg5_vs_ism_cycle_counts_match_oracle(scheme):
     assert abs(st["cycles"] - info["cycles"]) <= 1
 
 
-@pytest.mark.parametrize("bx", [N, P])
+@pytest.mark.parametrize("bx,by", [(N, N), (P, N), (D, DN)])
 @pytest.mark.parametrize("n", [8, 16])
-def test_acm_matches_oracle(bx, n):
+def test_acm_matches_oracle(bx, by, n):
     """ACM V(0,1) on the GPU against the oracle's (Sec. 3.2, Sec. 4.3.1): same cycle count,
     same limit x*."""
-    announce("acm", bx, n)
+    announce("acm", bx, by, n)
     nx, ny = 256, 128
     rng = np.random.default_rng(230 + n)
     b = rng.standard_normal((ny, nx))
-    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, precision="fp64", rtol=1e-10, check_every=1,
-               coarse_stencil="acm", lx=2.0)
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, bc_y=by, precision="fp64", rtol=1e-10,
+               check_every=1, coarse_stencil="acm", lx=2.0)
     x, st = s.solve(dev(b))
     x = host(x).reshape(ny, nx)
     assert st["status"] == 0
-    assert O.relative_residual(b, x, s.h, bx) <= 1e-10
-    _, info = O.acm_solve(b, s.h, n, bx, rtol=1e-10)
+    assert O.relative_residual(b, x, s.h, bx, by) <= 1e-10
+    _, info = O.acm_solve(b, s.h, n, bx, by, rtol=1e-10)
     assert abs(st["cycles"] - info["cycles"]) <= 1
-    xs = O.exact_solve(b, s.h, bx)
+    xs = O.exact_solve(b, s.h, bx, by)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
 
 

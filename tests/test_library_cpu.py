@@ -58,6 +58,8 @@ def _create(**kw):
     (dict(nx=0), L.ISM_ERR_INVALID),
     (dict(batch=0), L.ISM_ERR_INVALID),
     (dict(bc_x=7), L.ISM_ERR_INVALID),
+    (dict(bc_y=5), L.ISM_ERR_INVALID),
+    (dict(bc_x=-1), L.ISM_ERR_INVALID),
     (dict(precision=3), L.ISM_ERR_INVALID),
     (dict(nu=0), L.ISM_ERR_INVALID),
     (dict(rtol=0.0), L.ISM_ERR_INVALID),
