@@ -500,6 +500,115 @@ class CoarseSolver:
         return E.reshape(Rc.shape) - (E.mean() if self.singular else 0.0), it
 
 
+def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=None,
+                       max_iter=100000):
+    """Block-iterative Gauss-Seidel on A_c E = R_c to an absolute tolerance (Sec. 4: the
+    coarse grid is iterated by block GS, whose blocks run concurrently and which reduces to
+    serial GS on a single block; Sec. 4.3.1: the coarse stage ends when the absolute maximum
+    residual falls below its limit).
+
+    The coarse grid is cut into block x block tiles that are updated concurrently.  Inside a
+    tile the cells are visited in lexicographic order (I fastest), each set from its own
+    equation with the tile's newest values; cells of other tiles keep their values from the
+    previous iteration, so one iteration needs one synchronization.  A cell update is
+    E_C = (R_C - sum over the 8 neighbours of c_nb E_nb) / c_C, the neighbours taken in the
+    order (dj, di) = (-1,-1), (-1,0), (-1,1), (0,-1), (0,1), (1,-1), (1,0), (1,1) and the
+    products summed left to right (C is the (ncy, ncx, 3, 3) stencil of ``coarse_stencil_*``;
+    a periodic axis wraps).  Before each iteration the residual max|R_c - A_c E| is
+    compared with tol_c.  Without a Dirichlet face R_c is first projected to zero mean, the
+    compatibility condition of the singular system.  Returns (E, iterations).
+
+    Pinned by a cell-by-cell loop in the same order (bitwise), by block = grid reducing to
+    the lexicographic ``CoarseSolver.gauss_seidel`` and by convergence to the exact solve."""
+    ncy, ncx = Rc.shape
+    R = np.asarray(Rc, dtype=np.float64)
+    if singular(bc_x, bc_y):
+        R = R - R.mean()
+    E = np.zeros((ncy, ncx)) if E0 is None else np.asarray(E0, dtype=np.float64).copy()
+    per_x, per_y = faces(bc_x) is None, faces(bc_y) is None
+    order = [(dj, di) for dj in (-1, 0, 1) for di in (-1, 0, 1) if (dj, di) != (0, 0)]
+    J, I = np.indices((ncy, ncx))
+
+    def neighbour(a, dj, di):
+        """a at (J+dj, I+di) (0 off a walled grid, where the folded stencil has 0 too)."""
+        jj, ii = J + dj, I + di
+        if per_y:
+            jj = jj % ncy
+        if per_x:
+            ii = ii % ncx
+        ok = (jj >= 0) & (jj < ncy) & (ii >= 0) & (ii < ncx)
+        return np.where(ok, a[np.clip(jj, 0, ncy - 1), np.clip(ii, 0, ncx - 1)], 0.0)
+
+    def residual(E):
+        acc = C[:, :, 1, 1] * E
+        for dj, di in order:
+            acc = acc + C[:, :, dj + 1, di + 1] * neighbour(E, dj, di)
+        return R - acc
+
+    # the visiting order inside a tile, and for each local position the cells it names
+    # (one per tile) with their neighbours' flat indices and whether each lies in the tile
+    flatE = np.arange(ncy * ncx).reshape(ncy, ncx)
+    steps = []
+    for lj in range(block):
+        for li in range(block):
+            cj, ci = J[lj::block, li::block].ravel(), I[lj::block, li::block].ravel()
+            if cj.size == 0:
+                continue
+            nbs = []
+            for dj, di in order:
+                jj, ii = cj + dj, ci + di
+                if per_y:
+                    jj = jj % ncy
+                if per_x:
+                    ii = ii % ncx
+                ok = (jj >= 0) & (jj < ncy) & (ii >= 0) & (ii < ncx)
+                jc, ic = np.clip(jj, 0, ncy - 1), np.clip(ii, 0, ncx - 1)
+                same = ok & (jc // block == cj // block) & (ic // block == ci // block)
+                nbs.append((flatE[jc, ic], ok, same, C[cj, ci, dj + 1, di + 1]))
+            steps.append((flatE[cj, ci], nbs, C[cj, ci, 1, 1]))
+    it = 0
+    while np.max(np.abs(residual(E))) >= tol_c and it < max_iter:
+        new, old = E.ravel().copy(), E.ravel()
+        Rf = R.ravel()
+        for cells, nbs, cc in steps:
+            acc = np.zeros(cells.size)
+            for idx, ok, same, c in nbs:
+                acc = acc + c * np.where(same, new[idx], np.where(ok, old[idx], 0.0))
+            new[cells] = (Rf[cells] - acc) / cc
+        E = new.reshape(ncy, ncx)
+        it += 1
+    return E, it
+
+
+def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-6, x0=None,
+                      block=16, max_fine=1000000):
+    """The paper's simplest accommodative cycling, once per call (Sec. 4.3.1): restrict the
+    fine residual, iterate on the coarse grid by block GS until its absolute maximum
+    residual is below tol_c, prolongate and add, then iterate red-black GS on the fine grid
+    until the absolute maximum of the fine residual is below tol_f.
+
+    Units: the coarse system is R A' P E = R r' with r' = h^2 b~ - A' x as everywhere here,
+    so tol_c is in those units; tol_f bounds max|b~ - A x| (the residual of the pressure
+    equation itself, in the units of b).  The fine criterion is checked before every sweep.
+    Returns (x, info) with info = dict(coarse_iters, fine_iters, ncc_c, ncc_f): one
+    synchronization per coarse block-GS iteration and two per red-black fine iteration
+    (Sec. 4.3), NCC_c = I_c and NCC_f = 2 I_f."""
+    b = np.asarray(b, dtype=np.float64)
+    ny, nx = b.shape
+    bp = h * h * _project(b, bc_x, bc_y)
+    x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    C = coarse_stencil_ism(nx // n, ny // n, n, bc_x, bc_y)
+    Rc = restrict_sum(bp - laplacian(x, bc_x, bc_y), n)
+    E, ic = block_gauss_seidel(C, Rc, tol_c, block, bc_x, bc_y)
+    x = x + prolong_bilinear(E, n, bc_x, bc_y)
+    fi = 0
+    while np.max(np.abs(bp - laplacian(x, bc_x, bc_y))) >= tol_f * h * h and fi < max_fine:
+        x = red_black_gs(x, bp, bc_x, bc_y, sweeps=1)
+        fi += 1
+    return _project(x, bc_x, bc_y), dict(coarse_iters=ic, fine_iters=fi, ncc_c=ic,
+                                         ncc_f=2 * fi)
+
+
 # --------------------------------------------------------------------------------------
 # The exact discrete solution x* (what every solver must converge to)
 # --------------------------------------------------------------------------------------

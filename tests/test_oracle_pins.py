@@ -453,6 +453,85 @@ def test_coarse_gauss_seidel_option():
     assert it > 1
 
 
+def _blockgs_loop(C, R, block, iters, bcx, bcy):
+    """Block-iterative GS written cell by cell: tiles in any order (they only read the
+    previous iteration outside themselves), lexicographic inside a tile."""
+    ncy, ncx = R.shape
+    E = np.zeros((ncy, ncx))
+    order = [(dj, di) for dj in (-1, 0, 1) for di in (-1, 0, 1) if (dj, di) != (0, 0)]
+    for _ in range(iters):
+        old = E.copy()
+        for J in range(ncy):
+            for I in range(ncx):
+                s = 0.0
+                for dj, di in order:
+                    jj, ii = J + dj, I + di
+                    if bcx == P:
+                        ii %= ncx
+                    if bcy == P:
+                        jj %= ncy
+                    if not (0 <= jj < ncy and 0 <= ii < ncx):
+                        continue
+                    same = jj // block == J // block and ii // block == I // block
+                    # inside the tile the lexicographic predecessors are already new
+                    v = E[jj, ii] if same and (jj, ii) < (J, I) else old[jj, ii]
+                    s = s + C[J, I, dj + 1, di + 1] * v
+                E[J, I] = (R[J, I] - s) / C[J, I, 1, 1]
+    return E
+
+
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND), (D, D)])
+def test_block_gauss_seidel_matches_cell_loop(bcx, bcy):
+    ncx, ncy, block = 7, 6, 4
+    C = O.coarse_stencil_ism(ncx, ncy, 8, bcx, bcy)
+    R = np.random.default_rng(30).standard_normal((ncy, ncx))
+    Rp = R - R.mean() if O.singular(bcx, bcy) else R
+    E, it = O.block_gauss_seidel(C, R, 0.0, block, bcx, bcy, max_iter=3)
+    assert it == 3
+    np.testing.assert_array_equal(E, _blockgs_loop(C, Rp, block, 3, bcx, bcy))
+
+
+def test_block_gauss_seidel_one_tile_is_lexicographic_gs():
+    C = O.coarse_stencil_ism(12, 10, 8)
+    R = np.random.default_rng(31).standard_normal((10, 12))
+    E, it = O.block_gauss_seidel(C, R, 1e-9, block=16)
+    cs = O.CoarseSolver(O.coarse_matrix(C))
+    E2, it2 = cs.gauss_seidel(R, tol_c=1e-9)
+    assert it == it2
+    np.testing.assert_allclose(E - E.mean(), E2, atol=1e-12)
+
+
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (DN, P)])
+def test_block_gauss_seidel_converges_to_exact(bcx, bcy):
+    C = O.coarse_stencil_ism(12, 10, 8, bcx, bcy)
+    R = np.random.default_rng(32).standard_normal((10, 12))
+    E, it = O.block_gauss_seidel(C, R, 1e-10, block=4, bc_x=bcx, bc_y=bcy)
+    cs = O.CoarseSolver(O.coarse_matrix(C, bcx, bcy))
+    ref = cs.solve(R)
+    got = E - E.mean() if cs.singular else E
+    np.testing.assert_allclose(got, ref, atol=1e-8 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND)])
+def test_oneshot_accommodative_solve(bcx, bcy):
+    # Sec. 4.3.1: one coarse visit to tol_c, then fine red-black iterations until the
+    # absolute maximum residual is below tol_f; a tighter coarse criterion leaves less fine
+    # work, and with tol_c -> 0 the coarse stage is the exact coarse correction
+    nf, n = 64, 8
+    h = 1.0 / nf
+    b = O.div(*[np.random.default_rng(33).standard_normal(s) for s in
+                (((nf, nf) if bcx == P else (nf, nf + 1)), (nf + 1, nf))], h, bcx)
+    tol_f = 1e-6 * np.abs(b).max()
+    loose, info_l = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-2, tol_f=tol_f)
+    tight, info_t = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-9, tol_f=tol_f)
+    for x, info in ((loose, info_l), (tight, info_t)):
+        bt = b - b.mean() if O.singular(bcx, bcy) else b
+        assert np.abs(bt - O.laplacian(x, bcx, bcy) / h**2).max() < tol_f
+        assert info["ncc_f"] == 2 * info["fine_iters"] and info["ncc_c"] == info["coarse_iters"]
+    assert info_t["coarse_iters"] > info_l["coarse_iters"]
+    assert info_t["fine_iters"] <= info_l["fine_iters"]
+
+
 # ---------------------------------------------------------------- MAC operators
 
 
