@@ -73,6 +73,20 @@ extern "C" {
                              paper compares with (Sec. 3.2, Sec. 4, Sec. 4.3.1); FP64 only;
                              ism_cycle is unsupported on such a handle                         */
 
+/* Cycling (Sec. 4.3.1).  REPEAT: {restrict, exact coarse solve, prolongate, nu sweeps} until
+ * rtol, as described for ism_solve.  ONESHOT: the paper's simplest accommodative cycling,
+ * once per solve: restrict the residual, iterate the coarse grid by block Gauss-Seidel
+ * (Sec. 4; tiles of 16 x 16 coarse cells updated concurrently, lexicographic inside a tile)
+ * until its absolute maximum residual is below coarse_tol, prolongate and add, then iterate
+ * red-black Gauss-Seidel on the fine grid until the absolute maximum residual is below
+ * fine_tol.  Both criteria are in the units of A x = b~ (the coarse residual divided by h^2),
+ * which are the paper's on its h = 1 grids.  Every coarse iteration and every fine iteration
+ * is followed by one convergence read-back.  FP64, ISM or GMG5 stencil only; rtol,
+ * max_outer and nu are not used; max_cycles caps each stage's iterations.  The grids of a
+ * batch iterate together until all of them meet a criterion. */
+#define ISM_CYCLE_REPEAT 0
+#define ISM_CYCLE_ONESHOT 1
+
 #define ISM_F64 0 /* element type selector of the stage entry points: double */
 #define ISM_F32 1 /*                                                  float  */
 
@@ -100,7 +114,11 @@ typedef struct {
   int32_t stall_window; /* an inner solve also stops when its residual fell by less than   */
   double stall_drop;    /* stall_drop (a fraction) over the last >= stall_window cycles     */
   int32_t coarse_stencil; /* ISM_COARSE_ISM (default), ISM_COARSE_GMG5 or ISM_COARSE_ACM    */
-  int32_t reserved;       /* must be 0                                                      */
+  int32_t cycling;        /* ISM_CYCLE_REPEAT (default) or ISM_CYCLE_ONESHOT                */
+  double coarse_tol;      /* ISM_CYCLE_ONESHOT: the coarse block Gauss-Seidel stops once
+                             max |R (b~ - A x) - R A P E| < coarse_tol (default 1e-5)       */
+  double fine_tol;        /* ISM_CYCLE_ONESHOT: the fine sweeps stop once
+                             max |b~ - A x| < fine_tol (default 1e-6)                       */
 } ism_config;
 
 typedef struct {
@@ -114,6 +132,10 @@ typedef struct {
                           form), measured before the final mean removal                     */
   double rel_res_max;  /* max over the batch of max|b~ - A x| / max|b~|                     */
   double seconds;      /* wall time of the call                                              */
+  int32_t coarse_iters; /* ISM_CYCLE_ONESHOT: block Gauss-Seidel iterations on the coarse
+                           grid (I_c; one synchronization each, NCC_c = I_c, Sec. 4.3)      */
+  int32_t fine_iters;   /* ISM_CYCLE_ONESHOT: red-black iterations on the fine grid (I_f;
+                           two synchronizations each, NCC_f = 2 I_f)                       */
 } ism_stats;
 
 /* Fill cfg with defaults for an nx x ny grid of unit cell size 1/nx (unit square), Neumann
@@ -188,6 +210,16 @@ int ism_coarse_solve(ism_handle h, const double* rc, double* E);
  * rhs and e must be 16-byte aligned (ISM_ERR_INVALID otherwise). */
 int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
               int32_t zero_e, double* sumsq);
+
+/* Block Gauss-Seidel on each grid's coarse system A_c E = rc (the handle's ISM or GMG5
+ * stencil), as the ISM_CYCLE_ONESHOT coarse stage runs it (Sec. 4): from E = 0, one
+ * iteration at a time, until max |rc - A_c E| < tol (in the units of rc) on every grid or
+ * max_iter iterations.  Without a Dirichlet face rc is first projected to zero mean (the
+ * compatibility condition of the singular system; rc itself is not modified).  rc, E: FP64
+ * [batch][ny/n][nx/n].  *iters receives the number of iterations.  Returns
+ * ISM_NOT_CONVERGED if max_iter was reached first. */
+int ism_coarse_gs(ism_handle h, const double* rc, double* E, double tol, int32_t max_iter,
+                  int32_t* iters);
 
 /* The coarse stencil assembled on the device (ISM: from the face sums of Eq. 6-7; GMG5:
  * the 5-point stencil with one-sided wall rows):

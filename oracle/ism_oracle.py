@@ -510,7 +510,8 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
     The coarse grid is cut into block x block tiles that are updated concurrently.  Inside a
     tile the cells are visited in lexicographic order (I fastest), each set from its own
     equation with the tile's newest values; cells of other tiles keep their values from the
-    previous iteration, so one iteration needs one synchronization.  A cell update is
+    previous iteration, so one iteration needs one synchronization.  A periodic seam also
+    separates tiles: a neighbour reached across it counts as another tile's.  A cell update is
     E_C = (R_C - sum over the 8 neighbours of c_nb E_nb) / c_C, the neighbours taken in the
     order (dj, di) = (-1,-1), (-1,0), (-1,1), (0,-1), (0,1), (1,-1), (1,0), (1,1) and the
     products summed left to right (C is the (ncy, ncx, 3, 3) stencil of ``coarse_stencil_*``;
@@ -563,7 +564,8 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
                     ii = ii % ncx
                 ok = (jj >= 0) & (jj < ncy) & (ii >= 0) & (ii < ncx)
                 jc, ic = np.clip(jj, 0, ncy - 1), np.clip(ii, 0, ncx - 1)
-                same = ok & (jc // block == cj // block) & (ic // block == ci // block)
+                seam = (jj != cj + dj) | (ii != ci + di)  # reached across a periodic seam
+                same = ok & ~seam & (jc // block == cj // block) & (ic // block == ci // block)
                 nbs.append((flatE[jc, ic], ok, same, C[cj, ci, dj + 1, di + 1]))
             steps.append((flatE[cj, ci], nbs, C[cj, ci, 1, 1]))
     it = 0
@@ -587,9 +589,11 @@ def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-
     residual is below tol_c, prolongate and add, then iterate red-black GS on the fine grid
     until the absolute maximum of the fine residual is below tol_f.
 
-    Units: the coarse system is R A' P E = R r' with r' = h^2 b~ - A' x as everywhere here,
-    so tol_c is in those units; tol_f bounds max|b~ - A x| (the residual of the pressure
-    equation itself, in the units of b).  The fine criterion is checked before every sweep.
+    Units: both criteria are absolute maxima in the units of the pressure equation A x = b~
+    (the paper's grids have h = 1, where they coincide with its figures): tol_f bounds
+    max|b~ - A x| and tol_c bounds the residual of R A P E = R (b~ - A x), i.e. of the
+    h^2-scaled coarse system divided by h^2.  The fine criterion is checked before every
+    sweep.
     Returns (x, info) with info = dict(coarse_iters, fine_iters, ncc_c, ncc_f): one
     synchronization per coarse block-GS iteration and two per red-black fine iteration
     (Sec. 4.3), NCC_c = I_c and NCC_f = 2 I_f."""
@@ -599,7 +603,7 @@ def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     C = coarse_stencil_ism(nx // n, ny // n, n, bc_x, bc_y)
     Rc = restrict_sum(bp - laplacian(x, bc_x, bc_y), n)
-    E, ic = block_gauss_seidel(C, Rc, tol_c, block, bc_x, bc_y)
+    E, ic = block_gauss_seidel(C, Rc, tol_c * h * h, block, bc_x, bc_y)
     x = x + prolong_bilinear(E, n, bc_x, bc_y)
     fi = 0
     while np.max(np.abs(bp - laplacian(x, bc_x, bc_y))) >= tol_f * h * h and fi < max_fine:

@@ -30,6 +30,8 @@ ISM_PREC_MIXED = 1
 ISM_COARSE_ISM = 0
 ISM_COARSE_GMG5 = 1
 ISM_COARSE_ACM = 2
+ISM_CYCLE_REPEAT = 0
+ISM_CYCLE_ONESHOT = 1
 ISM_F64 = 0
 ISM_F32 = 1
 KERNEL_CLASSES = {"cycle": 0, "smooth": 1, "restrict": 2, "prolong": 3, "coarse": 4, "outer": 5}
@@ -45,7 +47,8 @@ class IsmConfig(ctypes.Structure):
         ("max_cycles", ctypes.c_int32), ("max_outer", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("fused", ctypes.c_int32),
         ("stall_window", ctypes.c_int32), ("stall_drop", ctypes.c_double),
-        ("coarse_stencil", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("coarse_stencil", ctypes.c_int32), ("cycling", ctypes.c_int32),
+        ("coarse_tol", ctypes.c_double), ("fine_tol", ctypes.c_double),
     ]
 
 
@@ -56,6 +59,7 @@ class IsmStats(ctypes.Structure):
         ("launches", ctypes.c_int64), ("host_syncs", ctypes.c_int64),
         ("rel_res_l2", ctypes.c_double), ("rel_res_max", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("coarse_iters", ctypes.c_int32), ("fine_iters", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -81,6 +85,7 @@ _SIGNATURES = {
     "ism_coarse_solve": (ctypes.c_int, [_P, _P, _P]),
     "ism_cycle": (ctypes.c_int, [_P, _I, _P, _P, _P, _I, _P]),
     "ism_coarse_stencil": (ctypes.c_int, [_P, _P]),
+    "ism_coarse_gs": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _I, ctypes.POINTER(_I)]),
     "ism_outer_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "ism_profile": (ctypes.c_int, [_P, _I]),
     "ism_profile_read": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_double),

@@ -25,7 +25,7 @@ using ism::Partials;
 namespace {
 
 // Slots of the per-grid device scalars; the array is slot-major, [kSlots][batch].
-enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, kSlots };
+enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, CMAX, MEAN_R, kSlots };
 
 // Adaptive convergence checks in flight at once (pinned read-back slots) and the number of
 // cycles the host enqueues past a check before it waits for that check's result.
@@ -59,6 +59,7 @@ struct ism_ctx {
   double* scal = nullptr;  // [kSlots][batch]
   double* fin = nullptr;   // chunk results of the two-stage reductions
   double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
+  double* coef = nullptr;  // coarse 9-point stencil [ncy][ncx][9] (block Gauss-Seidel)
   void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
   double* h_scal = nullptr;   // pinned mirror of scal, then kChecks slots of B check norms
   double* h_chk = nullptr;    // = h_scal + kSlots * batch
@@ -167,7 +168,15 @@ int validate(const ism_config* cfg, std::string& why) {
     return why = "coarse_stencil must be ISM_COARSE_ISM, ISM_COARSE_GMG5 or ISM_COARSE_ACM", ISM_ERR_INVALID;
   if (cfg->coarse_stencil == ISM_COARSE_ACM && cfg->precision != ISM_PREC_FP64)
     return why = "the ACM scheme runs in FP64 only", ISM_ERR_UNSUPPORTED;
-  if (cfg->reserved != 0) return why = "reserved must be 0", ISM_ERR_INVALID;
+  if (cfg->cycling != ISM_CYCLE_REPEAT && cfg->cycling != ISM_CYCLE_ONESHOT)
+    return why = "cycling must be ISM_CYCLE_REPEAT or ISM_CYCLE_ONESHOT", ISM_ERR_INVALID;
+  if (cfg->cycling == ISM_CYCLE_ONESHOT) {
+    if (!(cfg->coarse_tol > 0.0) || !(cfg->fine_tol > 0.0) || !std::isfinite(cfg->coarse_tol) ||
+        !std::isfinite(cfg->fine_tol))
+      return why = "coarse_tol and fine_tol must be positive and finite", ISM_ERR_INVALID;
+    if (cfg->precision != ISM_PREC_FP64 || cfg->coarse_stencil == ISM_COARSE_ACM)
+      return why = "one-shot cycling runs in FP64 with the ISM or GMG5 stencil", ISM_ERR_UNSUPPORTED;
+  }
   if (cfg->stall_window < 1 || !(cfg->stall_drop >= 0.0) || !(cfg->stall_drop < 1.0))
     return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
   if (!is_pow2_coarsen(cfg->coarsen))
@@ -559,6 +568,150 @@ int mean_of_b(ism_ctx* c, const double* b) {
   return finalize(c, c->p_sum, ism::SUM, 1.0 / double(c->g.plane), MEAN_B);
 }
 
+// The coarse grid of a handle as a plane of its own (for the per-grid scalar kernels).
+Geo coarse_geo(const Geo& g) {
+  Geo gc = g;
+  gc.nx = g.ncx;
+  gc.ny = g.ncy;
+  gc.plane = g.cplane;
+  return gc;
+}
+
+// Block Gauss-Seidel (Sec. 4) on every grid's A_c E = rc from E = 0, one synchronization per
+// iteration: each launch forms the residual of its incoming iterate and the next iterate;
+// the loop stops at the first iterate whose residual max is below tol on every grid (or
+// after max_iter updates).  The result stays in one of the t1 / t2 buffers (*E_out).
+int coarse_block_gs(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
+                    int* iters, bool* converged) {
+  const Geo& g = c->g;
+  const int B = g.batch, tiles = ism::coarse_bgs_tiles(g);
+  hipStream_t s = c->stream;
+  double* Ea = c->t1;
+  double* Eb = c->t2;
+  HIPCHK(c, hipMemsetAsync(Ea, 0, sizeof(double) * size_t(g.cplane) * B, s));
+  int it = 0;
+  bool done = false;
+  for (;;) {
+    LAUNCH(c, ism::launch_coarse_bgs(g, c->coef, rc, Ea, Eb, c->p_max, s));
+    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0,
+                                   c->scal + size_t(CMAX) * B, 1, 0, c->fin, s));
+    int rcode = read_scalars(c);
+    if (rcode) return rcode;
+    done = true;
+    for (int k = 0; k < B; ++k) {
+      const double m = c->h_scal[size_t(CMAX) * B + k];
+      if (!std::isfinite(m)) return set_err(c, ISM_ERR_NONFINITE, "non-finite coarse residual");
+      done = done && m < tol;
+    }
+    if (done || it >= max_iter) break;
+    std::swap(Ea, Eb);
+    ++it;
+  }
+  *E_out = Ea;
+  *iters = it;
+  *converged = done;
+  return ISM_OK;
+}
+
+// rc -= its mean, per grid (the compatibility projection of a singular coarse system).
+int project_coarse(ism_ctx* c, double* rc) {
+  const Geo& g = c->g;
+  int rcode = finalize(c, rc, ism::SUM, 1.0 / double(g.cplane), MEAN_R);
+  if (rcode) return rcode;
+  LAUNCH(c, ism::launch_sub_scalar(coarse_geo(g), rc, c->scal + size_t(MEAN_R) * g.batch, 1, 0,
+                                   c->stream));
+  return ISM_OK;
+}
+
+// ISM_CYCLE_ONESHOT (Sec. 4.3.1): restrict once, block GS on the coarse grid to coarse_tol,
+// prolongate and add, then red-black sweeps until max |b~ - A x| < fine_tol.  FP64.
+int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  c->launches = 0;
+  c->syncs = 0;
+  const Geo& g = c->g;
+  const int B = g.batch;
+  hipStream_t s = c->stream;
+  const double* mean = c->scal + size_t(MEAN_B) * B;
+  int rcode;
+  if ((rcode = mean_of_b(c, b))) return rcode;
+  // r' = h^2 b~ - A'x and its tile sums, the coarse right-hand side
+  Partials p0{nullptr, nullptr, c->p_bsq, c->p_bmax};
+  LAUNCH(c, ism::launch_outer_residual<double>(g, b, x, mean, c->h2, (double*)nullptr, c->rc, p0, s));
+  if ((rcode = finalize(c, c->p_bsq, ism::SUM, 1.0, BSQ))) return rcode;
+  if ((rcode = finalize(c, c->p_bmax, ism::MAX, 1.0, BMAX))) return rcode;
+  if (c->singular && (rcode = project_coarse(c, c->rc))) return rcode;
+  double* E = nullptr;
+  int ic = 0;
+  bool cconv = false;
+  const double h = c->h;
+  if ((rcode = coarse_block_gs(c, c->rc, c->cfg.coarse_tol * h * h, c->cfg.max_cycles, &E, &ic, &cconv)))
+    return rcode;
+  LAUNCH(c, ism::launch_prolong<double>(g, E, x, 0, s));
+  // b' as an array: the residual of x = 0
+  double* rhs = (double*)c->rT;
+  double* zero = (double*)c->eB;
+  HIPCHK(c, hipMemsetAsync(zero, 0, sizeof(double) * size_t(g.plane) * B, s));
+  Partials none{nullptr, nullptr, nullptr, nullptr};
+  LAUNCH(c, ism::launch_outer_residual<double>(g, b, zero, mean, c->h2, rhs, nullptr, none, s));
+  double* cur = x;
+  double* nxt = (double*)c->eA;
+  int fi = 0;
+  bool fconv = false;
+  std::vector<double> bnorm(B), bmax(B);
+  for (;;) {
+    Partials pc{c->p_sq, c->p_max, nullptr, nullptr};
+    LAUNCH(c, ism::launch_outer_residual<double>(g, b, cur, mean, c->h2, (double*)nullptr, nullptr, pc, s));
+    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
+    if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
+    if ((rcode = read_scalars(c))) return rcode;
+    fconv = true;
+    for (int k = 0; k < B; ++k) {
+      const double m = c->h_scal[size_t(RMAX) * B + k];
+      if (!std::isfinite(m) || !std::isfinite(c->h_scal[size_t(RSQ) * B + k]))
+        return set_err(c, ISM_ERR_NONFINITE, "non-finite value in b, x or the residual");
+      fconv = fconv && m < c->cfg.fine_tol * h * h;
+    }
+    if (fconv || fi >= c->cfg.max_cycles) break;
+    hipEvent_t ev = prof_start(c);
+    LAUNCH(c, ism::launch_rbgs<double>(g, rhs, cur, nxt, s, 1.0));
+    prof_stop(c, ISM_KERNEL_SMOOTH, ev);
+    std::swap(cur, nxt);
+    ++fi;
+  }
+  if (cur != x)
+    HIPCHK(c, hipMemcpyAsync(x, cur, sizeof(double) * size_t(g.plane) * B, hipMemcpyDeviceToDevice, s));
+  double rel_l2 = 0.0, rel_max = 0.0;
+  for (int k = 0; k < B; ++k) {
+    const double bn = std::sqrt(c->h_scal[size_t(BSQ) * B + k]), bm = c->h_scal[size_t(BMAX) * B + k];
+    rel_l2 = std::max(rel_l2, std::sqrt(c->h_scal[size_t(RSQ) * B + k]) / (bn > 0.0 ? bn : 1.0));
+    rel_max = std::max(rel_max, c->h_scal[size_t(RMAX) * B + k] / (bm > 0.0 ? bm : 1.0));
+  }
+  if (c->singular) {
+    LAUNCH(c, ism::launch_tile_sum(g, x, c->p_sum, s));
+    if ((rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(g.plane), MEAN_X))) return rcode;
+    LAUNCH(c, ism::launch_sub_scalar(g, x, c->scal + size_t(MEAN_X) * B, 1, 0, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->syncs++;
+  prof_collect(c);
+  const int status = (cconv && fconv) ? ISM_OK : ISM_NOT_CONVERGED;
+  if (st) {
+    st->status = status;
+    st->outer_iters = 0;
+    st->cycles = 1;
+    st->sweeps = fi;
+    st->launches = c->launches;
+    st->host_syncs = c->syncs;
+    st->rel_res_l2 = rel_l2;
+    st->rel_res_max = rel_max;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st->coarse_iters = ic;
+    st->fine_iters = fi;
+  }
+  return status;
+}
+
 template <typename T>
 int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -675,6 +828,9 @@ int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch) {
   cfg->fused = 1;
   cfg->stall_window = 8;
   cfg->stall_drop = 0.02;
+  cfg->cycling = ISM_CYCLE_REPEAT;
+  cfg->coarse_tol = 1e-5;  // the paper's coarse and fine criteria (Sec. 4.3.1, Fig. 3)
+  cfg->fine_tol = 1e-6;
   return ISM_OK;
 }
 
@@ -724,7 +880,7 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   const long long fin_count = std::max<long long>(g.cplane, (long long)(g.nx / 2) * (g.ny / 2));
   const size_t fin = align(sizeof(double) * g.batch * size_t(fin_count / 4096 + 2));
   const size_t tabs = align(sizeof(double) * g.ncx * g.ncx) + align(sizeof(double) * g.ncy * g.ncy) +
-                      align(sizeof(double) * g.cplane);
+                      align(sizeof(double) * g.cplane) + align(sizeof(double) * 9 * g.cplane);
   c->bytes = 3 * fine + 9 * coarse + scal + fin + tabs;
   he = hipMalloc((void**)&c->block, c->bytes);
   if (he != hipSuccess) {
@@ -744,7 +900,8 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   c->fin = (double*)p; p += fin;
   c->Vx = (double*)p; p += align(sizeof(double) * g.ncx * g.ncx);
   c->Vy = (double*)p; p += align(sizeof(double) * g.ncy * g.ncy);
-  c->invLam = (double*)p;
+  c->invLam = (double*)p; p += align(sizeof(double) * g.cplane);
+  c->coef = (double*)p;
 
   he = hipHostMalloc((void**)&c->h_scal, sizeof(double) * (kSlots + kChecks) * g.batch,
                      hipHostMallocDefault);
@@ -803,6 +960,8 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
   if (he == hipSuccess)
     he = hipMemcpyAsync(c->invLam, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, c->stream);
   if (he == hipSuccess) he = hipMemsetAsync(c->scal, 0, scal, c->stream);
+  if (he == hipSuccess && cfg->coarse_stencil != ISM_COARSE_ACM)
+    he = ism::launch_coarse_assemble(g, cfg->coarse_stencil == ISM_COARSE_GMG5, c->coef, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   if (he != hipSuccess) {
     if (c->acm_mem) (void)hipFree(c->acm_mem);
@@ -837,12 +996,15 @@ int ism_workspace_bytes(ism_handle c, size_t* bytes) {
 int ism_solve(ism_handle c, const double* b, double* x, ism_stats* st) {
   if (!c) return ISM_ERR_INVALID;
   if (!b || !x) return set_err(c, ISM_ERR_INVALID, "b and x must be device pointers");
+  if (st) *st = ism_stats{};
+  if (c->cfg.cycling == ISM_CYCLE_ONESHOT) return oneshot_solve(c, b, x, st);
   return c->tsize == 4 ? solve_impl<float>(c, b, x, st) : solve_impl<double>(c, b, x, st);
 }
 
 int ism_solve_adjoint(ism_handle c, const double* g, double* lam, ism_stats* st) {
-  // A is symmetric (cell-centred 5-point operator with Neumann or periodic boundaries), and
-  // the mean projection is self-adjoint, so the adjoint solve is the forward solve.
+  // A is symmetric (cell-centred 5-point operator with Neumann, Dirichlet or periodic
+  // boundaries), and the mean projection is self-adjoint, so the adjoint solve is the
+  // forward solve.
   return ism_solve(c, g, lam, st);
 }
 
@@ -967,6 +1129,27 @@ int ism_cycle(ism_handle c, int32_t dtype, const void* rhs, void* e, double* rc,
   if (dtype == ISM_F32) return cycle_impl<float>(c, (const float*)rhs, (float*)e, rc, zero_e, sumsq);
   if (dtype == ISM_F64) return cycle_impl<double>(c, (const double*)rhs, (double*)e, rc, zero_e, sumsq);
   return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
+}
+
+int ism_coarse_gs(ism_handle c, const double* rc, double* E, double tol, int32_t max_iter,
+                  int32_t* iters) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!rc || !E || !iters || !(tol >= 0.0) || max_iter < 0)
+    return set_err(c, ISM_ERR_INVALID, "bad arguments");
+  if (c->cfg.coarse_stencil == ISM_COARSE_ACM)
+    return set_err(c, ISM_ERR_UNSUPPORTED, "no 9-point coarse stencil on an ACM handle");
+  const size_t bytes = sizeof(double) * size_t(c->g.cplane) * c->g.batch;
+  HIPCHK(c, hipMemcpyAsync(c->rc, rc, bytes, hipMemcpyDeviceToDevice, c->stream));
+  int rcode;
+  if (c->singular && (rcode = project_coarse(c, c->rc))) return rcode;
+  double* out = nullptr;
+  int it = 0;
+  bool conv = false;
+  if ((rcode = coarse_block_gs(c, c->rc, tol, max_iter, &out, &it, &conv))) return rcode;
+  HIPCHK(c, hipMemcpyAsync(E, out, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *iters = it;
+  return conv ? ISM_OK : ISM_NOT_CONVERGED;
 }
 
 int ism_coarse_stencil(ism_handle c, double* coef) {

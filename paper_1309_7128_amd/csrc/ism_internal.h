@@ -97,6 +97,14 @@ hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long lo
 
 hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStream_t s);
 
+// One block-iterative Gauss-Seidel iteration on each grid's coarse system (coef: the
+// [ncy][ncx][9] stencil, shared by the batch): Eout from Ein, part_max[grid][tile] = max
+// |R - A_c Ein| over the tile.  Ein and Eout must not alias.  coarse_bgs_tiles(g) tiles per
+// grid.
+int coarse_bgs_tiles(const Geo& g);
+hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, const double* Ein,
+                             double* Eout, double* part_max, hipStream_t s);
+
 hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
                       hipStream_t s);
 hipError_t launch_grad(const Geo& g, const double* p, double h, double* gu, double* gv,

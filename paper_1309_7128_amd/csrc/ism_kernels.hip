@@ -494,6 +494,93 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
 }
 
 // ----------------------------------------------------------------------------------------
+// One block-iterative Gauss-Seidel iteration on the coarse system A_c E = R (Sec. 4: the
+// coarse grid is iterated by block GS, one synchronization per iteration).  A workgroup
+// owns a kCB x kCB tile of coarse cells: the tile and a ring of neighbours are staged in
+// LDS with the values of the previous iteration, then the tile's cells are updated in
+// lexicographic order (I fastest) in place, so a cell sees the new values of its tile's
+// predecessors and the old values of everything else (a periodic seam separates tiles: the
+// ring holds the copy from across it).  Lexicographic order is run as
+// hyperplanes li + 2 lj = s, s = 0 .. 3 (kCB - 1): the 9-point neighbours that precede a
+// cell lie on earlier hyperplanes and those that follow on later ones, so each hyperplane
+// is one parallel step.  Update: E_C = (R_C - sum of c_nb E_nb) / c_C, neighbours in the
+// order (dj, di) = (-1,-1) .. (1,1) without the centre, summed left to right.  Before the
+// update each cell forms the residual of the incoming iterate, R_C - (c_C E_C + sum ...),
+// and the workgroup writes the maximum of its magnitude to part_max[tile].
+// ----------------------------------------------------------------------------------------
+constexpr int kCB = 16;
+
+__global__ __launch_bounds__(kBlock) void k_coarse_bgs(Geo g, const double* __restrict__ coef,
+                                                       const double* __restrict__ R,
+                                                       const double* __restrict__ Ein,
+                                                       double* __restrict__ Eout,
+                                                       double* __restrict__ part_max) {
+  constexpr int LW = kCB + 2;
+  __shared__ double sE[LW * LW];
+  __shared__ double smax[kBlock / kWave];
+  const int li = threadIdx.x % kCB, lj = threadIdx.x / kCB;
+  const int I0 = blockIdx.x * kCB, J0 = blockIdx.y * kCB;
+  const long long cb = (long long)blockIdx.z * g.cplane;
+  const int I = I0 + li, J = J0 + lj;
+  const bool active = I < g.ncx && J < g.ncy;
+  // stage the tile and its ring (ring positions are other tiles' cells, or 0 off the grid)
+  for (int t = threadIdx.x; t < LW * LW; t += kBlock) {
+    const int rj = t / LW, ri = t - rj * LW;
+    int jj = J0 + rj - 1, ii = I0 + ri - 1;
+    bool ok = true;
+    if (g.per_y) jj = imod(jj, g.ncy);
+    else ok = ok && jj >= 0 && jj < g.ncy;
+    if (g.per_x) ii = imod(ii, g.ncx);
+    else ok = ok && ii >= 0 && ii < g.ncx;
+    sE[t] = ok ? Ein[cb + (long long)jj * g.ncx + ii] : 0.0;
+  }
+  // the LDS slot of each neighbour (one reached across a periodic seam is always the
+  // staged ring copy: the seam separates tiles)
+  int nb[9];
+  double c[9];
+  double r = 0.0;
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      nb[k] = (lj + k / 3) * LW + li + k % 3;
+      c[k] = coef[((long long)J * g.ncx + I) * 9 + k];
+    }
+    r = R[cb + (long long)J * g.ncx + I];
+  }
+  __syncthreads();
+  double amax = 0.0;
+  if (active) {
+    double acc = c[4] * sE[nb[4]];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      if (k != 4) acc = acc + c[k] * sE[nb[k]];
+    amax = fabs(r - acc);
+  }
+  amax = wave_max_group(amax, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = amax;
+  // hyperplane steps: each begins after the previous one's LDS writes (and, for s = 0, after
+  // the residual reads of the incoming iterate)
+  const int step = li + 2 * lj;
+  for (int s = 0; s < 3 * kCB - 2; ++s) {
+    __syncthreads();
+    if (active && step == s) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (k != 4) acc = acc + c[k] * sE[nb[k]];
+      sE[nb[4]] = (r - acc) / c[4];
+    }
+  }
+  __syncthreads();
+  if (active) Eout[cb + (long long)J * g.ncx + I] = sE[nb[4]];
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, smax[w]);
+    part_max[(long long)blockIdx.z * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+// ----------------------------------------------------------------------------------------
 // Staggered-grid operators (FP64).  nxu = number of u faces per row.
 // ----------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_div(Geo g, const double* __restrict__ u,
@@ -796,6 +883,17 @@ hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStrea
   const int cells = g.ncx * g.ncy;
   hipLaunchKernelGGL(k_coarse_assemble, dim3((cells + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
                      gmg5, coef);
+  return hipGetLastError();
+}
+
+int coarse_bgs_tiles(const Geo& g) {
+  return ((g.ncx + kCB - 1) / kCB) * ((g.ncy + kCB - 1) / kCB);
+}
+
+hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, const double* Ein,
+                             double* Eout, double* part_max, hipStream_t s) {
+  dim3 grid((g.ncx + kCB - 1) / kCB, (g.ncy + kCB - 1) / kCB, g.batch);
+  hipLaunchKernelGGL(k_coarse_bgs, grid, dim3(kBlock), 0, s, g, coef, R, Ein, Eout, part_max);
   return hipGetLastError();
 }
 

@@ -466,13 +466,17 @@ def _blockgs_loop(C, R, block, iters, bcx, bcy):
                 s = 0.0
                 for dj, di in order:
                     jj, ii = J + dj, I + di
+                    seam = False
                     if bcx == P:
+                        seam = seam or not 0 <= ii < ncx
                         ii %= ncx
                     if bcy == P:
+                        seam = seam or not 0 <= jj < ncy
                         jj %= ncy
                     if not (0 <= jj < ncy and 0 <= ii < ncx):
                         continue
-                    same = jj // block == J // block and ii // block == I // block
+                    # a periodic seam separates tiles
+                    same = not seam and jj // block == J // block and ii // block == I // block
                     # inside the tile the lexicographic predecessors are already new
                     v = E[jj, ii] if same and (jj, ii) < (J, I) else old[jj, ii]
                     s = s + C[J, I, dj + 1, di + 1] * v
@@ -480,9 +484,9 @@ def _blockgs_loop(C, R, block, iters, bcx, bcy):
     return E
 
 
-@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND), (D, D)])
-def test_block_gauss_seidel_matches_cell_loop(bcx, bcy):
-    ncx, ncy, block = 7, 6, 4
+@pytest.mark.parametrize("bcx,bcy,block", [(N, N, 4), (P, ND, 4), (D, D, 4), (P, P, 16)])
+def test_block_gauss_seidel_matches_cell_loop(bcx, bcy, block):
+    ncx, ncy = 7, 6
     C = O.coarse_stencil_ism(ncx, ncy, 8, bcx, bcy)
     R = np.random.default_rng(30).standard_normal((ncy, ncx))
     Rp = R - R.mean() if O.singular(bcx, bcy) else R
