@@ -69,10 +69,61 @@ def parse():
     ap.add_argument("--time-steps", type=int, default=0,
                     help="jet workload: this many successive warm-started solves per step (the "
                          "time loop); step t's right-hand side is step 0's shifted t cells in x")
+    ap.add_argument("--oneshot-table", type=int, default=0,
+                    help="only run this many warm-started time steps of the workload with the "
+                         "paper's one-shot accommodative cycling, for each tile size and coarse "
+                         "criterion of --oneshot-tiles / --oneshot-coarse-tol, one JSON line each")
+    ap.add_argument("--oneshot-tiles", default="16,32")
+    ap.add_argument("--oneshot-coarse-tol", default="1e-2,1e-3,1e-4",
+                    help="coarse criteria as fractions of max|b| (fine criterion: 1e-5 max|b|)")
     ap.add_argument("--cycles-only", type=int, default=0,
                     help="only run this many fused cycles on the workload grid (short program "
                          "for hardware-counter passes)")
     return ap.parse_args()
+
+
+def oneshot_table(w, args):
+    """The paper's iteration and synchronization counts (Sec. 4.3, Tables A.1-A.3) on a
+    synthetic time loop: step 0 is solved to the workload's tolerance with the default
+    cycling, then each step t = 1 .. K solves the right-hand side of step t (the jet's
+    perturbation moved t cells) warm-started from step t-1, with one-shot accommodative
+    cycling (block GS on the coarse grid to the coarse criterion, then fine red-black
+    iterations to the fine one).  Per configuration: mean I_c, I_f, NCC_c = I_c,
+    NCC_f = 2 I_f, NCC_t and N_Lap = NCC_f / 2 + NCC_c / n^2 per step, and wall time."""
+    import torch
+
+    from paper_1309_7128_amd import inputs
+    from paper_1309_7128_amd.solver import Solver
+
+    u, v = inputs.workload_fields(w.name, 0)
+    ref = Solver(w.nx, w.ny, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=w.coarsen, lx=w.lx, ly=w.ly,
+                 precision="mixed", rtol=w.rtol)
+    b0 = ref.div(torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda())
+    x0, _ = ref.solve(b0)
+    bmax = float(b0.abs().max())
+    steps = [torch.roll(b0, t, dims=-1) if w.bc_x == "periodic" else b0
+             for t in range(1, args.oneshot_table + 1)]
+    for n in [int(a) for a in args.oneshot_tiles.split(",")]:
+        for frac in [float(a) for a in args.oneshot_coarse_tol.split(",")]:
+            s = Solver(w.nx, w.ny, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=n, lx=w.lx, ly=w.ly,
+                       precision="fp64", cycling="oneshot", coarse_tol=frac * bmax,
+                       fine_tol=1e-5 * bmax, max_cycles=200000)
+            x = x0.clone()
+            ic = fi = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for bt in steps:
+                x, st = s.solve(bt, x)
+                ic += st["coarse_iters"]
+                fi += st["fine_iters"]
+            dt = time.perf_counter() - t0
+            k = len(steps)
+            ncc_c, ncc_f = ic / k, 2.0 * fi / k
+            print(json.dumps({"workload": w.name, "tile": n, "coarse_tol_frac": frac,
+                              "fine_tol_frac": 1e-5, "steps": k, "I_c": ic / k, "I_f": fi / k,
+                              "NCC_c": ncc_c, "NCC_f": ncc_f, "NCC_t": ncc_c + ncc_f,
+                              "N_Lap": ncc_f / 2.0 + ncc_c / float(n * n),
+                              "ms_per_step": round(1e3 * dt / k, 2)}), flush=True)
 
 
 def main():
@@ -103,6 +154,8 @@ def main():
     w = inputs.WORKLOADS[args.workload]
     if args.cycles_only > 0:
         return cycles_only(w, args)
+    if args.oneshot_table > 0:
+        return oneshot_table(w, args)
     u, v = inputs.workload_fields(w.name, 0) if w.batch == 1 else (None, None)
     if w.batch > 1:
         uv = [inputs.workload_fields(w.name, k) for k in range(w.batch)]
