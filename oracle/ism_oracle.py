@@ -242,6 +242,83 @@ def grad_adjoint(gu, gv, h, bc_x=NEUMANN, bc_y=NEUMANN):
     return out / h
 
 
+def predictor(u, v, p, h, dt, eta, bc_x=NEUMANN, walls=(0.0, 0.0, 0.0, 0.0)):
+    """The explicit predictor of Goda's scheme (Sec. 2.2, Eq. 3) on the staggered grid with
+    second-order central differences (Sec. 2.3):
+
+        v* = v + dt (-(v . grad) v + eta lap v) - G p,
+
+    p carrying the time step (p = dt times the pressure, so that the projection's solution
+    x of A x = D v* updates it as p + x and the velocity as v* - G x).  The signs of Eq. 1
+    and Eq. 3 are garbled in the text; this is the standard form they stand for.
+
+    Layout as ``div``: u (ny, nx+1) (or (ny, nx) periodic in x), v (ny+1, nx).  At an interior
+    u face (west face of cell (i, j)):
+      dudx = (u_E - u_W) / (2h), dudy = (u_N - u_S) / (2h), lap = (((u_E + u_W) + u_N) + u_S
+      - 4 u) / h^2, vbar = ((v_SW + v_SE) + (v_NW + v_NE)) / 4 (the four v faces around it),
+      u* = u + dt (eta lap - (u dudx + vbar dudy)) - (p_C - p_W) / h,
+    and the v faces alike with x and y exchanged (ubar from the four u faces around it).
+    Walls: the normal velocity on a wall face is kept; a tangential neighbour behind a wall
+    is the ghost 2 U_w - (the face's own value), U_w the wall's tangential velocity
+    (walls = (v on the west wall, v on the east wall, u on the south wall, u on the north
+    wall)); a periodic x axis wraps.  Returns (u*, v*).  Pinned by exactness on linear
+    fields, second-order consistency and by the projection step."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    ny, nx = p.shape
+    per = bc_x == PERIODIC
+    vw, ve, us, un = (float(a) for a in walls)
+    us_, vs_ = u.copy(), v.copy()
+    two_h, hh = 2.0 * h, h * h
+    # ---- u faces
+    irange = range(nx) if per else range(1, nx)
+    for j in range(ny):
+        for i in irange:
+            c = u[j, i]
+            ue = u[j, (i + 1) % nx] if per else u[j, i + 1]
+            uw = u[j, (i - 1) % nx] if per else u[j, i - 1]
+            un_ = u[j + 1, i] if j + 1 < ny else 2.0 * un - c
+            us_v = u[j - 1, i] if j > 0 else 2.0 * us - c
+            im = (i - 1) % nx
+            vbar = ((v[j, im] + v[j, i % nx]) + (v[j + 1, im] + v[j + 1, i % nx])) / 4.0
+            dudx = (ue - uw) / two_h
+            dudy = (un_ - us_v) / two_h
+            lap = ((((ue + uw) + un_) + us_v) - 4.0 * c) / hh
+            gp = (p[j, i % nx] - p[j, im]) / h
+            us_[j, i] = c + dt * (eta * lap - (c * dudx + vbar * dudy)) - gp
+    # ---- v faces (the wall rows j = 0 and j = ny keep their normal velocity)
+    for j in range(1, ny):
+        for i in range(nx):
+            c = v[j, i]
+            vn = v[j + 1, i]
+            vs = v[j - 1, i]
+            if per:
+                ve_, vw_ = v[j, (i + 1) % nx], v[j, (i - 1) % nx]
+            else:
+                ve_ = v[j, i + 1] if i + 1 < nx else 2.0 * ve - c
+                vw_ = v[j, i - 1] if i > 0 else 2.0 * vw - c
+            ip = (i + 1) % nx if per else i + 1
+            ubar = ((u[j - 1, i] + u[j - 1, ip]) + (u[j, i] + u[j, ip])) / 4.0
+            dvdx = (ve_ - vw_) / two_h
+            dvdy = (vn - vs) / two_h
+            lap = ((((ve_ + vw_) + vn) + vs) - 4.0 * c) / hh
+            gp = (p[j, i] - p[j - 1, i]) / h
+            vs_[j, i] = c + dt * (eta * lap - (ubar * dvdx + c * dvdy)) - gp
+    return us_, vs_
+
+
+def projection_step(u, v, p, h, dt, eta, bc_x=NEUMANN, walls=(0.0, 0.0, 0.0, 0.0)):
+    """One time step of Goda's incremental projection scheme (Sec. 2.2): the predictor
+    (Eq. 3), the pressure-change equation A x = D v* (Eq. 4, solved exactly here), then
+    v^{t+1} = v* - G x and p^{t+1} = p + x.  Returns (u, v, p)."""
+    us, vs = predictor(u, v, p, h, dt, eta, bc_x, walls)
+    b = div(us, vs, h, bc_x)
+    x = exact_solve(b, h, bc_x, NEUMANN)
+    gu, gv = grad(x, h, bc_x, NEUMANN)
+    return us - gu, vs - gv, p + x
+
+
 # --------------------------------------------------------------------------------------
 # Grid transfer (Sec. 3.3, Eq. 5)
 # --------------------------------------------------------------------------------------

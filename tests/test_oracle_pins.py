@@ -589,6 +589,97 @@ def test_divergence_theorem():
     assert abs(O.div(u, v, h).sum() * h * h - flux) < 1e-12
 
 
+# ---------------------------------------------------------------- predictor (Eq. 3)
+
+
+def _faces_xy(nx, ny, h, per=False):
+    xu = np.arange(nx if per else nx + 1) * h
+    yu = (np.arange(ny) + 0.5) * h
+    xv = (np.arange(nx) + 0.5) * h
+    yv = np.arange(ny + 1) * h
+    return np.meshgrid(xu, yu), np.meshgrid(xv, yv)
+
+
+def test_predictor_advection_exact_on_linear_fields():
+    nx, ny, h = 12, 10, 0.1
+    (Xu, Yu), (Xv, Yv) = _faces_xy(nx, ny, h)
+    u = 0.3 + 0.7 * Xu - 0.4 * Yu
+    v = 0.1 - 0.2 * Xv + 0.5 * Yv
+    us, vs = O.predictor(u, v, np.zeros((ny, nx)), h, 1.0, 0.0)
+    # -(u du/dx + v du/dy) and -(u dv/dx + v dv/dy) with v, u at the face
+    ru = -(u * 0.7 + (0.1 - 0.2 * Xu + 0.5 * Yu) * -0.4)
+    rv = -((0.3 + 0.7 * Xv - 0.4 * Yv) * -0.2 + v * 0.5)
+    np.testing.assert_allclose((us - u)[1:-1, 1:-1], ru[1:-1, 1:-1], atol=1e-14)
+    np.testing.assert_allclose((vs - v)[1:-1, 1:-1], rv[1:-1, 1:-1], atol=1e-14)
+
+
+def test_predictor_diffusion_and_pressure_terms():
+    nx, ny, h, dt, eta = 12, 10, 0.25, 0.5, 0.3
+    (Xu, Yu), (Xv, Yv) = _faces_xy(nx, ny, h)
+    # u = y^2 alone: no advection (du/dx = 0, v = 0), lap u = 2 exactly
+    u = Yu**2
+    v = np.zeros_like(Xv)
+    us, _ = O.predictor(u, v, np.zeros((ny, nx)), h, dt, eta)
+    np.testing.assert_allclose((us - u)[1:-1, 1:-1], dt * eta * 2.0, atol=1e-13)
+    # at rest, the predictor subtracts the face gradient of p
+    pp = np.random.default_rng(40).standard_normal((ny, nx))
+    us, vs = O.predictor(np.zeros_like(Xu), np.zeros_like(Xv), pp, h, dt, eta)
+    gu, gv = O.grad(pp, h)
+    np.testing.assert_allclose(us, -gu, atol=1e-15)
+    np.testing.assert_allclose(vs, -gv, atol=1e-15)
+
+
+def test_predictor_wall_ghosts_keep_a_matching_flow_steady():
+    # a uniform u equal to the velocity of the south and north walls, v = 0: every ghost
+    # equals the face value, so nothing changes
+    nx, ny, h = 8, 6, 0.5
+    u = np.full((ny, nx + 1), 0.7)
+    u[:, 0] = u[:, -1] = 0.0  # the x walls do not move normally... their faces stay as given
+    v = np.zeros((ny + 1, nx))
+    us, vs = O.predictor(u, v, np.zeros((ny, nx)), h, 0.1, 0.2, walls=(0.0, 0.0, 0.7, 0.7))
+    np.testing.assert_allclose(us[:, 2:-2], u[:, 2:-2], atol=1e-15)
+    np.testing.assert_array_equal(us[:, [0, -1]], u[:, [0, -1]])
+    np.testing.assert_array_equal(vs[[0, -1], :], v[[0, -1], :])
+
+
+def test_predictor_is_second_order_consistent():
+    # smooth fields on the periodic-x channel; the increment (v* - v) / dt against the
+    # analytic -(v . grad) v + eta lap v in the interior: error falls 4x per halving of h
+    def err(nx):
+        ny = nx
+        h = 1.0 / nx
+        (Xu, Yu), (Xv, Yv) = _faces_xy(nx, ny, h, per=True)
+        k = 2 * np.pi
+        u = np.sin(k * Xu) * np.cos(np.pi * Yu)
+        v = 0.5 * np.cos(k * Xv) * np.sin(np.pi * Yv)
+        eta = 0.05
+        us, _ = O.predictor(u, v, np.zeros((ny, nx)), h, 1.0, eta, bc_x=P)
+        vu = 0.5 * np.cos(k * Xu) * np.sin(np.pi * Yu)
+        F = (-(u * k * np.cos(k * Xu) * np.cos(np.pi * Yu) - vu * np.pi * np.sin(k * Xu) * np.sin(np.pi * Yu))
+             - eta * (k * k + np.pi**2) * u)
+        inner = slice(2, -2)
+        return np.abs((us - u)[inner] - F[inner]).max()
+
+    e1, e2 = err(32), err(64)
+    assert 3.6 < e1 / e2 < 4.4, (e1, e2)
+
+
+def test_projection_step_is_divergence_free():
+    nx, ny, h = 16, 12, 1.0 / 16
+    rng = np.random.default_rng(41)
+    u = rng.uniform(-1, 1, (ny, nx + 1))
+    v = rng.uniform(-1, 1, (ny + 1, nx))
+    u[:, 0] = u[:, -1] = 0.0
+    v[0, :] = v[-1, :] = 0.0
+    p0 = np.zeros((ny, nx))
+    un, vn, p1 = O.projection_step(u, v, p0, h, 0.01, 0.1, walls=(0.0, 0.0, 0.0, 1.0))
+    assert np.abs(O.div(un, vn, h)).max() < 1e-9 * np.abs(O.div(u, v, h)).max()
+    # the same step again with the new pressure keeps the face gradient consistent
+    us, vs = O.predictor(u, v, p0, h, 0.01, 0.1, walls=(0.0, 0.0, 0.0, 1.0))
+    gu, gv = O.grad(p1 - p0, h)
+    np.testing.assert_allclose(un, us - gu, atol=1e-14)
+
+
 # ---------------------------------------------------------------- cost accounting
 
 
