@@ -74,6 +74,10 @@ def parse():
                          "paper's one-shot accommodative cycling, for each tile size and coarse "
                          "criterion of --oneshot-tiles / --oneshot-coarse-tol, one JSON line each")
     ap.add_argument("--oneshot-tiles", default="16,32")
+    ap.add_argument("--time-loop", type=int, default=0,
+                    help="only run this many projection time steps (predictor, pressure solve, "
+                         "correction) of a shear-driven cavity of --time-loop-n cells per side")
+    ap.add_argument("--time-loop-n", type=int, default=2048)
     ap.add_argument("--oneshot-coarse-tol", default="1e-2,1e-3,1e-4",
                     help="coarse criteria as fractions of max|b| (fine criterion: 1e-5 max|b|)")
     ap.add_argument("--cycles-only", type=int, default=0,
@@ -126,6 +130,42 @@ def oneshot_table(w, args):
                               "ms_per_step": round(1e3 * dt / k, 2)}), flush=True)
 
 
+def time_loop(args):
+    """Projection time steps of Goda's scheme (Sec. 2.2) on a shear-driven cavity in the shape
+    of Benchmark I (Sec. 4.3.1): unit cells, dt = 1, viscosity 0.1, walls sliding
+    counter-clockwise at 0.1, from rest.  Each step is the explicit predictor, the divergence,
+    a mixed-precision pressure solve to 1e-8 warm-started from the previous pressure change,
+    and the correction.  The first 5 steps are warm-up; the rest are timed."""
+    import torch
+
+    from paper_1309_7128_amd.solver import Solver
+
+    n = args.time_loop_n
+    U = 0.1
+    walls = (-U, U, U, -U)
+    s = Solver(n, n, coarsen=32 if n >= 4096 else 16, lx=float(n), precision="mixed", rtol=1e-8,
+               nu=args.nu)
+    u = torch.zeros(s.u_shape, dtype=torch.float64, device="cuda")
+    v = torch.zeros(s.v_shape, dtype=torch.float64, device="cuda")
+    p = torch.zeros(s.cell_shape, dtype=torch.float64, device="cuda")
+    x = None
+    for _ in range(5):
+        u, v, p, x, _ = s.step(u, v, p, 1.0, 0.1, walls, x)
+    torch.cuda.synchronize()
+    cycles = 0
+    t0 = time.perf_counter()
+    for _ in range(args.time_loop):
+        u, v, p, x, st = s.step(u, v, p, 1.0, 0.1, walls, x)
+        cycles += st["cycles"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k = args.time_loop
+    print(json.dumps({"workload": f"cavity{n}_time_loop", "steps": k,
+                      "ms_per_step": round(1e3 * dt / k, 3),
+                      "Mdof_per_s": round(n * n * k / dt / 1e6, 2),
+                      "solve_cycles_per_step": cycles / k}), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -156,6 +196,8 @@ def main():
         return cycles_only(w, args)
     if args.oneshot_table > 0:
         return oneshot_table(w, args)
+    if args.time_loop > 0:
+        return time_loop(args)
     u, v = inputs.workload_fields(w.name, 0) if w.batch == 1 else (None, None)
     if w.batch > 1:
         uv = [inputs.workload_fields(w.name, k) for k in range(w.batch)]
@@ -216,8 +258,9 @@ def main():
         achieved = alg / launches / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(w.name, args.nu),
-                    "kernel": f"k_cycle<{'float' if w.precision == 'mixed' else 'double'}, {args.nu}, "
+                    "traffic": measured_traffic(w.name, args.nu if w.precision == "mixed" else args.nu_fp64),
+                    "kernel": f"k_cycle<{'float' if w.precision == 'mixed' else 'double'}, "
+                              f"{args.nu if w.precision == 'mixed' else args.nu_fp64}, "
                               f"{w.coarsen.bit_length() - 1}>",
                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
                     "bytes_per_launch": int(alg / launches)}

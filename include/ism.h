@@ -178,6 +178,25 @@ int ism_grad(ism_handle h, const double* p, double* gu, double* gv);
 int ism_div_adjoint(ism_handle h, const double* lam, double* gu, double* gv);
 int ism_grad_adjoint(ism_handle h, const double* gu, const double* gv, double* p);
 
+/* ---- One time step of Goda's incremental projection scheme (Sec. 2.2, Eq. 3-4):
+ *   ism_predict(u, v, p) -> (us, vs), the explicit predictor
+ *   ism_div(us, vs) -> b, ism_solve(b) -> x  (x: the pressure change, warm start allowed)
+ *   ism_correct(x, us, vs, p): us -= G x, vs -= G x, p += x  (the new velocity and pressure)
+ * p carries the time step (p = dt times the kinematic pressure).
+ *
+ * ism_predict: us = u + dt (eta lap u - (u . grad) u) - G p on every face (and vs alike),
+ * second-order central differences on the staggered grid (Sec. 2.3): at an interior u face
+ * dudx = (u_E - u_W) / (2h), dudy = (u_N - u_S) / (2h), lap = (((u_E + u_W) + u_N) + u_S - 4 u)
+ * / h^2, v at the face the mean of its four neighbouring v faces; v faces alike.  A wall face
+ * keeps its normal velocity; behind a wall a tangential neighbour is the ghost 2 U_w - (the
+ * face's value), with walls = {v of the west wall, v of the east wall, u of the south wall,
+ * u of the north wall} (a HOST array of 4 doubles; NULL = walls at rest).  eta is the
+ * kinematic viscosity.  us and vs must not alias u or v (ISM_ERR_INVALID).  The signs of
+ * Eq. 1 and Eq. 3 are garbled in the paper's text; this is the standard form. */
+int ism_predict(ism_handle h, const double* u, const double* v, const double* p, double dt,
+                double eta, const double* walls, double* us, double* vs);
+int ism_correct(ism_handle h, const double* x, double* u, double* v, double* p);
+
 /* ---- Stage entry points: one step of the cycle each, for step-by-step verification.
  * Fine arrays have the element type selected by dtype (ISM_F64 / ISM_F32) and layout
  * [batch][ny][nx]; coarse arrays are FP64 [batch][ny/n][nx/n].  rhs is in h^2 units

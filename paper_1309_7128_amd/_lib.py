@@ -86,6 +86,8 @@ _SIGNATURES = {
     "ism_cycle": (ctypes.c_int, [_P, _I, _P, _P, _P, _I, _P]),
     "ism_coarse_stencil": (ctypes.c_int, [_P, _P]),
     "ism_coarse_gs": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _I, ctypes.POINTER(_I)]),
+    "ism_predict": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "ism_correct": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "ism_outer_residual": (ctypes.c_int, [_P, _P, _P, _P]),
     "ism_profile": (ctypes.c_int, [_P, _I]),
     "ism_profile_read": (ctypes.c_int, [_P, _I, ctypes.POINTER(ctypes.c_double),

@@ -1131,6 +1131,26 @@ int ism_cycle(ism_handle c, int32_t dtype, const void* rhs, void* e, double* rc,
   return set_err(c, ISM_ERR_INVALID, "dtype must be ISM_F32 or ISM_F64");
 }
 
+int ism_predict(ism_handle c, const double* u, const double* v, const double* p, double dt,
+                double eta, const double* walls, double* us, double* vs) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!u || !v || !p || !us || !vs) return set_err(c, ISM_ERR_INVALID, "NULL array");
+  if (us == u || us == v || vs == u || vs == v)
+    return set_err(c, ISM_ERR_INVALID, "the predicted faces must not alias the input faces");
+  if (!std::isfinite(dt) || !std::isfinite(eta) || eta < 0.0)
+    return set_err(c, ISM_ERR_INVALID, "dt must be finite and eta finite and >= 0");
+  const double rest[4] = {0.0, 0.0, 0.0, 0.0};
+  LAUNCH(c, ism::launch_predict(c->g, u, v, p, c->h, dt, eta, walls ? walls : rest, us, vs, c->stream));
+  return ISM_OK;
+}
+
+int ism_correct(ism_handle c, const double* x, double* u, double* v, double* p) {
+  if (!c) return ISM_ERR_INVALID;
+  if (!x || !u || !v || !p) return set_err(c, ISM_ERR_INVALID, "NULL array");
+  LAUNCH(c, ism::launch_correct(c->g, x, c->h, u, v, p, c->stream));
+  return ISM_OK;
+}
+
 int ism_coarse_gs(ism_handle c, const double* rc, double* E, double tol, int32_t max_iter,
                   int32_t* iters) {
   if (!c) return ISM_ERR_INVALID;

@@ -517,9 +517,15 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
   }
   // Chunks of S::L rows (the shortest that keep the pipeline's warm-up rows a small share;
   // measured faster at 8192^2 than both shorter chunks that fill every SIMD with three waves
-  // and longer ones); wall strips, whose rows cost more, walk half as far.
+  // and longer ones); wall strips, whose rows cost more, walk half as far.  A launch with
+  // fewer than kUnits units (a small grid) takes more, shorter chunks of whole bands, down
+  // to 32 rows (one band when bands are longer): on 256 CUs parallelism then matters more
+  // than the re-read halo rows.
+  constexpr int kUnits = 2048;
   const int nb = g.ny / S::N;
-  const int Ci = (nb * S::N + S::L - 1) / S::L;
+  const int cmax = std::max(1, nb / std::max(1, 32 / S::N));
+  const int per = std::max(1, (ni + 2 * ne) * g.batch);
+  const int Ci = std::max((nb * S::N + S::L - 1) / S::L, std::min(cmax, (kUnits + per - 1) / per));
   const int Ce = std::min(2 * Ci, nb);
   // wall blocks padded to a multiple of 8 so that the XCD of a block (its index mod 8) is
   // known to the band mapping of the others

@@ -113,5 +113,11 @@ hipError_t launch_div_adjoint(const Geo& g, const double* lam, double h, double*
                               double* gv, hipStream_t s);
 hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv, double h,
                                double* p, hipStream_t s);
+// Explicit predictor (us, vs must not alias u, v) and the projection's correction.
+hipError_t launch_predict(const Geo& g, const double* u, const double* v, const double* p,
+                          double h, double dt, double eta, const double walls[4], double* us,
+                          double* vs, hipStream_t s);
+hipError_t launch_correct(const Geo& g, const double* x, double h, double* u, double* v, double* p,
+                          hipStream_t s);
 
 }  // namespace ism

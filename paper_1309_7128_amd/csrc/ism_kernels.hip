@@ -602,6 +602,28 @@ __global__ __launch_bounds__(kBlock) void k_div(Geo g, const double* __restrict_
   }
 }
 
+// G p on u face f of row j (pr = that row of p): (p_C - p_W) / h; zero on a Neumann wall
+// face; the mirror ghost -p behind a Dirichlet wall face.
+__device__ __forceinline__ double grad_u_face(const Geo& g, const double* pr, int f, double h) {
+  if (g.per_x) return (pr[f] - pr[f == 0 ? g.nx - 1 : f - 1]) / h;
+  if (f == 0) return (g.dmask & kDirW) ? (pr[0] - (-pr[0])) / h : 0.0;
+  if (f == g.nx) return (g.dmask & kDirE) ? ((-pr[g.nx - 1]) - pr[g.nx - 1]) / h : 0.0;
+  return (pr[f] - pr[f - 1]) / h;
+}
+
+// G p on v face f of column i (pb = the grid's p).
+__device__ __forceinline__ double grad_v_face(const Geo& g, const double* pb, int f, int i, double h) {
+  if (f == 0) {
+    const double q = pb[i];
+    return (g.dmask & kDirS) ? (q - (-q)) / h : 0.0;
+  }
+  if (f == g.ny) {
+    const double q = pb[(long long)(g.ny - 1) * g.nx + i];
+    return (g.dmask & kDirN) ? ((-q) - q) / h : 0.0;
+  }
+  return (pb[(long long)f * g.nx + i] - pb[(long long)(f - 1) * g.nx + i]) / h;
+}
+
 __global__ __launch_bounds__(kBlock) void k_grad_u(Geo g, const double* __restrict__ p, double h,
                                                    double* __restrict__ gu) {
   const int nxu = g.per_x ? g.nx : g.nx + 1;
@@ -611,13 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_u(Geo g, const double* __restri
     const long long bi = k / per;
     const int rem = int(k - bi * per);
     const int j = rem / nxu, f = rem - j * nxu;
-    const double* pr = p + bi * g.plane + (long long)j * g.nx;
-    double val;
-    if (g.per_x) val = (pr[f] - pr[f == 0 ? g.nx - 1 : f - 1]) / h;
-    else if (f == 0) val = (g.dmask & kDirW) ? (pr[0] - (-pr[0])) / h : 0.0;  // ghost -p
-    else if (f == g.nx) val = (g.dmask & kDirE) ? ((-pr[g.nx - 1]) - pr[g.nx - 1]) / h : 0.0;
-    else val = (pr[f] - pr[f - 1]) / h;
-    gu[k] = val;
+    gu[k] = grad_u_face(g, p + bi * g.plane + (long long)j * g.nx, f, h);
   }
 }
 
@@ -629,18 +645,126 @@ __global__ __launch_bounds__(kBlock) void k_grad_v(Geo g, const double* __restri
     const long long bi = k / per;
     const int rem = int(k - bi * per);
     const int f = rem / g.nx, i = rem - f * g.nx;
-    const double* pb = p + bi * g.plane;
-    double val;
-    if (f == 0) {
-      const double q = pb[i];
-      val = (g.dmask & kDirS) ? (q - (-q)) / h : 0.0;
-    } else if (f == g.ny) {
-      const double q = pb[(long long)(g.ny - 1) * g.nx + i];
-      val = (g.dmask & kDirN) ? ((-q) - q) / h : 0.0;
-    } else {
-      val = (pb[(long long)f * g.nx + i] - pb[(long long)(f - 1) * g.nx + i]) / h;
+    gv[k] = grad_v_face(g, p + bi * g.plane, f, i, h);
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// Explicit predictor of Goda's scheme (Sec. 2.2, Eq. 3) with second-order central
+// differences on the staggered grid (Sec. 2.3), FP64, one thread per face:
+//   v* = v + dt (eta lap v - (v . grad) v) - G p,
+// p carrying the time step.  Interior u face (west face of cell (i, j)):
+//   dudx = (u_E - u_W) / (2h), dudy = (u_N - u_S) / (2h),
+//   lap = (((u_E + u_W) + u_N) + u_S - 4 u) / h^2, vbar = ((v_SW + v_SE) + (v_NW + v_NE)) / 4,
+//   u* = u + dt (eta lap - (u dudx + vbar dudy)) - (p_C - p_W) / h;
+// v faces alike with x and y exchanged.  A wall face keeps its normal velocity; a tangential
+// neighbour behind a wall is the ghost 2 U_w - (the face's own value); a periodic x axis
+// wraps.  wall = tangential velocities (west wall v, east wall v, south wall u, north wall u).
+// ----------------------------------------------------------------------------------------
+struct Walls {
+  double vw, ve, us, un;
+};
+
+__global__ __launch_bounds__(kBlock) void k_predict_u(Geo g, const double* __restrict__ u,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ p, double h,
+                                                      double dt, double eta, Walls wl,
+                                                      double* __restrict__ us) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long per = (long long)g.ny * nxu, total = per * g.batch;
+  const double two_h = 2.0 * h, hh = h * h;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / per;
+    const int rem = int(k - bi * per);
+    const int j = rem / nxu, i = rem - j * nxu;
+    const double* ub = u + bi * per;
+    const double c = ub[(long long)j * nxu + i];
+    if (!g.per_x && (i == 0 || i == g.nx)) {  // wall face: normal velocity kept
+      us[k] = c;
+      continue;
     }
-    gv[k] = val;
+    const double* vb = v + bi * (long long)(g.ny + 1) * g.nx;
+    const double* pr = p + bi * g.plane + (long long)j * g.nx;
+    const int ie = g.per_x ? (i + 1 == g.nx ? 0 : i + 1) : i + 1;
+    const int im = g.per_x ? (i == 0 ? g.nx - 1 : i - 1) : i - 1;
+    const double ue = ub[(long long)j * nxu + ie], uw = ub[(long long)j * nxu + im];
+    const double un = j + 1 < g.ny ? ub[(long long)(j + 1) * nxu + i] : 2.0 * wl.un - c;
+    const double usv = j > 0 ? ub[(long long)(j - 1) * nxu + i] : 2.0 * wl.us - c;
+    const double vbar = ((vb[(long long)j * g.nx + im] + vb[(long long)j * g.nx + i]) +
+                         (vb[(long long)(j + 1) * g.nx + im] + vb[(long long)(j + 1) * g.nx + i])) /
+                        4.0;
+    const double dudx = (ue - uw) / two_h, dudy = (un - usv) / two_h;
+    const double lap = ((((ue + uw) + un) + usv) - 4.0 * c) / hh;
+    const double gp = (pr[i] - pr[im]) / h;
+    us[k] = c + dt * (eta * lap - (c * dudx + vbar * dudy)) - gp;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_predict_v(Geo g, const double* __restrict__ u,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ p, double h,
+                                                      double dt, double eta, Walls wl,
+                                                      double* __restrict__ vs) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long per = (long long)(g.ny + 1) * g.nx, total = per * g.batch;
+  const double two_h = 2.0 * h, hh = h * h;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const long long bi = k / per;
+    const int rem = int(k - bi * per);
+    const int j = rem / g.nx, i = rem - j * g.nx;
+    const double* vb = v + bi * per;
+    const double c = vb[(long long)j * g.nx + i];
+    if (j == 0 || j == g.ny) {  // wall face: normal velocity kept
+      vs[k] = c;
+      continue;
+    }
+    const double* ub = u + bi * (long long)g.ny * nxu;
+    const double* pb = p + bi * g.plane;
+    const double vn = vb[(long long)(j + 1) * g.nx + i], vsv = vb[(long long)(j - 1) * g.nx + i];
+    double ve, vw;
+    if (g.per_x) {
+      ve = vb[(long long)j * g.nx + (i + 1 == g.nx ? 0 : i + 1)];
+      vw = vb[(long long)j * g.nx + (i == 0 ? g.nx - 1 : i - 1)];
+    } else {
+      ve = i + 1 < g.nx ? vb[(long long)j * g.nx + i + 1] : 2.0 * wl.ve - c;
+      vw = i > 0 ? vb[(long long)j * g.nx + i - 1] : 2.0 * wl.vw - c;
+    }
+    const int ip = g.per_x ? (i + 1 == g.nx ? 0 : i + 1) : i + 1;
+    const double ubar = ((ub[(long long)(j - 1) * nxu + i] + ub[(long long)(j - 1) * nxu + ip]) +
+                         (ub[(long long)j * nxu + i] + ub[(long long)j * nxu + ip])) /
+                        4.0;
+    const double dvdx = (ve - vw) / two_h, dvdy = (vn - vsv) / two_h;
+    const double lap = ((((ve + vw) + vn) + vsv) - 4.0 * c) / hh;
+    const double gp = (pb[(long long)j * g.nx + i] - pb[(long long)(j - 1) * g.nx + i]) / h;
+    vs[k] = c + dt * (eta * lap - (ubar * dvdx + c * dvdy)) - gp;
+  }
+}
+
+// Correction of the projection step: u -= G x, v -= G x (the handle's G), p += x.
+__global__ __launch_bounds__(kBlock) void k_correct(Geo g, const double* __restrict__ x, double h,
+                                                    double* __restrict__ u, double* __restrict__ v,
+                                                    double* __restrict__ p) {
+  const int nxu = g.per_x ? g.nx : g.nx + 1;
+  const long long pu = (long long)g.ny * nxu, pv = (long long)(g.ny + 1) * g.nx;
+  const long long tu = pu * g.batch, tv = pv * g.batch, tp = g.plane * g.batch;
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < tu + tv + tp;
+       k += (long long)gridDim.x * kBlock) {
+    if (k < tu) {
+      const long long bi = k / pu;
+      const int rem = int(k - bi * pu);
+      const int j = rem / nxu, f = rem - j * nxu;
+      u[k] = u[k] - grad_u_face(g, x + bi * g.plane + (long long)j * g.nx, f, h);
+    } else if (k < tu + tv) {
+      const long long q = k - tu, bi = q / pv;
+      const int rem = int(q - bi * pv);
+      const int f = rem / g.nx, i = rem - f * g.nx;
+      v[q] = v[q] - grad_v_face(g, x + bi * g.plane, f, i, h);
+    } else {
+      const long long q = k - tu - tv;
+      p[q] = p[q] + x[q];
+    }
   }
 }
 
@@ -910,6 +1034,27 @@ hipError_t launch_grad(const Geo& g, const double* p, double h, double* gu, doub
   const long long nv_ = (long long)(g.ny + 1) * g.nx * g.batch;
   hipLaunchKernelGGL(k_grad_u, dim3(grid_stride_blocks(nu_)), dim3(kBlock), 0, s, g, p, h, gu);
   hipLaunchKernelGGL(k_grad_v, dim3(grid_stride_blocks(nv_)), dim3(kBlock), 0, s, g, p, h, gv);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(const Geo& g, const double* u, const double* v, const double* p,
+                          double h, double dt, double eta, const double walls[4], double* us,
+                          double* vs, hipStream_t s) {
+  const Walls wl{walls[0], walls[1], walls[2], walls[3]};
+  const long long nu_ = (long long)g.ny * (g.per_x ? g.nx : g.nx + 1) * g.batch;
+  const long long nv_ = (long long)(g.ny + 1) * g.nx * g.batch;
+  hipLaunchKernelGGL(k_predict_u, dim3(grid_stride_blocks(nu_)), dim3(kBlock), 0, s, g, u, v, p, h,
+                     dt, eta, wl, us);
+  hipLaunchKernelGGL(k_predict_v, dim3(grid_stride_blocks(nv_)), dim3(kBlock), 0, s, g, u, v, p, h,
+                     dt, eta, wl, vs);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct(const Geo& g, const double* x, double h, double* u, double* v, double* p,
+                          hipStream_t s) {
+  const long long total = (long long)g.ny * (g.per_x ? g.nx : g.nx + 1) * g.batch +
+                          (long long)(g.ny + 1) * g.nx * g.batch + g.plane * g.batch;
+  hipLaunchKernelGGL(k_correct, dim3(grid_stride_blocks(total)), dim3(kBlock), 0, s, g, x, h, u, v, p);
   return hipGetLastError();
 }
 

@@ -215,6 +215,38 @@ class Solver:
                                           self._arg(p, self.cell_shape)), self.handle)
         return p
 
+    # ---------------------------------------------------------------- time step
+    def predict(self, u, v, p, dt, eta, walls=None):
+        """Explicit predictor of Goda's scheme (Eq. 3): returns new (us, vs); walls =
+        (v west, v east, u south, u north) tangential wall velocities."""
+        us, vs = self._new(self.u_shape), self._new(self.v_shape)
+        wl = None if walls is None else (ctypes.c_double * 4)(*[float(a) for a in walls])
+        _check(self._lib.ism_predict(self.handle, self._arg(u, self.u_shape, name="u"),
+                                     self._arg(v, self.v_shape, name="v"),
+                                     self._arg(p, self.cell_shape, name="p"), float(dt), float(eta),
+                                     None if wl is None else ctypes.cast(wl, ctypes.c_void_p),
+                                     self._arg(us, self.u_shape), self._arg(vs, self.v_shape)),
+               self.handle)
+        return us, vs
+
+    def correct(self, x, u, v, p):
+        """u -= G x, v -= G x, p += x, in place."""
+        _check(self._lib.ism_correct(self.handle, self._arg(x, self.cell_shape, name="x"),
+                                     self._arg(u, self.u_shape, name="u"),
+                                     self._arg(v, self.v_shape, name="v"),
+                                     self._arg(p, self.cell_shape, name="p")), self.handle)
+        return u, v, p
+
+    def step(self, u, v, p, dt, eta, walls=None, x=None):
+        """One projection time step (Sec. 2.2): predictor, pressure-change solve, correction.
+        x (optional) warm-starts the pressure change.  Returns (u, v, p, x, stats)."""
+        us, vs = self.predict(u, v, p, dt, eta, walls)
+        b = self.div(us, vs)
+        x, st = self.solve(b, x)
+        p = p.clone()
+        self.correct(x, us, vs, p)
+        return us, vs, p, x, st
+
     # ---------------------------------------------------------------- stages
     def smooth(self, rhs, e, nsweeps=1):
         """nsweeps red-black sweeps on A' e = rhs, in place on e (float32 or float64)."""
