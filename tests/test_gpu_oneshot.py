@@ -59,6 +59,39 @@ def test_coarse_block_gs_matches_oracle(case):
         np.testing.assert_array_equal(E, ref)
 
 
+def test_coarse_block_gs_gmg5_stencil():
+    """Block GS on the 5-point coarse stencil of the GMG variant (Sec. 4.3.2), bitwise."""
+    announce("coarse_bgs_gmg5")
+    nx, ny, n = 512, 384, 16
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=D, bc_y=ND, coarse_stencil="gmg5")
+    Rc = np.random.default_rng(402).standard_normal((1, ny // n, nx // n))
+    tol = 1e-3 * np.abs(Rc).max()
+    E, it, conv = s.coarse_gs(dev(Rc), tol, max_iter=5000)
+    ref, it_ref = O.block_gauss_seidel(O.coarse_stencil_gmg5(nx // n, ny // n, n, D, ND), Rc[0],
+                                       tol, 16, D, ND)
+    assert conv and it == it_ref
+    np.testing.assert_array_equal(host(E)[0], ref)
+
+
+def test_oneshot_batch_meets_every_criterion():
+    """Grids of a batch iterate together until every one meets each criterion, so each ends
+    below the fine criterion and the counts are at least each grid's own."""
+    announce("oneshot_batch")
+    nx, ny, n = 128, 96, 16
+    h = 1.0 / nx
+    bs = np.stack([_mac_rhs(420 + k, nx, ny, h, D) * (1.0 + k) for k in range(2)])
+    m = np.abs(bs).max()
+    s = solver(nx=nx, ny=ny, batch=2, coarsen=n, bc_x=D, bc_y=D, cycling="oneshot",
+               coarse_tol=1e-2 * m, fine_tol=1e-4 * m)
+    x, st = s.solve(dev(bs))
+    x = host(x)
+    assert st["status"] == 0
+    for k in range(2):
+        assert np.abs(bs[k] - O.laplacian(x[k], D, D) / h**2).max() < 1e-4 * m
+        _, info = O.ism_solve_oneshot(bs[k], h, n, D, D, tol_c=1e-2 * m, tol_f=1e-4 * m)
+        assert st["coarse_iters"] >= info["coarse_iters"] and st["fine_iters"] >= info["fine_iters"]
+
+
 def test_coarse_block_gs_iteration_cap():
     announce("coarse_bgs_cap")
     s = solver(nx=256, ny=256, coarsen=16, bc_x=D, bc_y=D)
