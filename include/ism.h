@@ -251,12 +251,14 @@ int ism_coarse_stencil(ism_handle h, double* coef);
  * difference form). */
 int ism_outer_residual(ism_handle h, const double* b, const double* x, double* r);
 
-/* ---- Kernel timing.  While enabled, the handle brackets every launch of the kernel classes
+/* ---- Kernel timing.  While enabled, the handle brackets launches of the kernel classes
  * below with a pair of HIP events on its stream and accumulates their elapsed times at its
- * host synchronizations (the events are created once and reused).  ism_profile(h, 1) resets
- * the totals and starts timing, ism_profile(h, 0) stops it; ism_profile_read synchronizes
- * the stream and returns the total milliseconds and the number of timed launches of one
- * class since the last reset. */
+ * host synchronizations (the events are created once and reused).  ism_profile(h, n) with
+ * n >= 1 resets the totals and starts timing every n-th launch of each class (n = 1: every
+ * launch; each event record costs the stream a few microseconds, so a larger n keeps the
+ * timing from slowing the timed work); ism_profile(h, 0) stops it.  ism_profile_read
+ * synchronizes the stream and returns the total milliseconds and the number of timed
+ * launches of one class since the last reset. */
 #define ISM_KERNEL_CYCLE 0    /* fused two-level cycle kernel                        */
 #define ISM_KERNEL_SMOOTH 1   /* one red-black sweep (unfused form)                  */
 #define ISM_KERNEL_RESTRICT 2 /* residual + restriction (unfused form)               */

@@ -77,6 +77,8 @@ struct ism_ctx {
     hipEvent_t a, b;
   };
   bool prof = false;
+  int prof_every = 1;                             // time every prof_every-th launch of a class
+  int64_t prof_seen[ISM_KERNEL_CLASSES] = {};     // launches of each class since the reset
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<Pending> pending;
@@ -115,8 +117,9 @@ hipEvent_t prof_event(ism_ctx* c) {
   return c->ev_pool[c->ev_used++];
 }
 
-hipEvent_t prof_start(ism_ctx* c) {
+hipEvent_t prof_start(ism_ctx* c, int kind) {
   if (!c->prof) return nullptr;
+  if (c->prof_seen[kind]++ % c->prof_every != 0) return nullptr;  // not sampled
   hipEvent_t a = prof_event(c);
   if (a) (void)hipEventRecord(a, c->stream);
   return a;
@@ -296,27 +299,27 @@ template <typename T>
 int run_cycle(ism_ctx* c, const T* rhs, T** cur, T** spare, double* rc, double* psq, int zero_e) {
   const Geo& g = c->g;
   hipStream_t s = c->stream;
-  hipEvent_t ev = prof_start(c);
+  hipEvent_t ev = prof_start(c, ISM_KERNEL_COARSE);
   int rcode = coarse_solve(c, rc, c->E);
   if (rcode) return rcode;
   prof_stop(c, ISM_KERNEL_COARSE, ev);
   if (c->cfg.fused) {
-    ev = prof_start(c);
+    ev = prof_start(c, ISM_KERNEL_CYCLE);
     LAUNCH(c, ism::launch_cycle_fused<T>(g, rhs, *cur, *spare, c->E, rc, psq, c->cfg.nu, zero_e, s));
     prof_stop(c, ISM_KERNEL_CYCLE, ev);
     std::swap(*cur, *spare);
     return ISM_OK;
   }
-  ev = prof_start(c);
+  ev = prof_start(c, ISM_KERNEL_PROLONG);
   LAUNCH(c, ism::launch_prolong<T>(g, c->E, *cur, zero_e, s));
   prof_stop(c, ISM_KERNEL_PROLONG, ev);
   for (int k = 0; k < c->cfg.nu; ++k) {
-    ev = prof_start(c);
+    ev = prof_start(c, ISM_KERNEL_SMOOTH);
     LAUNCH(c, ism::launch_rbgs<T>(g, rhs, *cur, *spare, s));
     prof_stop(c, ISM_KERNEL_SMOOTH, ev);
     std::swap(*cur, *spare);
   }
-  ev = prof_start(c);
+  ev = prof_start(c, ISM_KERNEL_RESTRICT);
   LAUNCH(c, ism::launch_restrict<T>(g, rhs, *cur, rc, psq, s));
   prof_stop(c, ISM_KERNEL_RESTRICT, ev);
   return ISM_OK;
@@ -531,21 +534,21 @@ int acm_inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, 
     for (int l = 1; l < L; ++l)
       LAUNCH(c, ism::launch_agglomerate(acm_level(g, l), c->acm_r[l], nullptr, 1.0,
                                         l + 1 == L ? c->rc : c->acm_r[l + 1], nullptr, s));
-    hipEvent_t ev = prof_start(c);
+    hipEvent_t ev = prof_start(c, ISM_KERNEL_COARSE);
     int rcode = coarse_solve(c, c->rc, c->E);
     if (rcode) return rcode;
     prof_stop(c, ISM_KERNEL_COARSE, ev);
     const double* above = c->E;
     for (int l = L - 1; l >= 1; --l) {
       LAUNCH(c, ism::launch_inject(acm_level(g, l), above, c->acm_ea[l], 1, s));
-      ev = prof_start(c);
+      ev = prof_start(c, ISM_KERNEL_SMOOTH);
       LAUNCH(c, ism::launch_rbgs<double>(acm_level(g, l), c->acm_r[l], c->acm_ea[l], c->acm_eb[l], s,
                                          std::ldexp(1.0, -l)));
       prof_stop(c, ISM_KERNEL_SMOOTH, ev);
       above = c->acm_eb[l];
     }
     LAUNCH(c, ism::launch_inject(acm_level(g, 0), above, e0, k == 0, s));
-    ev = prof_start(c);
+    ev = prof_start(c, ISM_KERNEL_SMOOTH);
     LAUNCH(c, ism::launch_rbgs<double>(acm_level(g, 0), rhs, e0, sp0, s, 1.0));
     prof_stop(c, ISM_KERNEL_SMOOTH, ev);
     std::swap(e0, sp0);
@@ -673,7 +676,7 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
       fconv = fconv && m < c->cfg.fine_tol * h * h;
     }
     if (fconv || fi >= c->cfg.max_cycles) break;
-    hipEvent_t ev = prof_start(c);
+    hipEvent_t ev = prof_start(c, ISM_KERNEL_SMOOTH);
     LAUNCH(c, ism::launch_rbgs<double>(g, rhs, cur, nxt, s, 1.0));
     prof_stop(c, ISM_KERNEL_SMOOTH, ev);
     std::swap(cur, nxt);
@@ -728,7 +731,7 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   double rel_l2 = 0.0, rel_max = 0.0;
   for (bool first = true;; first = false) {
     Partials p{c->p_sq, c->p_max, first ? c->p_bsq : nullptr, first ? c->p_bmax : nullptr};
-    hipEvent_t ev = prof_start(c);
+    hipEvent_t ev = prof_start(c, ISM_KERNEL_OUTER);
     LAUNCH(c, ism::launch_outer_residual<T>(g, b, x, c->scal + size_t(MEAN_B) * B, c->h2, (T*)c->rT,
                                             c->rc, p, s));
     prof_stop(c, ISM_KERNEL_OUTER, ev);
@@ -1198,7 +1201,10 @@ int ism_profile(ism_handle c, int32_t enable) {
     c->prof_ms[k] = 0.0;
     c->prof_n[k] = 0;
   }
+  if (enable < 0) return set_err(c, ISM_ERR_INVALID, "enable must be >= 0");
+  for (int k = 0; k < ISM_KERNEL_CLASSES; ++k) c->prof_seen[k] = 0;
   c->prof = enable != 0;
+  c->prof_every = enable > 0 ? enable : 1;
   return ISM_OK;
 }
 

@@ -312,9 +312,10 @@ class Solver:
                                             self._arg(r, self.cell_shape)), self.handle)
         return r
 
-    def profile(self, enable=True):
-        """Start (reset) or stop per-kernel-class event timing inside the library."""
-        _check(self._lib.ism_profile(self.handle, int(bool(enable))), self.handle)
+    def profile(self, enable=True, every=1):
+        """Start (reset) or stop per-kernel-class event timing inside the library; every = n
+        times every n-th launch of each class."""
+        _check(self._lib.ism_profile(self.handle, int(every) if enable else 0), self.handle)
 
     def profile_read(self):
         """{class: (total_ms, launches)} since the last profile(True)."""

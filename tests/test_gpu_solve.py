@@ -318,3 +318,10 @@ def test_kernel_timer_counts_launches():
     assert prof["cycle"][1] == st["cycles"] and prof["coarse"][1] == st["cycles"]
     assert prof["outer"][1] == st["outer_iters"] + 1
     assert prof["cycle"][0] > 0.0
+    # every 4th launch of each class: launches 0, 4, 8, ... of the solve
+    s.profile(True, every=4)
+    x, st = s.solve(b)
+    prof = s.profile_read()
+    s.profile(False)
+    assert prof["cycle"][1] == (st["cycles"] + 3) // 4 and prof["coarse"][1] == (st["cycles"] + 3) // 4
+    assert prof["outer"][1] == (st["outer_iters"] + 1 + 3) // 4
