@@ -496,8 +496,10 @@ def coarse_stencil_acm(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
 def coarse_stencil_gmg5(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
     """Aggressive-coarsening GMG variant: the 5-point stencil rediscretized at spacing nh
     (Sec. 3.2 GMG; Sec. 4.3.2 compares ISM with this "five point coarse grid stencil").
-    With the restriction summing h^2-scaled residuals, the coarse equation in the same
-    units has unit coefficients.  Parity unpinned beyond its structure (a reading)."""
+    With the restriction summing h^2-scaled residuals (n^2 of them, so H^2 times the mean
+    residual), the coarse equation in the same units has unit coefficients.  Pinned by the
+    closed form K (x) I + I (x) K with each wall kind's end, its eigenpairs, and exactness
+    H^2 lap p on quadratics."""
     return coarse_stencil_acm(ncx, ncy, 1, bc_x, bc_y)
 
 

@@ -278,6 +278,49 @@ def test_ism_coarse_eigenvalues(bcx, bcy):
         np.testing.assert_allclose(Ac @ v.ravel(), lam * v.ravel(), atol=1e-13)
 
 
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, N), (D, ND)])
+def test_gmg5_coarse_matrix_closed_form(bcx, bcy):
+    # the 5-point stencil rediscretized at spacing H = n h, in the units of the summed
+    # residual: K (x) I + I (x) K with K = [1, -2, 1] and the one-sided ends of each wall
+    # kind (derived by hand: a Neumann ghost equals the cell, a Dirichlet ghost negates it)
+    ncx, ncy = 6, 5
+
+    def K(nc, bc):
+        k = -2 * np.eye(nc) + np.eye(nc, k=1) + np.eye(nc, k=-1)
+        if bc == P:
+            k[0, -1] = k[-1, 0] = 1
+            return k
+        for end, f in zip((0, -1), O.faces(bc)):
+            k[end, end] = -1 if f == "N" else -3
+        return k
+
+    ref = np.kron(np.eye(ncy), K(ncx, bcx)) + np.kron(K(ncy, bcy), np.eye(ncx))
+    Ac = O.coarse_matrix(O.coarse_stencil_gmg5(ncx, ncy, 16, bcx, bcy), bcx, bcy).toarray()
+    np.testing.assert_allclose(Ac, ref, atol=1e-15)
+    # eigenpairs: products of the 1D modes with eigenvalue -4 sin^2(th_k / 2) - 4 sin^2(th_l / 2)
+    J, I = np.indices((ncy, ncx))
+    for k, l in [(0, 1), (2, 3), (4, 1)]:
+        v = (_mode(ncx, k, bcx, I) * _mode(ncy, l, bcy, J)).ravel()
+        lam = -4 * np.sin(_theta(ncx, k, bcx) / 2) ** 2 - 4 * np.sin(_theta(ncy, l, bcy) / 2) ** 2
+        np.testing.assert_allclose(Ac @ v, lam * v, atol=1e-13)
+
+
+def test_gmg5_is_consistent_at_the_coarse_spacing():
+    # on a quadratic sampled at the coarse centres the interior rows give H^2 lap p (exact
+    # for the 5-point stencil), H = n h: the coarse equation in the units of R r', which sums
+    # n^2 residuals scaled by h^2
+    n, h = 8, 0.1
+    H = n * h
+    C = O.coarse_stencil_gmg5(7, 6, n)
+    J, I = np.indices((6, 7))
+    X, Y = H * (I + 0.5), H * (J + 0.5)
+    p = 0.3 * X**2 - 0.7 * X * Y + 1.1 * Y**2
+    Ac = O.coarse_matrix(C)
+    got = (Ac @ p.ravel()).reshape(6, 7)
+    np.testing.assert_allclose(got[1:-1, 1:-1], H * H * (2 * 0.3 + 2 * 1.1) * np.ones((4, 5)),
+                               rtol=1e-12)
+
+
 def test_acm_coarse_is_n_times_five_point():
     for n in (2, 4, 16):
         C = O.coarse_stencil_acm(5, 4, n)
