@@ -107,6 +107,32 @@ def test_dirichlet_outlet_2048_mixed():
     assert np.linalg.norm(host(x).reshape(ny, nx) - xs) / np.linalg.norm(xs) < 1e-6
 
 
+@pytest.mark.parametrize("nx,ny,n,bx,by", [(8, 8, 4, N, N), (32, 16, 16, P, N), (16, 16, 8, D, D),
+                                           (16, 8, 4, P, ND)])
+@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_smallest_grids_against_dense_solve(nx, ny, n, bx, by, fused, prec):
+    """Grids of two coarse cells per axis or fewer columns than one strip of the fused
+    kernel: the solve still reaches the dense solution."""
+    announce("tiny", nx, ny, n, bx, by, fused, prec)
+    b = np.random.default_rng(260).standard_normal((ny, nx))
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, bc_y=by, precision=prec, rtol=1e-10,
+               fused=fused, nu=2, lx=float(nx))
+    x, st = s.solve(dev(b))
+    assert st["status"] == 0
+    xd = O.dense_solve(b, s.h, bx, by)
+    np.testing.assert_allclose(host(x).reshape(ny, nx), xd, rtol=0, atol=1e-7 * np.abs(xd).max())
+
+
+@pytest.mark.parametrize("bx,by", [(D, D), (N, ND)])
+def test_zero_rhs_with_dirichlet_gives_zero(bx, by):
+    announce("zero_rhs_dirichlet", bx, by)
+    s = solver(nx=64, ny=64, coarsen=16, bc_x=bx, bc_y=by)
+    x, st = s.solve(torch.zeros((64, 64), dtype=torch.float64, device="cuda"))
+    assert st["status"] == 0 and st["cycles"] == 0
+    assert np.abs(host(x)).max() == 0.0
+
+
 def test_mixed_outer_steps_match_oracle_emulation():
     announce("mixed_vs_oracle")
     nx = ny = 256
