@@ -661,27 +661,32 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   double* nxt = (double*)c->eA;
   int fi = 0;
   bool fconv = false;
-  std::vector<double> bnorm(B), bmax(B);
+  // each sweep also returns max |b' - A' cur| of its incoming iterate, per tile
+  const int tiles = ism::rbgs_tiles(g);
+  if (tiles > g.cplane) return set_err(c, ISM_ERR_UNSUPPORTED, "sweep tiles exceed the partials");
   for (;;) {
-    Partials pc{c->p_sq, c->p_max, nullptr, nullptr};
-    LAUNCH(c, ism::launch_outer_residual<double>(g, b, cur, mean, c->h2, (double*)nullptr, nullptr, pc, s));
-    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
-    if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
+    hipEvent_t ev = prof_start(c, ISM_KERNEL_SMOOTH);
+    LAUNCH(c, ism::launch_rbgs<double>(g, rhs, cur, nxt, s, 1.0, c->p_max));
+    prof_stop(c, ISM_KERNEL_SMOOTH, ev);
+    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0,
+                                   c->scal + size_t(RMAX) * B, 1, 0, c->fin, s));
     if ((rcode = read_scalars(c))) return rcode;
     fconv = true;
     for (int k = 0; k < B; ++k) {
       const double m = c->h_scal[size_t(RMAX) * B + k];
-      if (!std::isfinite(m) || !std::isfinite(c->h_scal[size_t(RSQ) * B + k]))
-        return set_err(c, ISM_ERR_NONFINITE, "non-finite value in b, x or the residual");
+      if (!std::isfinite(m)) return set_err(c, ISM_ERR_NONFINITE, "non-finite value in b, x or the residual");
       fconv = fconv && m < c->cfg.fine_tol * h * h;
     }
-    if (fconv || fi >= c->cfg.max_cycles) break;
-    hipEvent_t ev = prof_start(c, ISM_KERNEL_SMOOTH);
-    LAUNCH(c, ism::launch_rbgs<double>(g, rhs, cur, nxt, s, 1.0));
-    prof_stop(c, ISM_KERNEL_SMOOTH, ev);
+    if (fconv || fi >= c->cfg.max_cycles) break;  // cur is the result (nxt one sweep past it)
     std::swap(cur, nxt);
     ++fi;
   }
+  // the reported norms: one residual pass over the result
+  Partials pc{c->p_sq, c->p_max, nullptr, nullptr};
+  LAUNCH(c, ism::launch_outer_residual<double>(g, b, cur, mean, c->h2, (double*)nullptr, nullptr, pc, s));
+  if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
+  if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
+  if ((rcode = read_scalars(c))) return rcode;
   if (cur != x)
     HIPCHK(c, hipMemcpyAsync(x, cur, sizeof(double) * size_t(g.plane) * B, hipMemcpyDeviceToDevice, s));
   double rel_l2 = 0.0, rel_max = 0.0;

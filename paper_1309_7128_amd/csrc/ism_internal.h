@@ -34,9 +34,12 @@ struct Partials {
 // neighbours' tiles).
 // The right-hand side is multiplied by rscale as it is read (a power of two on the ACM
 // levels, so the product is exact).
+// With part_max, also max |rhs - A'e_in| per tile into part_max[grid][tile]
+// (rbgs_tiles(g) tiles per grid).
 template <typename T>
 hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* e_in, T* e_out, hipStream_t s,
-                       T rscale = T(1));
+                       T rscale = T(1), double* part_max = nullptr);
+int rbgs_tiles(const Geo& g);
 
 // ACM (FP64): out = 2x2 sums of (r - scale A'e) on the level grid g (e may be null) with
 // per-output sums of squares; ef (+)= piecewise-constant injection of the level above.

@@ -17,11 +17,14 @@ namespace {
 // ----------------------------------------------------------------------------------------
 // One red-black sweep (red on the tile plus one ring, black on the tile), LDS-staged.
 // Tile 64 x 32 cells per workgroup; e is staged with a halo of 2, rhs with a halo of 1.
+// With part_max, the workgroup also writes max |rhs - A'ein| over its tile (the residual of
+// the incoming iterate, from the staged values) to part_max[tile].
 // ----------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rhs,
                                                  const T* __restrict__ ein,
-                                                 T* __restrict__ eout, T rscale) {
+                                                 T* __restrict__ eout, T rscale,
+                                                 double* __restrict__ part_max) {
   constexpr int TX = 64, TY = 32;
   constexpr int LE = TX + 4, HE = TY + 4;
   constexpr int LR = TX + 2, HR = TY + 2;
@@ -48,6 +51,28 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rh
     sr[t] = v;
   }
   __syncthreads();
+  if (part_max) {
+    __shared__ double smax[kBlock / kWave];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < TY * TX; t += kBlock) {
+      const int r = t / TX, c = t - r * TX;
+      const int i = x0 + c, j = y0 + r;
+      if (i >= g.nx || j >= g.ny) continue;
+      const int idx = (r + 2) * LE + c + 2;
+      const T res = sr[(r + 1) * LR + (c + 1)] -
+                    lap5<T>(se[idx], se[idx - 1], se[idx + 1], se[idx - LE], se[idx + LE],
+                            cell_faces(g, i, j));
+      m = fmax(m, fabs(double(res)));
+    }
+    m = wave_max_group(m, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = m;
+    __syncthreads();  // the residual reads of se end before the red cells are overwritten
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, smax[w]);
+      part_max[(long long)blockIdx.z * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] =
+          fmax(m, smax[0]);
+    }
+  }
 
   // red cells of rows/cols 1 .. TY+2 / TX+2 of the staged region
   constexpr int RW = (TX + 2) / 2;
@@ -909,11 +934,14 @@ inline dim3 strip_grid(const Geo& g) {
 // ---------------------------------------------------------------------------- launchers
 
 template <typename T>
-hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* ein, T* eout, hipStream_t s, T rscale) {
+hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* ein, T* eout, hipStream_t s, T rscale,
+                       double* part_max) {
   dim3 grid((g.nx + 63) / 64, (g.ny + 31) / 32, g.batch);
-  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout, rscale);
+  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout, rscale, part_max);
   return hipGetLastError();
 }
+
+int rbgs_tiles(const Geo& g) { return ((g.nx + 63) / 64) * ((g.ny + 31) / 32); }
 
 hipError_t launch_agglomerate(const Geo& g, const double* r, const double* e, double scale,
                               double* out, double* psq, hipStream_t s) {
@@ -1074,8 +1102,10 @@ hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv,
   return hipGetLastError();
 }
 
-template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t, float);
-template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t, double);
+template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t, float,
+                                       double*);
+template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t,
+                                        double, double*);
 template hipError_t launch_restrict<float>(const Geo&, const float*, const float*, double*, double*, hipStream_t);
 template hipError_t launch_restrict<double>(const Geo&, const double*, const double*, double*, double*, hipStream_t);
 template hipError_t launch_prolong<float>(const Geo&, const double*, float*, int, hipStream_t);
