@@ -586,11 +586,12 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
     serial GS on a single block; Sec. 4.3.1: the coarse stage ends when the absolute maximum
     residual falls below its limit).
 
-    The coarse grid is cut into block x block tiles that are updated concurrently.  Inside a
-    tile the cells are visited in lexicographic order (I fastest), each set from its own
-    equation with the tile's newest values; cells of other tiles keep their values from the
-    previous iteration, so one iteration needs one synchronization.  A periodic seam also
-    separates tiles: a neighbour reached across it counts as another tile's.  A cell update is
+    The coarse grid is cut into tiles of block x block cells (or by x bx when block is a pair
+    (by, bx)), aligned at cell 0 of each axis, that are updated concurrently.  Inside a tile
+    the cells are visited in lexicographic order (I fastest), each set from its own equation
+    with the tile's newest values; cells of other tiles keep their values from the previous
+    iteration, so one iteration needs one synchronization.  On a periodic axis a neighbour is
+    found by wrapping and belongs to whichever tile holds the wrapped cell.  A cell update is
     E_C = (R_C - sum over the 8 neighbours of c_nb E_nb) / c_C, the neighbours taken in the
     order (dj, di) = (-1,-1), (-1,0), (-1,1), (0,-1), (0,1), (1,-1), (1,0), (1,1) and the
     products summed left to right (C is the (ncy, ncx, 3, 3) stencil of ``coarse_stencil_*``;
@@ -601,6 +602,7 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
     Pinned by a cell-by-cell loop in the same order (bitwise), by block = grid reducing to
     the lexicographic ``CoarseSolver.gauss_seidel`` and by convergence to the exact solve."""
     ncy, ncx = Rc.shape
+    by, bx = (block, block) if np.isscalar(block) else (int(block[0]), int(block[1]))
     R = np.asarray(Rc, dtype=np.float64)
     if singular(bc_x, bc_y):
         R = R - R.mean()
@@ -629,9 +631,9 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
     # (one per tile) with their neighbours' flat indices and whether each lies in the tile
     flatE = np.arange(ncy * ncx).reshape(ncy, ncx)
     steps = []
-    for lj in range(block):
-        for li in range(block):
-            cj, ci = J[lj::block, li::block].ravel(), I[lj::block, li::block].ravel()
+    for lj in range(by):
+        for li in range(bx):
+            cj, ci = J[lj::by, li::bx].ravel(), I[lj::by, li::bx].ravel()
             if cj.size == 0:
                 continue
             nbs = []
@@ -643,8 +645,7 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
                     ii = ii % ncx
                 ok = (jj >= 0) & (jj < ncy) & (ii >= 0) & (ii < ncx)
                 jc, ic = np.clip(jj, 0, ncy - 1), np.clip(ii, 0, ncx - 1)
-                seam = (jj != cj + dj) | (ii != ci + di)  # reached across a periodic seam
-                same = ok & ~seam & (jc // block == cj // block) & (ic // block == ci // block)
+                same = ok & (jc // by == cj // by) & (ic // bx == ci // bx)
                 nbs.append((flatE[jc, ic], ok, same, C[cj, ci, dj + 1, di + 1]))
             steps.append((flatE[cj, ci], nbs, C[cj, ci, 1, 1]))
     it = 0
@@ -929,9 +930,10 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
 def acm_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, rtol=1e-10, x0=None, max_cycles=100000):
     """Additive correction multigrid with 2x2 agglomeration down to spacing n h.
 
-    Sec. 3.2: coarse equations are sums of fine equations and the coarse result is added
-    to the fine solution without interpolation; Sec. 4: red-black GS on every level; Sec.
-    4.3.1: V cycles without pre-smoothing and one post-smoothing per level.  Summing the
+    Sec. 3.2: each coarse equation is the sum of the fine equations it covers, and the
+    coarse result is added back piecewise constant.  Sec. 4: the smoother is red-black GS on
+    every level.  Sec. 4.3.1 fixes the cycle shape: the descent only restricts, and on the
+    way up every level gets a single sweep after its correction.  Summing the
     2x2 fine equations of a 5-point operator gives twice the 5-point operator, so level l
     (spacing 2^l h) carries 2^l A'.  The coarsest level is solved exactly (zero mean).
     Launch count per cycle as a GPU implementation would issue them: per non-coarsest level
