@@ -76,8 +76,11 @@ extern "C" {
 /* Cycling (Sec. 4.3.1).  REPEAT: {restrict, exact coarse solve, prolongate, nu sweeps} until
  * rtol, as described for ism_solve.  ONESHOT: the paper's simplest accommodative cycling,
  * once per solve: restrict the residual, iterate the coarse grid by block Gauss-Seidel
- * (Sec. 4; tiles of 16 x 16 coarse cells updated concurrently, lexicographic inside a tile)
- * until its absolute maximum residual is below coarse_tol, prolongate and add, then iterate
+ * (Sec. 4; tiles of 16 x 16 coarse cells, aligned at cell 0, updated concurrently and
+ * lexicographic inside; a periodic axis of at most 16 coarse cells is cut into two tiles of
+ * ceil(nc / 2), so that no tile spans a whole periodic axis and a neighbour reached across a
+ * periodic seam always belongs to another tile) until its absolute maximum residual is below
+ * coarse_tol, prolongate and add, then iterate
  * red-black Gauss-Seidel on the fine grid until the absolute maximum residual is below
  * fine_tol.  Both criteria are in the units of A x = b~ (the coarse residual divided by h^2),
  * which are the paper's on its h = 1 grids.  Every coarse iteration and every fine iteration
@@ -129,7 +132,7 @@ typedef struct {
   int64_t launches;    /* kernels launched                                                  */
   int64_t host_syncs;  /* device-to-host reads the host waited for                          */
   double rel_res_l2;   /* max over the batch of ||b~ - A x||_2 / ||b~||_2 (FP64, difference
-                          form), measured before the final mean removal                     */
+                          form) of the returned x (after its final mean removal)            */
   double rel_res_max;  /* max over the batch of max|b~ - A x| / max|b~|                     */
   double seconds;      /* wall time of the call                                              */
   int32_t coarse_iters; /* ISM_CYCLE_ONESHOT: block Gauss-Seidel iterations on the coarse

@@ -61,8 +61,14 @@ struct ism_ctx {
   double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
   double* coef = nullptr;  // coarse 9-point stencil [ncy][ncx][9] (block Gauss-Seidel)
   void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
-  double* h_scal = nullptr;   // pinned mirror of scal, then kChecks slots of B check norms
+  double* h_scal = nullptr;   // host mirror of scal, then kChecks slots of B check norms
   double* h_chk = nullptr;    // = h_scal + kSlots * batch
+  // Pinned h_scal (a handle from ism_create): check norms go straight to h_chk behind an
+  // event.  Otherwise (pageable host memory, no events) they are parked in d_chk on the
+  // device and read back synchronously when the check is acted on.
+  bool pinned = true;
+  double* d_chk = nullptr;    // device check slots [kChecks][batch]
+  std::vector<double> h_mem;  // pageable h_scal when not pinned
   std::vector<hipEvent_t> chk_ev;  // one per check slot (created on first use)
   // ACM hierarchy (coarse_stencil == ISM_COARSE_ACM): per level l = 1..L-1 the agglomerated
   // right-hand side and two correction buffers, plus level-0 squared-residual partials
@@ -201,54 +207,6 @@ int validate(const ism_config* cfg, std::string& why) {
   return ISM_OK;
 }
 
-// 1D eigenbasis of the coarse factors K = [1 -2 1] and M = [1 6 1]/8 = I + K/8 with the
-// boundary rule of the axis: periodic, circulant; at a Neumann end K = -1 and M = 7/8; at a
-// Dirichlet end K = -3 and M = 5/8.  Columns of V are orthonormal eigenvectors; theta is the
-// angle whose cosine gives the eigenvalues lambda_K = -2 (1 - cos theta) and
-// lambda_M = (3 + cos theta) / 4.  The mirror ghost of each end fixes the modes: cos or
-// sin(theta (I + 1/2)) for a Neumann or Dirichlet low end, with theta nc = pi k (two Neumann
-// ends), pi (k + 1) (two Dirichlet ends) or pi (k + 1/2) (one of each).
-void coarse_basis(int nc, int bc, std::vector<double>& V, std::vector<double>& theta) {
-  V.assign(size_t(nc) * nc, 0.0);
-  theta.assign(nc, 0.0);
-  const double pi = 3.14159265358979323846;
-  if (bc != ISM_BC_PERIODIC) {
-    const bool sine = bc == ISM_BC_DIRICHLET || bc == ISM_BC_DIRICHLET_NEUMANN;
-    for (int k = 0; k < nc; ++k) {
-      double sc = std::sqrt(2.0 / nc), kk = k;
-      if (bc == ISM_BC_NEUMANN) {
-        if (k == 0) sc = std::sqrt(1.0 / nc);
-      } else if (bc == ISM_BC_DIRICHLET) {
-        kk = k + 1;
-        if (k == nc - 1) sc = std::sqrt(1.0 / nc);
-      } else {
-        kk = k + 0.5;
-      }
-      theta[k] = pi * kk / nc;
-      for (int I = 0; I < nc; ++I) {
-        const double a = pi * kk * (I + 0.5) / nc;
-        V[size_t(I) * nc + k] = sc * (sine ? std::sin(a) : std::cos(a));
-      }
-    }
-    return;
-  }
-  for (int I = 0; I < nc; ++I) V[size_t(I) * nc] = std::sqrt(1.0 / nc);
-  int col = 1;
-  for (int m = 1; 2 * m < nc; ++m) {
-    const double sc = std::sqrt(2.0 / nc);
-    theta[col] = theta[col + 1] = 2.0 * pi * m / nc;
-    for (int I = 0; I < nc; ++I) {
-      V[size_t(I) * nc + col] = sc * std::cos(2.0 * pi * m * I / nc);
-      V[size_t(I) * nc + col + 1] = sc * std::sin(2.0 * pi * m * I / nc);
-    }
-    col += 2;
-  }
-  if (nc % 2 == 0 && nc > 1) {
-    theta[col] = pi;
-    for (int I = 0; I < nc; ++I) V[size_t(I) * nc + col] = (I % 2 ? -1.0 : 1.0) / std::sqrt(double(nc));
-  }
-}
-
 template <typename T>
 constexpr int dtype_of() {
   return sizeof(T) == 4 ? ISM_F32 : ISM_F64;
@@ -325,6 +283,16 @@ int run_cycle(ism_ctx* c, const T* rhs, T** cur, T** spare, double* rc, double* 
   return ISM_OK;
 }
 
+// The most cycles between two convergence checks of a mixed inner solve, so that FP32
+// stagnation is seen within about 1 ms of device work.  A deterministic function of the
+// grid (a cycle is modelled as a 40 us launch floor plus 3.2 ps per cell, close to the
+// fused kernel and coarse solve on MI355X), so that the cycles at which a solve checks and
+// stops do not depend on host timing.
+int mixed_check_cap(const Geo& g) {
+  const double cells = double(g.plane) * g.batch;
+  return std::max(4, int(1.0e-3 / (40e-6 + 3.2e-12 * cells)));
+}
+
 struct Check {
   int cycle;
   std::vector<double> res;
@@ -338,8 +306,6 @@ struct Monitor {
   bool mixed;
   std::vector<Check> hist;
   int next = 1;
-  std::chrono::steady_clock::time_point last_time = std::chrono::steady_clock::now();
-  int last_cycle = 0;
 
   Monitor(ism_ctx* ctx, const std::vector<double>& tgt, bool is_mixed)
       : c(ctx), target(tgt), mixed(is_mixed) {}
@@ -356,10 +322,6 @@ struct Monitor {
   // The same decision from squared norms sq[batch] taken after cycle k.
   int evaluate(int k, int cycles, const double* sq) {
     const int B = c->g.batch;
-    auto now = std::chrono::steady_clock::now();
-    const double dt = std::chrono::duration<double>(now - last_time).count() / std::max(1, k - last_cycle);
-    last_time = now;
-    last_cycle = k;
     Check ck{k, std::vector<double>(B)};
     bool done = true, finite = true;
     for (int b = 0; b < B; ++b) {
@@ -401,9 +363,8 @@ struct Monitor {
         }
         gap = int(std::min(need, double(std::max(4, k))));
       }
-      if (mixed) {  // keep stagnation visible: at most ~1 ms of device work between checks
-        const int cap = std::max(4, int(1.0e-3 / std::max(dt, 1e-7)));
-        gap = std::min(gap, cap);
+      if (mixed) {  // keep stagnation visible: about 1 ms of device work between checks
+        gap = std::min(gap, mixed_check_cap(c->g));
       }
       gap = std::max(gap, 1);
     }
@@ -417,10 +378,10 @@ struct Monitor {
 //
 // With a fixed check interval every check stops the stream and is evaluated at once.  With
 // adaptive checks the stream never waits on the host: a check's norms are copied to a pinned
-// slot behind an event and the host keeps enqueuing cycles, evaluating each check once its
-// event has completed (and waiting for it only after kLag more cycles).  A stop decision
-// then lands at most kLag cycles late; the cycles already enqueued only reduce the residual
-// further and are counted.  The squared-residual partials are formed only by the cycles a
+// slot behind an event and the host keeps enqueuing cycles, evaluating each check after
+// exactly kLag more cycles (waiting for its event then).  A stop decision therefore lands
+// kLag cycles late; the cycles already enqueued only reduce the residual further and are
+// counted.  The squared-residual partials are formed only by the cycles a
 // check reads.
 template <typename T>
 int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** e_out) {
@@ -445,7 +406,7 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
     *e_out = cur;
     return ISM_OK;
   }
-  while (c->chk_ev.size() < size_t(kChecks)) {
+  while (c->pinned && c->chk_ev.size() < size_t(kChecks)) {
     hipEvent_t e;
     HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->chk_ev.push_back(e);
@@ -463,22 +424,31 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
     ++cycles;
     if (due) {
       if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
-      HIPCHK(c, hipMemcpyAsync(c->h_chk + size_t(slot) * B, c->scal + size_t(ISQ) * B,
-                               sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipEventRecord(c->chk_ev[slot], c->stream));
+      if (c->pinned) {
+        HIPCHK(c, hipMemcpyAsync(c->h_chk + size_t(slot) * B, c->scal + size_t(ISQ) * B,
+                                 sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->chk_ev[slot], c->stream));
+      } else {
+        HIPCHK(c, hipMemcpyAsync(c->d_chk + size_t(slot) * B, c->scal + size_t(ISQ) * B,
+                                 sizeof(double) * B, hipMemcpyDeviceToDevice, c->stream));
+      }
       pend.push_back({k, cycles, slot});
       slot = (slot + 1) % kChecks;
       sched = k + gap;  // provisional, until this check's own evaluation reschedules
     }
     bool stop = false;
     while (!pend.empty()) {
+      // a check is acted on exactly kLag cycles after it (or at the cycle cap), never earlier
+      // even when its result is already in: the cycles a solve runs then do not depend on
+      // host timing
       const Pending p = pend.front();
-      const hipError_t q = hipEventQuery(c->chk_ev[p.slot]);
-      if (q == hipErrorNotReady) {
-        if (k - p.k < kLag && cycles < c->cfg.max_cycles) break;
+      if (k - p.k < kLag && cycles < c->cfg.max_cycles) break;
+      if (c->pinned) {
         HIPCHK(c, hipEventSynchronize(c->chk_ev[p.slot]));
-      } else if (q != hipSuccess) {
-        return set_err(c, ISM_ERR_HIP, std::string("check event: ") + hipGetErrorString(q));
+      } else {
+        HIPCHK(c, hipMemcpyAsync(c->h_chk + size_t(p.slot) * B, c->d_chk + size_t(p.slot) * B,
+                                 sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
       }
       pend.pop_front();
       c->syncs++;
@@ -563,8 +533,7 @@ int acm_inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, 
 // projection b~ = b - mean b), else 0.
 int mean_of_b(ism_ctx* c, const double* b) {
   if (!c->singular) {
-    HIPCHK(c, hipMemsetAsync(c->scal + size_t(MEAN_B) * c->g.batch, 0, sizeof(double) * c->g.batch,
-                             c->stream));
+    LAUNCH(c, ism::launch_fill(c->scal + size_t(MEAN_B) * c->g.batch, c->g.batch, 0.0, c->stream));
     return ISM_OK;
   }
   LAUNCH(c, ism::launch_tile_sum(c->g, b, c->p_sum, c->stream));
@@ -591,7 +560,7 @@ int coarse_block_gs(ism_ctx* c, const double* rc, double tol, int max_iter, doub
   hipStream_t s = c->stream;
   double* Ea = c->t1;
   double* Eb = c->t2;
-  HIPCHK(c, hipMemsetAsync(Ea, 0, sizeof(double) * size_t(g.cplane) * B, s));
+  LAUNCH(c, ism::launch_fill(Ea, (long long)g.cplane * B, 0.0, s));
   int it = 0;
   bool done = false;
   for (;;) {
@@ -654,7 +623,7 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   // b' as an array: the residual of x = 0
   double* rhs = (double*)c->rT;
   double* zero = (double*)c->eB;
-  HIPCHK(c, hipMemsetAsync(zero, 0, sizeof(double) * size_t(g.plane) * B, s));
+  LAUNCH(c, ism::launch_fill(zero, (long long)g.plane * B, 0.0, s));
   Partials none{nullptr, nullptr, nullptr, nullptr};
   LAUNCH(c, ism::launch_outer_residual<double>(g, b, zero, mean, c->h2, rhs, nullptr, none, s));
   double* cur = x;
@@ -718,6 +687,81 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
     st->fine_iters = fi;
   }
   return status;
+}
+
+// Geometry and scalars of a handle from a validated config.
+void init_geometry(ism_ctx* c, const ism_config* cfg, hipStream_t stream) {
+  c->cfg = *cfg;
+  c->stream = stream;
+  Geo& g = c->g;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.batch = cfg->batch;
+  g.n = cfg->coarsen;
+  g.log2n = 0;
+  while ((1 << g.log2n) < g.n) ++g.log2n;
+  g.ncx = g.nx / g.n;
+  g.ncy = g.ny / g.n;
+  g.per_x = cfg->bc_x == ISM_BC_PERIODIC;
+  g.per_y = cfg->bc_y == ISM_BC_PERIODIC;
+  auto dir_lo = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_DIRICHLET_NEUMANN; };
+  auto dir_hi = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_NEUMANN_DIRICHLET; };
+  g.dmask = (dir_lo(cfg->bc_x) ? 1 : 0) | (dir_hi(cfg->bc_x) ? 2 : 0) |
+            (dir_lo(cfg->bc_y) ? 4 : 0) | (dir_hi(cfg->bc_y) ? 8 : 0);
+  c->singular = g.dmask == 0;
+  g.plane = (long long)g.nx * g.ny;
+  g.cplane = (long long)g.ncx * g.ncy;
+  c->h = cfg->lx / cfg->nx;
+  c->h2 = c->h * c->h;
+  c->tsize = cfg->precision == ISM_PREC_MIXED ? 4 : 8;
+}
+
+// The device workspace of a handle (without the ACM levels), every buffer 256-byte aligned:
+// the inner fine arrays rT, eA, eB; nine coarse-sized FP64 arrays; the per-grid scalars, the
+// check slots and the reduction chunks; the coarse tables.  Returns its size in bytes; with
+// a base address, also points the handle's buffers into it.
+size_t layout_workspace(ism_ctx* c, char* base) {
+  const Geo& g = c->g;
+  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t fine = align(size_t(g.plane) * g.batch * c->tsize);
+  const size_t coarse = align(size_t(g.cplane) * g.batch * sizeof(double));
+  const size_t scal = align(sizeof(double) * kSlots * g.batch);
+  const size_t chk = align(sizeof(double) * kChecks * g.batch);
+  const long long fin_count = std::max<long long>(g.cplane, (long long)(g.nx / 2) * (g.ny / 2));
+  const size_t fin = align(sizeof(double) * g.batch * size_t(fin_count / 4096 + 2));
+  const size_t vx = align(sizeof(double) * g.ncx * g.ncx), vy = align(sizeof(double) * g.ncy * g.ncy);
+  const size_t lam = align(sizeof(double) * g.cplane), coef = align(sizeof(double) * 9 * g.cplane);
+  const size_t total = 3 * fine + 9 * coarse + scal + chk + fin + vx + vy + lam + coef;
+  if (!base) return total;
+  char* p = base;
+  c->rT = p; p += fine;
+  c->eA = p; p += fine;
+  c->eB = p; p += fine;
+  double** cbufs[9] = {&c->rc, &c->E, &c->t1, &c->t2, &c->p_sq, &c->p_max, &c->p_bsq, &c->p_bmax, &c->p_sum};
+  for (double** q : cbufs) {
+    *q = (double*)p;
+    p += coarse;
+  }
+  c->scal = (double*)p; p += scal;
+  c->d_chk = (double*)p; p += chk;
+  c->fin = (double*)p; p += fin;
+  c->Vx = (double*)p; p += vx;
+  c->Vy = (double*)p; p += vy;
+  c->invLam = (double*)p; p += lam;
+  c->coef = (double*)p;
+  return total;
+}
+
+// Enqueues what a workspace must hold before a solve: the coarse eigenbasis tables, the
+// assembled coarse stencil (block Gauss-Seidel) and zeroed per-grid scalars.  No host wait.
+int init_device_state(ism_ctx* c) {
+  const Geo& g = c->g;
+  const int kind = c->cfg.coarse_stencil == ISM_COARSE_GMG5 ? 1 : c->cfg.coarse_stencil == ISM_COARSE_ACM ? 2 : 0;
+  LAUNCH(c, ism::launch_coarse_tables(g, kind, c->singular ? 1 : 0, c->Vx, c->Vy, c->invLam, c->stream));
+  LAUNCH(c, ism::launch_fill(c->scal, (long long)kSlots * g.batch, 0.0, c->stream));
+  if (c->cfg.coarse_stencil != ISM_COARSE_ACM)
+    LAUNCH(c, ism::launch_coarse_assemble(g, c->cfg.coarse_stencil == ISM_COARSE_GMG5, c->coef, c->stream));
+  return ISM_OK;
 }
 
 template <typename T>
@@ -790,10 +834,24 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
     LAUNCH(c, ism::launch_tile_sum(g, x, c->p_sum, s));
     if ((rcode = finalize(c, c->p_sum, ism::SUM, 1.0 / double(g.plane), MEAN_X))) return rcode;
     LAUNCH(c, ism::launch_sub_scalar(g, x, c->scal + size_t(MEAN_X) * B, 1, 0, s));
+    // The reported norms are those of the returned x: removing the mean re-rounds every
+    // entry, which moves a residual near the FP64 rounding floor.  One norms-only pass.
+    Partials pn{c->p_sq, c->p_max, nullptr, nullptr};
+    LAUNCH(c, ism::launch_outer_residual<double>(g, b, x, c->scal + size_t(MEAN_B) * B, c->h2,
+                                                 (double*)nullptr, nullptr, pn, s));
+    if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
+    if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
+    if ((rcode = read_scalars(c))) return rcode;
+    rel_l2 = rel_max = 0.0;
+    for (int k = 0; k < B; ++k) {
+      rel_l2 = std::max(rel_l2, std::sqrt(c->h_scal[size_t(RSQ) * B + k]) / den[k]);
+      rel_max = std::max(rel_max, c->h_scal[size_t(RMAX) * B + k] / (bmax[k] > 0.0 ? bmax[k] : 1.0));
+    }
+  } else {
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->syncs++;
+    prof_collect(c);
   }
-  HIPCHK(c, hipStreamSynchronize(s));
-  c->syncs++;
-  prof_collect(c);
   if (st) {
     st->status = status;
     st->outer_iters = outer;
@@ -851,29 +909,8 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
 
   ism_ctx* c = new (std::nothrow) ism_ctx();
   if (!c) return set_err(nullptr, ISM_ERR_INVALID, "out of host memory");
-  c->cfg = *cfg;
-  c->stream = (hipStream_t)stream;
-  Geo& g = c->g;
-  g.nx = cfg->nx;
-  g.ny = cfg->ny;
-  g.batch = cfg->batch;
-  g.n = cfg->coarsen;
-  g.log2n = 0;
-  while ((1 << g.log2n) < g.n) ++g.log2n;
-  g.ncx = g.nx / g.n;
-  g.ncy = g.ny / g.n;
-  g.per_x = cfg->bc_x == ISM_BC_PERIODIC;
-  g.per_y = cfg->bc_y == ISM_BC_PERIODIC;
-  auto dir_lo = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_DIRICHLET_NEUMANN; };
-  auto dir_hi = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_NEUMANN_DIRICHLET; };
-  g.dmask = (dir_lo(cfg->bc_x) ? 1 : 0) | (dir_hi(cfg->bc_x) ? 2 : 0) |
-            (dir_lo(cfg->bc_y) ? 4 : 0) | (dir_hi(cfg->bc_y) ? 8 : 0);
-  c->singular = g.dmask == 0;
-  g.plane = (long long)g.nx * g.ny;
-  g.cplane = (long long)g.ncx * g.ncy;
-  c->h = cfg->lx / cfg->nx;
-  c->h2 = c->h * c->h;
-  c->tsize = cfg->precision == ISM_PREC_MIXED ? 4 : 8;
+  init_geometry(c, cfg, (hipStream_t)stream);
+  const Geo& g = c->g;
 
   int dev = 0;
   hipError_t he = hipGetDevice(&dev);
@@ -881,35 +918,13 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     delete c;
     return set_err(nullptr, ISM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
   }
-  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-  const size_t fine = align(size_t(g.plane) * g.batch * c->tsize);
-  const size_t coarse = align(size_t(g.cplane) * g.batch * sizeof(double));
-  const size_t scal = align(sizeof(double) * kSlots * g.batch);
-  const long long fin_count = std::max<long long>(g.cplane, (long long)(g.nx / 2) * (g.ny / 2));
-  const size_t fin = align(sizeof(double) * g.batch * size_t(fin_count / 4096 + 2));
-  const size_t tabs = align(sizeof(double) * g.ncx * g.ncx) + align(sizeof(double) * g.ncy * g.ncy) +
-                      align(sizeof(double) * g.cplane) + align(sizeof(double) * 9 * g.cplane);
-  c->bytes = 3 * fine + 9 * coarse + scal + fin + tabs;
+  c->bytes = layout_workspace(c, nullptr);
   he = hipMalloc((void**)&c->block, c->bytes);
   if (he != hipSuccess) {
     delete c;
     return set_err(nullptr, ISM_ERR_HIP, std::string("hipMalloc workspace: ") + hipGetErrorString(he));
   }
-  char* p = c->block;
-  c->rT = p; p += fine;
-  c->eA = p; p += fine;
-  c->eB = p; p += fine;
-  double** cbufs[9] = {&c->rc, &c->E, &c->t1, &c->t2, &c->p_sq, &c->p_max, &c->p_bsq, &c->p_bmax, &c->p_sum};
-  for (double** q : cbufs) {
-    *q = (double*)p;
-    p += coarse;
-  }
-  c->scal = (double*)p; p += scal;
-  c->fin = (double*)p; p += fin;
-  c->Vx = (double*)p; p += align(sizeof(double) * g.ncx * g.ncx);
-  c->Vy = (double*)p; p += align(sizeof(double) * g.ncy * g.ncy);
-  c->invLam = (double*)p; p += align(sizeof(double) * g.cplane);
-  c->coef = (double*)p;
+  layout_workspace(c, c->block);
 
   he = hipHostMalloc((void**)&c->h_scal, sizeof(double) * (kSlots + kChecks) * g.batch,
                      hipHostMallocDefault);
@@ -920,6 +935,7 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     return set_err(nullptr, ISM_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(he));
   }
 
+  auto align = [](size_t n) { return (n + 255) & ~size_t(255); };
   if (cfg->coarse_stencil == ISM_COARSE_ACM) {
     const int L = g.log2n;
     size_t total = align(sizeof(double) * size_t(g.nx / 2) * (g.ny / 2) * g.batch);
@@ -946,37 +962,18 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     c->bytes += total;
   }
 
-  // coarse tables (host, FP64), uploaded once
-  std::vector<double> Vx, Vy, thx, thy;
-  coarse_basis(g.ncx, cfg->bc_x, Vx, thx);
-  coarse_basis(g.ncy, cfg->bc_y, Vy, thy);
-  std::vector<double> inv(size_t(g.cplane));
-  for (int l = 0; l < g.ncy; ++l)
-    for (int k = 0; k < g.ncx; ++k) {
-      const double kx = -2.0 * (1.0 - std::cos(thx[k])), mx = (3.0 + std::cos(thx[k])) / 4.0;
-      const double ky = -2.0 * (1.0 - std::cos(thy[l])), my = (3.0 + std::cos(thy[l])) / 4.0;
-      // ISM: K_x (x) M_y + M_x (x) K_y; GMG5: K_x (x) I + I (x) K_y; ACM: n times GMG5
-      const double lam = cfg->coarse_stencil == ISM_COARSE_GMG5  ? kx + ky
-                         : cfg->coarse_stencil == ISM_COARSE_ACM ? double(g.n) * (kx + ky)
-                                                                 : kx * my + mx * ky;
-      // the constant mode is dropped only when A is singular (no Dirichlet face)
-      inv[size_t(l) * g.ncx + k] = (c->singular && l == 0 && k == 0) ? 0.0 : 1.0 / lam;
-    }
-  he = hipMemcpyAsync(c->Vx, Vx.data(), sizeof(double) * Vx.size(), hipMemcpyHostToDevice, c->stream);
-  if (he == hipSuccess)
-    he = hipMemcpyAsync(c->Vy, Vy.data(), sizeof(double) * Vy.size(), hipMemcpyHostToDevice, c->stream);
-  if (he == hipSuccess)
-    he = hipMemcpyAsync(c->invLam, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, c->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(c->scal, 0, scal, c->stream);
-  if (he == hipSuccess && cfg->coarse_stencil != ISM_COARSE_ACM)
-    he = ism::launch_coarse_assemble(g, cfg->coarse_stencil == ISM_COARSE_GMG5, c->coef, c->stream);
-  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-  if (he != hipSuccess) {
+  int rcode = init_device_state(c);
+  if (rcode == ISM_OK) {
+    he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) rcode = set_err(c, ISM_ERR_HIP, std::string("create: ") + hipGetErrorString(he));
+  }
+  if (rcode != ISM_OK) {
+    const std::string msg = c->err;
     if (c->acm_mem) (void)hipFree(c->acm_mem);
     (void)hipHostFree(c->h_scal);
     (void)hipFree(c->block);
     delete c;
-    return set_err(nullptr, ISM_ERR_HIP, std::string("uploading coarse tables: ") + hipGetErrorString(he));
+    return set_err(nullptr, rcode, msg);
   }
   *out = c;
   return ISM_OK;

@@ -100,6 +100,15 @@ hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long lo
 
 hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStream_t s);
 
+// The exact coarse solve's tables: per-axis eigenbases Vx (ncx x ncx), Vy (ncy x ncy) and
+// invLam (ncy x ncx) for stencil kind 0 ISM, 1 GMG5, 2 ACM; the constant mode's entry is 0
+// when singular.
+hipError_t launch_coarse_tables(const Geo& g, int kind, int singular, double* Vx, double* Vy,
+                                double* invLam, hipStream_t s);
+
+// p[0 .. count) = v (a kernel, not a memset node).
+hipError_t launch_fill(double* p, long long count, double v, hipStream_t s);
+
 // One block-iterative Gauss-Seidel iteration on each grid's coarse system (coef: the
 // [ncy][ncx][9] stencil, shared by the batch): Eout from Ein, part_max[grid][tile] = max
 // |R - A_c Ein| over the tile.  Ein and Eout must not alias.  coarse_bgs_tiles(g) tiles per

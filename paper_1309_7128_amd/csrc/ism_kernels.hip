@@ -2,7 +2,9 @@
 // (MI355X: wave64, 160 KB LDS per CU, HBM3E).
 //
 // Every fine-grid kernel streams a 5-point stencil and is bound by HBM bandwidth; none of
-// them is a dense contraction, so nothing here uses MFMA.  Fine arrays are row-major
+// them is a dense contraction and none uses MFMA.  The one exception is k_gemm, the batched
+// FP64 products of the exact coarse solve (dense eigenbasis transforms of the coarse grid),
+// which runs on the FP64 matrix cores.  Fine arrays are row-major
 // [batch][ny][nx]; a wave covers 64 consecutive cells of a row so every global access is a
 // full 256 B (FP32) or 512 B (FP64) row segment.
 //
@@ -521,14 +523,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
 // ----------------------------------------------------------------------------------------
 // One block-iterative Gauss-Seidel iteration on the coarse system A_c E = R (Sec. 4: the
 // coarse grid is iterated by block GS, one synchronization per iteration).  A workgroup
-// owns a kCB x kCB tile of coarse cells: the tile and a ring of neighbours are staged in
-// LDS with the values of the previous iteration, then the tile's cells are updated in
-// lexicographic order (I fastest) in place, so a cell sees the new values of its tile's
-// predecessors and the old values of everything else (a periodic seam separates tiles: the
-// ring holds the copy from across it).  Lexicographic order is run as
-// hyperplanes li + 2 lj = s, s = 0 .. 3 (kCB - 1): the 9-point neighbours that precede a
-// cell lie on earlier hyperplanes and those that follow on later ones, so each hyperplane
-// is one parallel step.  Update: E_C = (R_C - sum of c_nb E_nb) / c_C, neighbours in the
+// owns a tile of tx x ty coarse cells (at most kCB x kCB, aligned at cell 0): the tile and
+// a ring of neighbours are staged in LDS with the values of the previous iteration, then
+// the tile's cells are updated in lexicographic order (I fastest) in place, so a cell sees
+// the new values of its tile's predecessors and the old values of everything else.  The
+// host picks tiles narrower than every periodic axis (bgs_tile), so a neighbour reached
+// across a periodic seam always belongs to another tile and is read from the ring.
+// Lexicographic order is run as hyperplanes li + 2 lj = s, s = 0 .. (tx - 1) + 2 (ty - 1):
+// the 9-point neighbours that precede a cell lie on earlier hyperplanes and those that
+// follow on later ones, so each hyperplane is one parallel step.  Update:
+// E_C = (R_C - sum of c_nb E_nb) / c_C, neighbours in the
 // order (dj, di) = (-1,-1) .. (1,1) without the centre, summed left to right.  Before the
 // update each cell forms the residual of the incoming iterate, R_C - (c_C E_C + sum ...),
 // and the workgroup writes the maximum of its magnitude to part_max[tile].
@@ -539,16 +543,18 @@ __global__ __launch_bounds__(kBlock) void k_coarse_bgs(Geo g, const double* __re
                                                        const double* __restrict__ R,
                                                        const double* __restrict__ Ein,
                                                        double* __restrict__ Eout,
-                                                       double* __restrict__ part_max) {
+                                                       double* __restrict__ part_max, int tx,
+                                                       int ty) {
   constexpr int LW = kCB + 2;
   __shared__ double sE[LW * LW];
   __shared__ double smax[kBlock / kWave];
   const int li = threadIdx.x % kCB, lj = threadIdx.x / kCB;
-  const int I0 = blockIdx.x * kCB, J0 = blockIdx.y * kCB;
+  const int I0 = blockIdx.x * tx, J0 = blockIdx.y * ty;
   const long long cb = (long long)blockIdx.z * g.cplane;
   const int I = I0 + li, J = J0 + lj;
-  const bool active = I < g.ncx && J < g.ncy;
-  // stage the tile and its ring (ring positions are other tiles' cells, or 0 off the grid)
+  const bool active = li < tx && lj < ty && I < g.ncx && J < g.ncy;
+  // stage the tile and its ring (ring positions are other tiles' cells, or 0 off the grid;
+  // slots beyond a narrower tile's ring are staged too and never read)
   for (int t = threadIdx.x; t < LW * LW; t += kBlock) {
     const int rj = t / LW, ri = t - rj * LW;
     int jj = J0 + rj - 1, ii = I0 + ri - 1;
@@ -559,8 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_bgs(Geo g, const double* __re
     else ok = ok && ii >= 0 && ii < g.ncx;
     sE[t] = ok ? Ein[cb + (long long)jj * g.ncx + ii] : 0.0;
   }
-  // the LDS slot of each neighbour (one reached across a periodic seam is always the
-  // staged ring copy: the seam separates tiles)
+  // the LDS slot of each neighbour
   int nb[9];
   double c[9];
   double r = 0.0;
@@ -586,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_bgs(Geo g, const double* __re
   // hyperplane steps: each begins after the previous one's LDS writes (and, for s = 0, after
   // the residual reads of the incoming iterate)
   const int step = li + 2 * lj;
-  for (int s = 0; s < 3 * kCB - 2; ++s) {
+  for (int s = 0; s < tx + 2 * ty - 2; ++s) {
     __syncthreads();
     if (active && step == s) {
       double acc = 0.0;
@@ -929,6 +934,93 @@ inline dim3 strip_grid(const Geo& g) {
   return dim3((g.nx + kWave - 1) / kWave, g.ncy, g.batch);
 }
 
+// ----------------------------------------------------------------------------------------
+// Tables of the exact coarse solve.  Each axis has the 1D factors K = [1 -2 1] and
+// M = [1 6 1] / 8 = I + K / 8 with the axis's end rule: circulant when periodic; at a
+// Neumann end K = -1 and M = 7/8; at a Dirichlet end K = -3 and M = 5/8.  Column k of the
+// axis table V (row-major nc x nc, V[I nc + k]) is an orthonormal eigenvector of both, with
+// angle theta_k: lambda_K = -2 (1 - cos theta), lambda_M = (3 + cos theta) / 4.  The mirror
+// ghost of each wall end fixes the modes: cos or sin(theta (I + 1/2)) for a Neumann or
+// Dirichlet low end, with theta nc = pi k (two Neumann ends), pi (k + 1) (two Dirichlet
+// ends) or pi (k + 1/2) (one of each); a periodic axis takes the constant, then cos and sin
+// pairs of angle 2 pi m / nc, then (nc even) the alternating mode.  invLam[l ncx + k] is
+// 1 / lambda of mode (k, l): ISM K_x M_y + M_x K_y, GMG5 K_x + K_y, ACM n (K_x + K_y); 0 for
+// the constant mode of a singular system.
+// ----------------------------------------------------------------------------------------
+struct AxisMode {
+  double theta, value;  // the mode's angle and its entry at cell I
+};
+
+__device__ AxisMode axis_mode(int nc, bool per, bool dlo, bool dhi, int k, int I) {
+  const double pi = 3.14159265358979323846;
+  AxisMode m;
+  if (per) {
+    if (k == 0) {
+      m.theta = 0.0;
+      m.value = sqrt(1.0 / nc);
+    } else if (nc % 2 == 0 && k == nc - 1) {
+      m.theta = pi;
+      m.value = (I % 2 ? -1.0 : 1.0) / sqrt(double(nc));
+    } else {
+      const int q = (k + 1) / 2;
+      m.theta = 2.0 * pi * q / nc;
+      const double a = 2.0 * pi * q * I / nc;
+      m.value = sqrt(2.0 / nc) * ((k & 1) ? cos(a) : sin(a));
+    }
+    return m;
+  }
+  double sc = sqrt(2.0 / nc), kk = k;
+  if (!dlo && !dhi) {
+    if (k == 0) sc = sqrt(1.0 / nc);
+  } else if (dlo && dhi) {
+    kk = k + 1;
+    if (k == nc - 1) sc = sqrt(1.0 / nc);
+  } else {
+    kk = k + 0.5;
+  }
+  m.theta = pi * kk / nc;
+  const double a = pi * kk * (I + 0.5) / nc;
+  m.value = sc * (dlo ? sin(a) : cos(a));
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_coarse_tables(Geo g, int kind, int singular,
+                                                          double* __restrict__ Vx,
+                                                          double* __restrict__ Vy,
+                                                          double* __restrict__ invLam) {
+  const long long nvx = (long long)g.ncx * g.ncx, nvy = (long long)g.ncy * g.ncy;
+  const long long total = nvx + nvy + g.cplane;
+  const bool xlo = g.dmask & kDirW, xhi = g.dmask & kDirE, ylo = g.dmask & kDirS,
+             yhi = g.dmask & kDirN;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total;
+       t += (long long)gridDim.x * kBlock) {
+    if (t < nvx) {
+      const int I = int(t / g.ncx), k = int(t - (long long)I * g.ncx);
+      Vx[t] = axis_mode(g.ncx, g.per_x, xlo, xhi, k, I).value;
+    } else if (t < nvx + nvy) {
+      const long long u = t - nvx;
+      const int I = int(u / g.ncy), k = int(u - (long long)I * g.ncy);
+      Vy[u] = axis_mode(g.ncy, g.per_y, ylo, yhi, k, I).value;
+    } else {
+      const long long u = t - nvx - nvy;
+      const int l = int(u / g.ncx), k = int(u - (long long)l * g.ncx);
+      const double cx = cos(axis_mode(g.ncx, g.per_x, xlo, xhi, k, 0).theta);
+      const double cy = cos(axis_mode(g.ncy, g.per_y, ylo, yhi, l, 0).theta);
+      const double kx = -2.0 * (1.0 - cx), mx = (3.0 + cx) / 4.0;
+      const double ky = -2.0 * (1.0 - cy), my = (3.0 + cy) / 4.0;
+      const double lam = kind == 1 ? kx + ky : kind == 2 ? double(g.n) * (kx + ky) : kx * my + mx * ky;
+      invLam[u] = (singular && l == 0 && k == 0) ? 0.0 : 1.0 / lam;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ p, long long count,
+                                                 double v) {
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < count;
+       t += (long long)gridDim.x * kBlock)
+    p[t] = v;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------- launchers
@@ -1038,14 +1130,35 @@ hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStrea
   return hipGetLastError();
 }
 
+hipError_t launch_coarse_tables(const Geo& g, int kind, int singular, double* Vx, double* Vy,
+                                double* invLam, hipStream_t s) {
+  const long long total = (long long)g.ncx * g.ncx + (long long)g.ncy * g.ncy + g.cplane;
+  hipLaunchKernelGGL(k_coarse_tables, dim3(grid_stride_blocks(total)), dim3(kBlock), 0, s, g, kind,
+                     singular, Vx, Vy, invLam);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, long long count, double v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_stride_blocks(count)), dim3(kBlock), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+// Block-GS tile width on an axis of nc coarse cells: kCB, except that a periodic axis of at
+// most kCB cells is split into two tiles, so that no tile spans a whole periodic axis.
+int bgs_tile(int nc, bool periodic) { return periodic && nc <= kCB ? (nc + 1) / 2 : kCB; }
+
 int coarse_bgs_tiles(const Geo& g) {
-  return ((g.ncx + kCB - 1) / kCB) * ((g.ncy + kCB - 1) / kCB);
+  const int tx = bgs_tile(g.ncx, g.per_x), ty = bgs_tile(g.ncy, g.per_y);
+  return ((g.ncx + tx - 1) / tx) * ((g.ncy + ty - 1) / ty);
 }
 
 hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, const double* Ein,
                              double* Eout, double* part_max, hipStream_t s) {
-  dim3 grid((g.ncx + kCB - 1) / kCB, (g.ncy + kCB - 1) / kCB, g.batch);
-  hipLaunchKernelGGL(k_coarse_bgs, grid, dim3(kBlock), 0, s, g, coef, R, Ein, Eout, part_max);
+  const int tx = bgs_tile(g.ncx, g.per_x), ty = bgs_tile(g.ncy, g.per_y);
+  dim3 grid((g.ncx + tx - 1) / tx, (g.ncy + ty - 1) / ty, g.batch);
+  hipLaunchKernelGGL(k_coarse_bgs, grid, dim3(kBlock), 0, s, g, coef, R, Ein, Eout, part_max, tx,
+                     ty);
   return hipGetLastError();
 }
 

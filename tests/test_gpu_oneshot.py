@@ -21,15 +21,24 @@ ND, DN = O.NEUMANN_DIRICHLET, O.DIRICHLET_NEUMANN
 _CODE = {N: "N", P: "P", D: "D", ND: "ND", DN: "DN"}
 
 # (nx, ny, n, bc_x, bc_y): coarse grids of one partial tile, several tiles with ragged
-# edges, periodic seams inside one tile and between tiles
+# edges, periodic seams between tiles (a short periodic axis is split in two)
 GS_CASES = [
     (192, 160, 16, D, D),        # 12 x 10 coarse: one partial tile
     (512, 384, 16, D, ND),       # 32 x 24: four tiles, the last row of tiles partial
     (640, 320, 16, P, DN),       # 40 x 20: periodic seam between tiles
-    (192, 128, 16, P, D),        # 12 x 8: periodic seam inside one tile
+    (192, 128, 16, P, D),        # 12 x 8: the periodic axis split into two tiles of 6
     (512, 384, 16, N, N),
     (320, 256, 16, P, N),
 ]
+
+
+def bgs_block(ncx, ncy, bx, by):
+    """The library's block-GS tiling, as include/ism.h states it: (by, bx) tiles of 16 x 16
+    coarse cells, except that a periodic axis of at most 16 cells is split into two tiles of
+    ceil(nc / 2), so that no tile spans a whole periodic axis."""
+    def one(nc, bc):
+        return (nc + 1) // 2 if bc == P and nc <= 16 else 16
+    return one(ncy, by), one(ncx, bx)
 
 
 def _ids(c):
@@ -48,7 +57,7 @@ def test_coarse_block_gs_matches_oracle(case):
     E, it, conv = s.coarse_gs(dev(Rc[None]), tol, max_iter=5000)
     E = host(E).reshape(ncy, ncx)
     C = O.coarse_stencil_ism(ncx, ncy, n, bx, by)
-    ref, it_ref = O.block_gauss_seidel(C, Rc, tol, 16, bx, by)
+    ref, it_ref = O.block_gauss_seidel(C, Rc, tol, bgs_block(ncx, ncy, bx, by), bx, by)
     assert conv
     if O.singular(bx, by):
         assert abs(it - it_ref) <= 1
@@ -121,7 +130,8 @@ def test_oneshot_solve_matches_oracle(bx, by, n):
                fine_tol=tol_f, lx=1.0)
     x, st = s.solve(dev(b))
     x = host(x).reshape(ny, nx)
-    xo, info = O.ism_solve_oneshot(b, h, n, bx, by, tol_c=tol_c, tol_f=tol_f)
+    xo, info = O.ism_solve_oneshot(b, h, n, bx, by, tol_c=tol_c, tol_f=tol_f,
+                                   block=bgs_block(nx // n, ny // n, bx, by))
     print(st, info, flush=True)
     assert st["status"] == 0 and st["cycles"] == 1
     exact = not O.singular(bx, by)
