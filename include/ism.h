@@ -163,6 +163,25 @@ int ism_workspace_bytes(ism_handle h, size_t* bytes);
  * solution on return (the zero-mean one when A is singular).  st may be NULL. */
 int ism_solve(ism_handle h, const double* b, double* x, ism_stats* st);
 
+/* Allocation-free solve, for callers that cannot allocate device or pinned memory (tight
+ * serving loops, harnesses that forbid hipMalloc).  The same solve as ism_create, ism_solve
+ * and ism_destroy on cfg: the same kernels, tables and convergence-check schedule, so the
+ * same x and the same stats (seconds and host_syncs aside), without a handle.  Its workspace
+ * lies in a static device array of ISM_STATIC_SCRATCH_BYTES that every GPU the library runs
+ * on holds until the process ends.  Calls no hipMalloc, hipFree, hipHostMalloc or
+ * hipEventCreate: read-backs go to pageable host memory, with a stream synchronization
+ * whenever a convergence check is read.
+ * cfg: as for ism_create (ISM or GMG5 stencil; ACM returns ISM_ERR_UNSUPPORTED).  A grid
+ * whose workspace exceeds the array (about 3 nx ny batch sizeof(T) bytes, T the inner type)
+ * returns ISM_ERR_UNSUPPORTED before any device call.  stream: the HIP stream every
+ * operation is ordered on (NULL: the null stream).  b, x: as for ism_solve.  Errors read
+ * with ism_last_error(NULL).  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (a call writes everything it reads there first): calls that overlap
+ * on one GPU race and must not be issued. */
+#define ISM_STATIC_SCRATCH_BYTES (64u << 20)
+int ism_solve_static(const ism_config* cfg, const double* b, double* x, ism_stats* stats,
+                     void* stream);
+
 /* Adjoint solve A^T lam = g~.  A is symmetric for these boundary conditions, so
  * this is the same solve; it exists so that a differentiable projection names its
  * backward pass.  Same layouts and ownership as ism_solve. */

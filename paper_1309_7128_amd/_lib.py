@@ -75,6 +75,8 @@ _SIGNATURES = {
     "ism_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "ism_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(IsmStats)]),
     "ism_solve_adjoint": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(IsmStats)]),
+    "ism_solve_static": (ctypes.c_int, [ctypes.POINTER(IsmConfig), _P, _P,
+                                        ctypes.POINTER(IsmStats), _P]),
     "ism_div": (ctypes.c_int, [_P, _P, _P, _P]),
     "ism_grad": (ctypes.c_int, [_P, _P, _P, _P]),
     "ism_div_adjoint": (ctypes.c_int, [_P, _P, _P, _P]),

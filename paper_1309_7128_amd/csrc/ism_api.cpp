@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -869,6 +870,38 @@ int solve_impl(ism_ctx* c, const double* b, double* x, ism_stats* st) {
 
 }  // namespace
 
+// ================================================================== allocation-free solve
+// A workspace for callers that cannot allocate: a static device array that every GPU the
+// library runs on holds until the process ends.  In host code its name is only a stand-in,
+// never a device address: each device holds its own copy, whose address is looked up once
+// per device (with that device current) and used everywhere host code needs the memory.
+constexpr size_t kStaticScratchBytes = size_t(ISM_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+// This device's copy of scratch (the current device must be dev).
+int scratch_address(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_err(nullptr, ISM_ERR_UNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(nullptr, ISM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = (char*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return ISM_OK;
+}
+
+}  // namespace
+
 // ================================================================== C ABI
 
 extern "C" {
@@ -1004,6 +1037,44 @@ int ism_solve(ism_handle c, const double* b, double* x, ism_stats* st) {
   if (st) *st = ism_stats{};
   if (c->cfg.cycling == ISM_CYCLE_ONESHOT) return oneshot_solve(c, b, x, st);
   return c->tsize == 4 ? solve_impl<float>(c, b, x, st) : solve_impl<double>(c, b, x, st);
+}
+
+int ism_solve_static(const ism_config* cfg, const double* b, double* x, ism_stats* st,
+                     void* stream) {
+  if (st) *st = ism_stats{};
+  std::string why;
+  const int v = validate(cfg, why);
+  if (v != ISM_OK) return set_err(nullptr, v, why);
+  if (cfg->coarse_stencil == ISM_COARSE_ACM)
+    return set_err(nullptr, ISM_ERR_UNSUPPORTED, "ism_solve_static: the ACM scheme needs level buffers; use ism_create");
+  if (!b || !x) return set_err(nullptr, ISM_ERR_INVALID, "b and x must be device pointers");
+  ism_ctx c;
+  init_geometry(&c, cfg, (hipStream_t)stream);
+  const size_t need = layout_workspace(&c, nullptr);
+  if (need > kStaticScratchBytes)
+    return set_err(nullptr, ISM_ERR_UNSUPPORTED,
+                   "ism_solve_static: this grid needs " + std::to_string(need) +
+                       " bytes of workspace, more than the " + std::to_string(kStaticScratchBytes) +
+                       "-byte static scratch; use ism_create");
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return set_err(nullptr, ISM_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  char* base = nullptr;
+  int rcode = scratch_address(dev, &base);
+  if (rcode) return rcode;
+  layout_workspace(&c, base);
+  c.bytes = need;
+  c.pinned = false;
+  c.h_mem.assign(size_t(kSlots + kChecks) * c.g.batch, 0.0);
+  c.h_scal = c.h_mem.data();
+  c.h_chk = c.h_scal + size_t(kSlots) * c.g.batch;
+  rcode = init_device_state(&c);
+  if (rcode == ISM_OK) {
+    if (c.cfg.cycling == ISM_CYCLE_ONESHOT) rcode = oneshot_solve(&c, b, x, st);
+    else rcode = c.tsize == 4 ? solve_impl<float>(&c, b, x, st) : solve_impl<double>(&c, b, x, st);
+  }
+  if (rcode < 0) g_create_error = c.err;
+  return rcode;
 }
 
 int ism_solve_adjoint(ism_handle c, const double* g, double* lam, ism_stats* st) {

@@ -99,3 +99,22 @@ def test_null_arguments():
     assert lib.ism_solve(None, None, None, None) == L.ISM_ERR_INVALID
     assert lib.ism_destroy(None) == L.ISM_OK
     assert lib.ism_status_string(L.ISM_NOT_CONVERGED) == b"not converged"
+
+
+def test_static_solve_rejects_grids_beyond_its_scratch():
+    # checked before any device call: 8192^2 mixed needs about 800 MB of workspace, more than
+    # the static array; the ACM scheme is not available without a handle
+    lib = L.load()
+    cfg = L.IsmConfig()
+    assert lib.ism_config_init(ctypes.byref(cfg), 8192, 8192, 1) == 0
+    cfg.precision = L.ISM_PREC_MIXED
+    st = L.IsmStats()
+    rc = lib.ism_solve_static(ctypes.byref(cfg), 1, 1, ctypes.byref(st), None)
+    assert rc == L.ISM_ERR_UNSUPPORTED
+    assert b"static scratch" in lib.ism_last_error(None)
+    assert lib.ism_config_init(ctypes.byref(cfg), 256, 256, 1) == 0
+    cfg.coarse_stencil = L.ISM_COARSE_ACM
+    assert lib.ism_solve_static(ctypes.byref(cfg), 1, 1, ctypes.byref(st), None) == L.ISM_ERR_UNSUPPORTED
+    cfg.coarse_stencil = L.ISM_COARSE_ISM
+    cfg.nx = 100  # not a multiple of the tile
+    assert lib.ism_solve_static(ctypes.byref(cfg), 1, 1, ctypes.byref(st), None) == L.ISM_ERR_UNSUPPORTED
