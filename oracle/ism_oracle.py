@@ -95,7 +95,7 @@ def _neighbours(p, bc_x, bc_y):
 
 
 def laplacian(p, bc_x=NEUMANN, bc_y=NEUMANN):
-    """A'p: the sum of (p_nb - p_C) over the four faces, in the order W, E, S, N.
+    """A'p: the sum of (p_nb - p_C) over the four faces, added as (W + E) + (S + N).
 
     Sec. 2.3 (five-point Laplacian) and Sec. 3.3 (its finite-volume reading: a sum of face
     fluxes).  A Neumann wall face carries no flux; a Dirichlet wall face carries
@@ -106,7 +106,7 @@ def laplacian(p, bc_x=NEUMANN, bc_y=NEUMANN):
     zero = np.zeros((), dtype=p.dtype)
     d = {k: np.where(pres, val - p, np.where(dw, (-p) - p, zero))
          for k, (val, pres, dw) in nb.items()}
-    return ((d["W"] + d["E"]) + d["S"]) + d["N"]
+    return (d["W"] + d["E"]) + (d["S"] + d["N"])
 
 
 def neighbour_count(nx, ny, bc_x=NEUMANN, bc_y=NEUMANN):
@@ -128,7 +128,7 @@ def red_black_gs(p, rhs, bc_x=NEUMANN, bc_y=NEUMANN, sweeps=1):
 
     A sweep updates the red cells ((i + j) even) and then the black cells.  A cell is set
     so that its own equation holds: p_C = (sum of existing neighbour values - rhs_C) / m_C,
-    with the neighbour values summed in the order W, E, S, N (a neighbour behind a wall
+    with the neighbour values added as (W + E) + (S + N) (a neighbour behind a wall
     counting 0), m_C the diagonal of ``neighbour_count`` and the division taken as a
     product with 1/m_C rounded to the working precision.  No over-relaxation factor is
     given in the paper; this is plain Gauss-Seidel.  Pinned by a cell-by-cell sequential
@@ -144,7 +144,7 @@ def red_black_gs(p, rhs, bc_x=NEUMANN, bc_y=NEUMANN, sweeps=1):
     for _ in range(sweeps):
         for colour in (red, ~red):
             nb = _neighbours(p, bc_x, bc_y)
-            s = ((nb["W"][0] + nb["E"][0]) + nb["S"][0]) + nb["N"][0]
+            s = (nb["W"][0] + nb["E"][0]) + (nb["S"][0] + nb["N"][0])
             new = (s - rhs) * inv_m
             p = np.where(colour, new, p)
     return p
@@ -364,23 +364,31 @@ def _interp_axis(nf, n, bc):
     return lo, hi, t, s_lo, s_hi
 
 
-def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN):
+def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN, dtype=np.float64):
     """P E: bilinear interpolation of the coarse values to every fine cell centre.
 
     Eq. 5 with origin at the south-west centre Q11 of the surrounding rectangle, in
     coordinates scaled by the rectangle size: p = Q11 (1-x)(1-y) + Q21 x (1-y) + Q12 (1-x) y
     + Q22 x y, evaluated in nested form, first along x on the lower and upper coarse rows,
     then along y: p = (Q11 (1-x) + Q21 x)(1-y) + (Q12 (1-x) + Q22 x) y.  The same
-    interpolation serves the coarse stencil and the prolongation (Sec. 3.3).  Pinned by
-    exactness on constants and bilinear fields, dyadic weights and the coarse-stencil
-    identities."""
+    interpolation serves the coarse stencil and the prolongation (Sec. 3.3).
+
+    dtype is the fine arithmetic.  The x step works on coarse rows (coarse-grid data, FP64)
+    and is rounded to dtype; the y step, one per fine cell, is evaluated in dtype.  In FP64
+    this is the plain FP64 evaluation.  Pinned by exactness on constants and bilinear fields,
+    dyadic weights and the coarse-stencil identities (FP64), and by the FP32 result lying
+    within its rounding bound of the FP64 one."""
     ncy, ncx = E.shape
     ilo, ihi, tx, sxl, sxh = _interp_axis(ncx * n, n, bc_x)
     jlo, jhi, ty, syl, syh = _interp_axis(ncy * n, n, bc_y)
     E = np.asarray(E, dtype=np.float64)
     # along x, every coarse row (a ghost centre's value negated exactly by its sign)
     ex = (E[:, ilo] * sxl[None, :]) * (1 - tx)[None, :] + (E[:, ihi] * sxh[None, :]) * tx[None, :]
-    return (ex[jlo, :] * syl[:, None]) * (1 - ty)[:, None] + (ex[jhi, :] * syh[:, None]) * ty[:, None]
+    ex = ex.astype(dtype)
+    # along y in dtype (the weights are dyadic and the signs +-1, both exact in either type)
+    wl, wh = (1 - ty).astype(dtype)[:, None], ty.astype(dtype)[:, None]
+    sl, sh = syl.astype(dtype)[:, None], syh.astype(dtype)[:, None]
+    return (ex[jlo, :] * sl) * wl + (ex[jhi, :] * sh) * wh
 
 
 def inject_constant(E, n):
@@ -878,9 +886,10 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
 
     Not in the paper (its solver is FP32 throughout, Sec. 4.2).  Outer step in FP64:
     r = b' - A'x; stop if ||r|| <= rtol ||b'||.  Inner solve of A'e = r from e = 0: the fine
-    arrays e and r32 = fp32(r) and every fine operation are FP32; restriction sums, the
-    coarse solve and the bilinear interpolation are FP64, the interpolated correction is
-    added to e in FP64 and rounded to FP32.  The first restriction sums the FP64 r.  The
+    arrays e and r32 = fp32(r) and every fine operation are FP32: smoothing, the residual and
+    the prolongation (its x step on the FP64 coarse rows rounded to FP32, its y step and the
+    addition to e in FP32); restriction sums and the coarse solve are FP64.  The first
+    restriction sums the FP64 r.  The
     inner loop stops when ||r32 - A'e|| <= max(inner_rtol ||r||, rtol ||b'|| / 2), or when
     the residual fell by less than stall_drop over the last stall_window cycles, or at
     max_inner.  Then x += e in FP64.  Returns (x, info)."""
@@ -906,7 +915,7 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
         inner_hist = []
         for _ in range(max_inner):
             E = cs.solve(Rc)
-            e = (e.astype(np.float64) + prolong_bilinear(E, n, bc_x, bc_y)).astype(np.float32)
+            e = e + prolong_bilinear(E, n, bc_x, bc_y, np.float32)
             e = red_black_gs(e, r32, bc_x, bc_y, sweeps=nu)
             res = r32 - laplacian(e, bc_x, bc_y)
             res64 = res.astype(np.float64)

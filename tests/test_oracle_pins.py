@@ -104,7 +104,8 @@ def test_exact_solve_residual_256(bcx, bcy):
 
 
 def _sequential_rbgs(p, rhs, bcx, bcy):
-    """Cell-by-cell Gauss-Seidel, red cells first, each cell solved for its own equation."""
+    """Cell-by-cell Gauss-Seidel, red cells first, each cell solved for its own equation
+    (the existing neighbours added per axis, x pair plus y pair)."""
     p = p.copy()
     ny, nx = p.shape
     for colour in (0, 1):
@@ -112,13 +113,16 @@ def _sequential_rbgs(p, rhs, bcx, bcy):
             for i in range(nx):
                 if (i + j) % 2 != colour:
                     continue
-                s, m = 0.0, 0
+                sx, sy, m = 0.0, 0.0, 0
                 for dj, di in ((0, -1), (0, 1), (-1, 0), (1, 0)):
                     jj, ii = j + dj, i + di
                     if bcx == P:
                         ii %= nx
                     if 0 <= ii < nx and 0 <= jj < ny:
-                        s += p[jj, ii]
+                        if di:
+                            sx += p[jj, ii]
+                        else:
+                            sy += p[jj, ii]
                         m += 1
                     else:
                         # behind a wall: the equation's ghost is +p (Neumann: no term) or
@@ -127,7 +131,7 @@ def _sequential_rbgs(p, rhs, bcx, bcy):
                         low = di < 0 or dj < 0
                         dirichlet = bc == D or (bc == ND and not low) or (bc == DN and low)
                         m += 2 if dirichlet else 0
-                p[j, i] = (s - rhs[j, i]) * (1.0 / m)
+                p[j, i] = ((sx + sy) - rhs[j, i]) * (1.0 / m)
     return p
 
 
@@ -190,6 +194,27 @@ def test_prolong_exact_on_constants_and_bilinear(n, bcx, bcy):
     j, i = np.indices(p.shape)
     inner = (i + 0.5 > n / 2) & (i + 0.5 < n * (ncx - 0.5)) & (j + 0.5 > n / 2) & (j + 0.5 < n * (ncy - 0.5))
     np.testing.assert_allclose(p[inner], f(i + 0.5, j + 0.5)[inner], atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [4, 32])
+@pytest.mark.parametrize("bcx,bcy", BCS)
+def test_prolong_fp32_within_its_rounding_of_fp64(n, bcx, bcy):
+    # the FP32 form rounds the x-interpolated coarse rows once, then rounds each of the two
+    # y products and their sum: at most 3 relative roundings of u = 2^-24 on each term
+    ncx, ncy = 5, 4
+    E = np.random.default_rng(60).standard_normal((ncy, ncx))
+    p64 = O.prolong_bilinear(E, n, bcx, bcy)
+    p32 = O.prolong_bilinear(E, n, bcx, bcy, np.float32)
+    assert p32.dtype == np.float32
+    # sum over the four corners of |Q| times its weight (ghost signs dropped)
+    ilo, ihi, tx, _, _ = O._interp_axis(ncx * n, n, bcx)
+    jlo, jhi, ty, _, _ = O._interp_axis(ncy * n, n, bcy)
+    ax = np.abs(E[:, ilo]) * (1 - tx) + np.abs(E[:, ihi]) * tx
+    absP = ax[jlo, :] * (1 - ty)[:, None] + ax[jhi, :] * ty[:, None]
+    u = 2.0 ** -24
+    assert np.all(np.abs(p32.astype(np.float64) - p64) <= 3.01 * u * absP)
+    # the rounding is that of FP32 (not merely small): some cells differ from the FP64 value
+    assert np.any(p32.astype(np.float64) != p64)
 
 
 def test_prolong_weights_are_dyadic():
