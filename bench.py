@@ -68,7 +68,11 @@ def parse():
                     help="time every n-th launch of each kernel class inside the timed region "
                          "(each HIP event record costs the stream a few microseconds)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
-                    help="only run a plain device copy of this many GiB (counter calibration)")
+                    help="only run a plain device copy of this many GiB, three times (copy "
+                         "ceiling and counter calibration)")
+    ap.add_argument("--read-gib", type=float, default=0.0,
+                    help="only run a plain device read (a sum) of this many GiB, three times "
+                         "(counter calibration)")
     ap.add_argument("--time-steps", type=int, default=0,
                     help="jet workload: this many successive warm-started solves per step (the "
                          "time loop); step t's right-hand side is step 0's shifted t cells in x")
@@ -192,6 +196,14 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+    if args.read_gib > 0:
+        n = int(args.read_gib * (1 << 30) // 4)
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            tot = a.sum()
+        torch.cuda.synchronize()
+        print(json.dumps({"read_bytes": 4 * n, "sum": float(tot)}))
         return
 
     w = inputs.WORKLOADS[args.workload]
@@ -378,7 +390,7 @@ def cpu_baseline(w, b_dev, gpu_cycles, gpu_outer, nu):
         t0 = time.perf_counter()
         for _ in range(n_cyc):
             E = cs.solve(Rc)
-            e = (e.astype(np.float64) + O.prolong_bilinear(E, n, bx, by)).astype(ft)
+            e = e + O.prolong_bilinear(E, n, bx, by, ft)
             e = O.red_black_gs(e, rT, bx, by, sweeps=nu)
             res = rT - O.laplacian(e, bx, by)
             Rc = O.restrict_sum(res.astype(np.float64), n)

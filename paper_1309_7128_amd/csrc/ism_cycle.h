@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 
 #include "ism_device.h"
 
@@ -14,12 +15,13 @@ namespace {
 // Fused two-level cycle kernel: row-pipelined temporal blocking in registers.
 //
 // One wave owns a strip of LW = 64 CPL columns (CPL consecutive cells per lane) and a run of
-// L output rows, and walks up the strip one row at a time holding a ring of P rows of e and
-// rhs in registers.  When row t enters it receives the bilinear coarse correction (Eq. 5).
-// Then half-step k = 1 .. 2 NU (odd k red, even k black) updates its colour on row t - k:
-// at that moment row t - k + 1 has just had half-step k - 1 and row t - k - 1 still waits
-// for half-step k + 1, so every cell sees exactly the neighbours the k-th half-step of a
-// whole-grid sweep would give it.  Row t - 2 NU - 1 is then final: its residual is formed,
+// L output rows, and walks along the strip one row at a time (up, or down for every other
+// chunk) holding a ring of P rows of e and rhs in registers.  When row t enters it receives
+// the bilinear coarse correction (Eq. 5).  Then half-step k = 1 .. 2 NU (odd k red, even k
+// black) updates its colour on the row that entered k steps earlier: at that moment the row
+// after it has just had half-step k - 1 and the row before it still waits for half-step
+// k + 1, so every cell sees exactly the neighbours the k-th half-step of a whole-grid sweep
+// would give it.  The row that entered 2 NU + 1 steps earlier is then final: its residual is formed,
 // summed over the n x n coarse tiles, and the row is written out.  East and west neighbours
 // across lanes come from DPP wavefront shifts, so the half-steps touch neither LDS nor
 // memory.  The strip's PX >= 2 NU + 1 outer columns on each side and its first H rows absorb
@@ -44,13 +46,13 @@ struct Stream {
   // rows read ahead, through a per-wave LDS ring of DL slots (16-byte chunks per lane of e
   // and rhs in each)
   static constexpr int C16 = CPL * int(sizeof(T)) / 16;
-  static constexpr int DL = sizeof(T) == 4 ? 4 : 3;
+  static constexpr int DL = sizeof(T) == 4 ? 5 : 3;
   static constexpr int SLOT = 2 * C16 * kWave * 16;  // bytes per ring slot
   // register ring rows: 2 NU + 3 live, even (fixed row parity per slot)
   static constexpr int P = 2 * NU + 4;
   static constexpr int L = N >= 8 ? 128 : 64;  // output rows per unit (half that by a wall)
   // coarse rows and columns one walk interpolates from, at most (staged in LDS per wave)
-  static constexpr int NR = (L + 2 * H - 1) / N + 3;
+  static constexpr int NR = (L + 2 * H) / N + 3;
   static constexpr int NC = LW / N + 3;
   static_assert(N >= CPL && VW >= N && VW % N == 0 && PX % CPL == 0, "strip geometry");
   static_assert(P % 2 == 0 && P >= 2 * NU + 3, "ring length");
@@ -178,17 +180,37 @@ __device__ __forceinline__ void unpack_cells(const Vec4u (&v)[K], int c0, T (&ou
   }
 }
 
-// One wave's walk up its strip: output rows y0 .. y0 + min(L, ny - y0) - 1 of the strip whose
-// first read column is xs.  EDGE: the strip reads columns behind a wall (x not periodic),
-// handled lane by lane; otherwise every column it reads exists (possibly wrapped).
-template <typename T, int NU, int LOG2N, bool EDGE>
+// Kinds of walk.  PLAIN: every row and column the walk reads exists in the grid (possibly
+// wrapped), so every cell has four neighbours and diagonal 4.  ROWS: the rows may reach
+// past a wall in y (or off the grid); every column exists.  EDGE: the strip also reads
+// columns behind a wall in x, handled lane by lane.
+enum WalkKind { kPlain = 0, kRows = 1, kEdge = 2 };
+
+// One wave's walk along its strip: output rows y0 .. y0 + min(L, ny - y0) - 1 of the strip
+// whose first read column is xs, walking up (rows ys = y0 - H .. y0 + L + H - 1) or, with
+// down, down (rows y0 + L + H .. ys: one extra row at the top so that every ring slot sees
+// rows of the same parity either way).  A red-black sweep does not depend on the order its
+// rows are visited in, so both walks give the same cells bit for bit; the coarse-tile sums
+// add the rows in walk order.  Neighbouring chunks walk in opposite directions so that both
+// reach the rows around their common boundary at about the same time, and the second read
+// of those halo rows can hit in cache.
+//
+// A PLAIN walk keeps rhs / 4 in its ring instead of rhs (exact: a power of two) and sets a
+// cell to fma(sum, 1/4, -rhs/4), which rounds (sum - rhs) / 4 once: bit for bit the value
+// (sum - rhs) * (1/4) of the other walks, one operation instead of two.  Its residual
+// fma(rhs/4, 4, -A'e) is likewise exactly rhs - A'e rounded once.  (Both hold while rhs / 4
+// stays a normal number, i.e. |rhs| >= 2^-124 or rhs = 0.)
+template <typename T, int NU, int LOG2N, int KIND>
 __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ rb,
                                            const T* __restrict__ eb, T* __restrict__ ob,
                                            const double* __restrict__ Eb, double* __restrict__ rc,
                                            double* __restrict__ psq, double* __restrict__ sE,
-                                           double2* __restrict__ sX, Vec4u* __restrict__ sR,
-                                           long long coff, int zero_e, int xs, int y0, int L) {
+                                           typename Vec16<T>::type* __restrict__ sX,
+                                           Vec4u* __restrict__ sR, long long coff, int zero_e,
+                                           int xs, int y0, int L, bool down) {
   using S = Stream<T, NU, LOG2N>;
+  using V16 = typename Vec16<T>::type;
+  constexpr bool EDGE = KIND == kEdge, PLAIN = KIND == kPlain;
   constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
   constexpr int G = N / CPL;  // lanes per coarse tile
   constexpr double inv2n = 1.0 / double(2 * N);
@@ -205,7 +227,10 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   const T iwS = inv_diag<T>(mxw + mys), iwM = inv_diag<T>(mxw + 2), iwN = inv_diag<T>(mxw + myn);
   const T ieS = inv_diag<T>(mxe + mys), ieM = inv_diag<T>(mxe + 2), ieN = inv_diag<T>(mxe + myn);
   const int ys = y0 - H;
-  const int yend = y0 + min(L, g.ny - y0) + H;  // rows ys .. yend - 1 are read
+  const int yend = y0 + min(L, g.ny - y0) + H;  // rows ys .. yend - 1 are output or halo
+  const int nrows = yend - ys + (down ? 1 : 0);  // rows the walk reads
+  const int dir = down ? -1 : 1;
+  const int t0 = down ? yend : ys;  // first row read; row of step s: t0 + dir s
 
   // this lane's first column (unwrapped), the column it is read from, whether it exists
   const int cu = xs + CPL * lane;
@@ -220,12 +245,12 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   const bool lane_out = lane >= PX / CPL && lane < (PX + VW) / CPL && cu < g.nx;
 
   // The coarse values the walk interpolates from (Eq. 5, boundary rule applied), staged in
-  // this wave's LDS block: rows crow(ys) .. crow(yend - 1) + 1, columns from the lower
+  // this wave's LDS block: rows crow(ys) .. crow(yend) + 1, columns from the lower
   // neighbour of the strip's first column on.  Only this wave reads them.
   auto crow = [](int t) { return (t - N / 2) >> LOG2N; };  // lower coarse row of fine row t
   const int J0 = crow(ys), I0 = (xs - N / 2) >> LOG2N;
   {
-    const int nr = crow(yend - 1) + 2 - J0;
+    const int nr = crow(yend) + 2 - J0;
     for (int i = lane; i < nr * S::NC; i += kWave) {
       const int rr = i / S::NC, c = i - rr * S::NC;
       int J = J0 + rr, I = I0 + c;
@@ -262,10 +287,11 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
     }
   };
 
-  // The ring: e and rhs of rows t - P + 1 .. t in slot (row - ys) mod P, and per slot the
-  // row's inverse diagonals (uniform): for cells with both x-neighbours, and (EDGE) for the
-  // west and east wall cells; 0 for rows off the grid and rows not read yet, which the
-  // half-steps then leave at 0.
+  // The ring: e and rhs (PLAIN: rhs / 4) of the last P rows read, the row of step s in slot
+  // s mod P,
+  // and per slot the row's inverse diagonals (uniform): for cells with both x-neighbours,
+  // and (EDGE) for the west and east wall cells; 0 for rows off the grid and rows not read
+  // yet, which the half-steps then leave at 0.
   T e[P][CPL], r[P][CPL];
   T invs[P], iws[P], ies[P];
 #pragma unroll
@@ -274,27 +300,39 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 #pragma unroll
     for (int p = 0; p < CPL; ++p) e[q][p] = r[q][p] = T(0);
   }
-  // Coarse rows J interpolated along x at the lane's cells, kept in LDS buffer J & 1 (each
-  // lane reads back only what it wrote): [buffer][cell pair][lane].
+  // Coarse rows J interpolated along x at the lane's cells (FP64, rounded to T), kept in LDS
+  // buffer J & 1 (each lane reads back only what it wrote): [buffer][16-byte chunk][lane].
+  constexpr int K16 = 16 / int(sizeof(T)), C16X = CPL / K16;
   auto put_x = [&](int J) {
     double v[CPL];
     interp_x(J, v);
-    double2* d = sX + (J & 1) * (CPL / 2) * kWave + lane;
+    V16* d = sX + (J & 1) * C16X * kWave + lane;
 #pragma unroll
-    for (int q = 0; q < CPL / 2; ++q) d[q * kWave] = make_double2(v[2 * q], v[2 * q + 1]);
+    for (int q = 0; q < C16X; ++q) {
+      V16 w;
+#pragma unroll
+      for (int k = 0; k < K16; ++k) (&w.x)[k] = T(v[q * K16 + k]);
+      d[q * kWave] = w;
+    }
   };
-  int jc = J0;
+  int jc = crow(t0);
   put_x(jc);
   put_x(jc + 1);
   // the next row to read, wrapped or clamped into the grid
-  int jn = g.per_y ? imod(ys, g.ny) : min(max(ys, 0), g.ny - 1);
-  // Rows are read DL ahead by LDS-DMA into this wave's LDS ring (slot (row - ys) mod DL:
+  int jn = g.per_y ? imod(t0, g.ny) : min(max(t0, 0), g.ny - 1);
+  // Rows are read DL ahead by LDS-DMA into this wave's LDS ring (slot (step) mod DL:
   // the C16 chunks of e, then those of rhs) and enter the register ring when used.  Every row
-  // issues the same 2 C16 loads (e is read even when it is ignored), so when row t enters,
-  // the loads of rows t + 1 .. t + DL - 1 at most may still be outstanding besides stores:
-  // waiting until no more than that many operations are outstanding guarantees row t landed.
+  // issues the same 2 C16 loads (e is read even when it is ignored), and every output row
+  // C16 stores, after the loads of the row DL steps ahead.  Vector memory operations
+  // complete in issue order, so when row t enters, the operations issued after its loads
+  // (the loads of the next DL - 1 rows, and the stores of the last DL - 1 iterations once
+  // output has begun) may still be outstanding: waiting until no more than that many are
+  // guarantees row t landed.  Fewer than counted (before output begins) would be unsafe, so
+  // the count with stores applies only from the step whose DL - 1 predecessors all stored;
+  // extra stores (the coarse-tile sums) only make a wait longer.
   constexpr int DL = S::DL, C16 = S::C16;
-  constexpr int NWAIT = 2 * C16 * (DL - 1);
+  constexpr int NWAIT = 2 * C16 * (DL - 1), NWAIT_OUT = 3 * C16 * (DL - 1);
+  const int st_out = 2 * H + (down ? 1 : 0) + DL - 1;  // steps from which NWAIT_OUT holds
   const unsigned ring0 = lds_offset(sR);
   int qs = 0;  // LDS slot of the next row to enter
   auto fetch = [&](int t, int slot) {
@@ -305,18 +343,21 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
       dma16(eb + a + c * (16 / int(sizeof(T))), base + c * 1024);
       dma16(rb + a + c * (16 / int(sizeof(T))), base + (C16 + c) * 1024);
     }
-    jn = g.per_y ? (jn + 1 == g.ny ? 0 : jn + 1) : min(max(t + 1, 0), g.ny - 1);
+    if (g.per_y) jn = down ? (jn == 0 ? g.ny - 1 : jn - 1) : (jn + 1 == g.ny ? 0 : jn + 1);
+    else jn = min(max(t + dir, 0), g.ny - 1);
   };
 #pragma unroll
-  for (int q = 0; q < DL; ++q) fetch(ys + q, q);
+  for (int q = 0; q < DL; ++q) fetch(t0 + dir * q, q);
   double acc = 0.0, acc2 = 0.0;
 
-  for (int tb = ys; tb < yend; tb += P) {
+  for (int sb = 0; sb < nrows; sb += P) {
 #pragma unroll
     for (int ph = 0; ph < P; ++ph) {
-      const int t = tb + ph;
-      if (t < yend) {
-        // ys is odd (y0 even, H odd) and P even, so the parity of t is fixed per slot
+      const int st = sb + ph;
+      if (st < nrows) {
+        const int t = t0 + dir * st;
+        // t0 is odd (ys = y0 - H and yend = y0 + L + H, y0 and L even, H odd) and P even, so
+        // the parity of t is fixed per slot
         const int tpar = (1 + ph) & 1;
         // EDGE: the lane's first column, opaque so that the per-cell wall arithmetic below is
         // redone each row rather than held in registers for the walk
@@ -327,36 +368,41 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
         {
           if (crow(t) != jc) {  // next pair of coarse rows
             jc = crow(t);
-            put_x(jc + 1);
+            put_x(down ? jc : jc + 1);
           }
-          double xlo[CPL], xhi[CPL];
+          T xlo[CPL], xhi[CPL];
           {
-            const double2* a = sX + (jc & 1) * (CPL / 2) * kWave + lane;
-            const double2* b = sX + ((jc + 1) & 1) * (CPL / 2) * kWave + lane;
+            const V16* a = sX + (jc & 1) * C16X * kWave + lane;
+            const V16* b = sX + ((jc + 1) & 1) * C16X * kWave + lane;
 #pragma unroll
-            for (int q = 0; q < CPL / 2; ++q) {
-              const double2 u = a[q * kWave], w = b[q * kWave];
-              xlo[2 * q] = u.x;
-              xlo[2 * q + 1] = u.y;
-              xhi[2 * q] = w.x;
-              xhi[2 * q + 1] = w.y;
+            for (int q = 0; q < C16X; ++q) {
+              const V16 u = a[q * kWave], w = b[q * kWave];
+#pragma unroll
+              for (int k = 0; k < K16; ++k) {
+                xlo[q * K16 + k] = (&u.x)[k];
+                xhi[q * K16 + k] = (&w.x)[k];
+              }
             }
           }
+          // the y step of Eq. 5 in T (the weights are dyadic, exact in T)
           const int k = (t - N / 2) & (N - 1);
-          const double Y = double(2 * k + 1) * inv2n, Y1 = 1.0 - Y;
+          const T Y = T(double(2 * k + 1) * inv2n), Y1 = T(1) - Y;
           {
             Vec4u v[2 * C16];
-            lds_take<NWAIT>(ring0 + unsigned(qs) * S::SLOT + 16u * unsigned(lane), v);
+            const unsigned la = ring0 + unsigned(qs) * S::SLOT + 16u * unsigned(lane);
+            if (st >= st_out) lds_take<NWAIT_OUT>(la, v);
+            else lds_take<NWAIT>(la, v);
             T le[CPL];
             unpack_cells<T, CPL>(v, 0, le);
             unpack_cells<T, CPL>(v, C16, r[ph]);
 #pragma unroll
             for (int p = 0; p < CPL; ++p) {
               const T e0 = zero_e ? T(0) : le[p];
-              e[ph][p] = T(double(e0) + (xlo[p] * Y1 + xhi[p] * Y));
+              e[ph][p] = e0 + (xlo[p] * Y1 + xhi[p] * Y);
+              if (PLAIN) r[ph][p] = r[ph][p] * T(0.25);
             }
           }
-          const bool row_in = g.per_y || (t >= 0 && t < g.ny);
+          const bool row_in = PLAIN || g.per_y || (t >= 0 && t < g.ny);
           if (!row_in) {
 #pragma unroll
             for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
@@ -365,15 +411,15 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 #pragma unroll
             for (int p = 0; p < CPL; ++p) e[ph][p] = r[ph][p] = T(0);
           }
-          const bool first = !g.per_y && t == 0, last = !g.per_y && t == g.ny - 1;
-          invs[ph] = uniform(!row_in ? T(0) : (first ? icS : (last ? icN : T(0.25))));
+          const bool first = !PLAIN && !g.per_y && t == 0, last = !PLAIN && !g.per_y && t == g.ny - 1;
+          if (!PLAIN) invs[ph] = uniform(!row_in ? T(0) : (first ? icS : (last ? icN : T(0.25))));
           if (EDGE) {  // the wall cells of the row
             iws[ph] = uniform(!row_in ? T(0) : (first ? iwS : (last ? iwN : iwM)));
             ies[ph] = uniform(!row_in ? T(0) : (first ? ieS : (last ? ieN : ieM)));
           }
         }
 
-        // half-step k (odd red, even black) on row t - k
+        // half-step k (odd red, even black) on the row that entered k steps ago
 #pragma unroll
         for (int k = 1; k <= 2 * NU; ++k) {
           const int sc = (ph - k + P) % P, sb = (ph - k - 1 + P) % P, sa = (ph - k + 1 + P) % P;
@@ -384,7 +430,11 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             if ((p & 1) != p0) continue;
             const T w = p > 0 ? e[sc][p - 1] : lane_shift<kDppFromLeft>(e[sc][CPL - 1]);
             const T ea = p < CPL - 1 ? e[sc][p + 1] : lane_shift<kDppFromRight>(e[sc][0]);
-            const T sum = ((w + ea) + e[sb][p]) + e[sa][p];
+            const T sum = (w + ea) + (e[sb][p] + e[sa][p]);
+            if (PLAIN) {
+              e[sc][p] = fma(sum, T(0.25), -r[sc][p]);
+              continue;
+            }
             T inv = invs[sc];
             if (EDGE) {
               // 1 / diagonal: the row's interior value, the row's wall-cell value at the wall
@@ -398,23 +448,31 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
           }
         }
 
-        // row o = t - H is final: residual, write-back, coarse-tile sums
-        const int o = t - H;
-        if (o >= y0) {
+        // row o, entered H steps ago, is final: residual, write-back, coarse-tile sums
+        const int o = t - dir * H;
+        if (st >= H && o >= y0 && o < yend - H) {
           const int so = (ph - H + P) % P, sb = (ph - H - 1 + P) % P, sa = (ph - H + 1 + P) % P;
-          const bool hs = g.per_y || o > 0, hn = g.per_y || o < g.ny - 1;
+          const bool hs = PLAIN || g.per_y || o > 0, hn = PLAIN || g.per_y || o < g.ny - 1;
           const bool ds = !hs && (g.dmask & kDirS), dn = !hn && (g.dmask & kDirN);
+          // the rows in slots sb (entered one step before row o) and sa (one step after) are
+          // its south and north neighbours walking up, north and south walking down
+          const bool hb = down ? hn : hs, ha = down ? hs : hn, db = down ? dn : ds, da = down ? ds : dn;
           double d[CPL];
 #pragma unroll
           for (int p = 0; p < CPL; ++p) {
             const T c = e[so][p];
             const T w = p > 0 ? e[so][p - 1] : lane_shift<kDppFromLeft>(e[so][CPL - 1]);
             const T ea = p < CPL - 1 ? e[so][p + 1] : lane_shift<kDppFromRight>(e[so][0]);
-            const bool hw = !EDGE || cx + p > 0, he = !EDGE || cx + p < g.nx - 1;
-            const bool dw = EDGE && cx + p == 0 && (g.dmask & kDirW);
-            const bool de = EDGE && cx + p == g.nx - 1 && (g.dmask & kDirE);
-            d[p] = double(r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hs, hn, dw,
-                                             de, ds, dn));
+            if (PLAIN) {
+              const T lap = ((w - c) + (ea - c)) + ((e[sb][p] - c) + (e[sa][p] - c));
+              d[p] = double(fma(r[so][p], T(4), -lap));
+            } else {
+              const bool hw = !EDGE || cx + p > 0, he = !EDGE || cx + p < g.nx - 1;
+              const bool dw = EDGE && cx + p == 0 && (g.dmask & kDirW);
+              const bool de = EDGE && cx + p == g.nx - 1 && (g.dmask & kDirE);
+              d[p] = double(r[so][p] - lap5<T>(c, w, ea, e[sb][p], e[sa][p], hw, he, hb, ha, dw,
+                                               de, db, da));
+            }
             acc += d[p];
           }
           if (psq) {  // squared sums only when a convergence check reads them
@@ -422,7 +480,7 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             for (int p = 0; p < CPL; ++p) acc2 += d[p] * d[p];
           }
           if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
-          if (((o - y0) & (N - 1)) == N - 1) {
+          if (((o - y0) & (N - 1)) == (down ? 0 : N - 1)) {
             double a = acc, q = acc2;
 #pragma unroll
             for (int k = 1; k < G; k <<= 1) a += __shfl_down(a, k, kWave);
@@ -439,8 +497,8 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
           }
         }
 
-        // row t + DL into the LDS slot row t just left
-        fetch(t + DL, qs);
+        // the row DL steps ahead into the LDS slot row t just left
+        fetch(t + dir * DL, qs);
         qs = qs + 1 == DL ? 0 : qs + 1;
       }
     }
@@ -467,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   using S = Stream<T, NU, LOG2N>;
   constexpr int WPB = kBlock / kWave;
   __shared__ double sE[WPB][S::NR * S::NC];
-  __shared__ double2 sX[WPB][2 * (S::CPL / 2) * kWave];
+  __shared__ typename Vec16<T>::type sX[WPB][2 * (S::CPL * int(sizeof(T)) / 16) * kWave];
   __shared__ Vec4u sR[WPB][S::DL * S::SLOT / 16];
   const long long off = (long long)blockIdx.z * g.plane;
   const long long coff = (long long)blockIdx.z * g.cplane;
@@ -481,9 +539,9 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
     const int chunk = u / nstrip_e, sl = u - chunk * nstrip_e;
     const int strip = sl == 0 ? 0 : efirst + sl;
     const int b0 = chunk * nb / Ce, b1 = (chunk + 1) * nb / Ce;
-    cycle_walk<T, NU, LOG2N, true>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq, sE[w],
-                                   sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
-                                   b0 * S::N, (b1 - b0) * S::N);
+    cycle_walk<T, NU, LOG2N, kEdge>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
+                                    sE[w], sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
+                                    b0 * S::N, (b1 - b0) * S::N, chunk & 1);
     return;
   }
   int bi = b - nblk_e;
@@ -493,9 +551,15 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   if (u >= nstrip * Ci) return;
   const int chunk = u / nstrip, sl = u - chunk * nstrip;
   const int b0 = chunk * nb / Ci, b1 = (chunk + 1) * nb / Ci;
-  cycle_walk<T, NU, LOG2N, false>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq, sE[w],
-                                  sX[w], sR[w], coff, zero_e, (first + sl) * S::VW - S::PX,
-                                  b0 * S::N, (b1 - b0) * S::N);
+  const int y0 = b0 * S::N, len = (b1 - b0) * S::N, xs = (first + sl) * S::VW - S::PX;
+  const bool down = chunk & 1;  // odd chunks walk down
+  // a chunk whose rows, halo included, all lie inside the grid walks the plain way
+  if (g.per_y || (y0 - S::H >= 0 && y0 + len + S::H + (down ? 1 : 0) <= g.ny))
+    cycle_walk<T, NU, LOG2N, kPlain>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
+                                     sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down);
+  else
+    cycle_walk<T, NU, LOG2N, kRows>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
+                                    sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down);
 }
 
 template <typename T, int NU, int LOG2N>
@@ -515,17 +579,34 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
     efirst = ni;
     ne = ns - ni;
   }
-  // Chunks of S::L rows (the shortest that keep the pipeline's warm-up rows a small share;
-  // measured faster at 8192^2 than both shorter chunks that fill every SIMD with three waves
-  // and longer ones); wall strips, whose rows cost more, walk half as far.  A launch with
-  // fewer than kUnits units (a small grid) takes more, shorter chunks of whole bands, down
-  // to 32 rows (one band when bands are longer): on 256 CUs parallelism then matters more
-  // than the re-read halo rows.
-  constexpr int kUnits = 2048;
+  // Chunks of whole bands, all of one length where the band count allows it, between 32
+  // rows (one band when bands are longer) and S::L rows; wall strips, whose rows cost more,
+  // walk chunks half as long.  Among those lengths the launch takes the one whose number of
+  // units (waves) is closest to kUnits, about 1.6 rounds of the chip's wave slots at three
+  // waves per SIMD: enough waves that the hardware keeps every SIMD busy to the end, at the
+  // price of more re-read halo rows.  Measured on 8192^2 (nu = 5, 32h): 2 bands per chunk
+  // (4992 units) 194 us per launch, 4 bands (2496) 216 us, 1 band (9984) 204 us; chunk sets
+  // mixing two lengths were slower than either (the longer chunks set the launch time).
+  constexpr double kUnits = 4864.0;
   const int nb = g.ny / S::N;
-  const int cmax = std::max(1, nb / std::max(1, 32 / S::N));
-  const int per = std::max(1, (ni + 2 * ne) * g.batch);
-  const int Ci = std::max((nb * S::N + S::L - 1) / S::L, std::min(cmax, (kUnits + per - 1) / per));
+  const int bmin = std::max(1, 32 / S::N), bmax = std::max(1, S::L / S::N);
+  auto units = [&](int ci) { return double(ni * ci + ne * std::min(2 * ci, nb)) * g.batch; };
+  int Ci = 0;
+  double best = 0.0;
+  for (int bands = bmin; bands <= bmax; ++bands) {
+    if (nb % bands) continue;
+    const double u = std::max(1.0, units(nb / bands));
+    const double cost = std::fabs(std::log(u / kUnits));
+    if (Ci == 0 || cost < best) {
+      best = cost;
+      Ci = nb / bands;
+    }
+  }
+  if (Ci == 0) {  // no chunk length of whole bands divides the strip: floor or ceil lengths
+    const int cmax = std::max(1, nb / bmin);
+    const int per = std::max(1, (ni + 2 * ne) * g.batch);
+    Ci = std::max((nb + bmax - 1) / bmax, std::min(cmax, int(kUnits / per)));
+  }
   const int Ce = std::min(2 * Ci, nb);
   // wall blocks padded to a multiple of 8 so that the XCD of a block (its index mod 8) is
   // known to the band mapping of the others

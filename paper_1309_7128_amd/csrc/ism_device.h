@@ -3,18 +3,20 @@
 //
 // Arithmetic conventions (shared by every kernel so that a cell value never depends on the
 // kernel that produced it):
-//  * A'e (the 5-point Laplacian times h^2) in difference form,
-//    ((e_W - e_C) + (e_E - e_C)) + (e_S - e_C)) + (e_N - e_C) (Sec. 2.3 stencil).  Behind
+//  * A'e (the 5-point Laplacian times h^2) in difference form, added per axis,
+//    ((e_W - e_C) + (e_E - e_C)) + ((e_S - e_C) + (e_N - e_C)) (Sec. 2.3 stencil): the
+//    order is symmetric in each axis, so it does not depend on the direction rows or
+//    columns are visited in.  Behind
 //    a Neumann wall the term is absent; behind a Dirichlet wall the neighbour is the mirror
 //    ghost -e_C and the term is (-e_C) - e_C (Sec. 4.1 lists both wall kinds).
 //  * Red-black Gauss-Seidel (Sec. 3.1): red is (i + j) even; a cell is set to
-//    (((e_W + e_E) + e_S) + e_N - rhs_C) * (1 / m_C), a missing neighbour contributing 0 and
+//    (((e_W + e_E) + (e_S + e_N)) - rhs_C) * (1 / m_C), a missing neighbour contributing 0 and
 //    m_C the diagonal: 4, less one per Neumann wall face, plus one per Dirichlet wall face.
 //  * Bilinear interpolation (Eq. 5) reaches a ghost coarse centre behind a wall: the
 //    mirror image of the first centre, with the same value (Neumann) or the negated value
 //    (Dirichlet).
-//  * Bilinear prolongation (Eq. 5) evaluated in FP64 and added to the fine value in FP64,
-//    then rounded to the fine type.
+//  * Bilinear prolongation (Eq. 5) in nested form: the x step on the coarse rows in FP64,
+//    rounded to the fine type T; the y step and the addition to the fine value in T.
 // The library is compiled with -ffp-contract=off so these expressions round exactly as
 // written; products that are meant to fuse (the coarse transforms) call fma explicitly.
 #pragma once
@@ -104,8 +106,8 @@ template <typename T>
 __device__ __forceinline__ T lap5(T c, T w, T e, T s, T n, bool hw, bool he, bool hs, bool hn,
                                   bool dw = false, bool de = false, bool ds = false,
                                   bool dn = false) {
-  return ((face_term(c, w, hw, dw) + face_term(c, e, he, de)) + face_term(c, s, hs, ds)) +
-         face_term(c, n, hn, dn);
+  return (face_term(c, w, hw, dw) + face_term(c, e, he, de)) +
+         (face_term(c, s, hs, ds) + face_term(c, n, hn, dn));
 }
 
 template <typename T>
@@ -148,13 +150,9 @@ __device__ __forceinline__ void interp_coord(int gi, int n, int& lo, double& t) 
 }
 
 // Eq. 5 evaluated in nested form: interpolate along x on the lower and the upper coarse row,
-// then along y, p = (Q11 (1-X) + Q21 X) (1-Y) + (Q12 (1-X) + Q22 X) Y, rounded in this order.
+// then along y, p = (Q11 (1-X) + Q21 X) (1-Y) + (Q12 (1-X) + Q22 X) Y, rounded in this order
+// (one linear step of it here).
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a * (1.0 - t) + b * t; }
-
-__device__ __forceinline__ double bilinear(double q11, double q21, double q12, double q22,
-                                           double X, double Y) {
-  return lerp(lerp(q11, q21, X), lerp(q12, q22, X), Y);
-}
 
 }  // namespace
 }  // namespace ism

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rh
     int i = x0 + lx - 2;
     if (!map_cell(g, i, j)) continue;
     int idx = ly * LE + lx;
-    T s = ((se[idx - 1] + se[idx + 1]) + se[idx - LE]) + se[idx + LE];
+    T s = (se[idx - 1] + se[idx + 1]) + (se[idx - LE] + se[idx + LE]);
     se[idx] = (s - sr[(ly - 1) * LR + (lx - 1)]) * inv_count<T>(g, i, j);
   }
   __syncthreads();
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rh
     int i = x0 + lx - 2;
     if (i >= g.nx || j >= g.ny) continue;
     int idx = ly * LE + lx;
-    T s = ((se[idx - 1] + se[idx + 1]) + se[idx - LE]) + se[idx + LE];
+    T s = (se[idx - 1] + se[idx + 1]) + (se[idx - LE] + se[idx + LE]);
     se[idx] = (s - sr[(ly - 1) * LR + (lx - 1)]) * inv_count<T>(g, i, j);
   }
   __syncthreads();
@@ -197,12 +197,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
     sjl = ghost_clamp(jlo, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
     sjh = ghost_clamp(jhi, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
   }
-  // the signs multiply exactly, so negating a corner value commutes with the rounding
-  const double p = bilinear(sjl * sil * Eb[jlo * g.ncx + ilo], sjl * sih * Eb[jlo * g.ncx + ihi],
-                            sjh * sil * Eb[jhi * g.ncx + ilo], sjh * sih * Eb[jhi * g.ncx + ihi],
-                            X, Y);
+  // the signs multiply exactly, so negating a corner value commutes with the rounding; the
+  // x step on the coarse rows in FP64, rounded to T, the y step and the addition in T
+  const T lo = T(lerp(sjl * sil * Eb[jlo * g.ncx + ilo], sjl * sih * Eb[jlo * g.ncx + ihi], X));
+  const T hi = T(lerp(sjh * sil * Eb[jhi * g.ncx + ilo], sjh * sih * Eb[jhi * g.ncx + ihi], X));
+  const T Yt = T(Y);
+  const T p = lo * (T(1) - Yt) + hi * Yt;
   T* ec = e + (long long)blockIdx.z * g.plane + (long long)j * g.nx + i;
-  *ec = assign ? T(p) : T(double(*ec) + p);
+  *ec = assign ? p : T(*ec + p);
 }
 
 // ----------------------------------------------------------------------------------------
