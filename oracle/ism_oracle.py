@@ -323,14 +323,32 @@ def projection_step(u, v, p, h, dt, eta, bc_x=NEUMANN, walls=(0.0, 0.0, 0.0, 0.0
 # Grid transfer (Sec. 3.3, Eq. 5)
 # --------------------------------------------------------------------------------------
 
+def tile_layout(nf, n):
+    """The coarse cells along one axis of nf fine cells (Sec. 3.3, Sec. 4.1): tiles of n
+    cells from cell 0 on, the last one short when n does not divide nf (the padded domain:
+    that coarse cell covers only the cells that exist).  Returns (nc, sizes, starts,
+    centres); a coarse centre is the middle of its tile, in fine coordinates where fine cell
+    i spans [i, i + 1]."""
+    nc = -(-nf // n)
+    sizes = np.full(nc, n, dtype=np.int64)
+    sizes[-1] = nf - (nc - 1) * n
+    starts = np.arange(nc, dtype=np.int64) * n
+    return nc, sizes, starts, starts + sizes / 2.0
+
+
 def restrict_sum(r, n):
-    """R r: the sum of the fine values over each n x n tile, in FP64.
+    """R r: the sum of the fine values over each coarse tile (n x n, shorter in the last
+    row or column of tiles when n does not divide the grid), in FP64.
 
     Sec. 3.3: the coarse right-hand side is the sum of quantities already computed on the
     fine grid (the agglomeration of ACM).  Pinned by conservation (sum R r = sum r) and by
     brute force."""
     ny, nx = r.shape
-    return np.asarray(r, dtype=np.float64).reshape(ny // n, n, nx // n, n).sum(axis=(1, 3))
+    r = np.asarray(r, dtype=np.float64)
+    if nx % n == 0 and ny % n == 0:
+        return r.reshape(ny // n, n, nx // n, n).sum(axis=(1, 3))
+    sx, sy = tile_layout(nx, n)[2], tile_layout(ny, n)[2]
+    return np.add.reduceat(np.add.reduceat(r, sy, axis=0), sx, axis=1)
 
 
 def _interp_axis(nf, n, bc):
@@ -338,15 +356,27 @@ def _interp_axis(nf, n, bc):
     the upper one (Eq. 5 coordinates divided by the rectangle size) and the sign each
     centre value is taken with.
 
-    The coarse centre I sits at fine coordinate n (I + 1/2); fine centre i sits at i + 1/2.
-    Between a wall and the first centre the rectangle reaches a ghost centre, the mirror
-    image of the first one: an equal value behind a Neumann wall (the interpolant is held
-    constant, zero normal slope) and the negated value behind a Dirichlet wall (the
-    interpolant falls linearly to zero on the wall)."""
-    nc = nf // n
-    pos = (np.arange(nf) + 0.5) / n - 0.5
-    lo = np.floor(pos).astype(np.int64)
-    t = pos - lo
+    The coarse centre I sits in the middle of its tile (n (I + 1/2) for a full tile); fine
+    centre i sits at i + 1/2.  Between a wall and the first (last) coarse centre the
+    rectangle reaches a ghost centre, the mirror image of that centre in the wall: an equal
+    value behind a Neumann wall (the interpolant is held constant, zero normal slope) and the
+    negated value behind a Dirichlet wall (the interpolant falls linearly to zero on the
+    wall).  On a periodic axis the neighbour across the seam is the wrapped centre.  With a
+    short last tile the rectangles next to it are shorter than n (Eq. 5: the rectangle size
+    can differ because of padding), and t is the offset divided by the rectangle's size."""
+    nc, _, _, c = tile_layout(nf, n)
+    pos = np.arange(nf) + 0.5
+    if nf % n == 0:  # uniform tiles: rectangles of n cells
+        p = pos / n - 0.5
+        lo = np.floor(p).astype(np.int64)
+        t = p - lo
+    else:
+        lo = np.searchsorted(c, pos, side="right").astype(np.int64) - 1
+        below = c[-1] - nf if bc == PERIODIC else -c[0]      # the centre before centre 0
+        above = c[0] + nf if bc == PERIODIC else 2 * nf - c[-1]  # the centre after the last
+        cl = np.where(lo < 0, below, c[np.clip(lo, 0, nc - 1)])
+        ch = np.where(lo + 1 > nc - 1, above, c[np.clip(lo + 1, 0, nc - 1)])
+        t = (pos - cl) / (ch - cl)
     hi = lo + 1
     s_lo = np.ones(nf)
     s_hi = np.ones(nf)
@@ -364,7 +394,7 @@ def _interp_axis(nf, n, bc):
     return lo, hi, t, s_lo, s_hi
 
 
-def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN, dtype=np.float64):
+def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN, dtype=np.float64, fine_shape=None):
     """P E: bilinear interpolation of the coarse values to every fine cell centre.
 
     Eq. 5 with origin at the south-west centre Q11 of the surrounding rectangle, in
@@ -375,12 +405,14 @@ def prolong_bilinear(E, n, bc_x=NEUMANN, bc_y=NEUMANN, dtype=np.float64):
 
     dtype is the fine arithmetic.  The x step works on coarse rows (coarse-grid data, FP64)
     and is rounded to dtype; the y step, one per fine cell, is evaluated in dtype.  In FP64
-    this is the plain FP64 evaluation.  Pinned by exactness on constants and bilinear fields,
-    dyadic weights and the coarse-stencil identities (FP64), and by the FP32 result lying
-    within its rounding bound of the FP64 one."""
+    this is the plain FP64 evaluation.  fine_shape (ny, nx) gives a grid that n does not
+    divide (short last tiles); by default the tiles are full.  Pinned by exactness on
+    constants and bilinear fields, dyadic weights and the coarse-stencil identities (FP64),
+    and by the FP32 result lying within its rounding bound of the FP64 one."""
     ncy, ncx = E.shape
-    ilo, ihi, tx, sxl, sxh = _interp_axis(ncx * n, n, bc_x)
-    jlo, jhi, ty, syl, syh = _interp_axis(ncy * n, n, bc_y)
+    ny, nx = (ncy * n, ncx * n) if fine_shape is None else fine_shape
+    ilo, ihi, tx, sxl, sxh = _interp_axis(nx, n, bc_x)
+    jlo, jhi, ty, syl, syh = _interp_axis(ny, n, bc_y)
     E = np.asarray(E, dtype=np.float64)
     # along x, every coarse row (a ghost centre's value negated exactly by its sign)
     ex = (E[:, ilo] * sxl[None, :]) * (1 - tx)[None, :] + (E[:, ihi] * sxh[None, :]) * tx[None, :]
@@ -435,7 +467,61 @@ def _open_faces(ncx, ncy, bc_x, bc_y):
     return east, west, north, south
 
 
-def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
+def _centre(c, I, nf, bc):
+    """Position of coarse centre I on an axis with centres c, for I in -1 .. nc: the ghost
+    centres beyond the ends are the mirror images in the walls, or the wrapped centres on a
+    periodic axis."""
+    nc = len(c)
+    if 0 <= I < nc:
+        return c[I]
+    if bc == PERIODIC:
+        return c[-1] - nf if I < 0 else c[0] + nf
+    return -c[0] if I < 0 else 2 * nf - c[-1]
+
+
+def _coarse_stencil_ism_padded(nx, ny, n, bc_x, bc_y):
+    """The Eq. 6/7 face sums of ``coarse_stencil_ism`` on a grid that n does not divide:
+    the same sums, with each rectangle's own size (Eq. 5: the sizes differ next to a short
+    last tile), written face by face and fine face by fine face."""
+    ncx, sx, stx, cx = tile_layout(nx, n)
+    ncy, sy, sty, cy = tile_layout(ny, n)
+    C = np.zeros((ncy, ncx, 3, 3))
+    east_open, west_open, north_open, south_open = _open_faces(ncx, ncy, bc_x, bc_y)
+
+    def interp(c, k, nf, bc, I):
+        """fine cell k of tile I along the other axis: lower centre offset (-1 or 0
+        relative to I) and the weight of the upper centre"""
+        pos = k + 0.5
+        off = -1 if pos < c[I] else 0
+        lo, hi = _centre(c, I + off, nf, bc), _centre(c, I + off + 1, nf, bc)
+        return off, (pos - lo) / (hi - lo)
+
+    for J in range(ncy):
+        for I in range(ncx):
+            # east (+1) and west (-1) faces: the fine rows of tile J
+            for sign, is_open, d_lo in ((+1.0, east_open[J, I], 0), (-1.0, west_open[J, I], -1)):
+                if not is_open:
+                    continue
+                dx = _centre(cx, I + d_lo + 1, nx, bc_x) - _centre(cx, I + d_lo, nx, bc_x)
+                for k in range(sty[J], sty[J] + sy[J]):
+                    off, y = interp(cy, k, ny, bc_y, J)
+                    for dj, w in ((off, 1.0 - y), (off + 1, y)):
+                        C[J, I, dj + 1, d_lo + 2] += sign * w / dx
+                        C[J, I, dj + 1, d_lo + 1] -= sign * w / dx
+            # north (+1) and south (-1) faces: the fine columns of tile I
+            for sign, is_open, d_lo in ((+1.0, north_open[J, I], 0), (-1.0, south_open[J, I], -1)):
+                if not is_open:
+                    continue
+                dy = _centre(cy, J + d_lo + 1, ny, bc_y) - _centre(cy, J + d_lo, ny, bc_y)
+                for k in range(stx[I], stx[I] + sx[I]):
+                    off, x = interp(cx, k, nx, bc_x, I)
+                    for di, w in ((off, 1.0 - x), (off + 1, x)):
+                        C[J, I, d_lo + 2, di + 1] += sign * w / dy
+                        C[J, I, d_lo + 1, di + 1] -= sign * w / dy
+    return _fold(C, ncx, ncy, bc_x, bc_y)
+
+
+def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN, fine_shape=None):
     """The ISM coarse 9-point stencil, built by summing interpolated face fluxes.
 
     Sec. 3.3, Eq. 6 and Eq. 7.  For every coarse cell the equation is the sum, over the
@@ -450,9 +536,14 @@ def coarse_stencil_ism(ncx, ncy, n, bc_x=NEUMANN, bc_y=NEUMANN):
     (-p) - p of the wall cell.
 
     Returns C with shape (ncy, ncx, 3, 3): C[J, I, dj+1, di+1] multiplies the unknown at
-    (J+dj, I+di) (wrapped on a periodic axis).  Pinned by the brute-force product R A' P,
-    the closed-form interior stencil 1/4 [[1,2,1],[2,-12,2],[1,2,1]] and the closed-form
-    eigenvalues."""
+    (J+dj, I+di) (wrapped on a periodic axis).  fine_shape (ny, nx) gives a grid that n does
+    not divide: its last tiles are short and so are the rectangles next to them.  Pinned by
+    the brute-force product R A' P (with full and short tiles), the closed-form interior
+    stencil 1/4 [[1,2,1],[2,-12,2],[1,2,1]] and the closed-form eigenvalues."""
+    if fine_shape is not None and (fine_shape[0] != ncy * n or fine_shape[1] != ncx * n):
+        ny, nx = fine_shape
+        assert (ncy, ncx) == (tile_layout(ny, n)[0], tile_layout(nx, n)[0])
+        return _coarse_stencil_ism_padded(nx, ny, n, bc_x, bc_y)
     C = np.zeros((ncy, ncx, 3, 3))
     J, I = np.indices((ncy, ncx))
     half = n // 2
@@ -689,10 +780,11 @@ def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-
     ny, nx = b.shape
     bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
-    C = coarse_stencil_ism(nx // n, ny // n, n, bc_x, bc_y)
+    ncx, ncy = _coarse_shape(nx, ny, n)
+    C = coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y, (ny, nx))
     Rc = restrict_sum(bp - laplacian(x, bc_x, bc_y), n)
     E, ic = block_gauss_seidel(C, Rc, tol_c * h * h, block, bc_x, bc_y)
-    x = x + prolong_bilinear(E, n, bc_x, bc_y)
+    x = x + prolong_bilinear(E, n, bc_x, bc_y, fine_shape=(ny, nx))
     fi = 0
     while np.max(np.abs(bp - laplacian(x, bc_x, bc_y))) >= tol_f * h * h and fi < max_fine:
         x = red_black_gs(x, bp, bc_x, bc_y, sweeps=1)
@@ -830,13 +922,23 @@ def relative_residual(b, x, h, bc_x=NEUMANN, bc_y=NEUMANN):
 # The ISM two-level cycle (Sec. 3.3 stencil, Sec. 3.4 sparse V cycle, Sec. 4.3.1 cycling)
 # --------------------------------------------------------------------------------------
 
-def _stencil(kind, ncx, ncy, n, bc_x, bc_y):
-    return {"ism": coarse_stencil_ism, "acm": coarse_stencil_acm,
-            "gmg5": coarse_stencil_gmg5}[kind](ncx, ncy, n, bc_x, bc_y)
+def _coarse_shape(nx, ny, n, kind="ism"):
+    """(ncx, ncy) of a fine grid; only the ISM scheme takes grids that n does not divide."""
+    if kind != "ism" and (nx % n or ny % n):
+        raise ValueError("the comparison schemes need grids that are multiples of n")
+    return tile_layout(nx, n)[0], tile_layout(ny, n)[0]
 
 
-def _prolong(kind, E, n, bc_x, bc_y):
-    return inject_constant(E, n) if kind == "acm" else prolong_bilinear(E, n, bc_x, bc_y)
+def _stencil(kind, ncx, ncy, n, bc_x, bc_y, fine_shape=None):
+    if kind == "ism":
+        return coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y, fine_shape)
+    return {"acm": coarse_stencil_acm, "gmg5": coarse_stencil_gmg5}[kind](ncx, ncy, n, bc_x, bc_y)
+
+
+def _prolong(kind, E, n, bc_x, bc_y, fine_shape=None):
+    if kind == "acm":
+        return inject_constant(E, n)
+    return prolong_bilinear(E, n, bc_x, bc_y, fine_shape=fine_shape)
 
 
 def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
@@ -859,8 +961,8 @@ def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
     ny, nx = b.shape
     bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
-    ncx, ncy = nx // n, ny // n
-    cs = CoarseSolver(coarse_matrix(_stencil(stencil, ncx, ncy, n, bc_x, bc_y), bc_x, bc_y))
+    ncx, ncy = _coarse_shape(nx, ny, n, stencil)
+    cs = CoarseSolver(coarse_matrix(_stencil(stencil, ncx, ncy, n, bc_x, bc_y, (ny, nx)), bc_x, bc_y))
     bnorm = np.linalg.norm(bp)
     r = bp - laplacian(x, bc_x, bc_y)
     hist = [float(np.linalg.norm(r) / bnorm)]
@@ -871,7 +973,7 @@ def ism_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=None,
             E = cs.solve(Rc)
         else:
             E, _ = cs.gauss_seidel(Rc, tol_c=coarse_tol)
-        x = x + _prolong(stencil, E, n, bc_x, bc_y)
+        x = x + _prolong(stencil, E, n, bc_x, bc_y, (ny, nx))
         x = red_black_gs(x, bp, bc_x, bc_y, sweeps=nu)
         r = bp - laplacian(x, bc_x, bc_y)
         cycles += 1
@@ -897,8 +999,8 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
     ny, nx = b.shape
     bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
-    ncx, ncy = nx // n, ny // n
-    cs = CoarseSolver(coarse_matrix(coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y), bc_x, bc_y))
+    ncx, ncy = _coarse_shape(nx, ny, n)
+    cs = CoarseSolver(coarse_matrix(coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y, (ny, nx)), bc_x, bc_y))
     bnorm = np.linalg.norm(bp)
     outer_hist, cycles, outer = [], 0, 0
     while True:
@@ -915,7 +1017,7 @@ def ism_solve_mixed(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, nu=2, rtol=1e-10, x0=No
         inner_hist = []
         for _ in range(max_inner):
             E = cs.solve(Rc)
-            e = e + prolong_bilinear(E, n, bc_x, bc_y, np.float32)
+            e = e + prolong_bilinear(E, n, bc_x, bc_y, np.float32, (ny, nx))
             e = red_black_gs(e, r32, bc_x, bc_y, sweeps=nu)
             res = r32 - laplacian(e, bc_x, bc_y)
             res64 = res.astype(np.float64)
@@ -953,6 +1055,7 @@ def acm_solve(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, rtol=1e-10, x0=None, max_cycl
     L = int(round(math.log2(n)))
     bp = h * h * _project(b, bc_x, bc_y)
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    _coarse_shape(nx, ny, n, "acm")
     cs = CoarseSolver(coarse_matrix(coarse_stencil_acm(nx // n, ny // n, n, bc_x, bc_y),
                                     bc_x, bc_y))
 
@@ -993,9 +1096,9 @@ def _columns(fn, ncols, shape):
 def transfer_matrices(nx, ny, n, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
     """Dense R (Nc x N), P (N x Nc) and A' (N x N) built by applying the oracle's own
     functions to unit vectors."""
-    ncx, ncy = nx // n, ny // n
+    ncx, ncy = _coarse_shape(nx, ny, n, kind)
     R = _columns(lambda f: restrict_sum(f, n), nx * ny, (ny, nx))
-    P = _columns(lambda E: _prolong(kind, E, n, bc_x, bc_y), ncx * ncy, (ncy, ncx))
+    P = _columns(lambda E: _prolong(kind, E, n, bc_x, bc_y, (ny, nx)), ncx * ncy, (ncy, ncx))
     A = _columns(lambda f: laplacian(f, bc_x, bc_y), nx * ny, (ny, nx))
     return R, P, A
 
@@ -1005,7 +1108,8 @@ def two_grid_matrix(nx, ny, n, nu, bc_x=NEUMANN, bc_y=NEUMANN, kind="ism"):
     subspace when A is singular (tiny grids).  S is the red-black sweep applied to errors (zero right-hand
     side)."""
     R, P, A = transfer_matrices(nx, ny, n, bc_x, bc_y, kind)
-    C = _stencil(kind, nx // n, ny // n, n, bc_x, bc_y)
+    ncx, ncy = _coarse_shape(nx, ny, n, kind)
+    C = _stencil(kind, ncx, ncy, n, bc_x, bc_y, (ny, nx))
     Ac = coarse_matrix(C, bc_x, bc_y).toarray()
     N = nx * ny
     S = _columns(lambda f: red_black_gs(f, np.zeros_like(f), bc_x, bc_y, 1), N, (ny, nx))

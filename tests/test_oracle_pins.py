@@ -808,3 +808,99 @@ def test_cost_metrics_reproduce_paper_tables():
         # the printed values carry one decimal, so inputs and outputs are each off by <= 0.05
         assert abs(m["ncc_t"] - float(t)) <= 0.1 + 1e-9, (tab, scheme, n, crit)
         assert abs(m["n_lap"] - float(lap)) <= 0.05 + 0.025 + 0.05 / int(n) ** 2 + 1e-9, (tab, scheme, n, crit)
+
+
+# ---------------------------------------------------------------- grids that n does not divide
+# (Sec. 3.3: the interpolation rectangles differ next to the padding; Sec. 4.1: automated
+# padding).  The last tile of an axis covers the cells that exist; its coarse centre is its
+# middle.
+
+PADDED = [(50, 37, 16, N, N), (100, 70, 16, D, ND), (44, 36, 8, P, N), (72, 52, 32, DN, P),
+          (40, 30, 16, P, D), (20, 12, 16, N, D)]
+
+
+def _pid(c):
+    return f"{c[0]}x{c[1]}_n{c[2]}_{c[3]}-{c[4]}"
+
+
+def test_tile_layout():
+    for nf, n in ((50, 16), (48, 16), (17, 16), (5, 8), (1000, 16), (2000, 32)):
+        nc, sizes, starts, c = O.tile_layout(nf, n)
+        assert nc == -(-nf // n) and sizes.sum() == nf and 1 <= sizes[-1] <= n
+        assert np.all(sizes[:-1] == n) and np.all(starts == n * np.arange(nc))
+        np.testing.assert_array_equal(c, starts + sizes / 2.0)
+
+
+@pytest.mark.parametrize("case", PADDED, ids=_pid)
+def test_restrict_padded_is_tile_sum(case):
+    nx, ny, n = case[:3]
+    r = np.random.default_rng(70).standard_normal((ny, nx))
+    Rc = O.restrict_sum(r, n)
+    ncx, ncy = -(-nx // n), -(-ny // n)
+    assert Rc.shape == (ncy, ncx)
+    for J in range(ncy):
+        for I in range(ncx):
+            ref = sum(r[j, i] for j in range(n * J, min(n * J + n, ny))
+                      for i in range(n * I, min(n * I + n, nx)))
+            assert abs(Rc[J, I] - ref) < 1e-12
+    assert abs(Rc.sum() - r.sum()) < 1e-11
+
+
+@pytest.mark.parametrize("nf,n,bc", [(50, 16, N), (37, 8, N), (44, 8, P), (70, 16, D), (29, 4, DN)])
+def test_prolong_padded_reproduces_lines_between_centres(nf, n, bc):
+    # a linear function of position, sampled at the tile middles (the last tile's middle lies
+    # within its short extent), is reproduced at every fine centre between two coarse centres
+    nc = -(-nf // n)
+    sizes = [n] * (nc - 1) + [nf - (nc - 1) * n]
+    mid = np.array([n * I + sizes[I] / 2.0 for I in range(nc)])
+    f = lambda x: 0.7 - 0.3 * x  # noqa: E731
+    E = np.tile(f(mid), (3, 1))  # three identical coarse rows (a field constant in y)
+    p = O.prolong_bilinear(E, n, bc, N, fine_shape=(3 * n, nf))
+    x = np.arange(nf) + 0.5
+    inner = (x >= mid[0]) & (x <= mid[-1])
+    np.testing.assert_allclose(p[0, inner], f(x[inner]), atol=1e-13)
+    # constants are reproduced everywhere behind a Neumann wall and across a periodic seam
+    pc = O.prolong_bilinear(np.full((3, nc), 2.5), n, bc, N, fine_shape=(3 * n, nf))
+    if bc in (N, P):
+        np.testing.assert_allclose(pc, 2.5, atol=1e-14)
+    if O.faces(bc) is not None and O.faces(bc)[1] == "D":
+        # behind a Dirichlet wall the interpolant falls linearly to zero on the wall, over
+        # the half of the short last tile next to it
+        xl = x[x > mid[-1]]
+        np.testing.assert_allclose(pc[0, x > mid[-1]], 2.5 * (nf - xl) / (nf - mid[-1]), atol=1e-13)
+
+
+@pytest.mark.parametrize("case", PADDED, ids=_pid)
+def test_padded_stencil_is_galerkin_product(case):
+    # the Eq. 6/7 face sums with each rectangle's own size equal R A' P built from the
+    # restriction, the fine operator and the prolongation applied to unit vectors
+    nx, ny, n, bx, by = case
+    ncx, ncy = -(-nx // n), -(-ny // n)
+    R, P, A = O.transfer_matrices(nx, ny, n, bx, by)
+    C = O.coarse_stencil_ism(ncx, ncy, n, bx, by, fine_shape=(ny, nx))
+    Ac = O.coarse_matrix(C, bx, by).toarray()
+    np.testing.assert_allclose(Ac, R @ A @ P, atol=1e-12)
+    if O.singular(bx, by):  # conservative: the rows and columns sum to zero
+        np.testing.assert_allclose(Ac.sum(axis=0), 0.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", PADDED[:4], ids=_pid)
+def test_padded_ism_solve_reaches_exact_solution(case):
+    nx, ny, n, bx, by = case
+    h = 1.0 / nx
+    b = O.div(*[np.random.default_rng(71).uniform(-1, 1, sh) for sh in
+                (((ny, nx) if bx == P else (ny, nx + 1)), (ny + 1, nx))], h, bx)
+    xs = O.exact_solve(b, h, bx, by)
+    x, info = O.ism_solve(b, h, n, bx, by, nu=2, rtol=1e-11)
+    assert info["history"][-1] <= 1e-11
+    np.testing.assert_allclose(x, xs, atol=1e-8 * np.abs(xs).max())
+    xm, infom = O.ism_solve_mixed(b, h, n, bx, by, nu=2, rtol=1e-10)
+    assert O.relative_residual(b, xm, h, bx, by) <= 1e-10
+
+
+def test_comparison_schemes_refuse_padded_grids():
+    b = np.zeros((20, 24))
+    with pytest.raises(ValueError):
+        O.acm_solve(b, 0.1, 16)
+    with pytest.raises(ValueError):
+        O.ism_solve(b, 0.1, 16, stencil="gmg5")
