@@ -46,7 +46,8 @@ extern "C" {
 #define ISM_OK 0
 #define ISM_NOT_CONVERGED 1
 #define ISM_ERR_INVALID (-1)     /* null pointer, non-positive size, bad enum value       */
-#define ISM_ERR_UNSUPPORTED (-2) /* nx or ny not a multiple of coarsen, lx/nx != ly/ny,  
+#define ISM_ERR_UNSUPPORTED (-2) /* a size or option outside what is supported (see
+                                    ism_config: coarsen, padding), lx/nx != ly/ny,
                                     nx * ny >= 2^31                                      */
 #define ISM_ERR_HIP (-3)         /* a HIP runtime call failed; see ism_last_error        */
 #define ISM_ERR_NONFINITE (-4)   /* NaN or Inf met in b or during the iteration          */
@@ -96,11 +97,17 @@ extern "C" {
 typedef struct ism_ctx* ism_handle;
 
 typedef struct {
-  int32_t nx, ny;     /* fine cells along x and y (>= 2 * coarsen each)                     */
+  int32_t nx, ny;     /* fine cells along x and y (>= 2 each)                               */
   int32_t batch;      /* independent grids solved together (>= 1)                           */
   int32_t bc_x, bc_y; /* ISM_BC_* on the x faces (west/east) and the y faces (south/north)   */
-  int32_t coarsen;    /* tile edge n of the n x n restriction: 4, 8, 16 or 32 (Sec. 3.4);
-                         nx and ny must be multiples of it                                  */
+  int32_t coarsen;    /* tile edge n of the n x n restriction: 4, 8, 16 or 32 (Sec. 3.4).
+                         Tiles start at cell 0; where n does not divide nx (ny) the last
+                         tile of the axis is short and covers the cells that exist, its
+                         centre in its middle, and the interpolation rectangles next to it
+                         are shorter (the padded domain, Sec. 3.3 Eq. 5, Sec. 4.1): the
+                         coarse grid is ceil(ny/n) x ceil(nx/n).  Such a grid needs the
+                         ISM stencil, nx a multiple of 4 and ny even (ISM_ERR_UNSUPPORTED
+                         otherwise); the GMG5 and ACM stencils need multiples of n.     */
   double lx, ly;      /* domain size; lx/nx must equal ly/ny (square cells)                 */
   int32_t precision;  /* ISM_PREC_*                                                         */
   int32_t nu;         /* red-black sweeps per cycle after the coarse correction (>= 1);
@@ -221,7 +228,8 @@ int ism_correct(ism_handle h, const double* x, double* u, double* v, double* p);
 
 /* ---- Stage entry points: one step of the cycle each, for step-by-step verification.
  * Fine arrays have the element type selected by dtype (ISM_F64 / ISM_F32) and layout
- * [batch][ny][nx]; coarse arrays are FP64 [batch][ny/n][nx/n].  rhs is in h^2 units
+ * [batch][ny][nx]; coarse arrays are FP64 [batch][ncy][ncx] with ncy = ceil(ny/n) and
+ * ncx = ceil(nx/n) (ny/n and nx/n with full tiles).  rhs is in h^2 units
  * (the equation solved is A' e = rhs with A' = h^2 A). */
 
 /* nsweeps red-black Gauss-Seidel sweeps on A' e = rhs, red ((i + j) even) first; each cell
@@ -242,7 +250,11 @@ int ism_prolong(ism_handle h, int32_t dtype, const double* E, void* e);
 /* E = solution of A_c E = rc on each grid's coarse grid (without a Dirichlet face: the
  * zero-mean solution of A_c E = rc - mean(rc)), where A_c is the interpolated 9-point
  * stencil (Sec. 3.3, Eq. 6-7), or the 5-point one when the handle was created with
- * ISM_COARSE_GMG5.  Exact up to FP64 rounding. */
+ * ISM_COARSE_GMG5.  Exact up to FP64 rounding.  With a short last tile and no Dirichlet
+ * face, the solution returned is the one whose prolongation P E has zero mean (E itself
+ * then differs from the zero-mean solution by a constant), and rc is projected along the
+ * tile-size weights rather than the constants: the two agree when rc sums to zero, as the
+ * restriction of a compatible residual does. */
 int ism_coarse_solve(ism_handle h, const double* rc, double* E);
 
 /* One two-level cycle on A' e = rhs: E = coarse solve of rc; e += P E; nu red-black
@@ -257,14 +269,14 @@ int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
  * iteration at a time, until max |rc - A_c E| < tol (in the units of rc) on every grid or
  * max_iter iterations.  Without a Dirichlet face rc is first projected to zero mean (the
  * compatibility condition of the singular system; rc itself is not modified).  rc, E: FP64
- * [batch][ny/n][nx/n].  *iters receives the number of iterations.  Returns
+ * [batch][ncy][ncx].  *iters receives the number of iterations.  Returns
  * ISM_NOT_CONVERGED if max_iter was reached first. */
 int ism_coarse_gs(ism_handle h, const double* rc, double* E, double tol, int32_t max_iter,
                   int32_t* iters);
 
 /* The coarse stencil assembled on the device (ISM: from the face sums of Eq. 6-7; GMG5:
  * the 5-point stencil with one-sided wall rows):
- * coef is FP64 [ny/n][nx/n][9]; entry 3*(dj+1) + (di+1) multiplies the unknown at
+ * coef is FP64 [ncy][ncx][9]; entry 3*(dj+1) + (di+1) multiplies the unknown at
  * (J+dj, I+di) (wrapped on a periodic axis; the coefficient of a ghost behind a wall is
  * folded onto the unknown it mirrors, with a minus sign behind a Dirichlet wall). */
 int ism_coarse_stencil(ism_handle h, double* coef);

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libism.so")
-SOURCES = ["ism_kernels.hip", "ism_cycle_f32.hip", "ism_cycle_f64.hip", "ism_api.cpp"]
+SOURCES = ["ism_kernels.hip", "ism_cycle_f32.hip", "ism_cycle_f64.hip", "ism_api.cpp",
+           "ism_coarse_tables.cpp"]
 ARCH = os.environ.get("ISM_OFFLOAD_ARCH", "gfx950")
 
 # -ffp-contract=off: expressions round exactly as written (fused multiply-adds only where a

@@ -60,6 +60,10 @@ struct ism_ctx {
   double* scal = nullptr;  // [kSlots][batch]
   double* fin = nullptr;   // chunk results of the two-stage reductions
   double *Vx = nullptr, *Vy = nullptr, *invLam = nullptr;
+  // forward tables of the coarse solve: Vx, Vy themselves with full tiles, the pencil's left
+  // vectors when a tile size does not divide the axis (padded)
+  double *Fx = nullptr, *Fy = nullptr;
+  bool padded = false;
   double* coef = nullptr;  // coarse 9-point stencil [ncy][ncx][9] (block Gauss-Seidel)
   void* stage_tmp = nullptr;  // lazily allocated FP64-sized fine scratch for stage calls
   double* h_scal = nullptr;   // host mirror of scal, then kChecks slots of B check norms
@@ -191,8 +195,13 @@ int validate(const ism_config* cfg, std::string& why) {
     return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
   if (!is_pow2_coarsen(cfg->coarsen))
     return why = "coarsen must be 4, 8, 16 or 32", ISM_ERR_UNSUPPORTED;
-  if (cfg->nx % cfg->coarsen || cfg->ny % cfg->coarsen)
-    return why = "nx and ny must be multiples of coarsen", ISM_ERR_UNSUPPORTED;
+  if (cfg->nx % cfg->coarsen || cfg->ny % cfg->coarsen) {
+    // a short last tile (the padded domain of Sec. 4.1) is defined for the ISM stencil
+    if (cfg->coarse_stencil != ISM_COARSE_ISM)
+      return why = "nx or ny not a multiple of coarsen (padding) needs the ISM coarse stencil", ISM_ERR_UNSUPPORTED;
+    if (cfg->nx % 4 || cfg->ny % 2)
+      return why = "nx or ny not a multiple of coarsen (padding) needs nx a multiple of 4 and ny even", ISM_ERR_UNSUPPORTED;
+  }
   if (cfg->nx < 2 || cfg->ny < 2) return why = "the grid needs at least 2 cells per axis", ISM_ERR_UNSUPPORTED;
   const double hx = cfg->lx / cfg->nx, hy = cfg->ly / cfg->ny;
   if (std::fabs(hx - hy) > 1e-12 * hx) return why = "cells must be square (lx/nx == ly/ny)", ISM_ERR_UNSUPPORTED;
@@ -214,15 +223,19 @@ constexpr int dtype_of() {
 }
 
 // ------------------------------------------------------------------ coarse solve (FP64)
-// E = V_y ((V_y^T R_c V_x) .* Lambda^-1) V_x^T with the (0,0) entry of Lambda^-1 zero: the
-// zero-mean solution of K_x (x) M_y + M_x (x) K_y applied to E equal to R_c minus its mean.
+// E = V_y ((F_y^T R_c F_x) .* Lambda^-1) V_x^T with the (0,0) entry of Lambda^-1 zero when
+// A_c is singular.  With full tiles F = V (orthonormal): the zero-mean solution of
+// K_x (x) M_y + M_x (x) K_y applied to E equal to R_c minus its mean.  With a short last
+// tile F holds the left vectors of each padded axis's pencil; dropping the constant mode
+// then gives the solution whose prolongation P E has zero mean, for R_c minus a multiple
+// of the tile-size weights (equal to R_c when R_c sums to zero).
 int coarse_solve(ism_ctx* c, const double* rc, double* E) {
   const Geo& g = c->g;
   const int nx = g.ncx, ny = g.ncy, B = g.batch;
   const long long cp = g.cplane;
   hipStream_t s = c->stream;
-  LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, rc, cp, nx, 0, c->Vx, 0, nx, c->t1, cp, nx, nullptr, B, s));
-  LAUNCH(c, ism::launch_gemm(ny, nx, ny, 1, c->Vy, 0, ny, 0, c->t1, cp, nx, c->t2, cp, nx, c->invLam, B, s));
+  LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, rc, cp, nx, 0, c->Fx, 0, nx, c->t1, cp, nx, nullptr, B, s));
+  LAUNCH(c, ism::launch_gemm(ny, nx, ny, 1, c->Fy, 0, ny, 0, c->t1, cp, nx, c->t2, cp, nx, c->invLam, B, s));
   LAUNCH(c, ism::launch_gemm(ny, nx, ny, 0, c->Vy, 0, ny, 0, c->t2, cp, nx, c->t1, cp, nx, nullptr, B, s));
   LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, c->t1, cp, nx, 1, c->Vx, 0, nx, E, cp, nx, nullptr, B, s));
   return ISM_OK;
@@ -701,8 +714,9 @@ void init_geometry(ism_ctx* c, const ism_config* cfg, hipStream_t stream) {
   g.n = cfg->coarsen;
   g.log2n = 0;
   while ((1 << g.log2n) < g.n) ++g.log2n;
-  g.ncx = g.nx / g.n;
-  g.ncy = g.ny / g.n;
+  g.ncx = (g.nx + g.n - 1) / g.n;  // the last tile short when n does not divide the axis
+  g.ncy = (g.ny + g.n - 1) / g.n;
+  c->padded = g.nx % g.n || g.ny % g.n;
   g.per_x = cfg->bc_x == ISM_BC_PERIODIC;
   g.per_y = cfg->bc_y == ISM_BC_PERIODIC;
   auto dir_lo = [](int bc) { return bc == ISM_BC_DIRICHLET || bc == ISM_BC_DIRICHLET_NEUMANN; };
@@ -732,7 +746,9 @@ size_t layout_workspace(ism_ctx* c, char* base) {
   const size_t fin = align(sizeof(double) * g.batch * size_t(fin_count / 4096 + 2));
   const size_t vx = align(sizeof(double) * g.ncx * g.ncx), vy = align(sizeof(double) * g.ncy * g.ncy);
   const size_t lam = align(sizeof(double) * g.cplane), coef = align(sizeof(double) * 9 * g.cplane);
-  const size_t total = 3 * fine + 9 * coarse + scal + chk + fin + vx + vy + lam + coef;
+  const size_t fx = c->padded ? vx : 0, fy = c->padded ? vy : 0;
+  const size_t itab = align(sizeof(double2) * size_t(g.nx + g.ny));
+  const size_t total = 3 * fine + 9 * coarse + scal + chk + fin + vx + vy + lam + coef + fx + fy + itab;
   if (!base) return total;
   char* p = base;
   c->rT = p; p += fine;
@@ -749,16 +765,55 @@ size_t layout_workspace(ism_ctx* c, char* base) {
   c->Vx = (double*)p; p += vx;
   c->Vy = (double*)p; p += vy;
   c->invLam = (double*)p; p += lam;
-  c->coef = (double*)p;
+  c->coef = (double*)p; p += coef;
+  c->Fx = c->padded ? (double*)p : c->Vx; p += fx;
+  c->Fy = c->padded ? (double*)p : c->Vy; p += fy;
+  c->g.itab = p;
   return total;
 }
 
-// Enqueues what a workspace must hold before a solve: the coarse eigenbasis tables, the
-// assembled coarse stencil (block Gauss-Seidel) and zeroed per-grid scalars.  No host wait.
+// The coarse solve's tables of a padded grid, built on the host (the pencil of each axis
+// that a tile size does not divide, the closed form of the other) and copied to the
+// workspace; waits for the copies.
+int upload_padded_tables(ism_ctx* c) {
+  const Geo& g = c->g;
+  const bool xlo = g.dmask & 1, xhi = g.dmask & 2, ylo = g.dmask & 4, yhi = g.dmask & 8;
+  ism::AxisTable tx, ty;
+  std::string why;
+  if (!ism::coarse_axis_table(g.nx, g.n, g.ncx, g.per_x, xlo, xhi, tx, why) ||
+      !ism::coarse_axis_table(g.ny, g.n, g.ncy, g.per_y, ylo, yhi, ty, why))
+    return set_err(c, ISM_ERR_UNSUPPORTED, why);
+  std::vector<double> inv(size_t(g.cplane));
+  for (int l = 0; l < g.ncy; ++l)
+    for (int k = 0; k < g.ncx; ++k) {
+      const double lam = tx.k[k] * ty.m[l] + tx.m[k] * ty.k[l];
+      inv[size_t(l) * g.ncx + k] = (c->singular && l == 0 && k == 0) ? 0.0 : 1.0 / lam;
+    }
+  const std::pair<double*, const std::vector<double>*> copies[] = {
+      {c->Vx, &tx.V}, {c->Vy, &ty.V}, {c->Fx, &tx.F}, {c->Fy, &ty.F}, {c->invLam, &inv}};
+  for (const auto& cp : copies) {
+    const hipError_t e = hipMemcpyAsync(cp.first, cp.second->data(), sizeof(double) * cp.second->size(),
+                                        hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return set_err(c, ISM_ERR_HIP, std::string("coarse tables: ") + hipGetErrorString(e));
+  }
+  const hipError_t e = hipStreamSynchronize(c->stream);  // the host tables go out of scope
+  if (e != hipSuccess) return set_err(c, ISM_ERR_HIP, std::string("coarse tables: ") + hipGetErrorString(e));
+  return ISM_OK;
+}
+
+// Enqueues what a workspace must hold before a solve: the interpolation tables, the coarse
+// eigenbasis tables, the assembled coarse stencil (block Gauss-Seidel) and zeroed per-grid
+// scalars.  No host wait, but for the host-built tables of a padded grid.
 int init_device_state(ism_ctx* c) {
   const Geo& g = c->g;
   const int kind = c->cfg.coarse_stencil == ISM_COARSE_GMG5 ? 1 : c->cfg.coarse_stencil == ISM_COARSE_ACM ? 2 : 0;
-  LAUNCH(c, ism::launch_coarse_tables(g, kind, c->singular ? 1 : 0, c->Vx, c->Vy, c->invLam, c->stream));
+  LAUNCH(c, ism::launch_interp_tables(g, (double2*)g.itab, c->stream));
+  if (c->padded) {
+    const int rcode = upload_padded_tables(c);
+    if (rcode) return rcode;
+  } else {
+    LAUNCH(c, ism::launch_coarse_tables(g, kind, c->singular ? 1 : 0, c->Vx, c->Vy, c->invLam, c->stream));
+  }
   LAUNCH(c, ism::launch_fill(c->scal, (long long)kSlots * g.batch, 0.0, c->stream));
   if (c->cfg.coarse_stencil != ISM_COARSE_ACM)
     LAUNCH(c, ism::launch_coarse_assemble(g, c->cfg.coarse_stencil == ISM_COARSE_GMG5, c->coef, c->stream));

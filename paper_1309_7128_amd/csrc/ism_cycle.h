@@ -51,11 +51,23 @@ struct Stream {
   // register ring rows: 2 NU + 3 live, even (fixed row parity per slot)
   static constexpr int P = 2 * NU + 4;
   static constexpr int L = N >= 8 ? 128 : 64;  // output rows per unit (half that by a wall)
-  // coarse rows and columns one walk interpolates from, at most (staged in LDS per wave)
-  static constexpr int NR = (L + 2 * H) / N + 3;
-  static constexpr int NC = LW / N + 3;
+  // coarse rows and columns one walk interpolates from, at most (staged in LDS per wave):
+  // with full tiles (L + 2 H) / N + 3 rows and LW / N + 3 columns; next to a short last tile
+  // of a periodic axis the lower centres of a walk's first and last cells can each move out
+  // by one
+  static constexpr int NR = (L + 2 * H) / N + 5;
+  static constexpr int NC = LW / N + 4;
   static_assert(N >= CPL && VW >= N && VW % N == 0 && PX % CPL == 0, "strip geometry");
   static_assert(P % 2 == 0 && P >= 2 * NU + 3, "ring length");
+  // LDS of a workgroup of kBlock / kWave waves (coarse block, x-interpolated rows, read-ahead
+  // ring) and the waves per SIMD the launch is compiled for: as many as the 160 KiB of LDS
+  // per CU allow (one wave per SIMD per workgroup), at most three in FP32 and two in FP64,
+  // the most the ring's registers leave room for
+  static constexpr int LDS_BYTES =
+      (kBlock / kWave) * (NR * NC * 8 + 2 * C16 * kWave * 16 + DL * SLOT);
+  static constexpr int WAVES_LDS = (160 * 1024) / LDS_BYTES;
+  static constexpr int WAVES_REG = sizeof(T) == 4 ? 3 : 2;
+  static constexpr int WAVES = WAVES_LDS < 1 ? 1 : (WAVES_LDS < WAVES_REG ? WAVES_LDS : WAVES_REG);
 };
 
 
@@ -207,13 +219,14 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
                                            double* __restrict__ psq, double* __restrict__ sE,
                                            typename Vec16<T>::type* __restrict__ sX,
                                            Vec4u* __restrict__ sR, long long coff, int zero_e,
-                                           int xs, int y0, int L, bool down) {
+                                           int xs, int y0, int L, bool down,
+                                           const double2* __restrict__ tabx,
+                                           const double2* __restrict__ taby) {
   using S = Stream<T, NU, LOG2N>;
   using V16 = typename Vec16<T>::type;
   constexpr bool EDGE = KIND == kEdge, PLAIN = KIND == kPlain;
   constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
   constexpr int G = N / CPL;  // lanes per coarse tile
-  constexpr double inv2n = 1.0 / double(2 * N);
   const int lane = threadIdx.x & (kWave - 1);
   // Inverse diagonals, uniform over the walk.  The diagonal is 4, less one per Neumann wall
   // face, plus one per Dirichlet wall face (its ghost -e counts twice).  y part of the first
@@ -243,14 +256,62 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
     cw = col_in ? cu : 0;
   }
   const bool lane_out = lane >= PX / CPL && lane < (PX + VW) / CPL && cu < g.nx;
+  // whether the lane's cells exist (unwrapped): the others add nothing to a coarse tile sum
+  // (they matter where a short last tile shares its lane group with columns past the grid)
+  const bool lane_sum = cu >= 0 && cu < g.nx;
 
   // The coarse values the walk interpolates from (Eq. 5, boundary rule applied), staged in
   // this wave's LDS block: rows crow(ys) .. crow(yend) + 1, columns from the lower
   // neighbour of the strip's first column on.  Only this wave reads them.
-  auto crow = [](int t) { return (t - N / 2) >> LOG2N; };  // lower coarse row of fine row t
-  const int J0 = crow(ys), I0 = (xs - N / 2) >> LOG2N;
+  // Fine row t's lower coarse row and y weight (Eq. 5).  Where every rectangle is full (n
+  // rows: an axis that n divides, and every row a plain walk reads) a shift and a dyadic
+  // weight, also for rows past a wall or a periodic seam.  On an axis with a short last tile
+  // the walk reads the axis's table (entry .x the weight, .y the lower centre of the
+  // wrapped or clamped row), the lower centre unwrapped again on a periodic axis.
+  const bool tab_y = !PLAIN && (g.ny & (N - 1)), tab_x = !PLAIN && (g.nx & (N - 1));
+  auto row_interp = [&](int t, int& lo, double& w) {
+    if (!tab_y) {
+      lo = (t - N / 2) >> LOG2N;
+      w = double(2 * ((t - N / 2) & (N - 1)) + 1) * (1.0 / double(2 * N));
+    } else {
+      int shift = 0, tw;
+      if (g.per_y) {
+        const int k = floordiv(t, g.ny);
+        tw = t - k * g.ny;
+        shift = k * g.ncy;
+      } else {
+        tw = min(max(t, 0), g.ny - 1);
+      }
+      const double2 e = taby[tw];
+      lo = int(e.y) + shift;
+      w = e.x;
+    }
+  };
+  auto crow = [&](int t) {
+    int lo;
+    double w;
+    row_interp(t, lo, w);
+    return lo;
+  };
+  const int J0 = crow(ys);
+  // the lower centre of column xs, the strip's first
+  int I0;
+  if (!tab_x) {
+    I0 = (xs - N / 2) >> LOG2N;
+  } else {
+    int shift = 0, cb;
+    if (g.per_x) {
+      const int k = floordiv(xs, g.nx);
+      cb = xs - k * g.nx;
+      shift = k * g.ncx;
+    } else {
+      cb = min(max(xs, 0), g.nx - 1);
+    }
+    I0 = int(tabx[cb].y) + shift;
+  }
   {
-    const int nr = crow(yend) + 2 - J0;
+    // (the bound on the staged rows holds by the geometry; the clamp keeps it in memory)
+    const int nr = min(crow(yend) + 2 - J0, S::NR);
     for (int i = lane; i < nr * S::NC; i += kWave) {
       const int rr = i / S::NC, c = i - rr * S::NC;
       int J = J0 + rr, I = I0 + c;
@@ -267,26 +328,6 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // For n >= 8 all of a lane's cells lie between the same two coarse centres; for n = 4 its
-  // first and last two cells lie between consecutive pairs.
-  constexpr int NEC = N >= 8 ? 2 : 3;
-  const int crel = ((cu - N / 2) >> LOG2N) - I0;
-  // coarse row J interpolated along x at the lane's cells
-  auto interp_x = [&](int J, double (&out)[CPL]) {
-    const double* q = sE + (J - J0) * S::NC + crel;
-    double v[NEC];
-#pragma unroll
-    for (int k = 0; k < NEC; ++k) v[k] = q[k];
-    int c0 = cu;
-    asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
-#pragma unroll
-    for (int p = 0; p < CPL; ++p) {
-      const double X = double(2 * ((c0 + p - N / 2) & (N - 1)) + 1) * inv2n;
-      const int k = N >= 8 ? 0 : (p >> 1);
-      out[p] = lerp(v[k], v[k + 1], X);
-    }
-  };
-
   // The ring: e and rhs (PLAIN: rhs / 4) of the last P rows read, the row of step s in slot
   // s mod P,
   // and per slot the row's inverse diagonals (uniform): for cells with both x-neighbours,
@@ -304,15 +345,50 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   // buffer J & 1 (each lane reads back only what it wrote): [buffer][16-byte chunk][lane].
   constexpr int K16 = 16 / int(sizeof(T)), C16X = CPL / K16;
   auto put_x = [&](int J) {
-    double v[CPL];
-    interp_x(J, v);
+    const double* q = sE + (J - J0) * S::NC - I0;
     V16* d = sX + (J & 1) * C16X * kWave + lane;
+    int c0 = cu;
+    asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
+    if (!tab_x) {
+      // full rectangles: for n >= 8 all of a lane's cells lie between the same two coarse
+      // centres, for n = 4 its first and last two cells between consecutive pairs
+      constexpr int NEC = N >= 8 ? 2 : 3;
+      constexpr double inv2n = 1.0 / double(2 * N);
+      const double* qq = q + ((c0 - N / 2) >> LOG2N);
+      double v[NEC];
 #pragma unroll
-    for (int q = 0; q < C16X; ++q) {
-      V16 w;
+      for (int k = 0; k < NEC; ++k) v[k] = qq[k];
 #pragma unroll
-      for (int k = 0; k < K16; ++k) (&w.x)[k] = T(v[q * K16 + k]);
-      d[q * kWave] = w;
+      for (int cq = 0; cq < C16X; ++cq) {
+        V16 w;
+#pragma unroll
+        for (int k = 0; k < K16; ++k) {
+          const int p = cq * K16 + k;
+          const double X = double(2 * ((c0 + p - N / 2) & (N - 1)) + 1) * inv2n;
+          const int m = N >= 8 ? 0 : (p >> 1);
+          (&w.x)[k] = T(lerp(v[m], v[m + 1], X));
+        }
+        d[cq * kWave] = w;
+      }
+    } else {
+      // the axis's table at the lane's columns (wrapped or clamped; a lane's CPL cells lie in
+      // one period of a periodic axis, nx being a multiple of CPL), one cell at a time and
+      // each value stored at once: the ring holds most registers, and this path must not
+      // raise the kernel's register count
+      int cb = c0, shift = 0;
+      if (g.per_x) {
+        const int k = floordiv(c0, g.nx);
+        cb = c0 - k * g.nx;
+        shift = k * g.ncx;
+      }
+      T* dt = reinterpret_cast<T*>(d);
+#pragma unroll
+      for (int p = 0; p < CPL; ++p) {
+        const double2 e = tabx[g.per_x ? cb + p : min(max(cb + p, 0), g.nx - 1)];
+        const int lo = int(e.y) + shift;
+        dt[(p / K16) * kWave * K16 + p % K16] = T(lerp(q[lo], q[lo + 1], e.x));
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   };
   int jc = crow(t0);
@@ -366,8 +442,12 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 
         // row t enters: e = (zero_e ? 0 : e) + P E; cells behind a wall hold 0
         {
-          if (crow(t) != jc) {  // next pair of coarse rows
-            jc = crow(t);
+          // the row's lower coarse row and y weight (Eq. 5)
+          int jrow;
+          double Yd;
+          row_interp(t, jrow, Yd);
+          if (jrow != jc) {  // next pair of coarse rows
+            jc = jrow;
             put_x(down ? jc : jc + 1);
           }
           T xlo[CPL], xhi[CPL];
@@ -384,9 +464,16 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
               }
             }
           }
-          // the y step of Eq. 5 in T (the weights are dyadic, exact in T)
-          const int k = (t - N / 2) & (N - 1);
-          const T Y = T(double(2 * k + 1) * inv2n), Y1 = T(1) - Y;
+          // the y step of Eq. 5 in T (weights from FP64, dyadic and exact unless the row lies
+          // next to a short last tile; exact in T in a plain walk, so 1 - Y is too)
+          T Y, Y1;
+          if constexpr (PLAIN) {
+            Y = T(Yd);
+            Y1 = T(1) - Y;
+          } else {
+            Y = T(Yd);
+            Y1 = T(1.0 - Yd);
+          }
           {
             Vec4u v[2 * C16];
             const unsigned la = ring0 + unsigned(qs) * S::SLOT + 16u * unsigned(lane);
@@ -480,8 +567,11 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             for (int p = 0; p < CPL; ++p) acc2 += d[p] * d[p];
           }
           if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
-          if (((o - y0) & (N - 1)) == (down ? 0 : N - 1)) {
-            double a = acc, q = acc2;
+          // a tile's last row in walk order (walking up, the last row of the grid also ends a
+          // short last tile, which a plain walk never reaches)
+          if (((o - y0) & (N - 1)) == (down ? 0 : N - 1) || (!PLAIN && !down && o == g.ny - 1)) {
+            // a plain walk's lane groups lie wholly inside or wholly outside the grid
+            double a = PLAIN || lane_sum ? acc : 0.0, q = PLAIN || lane_sum ? acc2 : 0.0;
 #pragma unroll
             for (int k = 1; k < G; k <<= 1) a += __shfl_down(a, k, kWave);
             if (psq) {
@@ -514,21 +604,21 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 // strips first, first + 1, ... in Ci chunks, dealt out so that each XCD (the hardware deals
 // workgroups out round-robin over the 8 XCDs) runs one contiguous band of units.
 template <typename T, int NU, int LOG2N>
-__global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ rhs,
-                                                  const T* __restrict__ ein,
-                                                  T* __restrict__ eout,
-                                                  const double* __restrict__ E,
-                                                  double* __restrict__ rc,
-                                                  double* __restrict__ psq, int zero_e,
-                                                  int nb, int Ci, int nstrip, int first, int Ce,
-                                                  int nstrip_e, int efirst, int nblk_e) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Stream<T, NU, LOG2N>::WAVES)))
+void k_cycle(Geo g, const T* __restrict__ rhs, const T* __restrict__ ein, T* __restrict__ eout,
+             const double* __restrict__ E, double* __restrict__ rc, double* __restrict__ psq,
+             int zero_e, int nb, int Ci, int nstrip, int first, int Ce, int nstrip_e, int efirst,
+             int nblk_e) {
   using S = Stream<T, NU, LOG2N>;
   constexpr int WPB = kBlock / kWave;
   __shared__ double sE[WPB][S::NR * S::NC];
-  __shared__ typename Vec16<T>::type sX[WPB][2 * (S::CPL * int(sizeof(T)) / 16) * kWave];
+  __shared__ typename Vec16<T>::type sX[WPB][2 * S::C16 * kWave];
   __shared__ Vec4u sR[WPB][S::DL * S::SLOT / 16];
+  static_assert(sizeof(sE) + sizeof(sX) + sizeof(sR) == S::LDS_BYTES, "LDS budget");
   const long long off = (long long)blockIdx.z * g.plane;
   const long long coff = (long long)blockIdx.z * g.cplane;
+  const double2* tabx = reinterpret_cast<const double2*>(g.itab);
+  const double2* taby = tabx + g.nx;
   // the wave index, made visibly wave-uniform so that everything derived from it (strip,
   // rows, the walk's row bookkeeping) lives in scalar registers and scalar branches
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
@@ -541,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
     const int b0 = chunk * nb / Ce, b1 = (chunk + 1) * nb / Ce;
     cycle_walk<T, NU, LOG2N, kEdge>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
                                     sE[w], sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
-                                    b0 * S::N, (b1 - b0) * S::N, chunk & 1);
+                                    b0 * S::N, (b1 - b0) * S::N, chunk & 1, tabx, taby);
     return;
   }
   int bi = b - nblk_e;
@@ -553,13 +643,22 @@ __global__ __launch_bounds__(kBlock) void k_cycle(Geo g, const T* __restrict__ r
   const int b0 = chunk * nb / Ci, b1 = (chunk + 1) * nb / Ci;
   const int y0 = b0 * S::N, len = (b1 - b0) * S::N, xs = (first + sl) * S::VW - S::PX;
   const bool down = chunk & 1;  // odd chunks walk down
-  // a chunk whose rows, halo included, all lie inside the grid walks the plain way
-  if (g.per_y || (y0 - S::H >= 0 && y0 + len + S::H + (down ? 1 : 0) <= g.ny))
+  // A chunk walks the plain way when every row and column it reads lies inside the grid (or
+  // wraps) in full-size interpolation rectangles: below the centre of the last full tile
+  // when n does not divide the axis, where the rectangles next to the short tile begin.
+  const int ylo = y0 - S::H, yhi = y0 + len + S::H + (down ? 1 : 0);  // rows [ylo, yhi)
+  const bool pad_y = g.ny & (S::N - 1), pad_x = g.nx & (S::N - 1);
+  const int yfull = (g.ncy - 2) * S::N + S::N / 2, xfull = (g.ncx - 2) * S::N + S::N / 2;
+  const bool rows_ok = pad_y ? (ylo >= 0 && yhi <= yfull) : (g.per_y || (ylo >= 0 && yhi <= g.ny));
+  const bool cols_ok = !pad_x || (xs >= 0 && xs + S::LW <= xfull);
+  if (rows_ok && cols_ok)
     cycle_walk<T, NU, LOG2N, kPlain>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
-                                     sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down);
+                                     sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
+                                     taby);
   else
     cycle_walk<T, NU, LOG2N, kRows>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
-                                    sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down);
+                                    sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
+                                    taby);
 }
 
 template <typename T, int NU, int LOG2N>
@@ -588,7 +687,7 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
   // (4992 units) 194 us per launch, 4 bands (2496) 216 us, 1 band (9984) 204 us; chunk sets
   // mixing two lengths were slower than either (the longer chunks set the launch time).
   constexpr double kUnits = 4864.0;
-  const int nb = g.ny / S::N;
+  const int nb = (g.ny + S::N - 1) / S::N;  // bands of n rows, the last one short if n does not divide ny
   const int bmin = std::max(1, 32 / S::N), bmax = std::max(1, S::L / S::N);
   auto units = [&](int ci) { return double(ni * ci + ne * std::min(2 * ci, nb)) * g.batch; };
   int Ci = 0;

@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "ism_internal.h"
 
 namespace ism {
@@ -31,12 +33,12 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ int imod(int i, int n) {
+__host__ __device__ __forceinline__ int imod(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ int floordiv(int a, int n) {
+__host__ __device__ __forceinline__ int floordiv(int a, int n) {
   return a >= 0 ? a / n : -((-a + n - 1) / n);
 }
 
@@ -139,14 +141,89 @@ __device__ __forceinline__ double wave_max_group(double v, int group) {
   return v;
 }
 
-// Interpolation coordinate along one axis (Eq. 5): fine index -> lower coarse index
-// (unwrapped, may be -1 or the last+1) and the offset t = (2k+1)/(2n) of the fine centre
-// from the lower coarse centre, in units of the rectangle size n.
-__device__ __forceinline__ void interp_coord(int gi, int n, int& lo, double& t) {
-  int s = gi - (n >> 1);
-  lo = floordiv(s, n);
-  int k = s - lo * n;
-  t = double(2 * k + 1) / double(2 * n);
+// Coarse centres along one axis of nf fine cells split into tiles of n from cell 0 on, the
+// last tile short (m = nf - (nc - 1) n cells) when n does not divide nf: the padded domain,
+// whose last coarse cell covers the cells that exist (Sec. 3.3, Sec. 4.1).  Positions are in
+// doubled fine coordinates (fine cell i spans [2i, 2i + 2], its centre is 2i + 1), so every
+// centre is an integer: 2 I n + n for a full tile, 2 (nc - 1) n + m for the last.  The
+// centres -1 and nc beyond the ends are the mirror images of the first and last centre in
+// the walls, or on a periodic axis the wrapped centres.
+__host__ __device__ __forceinline__ int centre2(int I, int nf, int n, int nc, bool periodic) {
+  const int last = 2 * (nc - 1) * n + (nf - (nc - 1) * n);
+  const int first = nc > 1 ? n : last;
+  if (I < 0) return periodic ? last - 2 * nf : -first;
+  if (I >= nc) return periodic ? first + 2 * nf : 4 * nf - last;
+  return I < nc - 1 ? 2 * I * n + n : last;
+}
+
+// Interpolation coordinate along one axis (Eq. 5): for fine index i (any integer on a
+// periodic axis, where it is first wrapped into the grid), the lower coarse centre lo
+// (unwrapped: on a periodic axis lo + k nc for i + k nf; -1 or nc - 1 beyond a wall) and the
+// offset t of the fine centre from it, divided by the size of its rectangle.  With full tiles
+// the rectangle is n cells and t = (2k + 1) / (2n); next to a short tile it is shorter.
+__host__ __device__ __forceinline__ void interp_axis(int i, int nf, int n, int log2n, int nc, bool periodic,
+                                            int& lo, double& t) {
+  int shift = 0;
+  if (periodic) {
+    const int k = floordiv(i, nf);
+    i -= k * nf;
+    shift = k * nc;
+  }
+  const int p2 = 2 * i + 1;
+  if (p2 < centre2(0, nf, n, nc, periodic)) {
+    lo = -1;
+  } else if (p2 >= centre2(nc - 1, nf, n, nc, periodic)) {
+    lo = nc - 1;
+  } else {
+    lo = (i - (n >> 1)) >> log2n;  // between two centres of full tiles
+  }
+  const int c0 = centre2(lo, nf, n, nc, periodic), c1 = centre2(lo + 1, nf, n, nc, periodic);
+  // a full rectangle (2n in doubled units, a power of two): the quotient is the exact product
+  // with 1/(2n); a shorter one needs the division
+  t = c1 - c0 == 2 * n ? double(p2 - c0) * (0.5 / double(n)) : double(p2 - c0) / double(c1 - c0);
+  lo += shift;
+}
+
+// Mode k of a full axis of nc coarse cells (the common eigenvectors of the 1D coarse factors
+// [1 -2 1] and [1 6 1]/8 with the axis's end rules): its angle theta and its entry at cell I,
+// orthonormal.  A periodic axis takes the constant, then cos and sin pairs, then the
+// alternating mode; a wall axis the cosine (Neumann) or sine (Dirichlet) modes fixed by the
+// mirror ghost of each end.
+struct AxisMode {
+  double theta, value;  // the mode's angle and its entry at cell I
+};
+
+__host__ __device__ inline AxisMode axis_mode(int nc, bool per, bool dlo, bool dhi, int k, int I) {
+  const double pi = 3.14159265358979323846;
+  AxisMode m;
+  if (per) {
+    if (k == 0) {
+      m.theta = 0.0;
+      m.value = std::sqrt(1.0 / nc);
+    } else if (nc % 2 == 0 && k == nc - 1) {
+      m.theta = pi;
+      m.value = (I % 2 ? -1.0 : 1.0) / std::sqrt(double(nc));
+    } else {
+      const int q = (k + 1) / 2;
+      m.theta = 2.0 * pi * q / nc;
+      const double a = 2.0 * pi * q * I / nc;
+      m.value = std::sqrt(2.0 / nc) * ((k & 1) ? std::cos(a) : std::sin(a));
+    }
+    return m;
+  }
+  double sc = std::sqrt(2.0 / nc), kk = k;
+  if (!dlo && !dhi) {
+    if (k == 0) sc = std::sqrt(1.0 / nc);
+  } else if (dlo && dhi) {
+    kk = k + 1;
+    if (k == nc - 1) sc = std::sqrt(1.0 / nc);
+  } else {
+    kk = k + 0.5;
+  }
+  m.theta = pi * kk / nc;
+  const double a = pi * kk * (I + 0.5) / nc;
+  m.value = sc * (dlo ? std::sin(a) : std::cos(a));
+  return m;
 }
 
 // Eq. 5 evaluated in nested form: interpolate along x on the lower and the upper coarse row,

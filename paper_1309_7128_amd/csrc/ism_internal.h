@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 namespace ism {
 
 // Geometry of one handle, passed to every kernel by value.
@@ -17,6 +20,10 @@ struct Geo {
   int log2n;           // log2 of the tile edge
   long long plane;     // nx * ny
   long long cplane;    // ncx * ncy
+  // Interpolation tables (Eq. 5), nx entries for the columns then ny for the rows: .x the
+  // weight of the upper coarse centre, .y the lower centre (as a double; -1 below the first
+  // centre) of each fine index in the grid.  Device memory of the handle's workspace.
+  const void* itab;
 };
 
 enum Reduce { SUM = 0, MAX = 1 };
@@ -100,11 +107,28 @@ hipError_t launch_gemm(int M, int N, int K, int transA, const double* A, long lo
 
 hipError_t launch_coarse_assemble(const Geo& g, int gmg5, double* coef, hipStream_t s);
 
+// Fills the interpolation tables g.itab points to (nx + ny entries of double2).
+hipError_t launch_interp_tables(const Geo& g, double2* tab, hipStream_t s);
+
 // The exact coarse solve's tables: per-axis eigenbases Vx (ncx x ncx), Vy (ncy x ncy) and
 // invLam (ncy x ncx) for stencil kind 0 ISM, 1 GMG5, 2 ACM; the constant mode's entry is 0
 // when singular.
 hipError_t launch_coarse_tables(const Geo& g, int kind, int singular, double* Vx, double* Vy,
                                 double* invLam, hipStream_t s);
+
+// Tables of the exact coarse solve along one axis (row-major nc x nc): the eigenbasis V
+// (column k the k-th mode), the forward table F (F = V for an orthonormal V, else the left
+// vectors of the pencil, F^T = V^-1 M^-1) and the mode factors k, m with
+// 1/lambda = 1/(k_x m_y + m_x k_y) (ism_coarse_tables.cpp).
+struct AxisTable {
+  std::vector<double> V, F, k, m;
+};
+
+// The tables of an axis of nf fine cells in tiles of n (nc = ceil(nf / n) coarse cells):
+// closed forms when n divides nf, else the eigen-decomposition of the axis's pencil (K, M).
+// False, with a message in err, if the decomposition fails.
+bool coarse_axis_table(int nf, int n, int nc, bool per, bool dlo, bool dhi, AxisTable& t,
+                       std::string& err);
 
 // p[0 .. count) = v (a kernel, not a memset node).
 hipError_t launch_fill(double* p, long long count, double v, hipStream_t s);

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geo g, const T* __restrict_
   if (i < g.nx) {
     const int iw = g.per_x ? imod(i - 1, g.nx) : i - 1;
     const int ie = g.per_x ? imod(i + 1, g.nx) : i + 1;
-    for (int r = wave; r < g.n; r += 4) {
+    for (int r = wave; r < g.n && J * g.n + r < g.ny; r += 4) {
       const int j = J * g.n + r;
       const int js = g.per_y ? imod(j - 1, g.ny) : j - 1;
       const int jn = g.per_y ? imod(j + 1, g.ny) : j + 1;
@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
   const double* Eb = E + (long long)blockIdx.z * g.cplane;
   int ilo, jlo;
   double X, Y;
-  interp_coord(i, g.n, ilo, X);
-  interp_coord(j, g.n, jlo, Y);
+  interp_axis(i, g.nx, g.n, g.log2n, g.ncx, g.per_x, ilo, X);
+  interp_axis(j, g.ny, g.n, g.log2n, g.ncy, g.per_y, jlo, Y);
   int ihi = ilo + 1, jhi = jlo + 1;
   double sil = 1.0, sih = 1.0, sjl = 1.0, sjh = 1.0;  // -1 at a ghost behind a Dirichlet wall
   if (g.per_x) {
@@ -201,8 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
   // x step on the coarse rows in FP64, rounded to T, the y step and the addition in T
   const T lo = T(lerp(sjl * sil * Eb[jlo * g.ncx + ilo], sjl * sih * Eb[jlo * g.ncx + ihi], X));
   const T hi = T(lerp(sjh * sil * Eb[jhi * g.ncx + ilo], sjh * sih * Eb[jhi * g.ncx + ihi], X));
-  const T Yt = T(Y);
-  const T p = lo * (T(1) - Yt) + hi * Yt;
+  const T p = lo * T(1.0 - Y) + hi * T(Y);
   T* ec = e + (long long)blockIdx.z * g.plane + (long long)j * g.nx + i;
   *ec = assign ? p : T(*ec + p);
 }
@@ -231,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_residual(Geo g, const double* 
   if (i < g.nx) {
     const int iw = g.per_x ? imod(i - 1, g.nx) : i - 1;
     const int ie = g.per_x ? imod(i + 1, g.nx) : i + 1;
-    for (int r = wave; r < g.n; r += 4) {
+    for (int r = wave; r < g.n && J * g.n + r < g.ny; r += 4) {
       const int j = J * g.n + r;
       const int js = g.per_y ? imod(j - 1, g.ny) : j - 1;
       const int jn = g.per_y ? imod(j + 1, g.ny) : j + 1;
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_sum(Geo g, const double* __rest
   const int i = x0 + lane;
   double acc = 0.0;
   if (i < g.nx)
-    for (int r = wave; r < g.n; r += 4) acc += xb[(long long)(J * g.n + r) * g.nx + i];
+    for (int r = wave; r < g.n && J * g.n + r < g.ny; r += 4) acc += xb[(long long)(J * g.n + r) * g.nx + i];
   acc = wave_sum_group(acc, g.n);
   if ((lane & (g.n - 1)) == 0) s1[wave][lane >> g.log2n] = acc;
   __syncthreads();
@@ -447,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
   double c[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) c[a][b] = 0.0;
-  const int n = g.n, half = n / 2;
+  const int n = g.n;
   const bool openE = g.per_x || I < g.ncx - 1 || (g.dmask & kDirE);
   const bool openW = g.per_x || I > 0 || (g.dmask & kDirW);
   const bool openN = g.per_y || J < g.ncy - 1 || (g.dmask & kDirN);
@@ -458,37 +457,56 @@ __global__ __launch_bounds__(kBlock) void k_coarse_assemble(Geo g, int gmg5,
     if (openN) c[2][1] += 1.0, c[1][1] -= 1.0;
     if (openS) c[0][1] += 1.0, c[1][1] -= 1.0;
   }
-  for (int k = 0; k < (gmg5 ? 0 : n); ++k) {
-    // along the face, the fine centre k of the coarse cell lies between coarse centres
-    // lo and lo + 1 (relative offsets -1/0 or 0/+1) at scaled distance t from the lower one
-    const int lo = k < half ? -1 : 0;
-    const double t = double(2 * k + 1 + (k < half ? n : -n)) / double(2 * n);
-    const double wl = (1.0 - t) / double(n), wh = t / double(n);
-    // x faces (Eq. 6): derivative across the face between columns d and d+1 (relative)
-    if (openE) {  // outward +x, columns 0 -> +1
-      c[lo + 1][2] += wl;
-      c[lo + 1][1] -= wl;
-      c[lo + 2][2] += wh;
-      c[lo + 2][1] -= wh;
+  // Eq. 6 / Eq. 7 face sums, fine row by fine row (x faces) and fine column by fine column
+  // (y faces): the fine centre k of the tile lies between coarse centres lo and lo + 1
+  // (relative offset off = -1 or 0) with weight t of the upper one (interp_axis: the
+  // rectangle's own size next to a short last tile), and the derivative across a face
+  // divides by the distance of the two centres it separates (n with full tiles; a ghost
+  // centre is the mirror image in the wall or the wrapped centre).
+  const int x0 = I * n, y0 = J * n;
+  const int kx = gmg5 ? 0 : min(n, g.nx - x0), ky = gmg5 ? 0 : min(n, g.ny - y0);
+  const double dxE = 0.5 * double(centre2(I + 1, g.nx, n, g.ncx, g.per_x) - centre2(I, g.nx, n, g.ncx, g.per_x));
+  const double dxW = 0.5 * double(centre2(I, g.nx, n, g.ncx, g.per_x) - centre2(I - 1, g.nx, n, g.ncx, g.per_x));
+  const double dyN = 0.5 * double(centre2(J + 1, g.ny, n, g.ncy, g.per_y) - centre2(J, g.ny, n, g.ncy, g.per_y));
+  const double dyS = 0.5 * double(centre2(J, g.ny, n, g.ncy, g.per_y) - centre2(J - 1, g.ny, n, g.ncy, g.per_y));
+  for (int k = 0; k < max(kx, ky); ++k) {
+    int lo;
+    double t;
+    if (k < ky) {  // x faces (Eq. 6): fine row y0 + k, columns I + d and I + d + 1
+      interp_axis(y0 + k, g.ny, n, g.log2n, g.ncy, g.per_y, lo, t);
+      const int off = lo - J;
+      if (openE) {  // outward +x, columns 0 -> +1
+        const double wl = (1.0 - t) / dxE, wh = t / dxE;
+        c[off + 1][2] += wl;
+        c[off + 1][1] -= wl;
+        c[off + 2][2] += wh;
+        c[off + 2][1] -= wh;
+      }
+      if (openW) {  // outward -x, columns -1 -> 0
+        const double wl = (1.0 - t) / dxW, wh = t / dxW;
+        c[off + 1][1] -= wl;
+        c[off + 1][0] += wl;
+        c[off + 2][1] -= wh;
+        c[off + 2][0] += wh;
+      }
     }
-    if (openW) {  // outward -x, columns -1 -> 0
-      c[lo + 1][1] -= wl;
-      c[lo + 1][0] += wl;
-      c[lo + 2][1] -= wh;
-      c[lo + 2][0] += wh;
-    }
-    // y faces (Eq. 7)
-    if (openN) {
-      c[2][lo + 1] += wl;
-      c[1][lo + 1] -= wl;
-      c[2][lo + 2] += wh;
-      c[1][lo + 2] -= wh;
-    }
-    if (openS) {
-      c[1][lo + 1] -= wl;
-      c[0][lo + 1] += wl;
-      c[1][lo + 2] -= wh;
-      c[0][lo + 2] += wh;
+    if (k < kx) {  // y faces (Eq. 7): fine column x0 + k
+      interp_axis(x0 + k, g.nx, n, g.log2n, g.ncx, g.per_x, lo, t);
+      const int off = lo - I;
+      if (openN) {
+        const double wl = (1.0 - t) / dyN, wh = t / dyN;
+        c[2][off + 1] += wl;
+        c[1][off + 1] -= wl;
+        c[2][off + 2] += wh;
+        c[1][off + 2] -= wh;
+      }
+      if (openS) {
+        const double wl = (1.0 - t) / dyS, wh = t / dyS;
+        c[1][off + 1] -= wl;
+        c[0][off + 1] += wl;
+        c[1][off + 2] -= wh;
+        c[0][off + 2] += wh;
+      }
     }
   }
   if (!g.per_x) {
@@ -949,43 +967,6 @@ inline dim3 strip_grid(const Geo& g) {
 // 1 / lambda of mode (k, l): ISM K_x M_y + M_x K_y, GMG5 K_x + K_y, ACM n (K_x + K_y); 0 for
 // the constant mode of a singular system.
 // ----------------------------------------------------------------------------------------
-struct AxisMode {
-  double theta, value;  // the mode's angle and its entry at cell I
-};
-
-__device__ AxisMode axis_mode(int nc, bool per, bool dlo, bool dhi, int k, int I) {
-  const double pi = 3.14159265358979323846;
-  AxisMode m;
-  if (per) {
-    if (k == 0) {
-      m.theta = 0.0;
-      m.value = sqrt(1.0 / nc);
-    } else if (nc % 2 == 0 && k == nc - 1) {
-      m.theta = pi;
-      m.value = (I % 2 ? -1.0 : 1.0) / sqrt(double(nc));
-    } else {
-      const int q = (k + 1) / 2;
-      m.theta = 2.0 * pi * q / nc;
-      const double a = 2.0 * pi * q * I / nc;
-      m.value = sqrt(2.0 / nc) * ((k & 1) ? cos(a) : sin(a));
-    }
-    return m;
-  }
-  double sc = sqrt(2.0 / nc), kk = k;
-  if (!dlo && !dhi) {
-    if (k == 0) sc = sqrt(1.0 / nc);
-  } else if (dlo && dhi) {
-    kk = k + 1;
-    if (k == nc - 1) sc = sqrt(1.0 / nc);
-  } else {
-    kk = k + 0.5;
-  }
-  m.theta = pi * kk / nc;
-  const double a = pi * kk * (I + 0.5) / nc;
-  m.value = sc * (dlo ? sin(a) : cos(a));
-  return m;
-}
-
 __global__ __launch_bounds__(kBlock) void k_coarse_tables(Geo g, int kind, int singular,
                                                           double* __restrict__ Vx,
                                                           double* __restrict__ Vy,
@@ -1013,6 +994,18 @@ __global__ __launch_bounds__(kBlock) void k_coarse_tables(Geo g, int kind, int s
       const double lam = kind == 1 ? kx + ky : kind == 2 ? double(g.n) * (kx + ky) : kx * my + mx * ky;
       invLam[u] = (singular && l == 0 && k == 0) ? 0.0 : 1.0 / lam;
     }
+  }
+}
+
+// The interpolation tables of Geo::itab: entry i < nx for column i, nx + j for row j.
+__global__ __launch_bounds__(kBlock) void k_interp_tables(Geo g, double2* __restrict__ tab) {
+  const int total = g.nx + g.ny;
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < total; k += gridDim.x * kBlock) {
+    int lo;
+    double t;
+    if (k < g.nx) interp_axis(k, g.nx, g.n, g.log2n, g.ncx, g.per_x, lo, t);
+    else interp_axis(k - g.nx, g.ny, g.n, g.log2n, g.ncy, g.per_y, lo, t);
+    tab[k] = make_double2(t, double(lo));
   }
 }
 
@@ -1137,6 +1130,12 @@ hipError_t launch_coarse_tables(const Geo& g, int kind, int singular, double* Vx
   const long long total = (long long)g.ncx * g.ncx + (long long)g.ncy * g.ncy + g.cplane;
   hipLaunchKernelGGL(k_coarse_tables, dim3(grid_stride_blocks(total)), dim3(kBlock), 0, s, g, kind,
                      singular, Vx, Vy, invLam);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_tables(const Geo& g, double2* tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp_tables, dim3(grid_stride_blocks(g.nx + g.ny)), dim3(kBlock), 0, s, g,
+                     tab);
   return hipGetLastError();
 }
 

@@ -137,7 +137,7 @@ class Solver:
 
     @property
     def coarse_shape(self):
-        return (self.batch, self.ny // self.n, self.nx // self.n)
+        return (self.batch, -(-self.ny // self.n), -(-self.nx // self.n))
 
     def _arg(self, t, shape, dtype=torch.float64, name="array"):
         if not isinstance(t, torch.Tensor):
@@ -300,7 +300,7 @@ class Solver:
         return E, it.value, code == L.ISM_OK
 
     def coarse_stencil(self):
-        ncy, ncx = self.ny // self.n, self.nx // self.n
+        ncy, ncx = self.coarse_shape[1:]
         coef = self._new((ncy, ncx, 3, 3))
         _check(self._lib.ism_coarse_stencil(self.handle, ctypes.c_void_p(coef.data_ptr())), self.handle)
         return coef

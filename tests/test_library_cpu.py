@@ -71,7 +71,11 @@ def _create(**kw):
     (dict(max_cycles=0), L.ISM_ERR_INVALID),
     (dict(lx=-1.0), L.ISM_ERR_INVALID),
     (dict(coarsen=12), L.ISM_ERR_UNSUPPORTED),
-    (dict(nx=72, ny=64, lx=72 / 64), L.ISM_ERR_UNSUPPORTED),  # 72 % 16 != 0
+    # a grid that coarsen does not divide (padded) takes the ISM stencil, nx % 4 == 0, ny even
+    (dict(nx=72, coarse_stencil=1), L.ISM_ERR_UNSUPPORTED),
+    (dict(nx=72, coarse_stencil=2), L.ISM_ERR_UNSUPPORTED),
+    (dict(nx=70, lx=70 / 64), L.ISM_ERR_UNSUPPORTED),
+    (dict(ny=63, ly=63 / 64), L.ISM_ERR_UNSUPPORTED),
     (dict(ly=2.0), L.ISM_ERR_UNSUPPORTED),                    # non-square cells
     (dict(nu=5, fused=1), L.ISM_ERR_UNSUPPORTED),              # FP64 fused kernel: nu <= 4
     (dict(nu=6, fused=1, precision=1), L.ISM_ERR_UNSUPPORTED), # FP32 fused kernel: nu <= 5
