@@ -762,7 +762,7 @@ def block_gauss_seidel(C, Rc, tol_c, block=16, bc_x=NEUMANN, bc_y=NEUMANN, E0=No
 
 
 def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-6, x0=None,
-                      block=16, max_fine=1000000):
+                      block=16, max_fine=1000000, precision="fp64"):
     """The paper's simplest accommodative cycling, once per call (Sec. 4.3.1): restrict the
     fine residual, iterate on the coarse grid by block GS until its absolute maximum
     residual is below tol_c, prolongate and add, then iterate red-black GS on the fine grid
@@ -773,6 +773,13 @@ def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-
     max|b~ - A x| and tol_c bounds the residual of R A P E = R (b~ - A x), i.e. of the
     h^2-scaled coarse system divided by h^2.  The fine criterion is checked before every
     sweep.
+
+    precision="fp32" runs the fine stage in the paper's single precision (Sec. 4.2) as a
+    correction: r = h^2 b~ - A'x in FP64, its tile sums the coarse right-hand side (the coarse
+    stage stays FP64, as on the host in the paper's setting), then e = P E and the red-black
+    sweeps on A'e = fp32(r) entirely in FP32, the criterion on the FP32 residual
+    max|fp32(r) - A'e| compared in FP64, and finally x + e in FP64.
+
     Returns (x, info) with info = dict(coarse_iters, fine_iters, ncc_c, ncc_f): one
     synchronization per coarse block-GS iteration and two per red-black fine iteration
     (Sec. 4.3), NCC_c = I_c and NCC_f = 2 I_f."""
@@ -782,13 +789,24 @@ def ism_solve_oneshot(b, h, n, bc_x=NEUMANN, bc_y=NEUMANN, tol_c=1e-5, tol_f=1e-
     x = np.zeros_like(bp) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     ncx, ncy = _coarse_shape(nx, ny, n)
     C = coarse_stencil_ism(ncx, ncy, n, bc_x, bc_y, (ny, nx))
-    Rc = restrict_sum(bp - laplacian(x, bc_x, bc_y), n)
-    E, ic = block_gauss_seidel(C, Rc, tol_c * h * h, block, bc_x, bc_y)
-    x = x + prolong_bilinear(E, n, bc_x, bc_y, fine_shape=(ny, nx))
+    r = bp - laplacian(x, bc_x, bc_y)
+    E, ic = block_gauss_seidel(C, restrict_sum(r, n), tol_c * h * h, block, bc_x, bc_y)
     fi = 0
-    while np.max(np.abs(bp - laplacian(x, bc_x, bc_y))) >= tol_f * h * h and fi < max_fine:
-        x = red_black_gs(x, bp, bc_x, bc_y, sweeps=1)
-        fi += 1
+    if precision == "fp64":
+        x = x + prolong_bilinear(E, n, bc_x, bc_y, fine_shape=(ny, nx))
+        while np.max(np.abs(bp - laplacian(x, bc_x, bc_y))) >= tol_f * h * h and fi < max_fine:
+            x = red_black_gs(x, bp, bc_x, bc_y, sweeps=1)
+            fi += 1
+    elif precision == "fp32":
+        r32 = r.astype(np.float32)
+        e = prolong_bilinear(E, n, bc_x, bc_y, np.float32, fine_shape=(ny, nx))
+        while (float(np.max(np.abs(r32 - laplacian(e, bc_x, bc_y)))) >= tol_f * h * h
+               and fi < max_fine):
+            e = red_black_gs(e, r32, bc_x, bc_y, sweeps=1)
+            fi += 1
+        x = x + e.astype(np.float64)
+    else:
+        raise ValueError("precision must be 'fp64' or 'fp32'")
     return _project(x, bc_x, bc_y), dict(coarse_iters=ic, fine_iters=fi, ncc_c=ic,
                                          ncc_f=2 * fi)
 

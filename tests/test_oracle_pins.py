@@ -608,6 +608,31 @@ def test_oneshot_accommodative_solve(bcx, bcy):
     assert info_t["fine_iters"] <= info_l["fine_iters"]
 
 
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND), (D, D)])
+def test_oneshot_fp32_form(bcx, bcy):
+    # Sec. 4.2: the paper's solver is single precision.  The FP32 form keeps the coarse stage
+    # in FP64 on the same restricted residual, so it takes exactly the FP64 form's coarse
+    # iterations; with a fine criterion far above FP32 resolution the fine stage crosses it
+    # within a sweep or two of the FP64 form, its result meets the criterion up to FP32
+    # rounding, and it differs from the FP64 result by FP32 rounding only (but does differ:
+    # the fine arithmetic is single precision)
+    nf, n = 64, 8
+    h = 1.0 / nf
+    b = O.div(*[np.random.default_rng(34).standard_normal(s) for s in
+                (((nf, nf) if bcx == P else (nf, nf + 1)), (nf + 1, nf))], h, bcx)
+    tol_f = 1e-4 * np.abs(b).max()
+    x64, i64 = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-2, tol_f=tol_f)
+    x32, i32 = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-2, tol_f=tol_f, precision="fp32")
+    assert i32["coarse_iters"] == i64["coarse_iters"]
+    assert abs(i32["fine_iters"] - i64["fine_iters"]) <= 2
+    bt = b - b.mean() if O.singular(bcx, bcy) else b
+    assert np.abs(bt - O.laplacian(x32, bcx, bcy) / h**2).max() < 1.01 * tol_f
+    d = np.abs(x32 - x64).max() / np.abs(x64).max()
+    assert 0.0 < d < 1e-5
+    with pytest.raises(ValueError):
+        O.ism_solve_oneshot(b, h, n, bcx, bcy, precision="fp16")
+
+
 # ---------------------------------------------------------------- MAC operators
 
 
