@@ -81,6 +81,8 @@ def parse():
                          "paper's one-shot accommodative cycling, for each tile size and coarse "
                          "criterion of --oneshot-tiles / --oneshot-coarse-tol, one JSON line each")
     ap.add_argument("--oneshot-tiles", default="16,32")
+    ap.add_argument("--oneshot-precision", default="fp64,mixed",
+                    help="fine-stage precision of the one-shot table: fp64 and/or mixed (FP32)")
     ap.add_argument("--time-loop", type=int, default=0,
                     help="only run this many projection time steps (predictor, pressure solve, "
                          "correction) of a shear-driven cavity of --time-loop-n cells per side")
@@ -121,27 +123,31 @@ def oneshot_table(w, args):
     bmax = float(b0.abs().max())
     steps = [torch.roll(b0, t, dims=-1) if w.bc_x == "periodic" else b0
              for t in range(1, args.oneshot_table + 1)]
-    for n in [int(a) for a in args.oneshot_tiles.split(",")]:
-        for frac in [float(a) for a in args.oneshot_coarse_tol.split(",")]:
-            s = Solver(w.nx, w.ny, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=n, lx=w.lx, ly=w.ly,
-                       precision="fp64", cycling="oneshot", coarse_tol=frac * bmax,
-                       fine_tol=1e-5 * bmax, max_cycles=200000)
-            x = x0.clone()
-            ic = fi = 0
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for bt in steps:
-                x, st = s.solve(bt, x)
-                ic += st["coarse_iters"]
-                fi += st["fine_iters"]
-            dt = time.perf_counter() - t0
-            k = len(steps)
-            ncc_c, ncc_f = ic / k, 2.0 * fi / k
-            print(json.dumps({"workload": w.name, "tile": n, "coarse_tol_frac": frac,
-                              "fine_tol_frac": 1e-5, "steps": k, "I_c": ic / k, "I_f": fi / k,
-                              "NCC_c": ncc_c, "NCC_f": ncc_f, "NCC_t": ncc_c + ncc_f,
-                              "N_Lap": ncc_f / 2.0 + ncc_c / float(n * n),
-                              "ms_per_step": round(1e3 * dt / k, 2)}), flush=True)
+    configs = [(prec, n, frac) for prec in args.oneshot_precision.split(",")
+               for n in [int(a) for a in args.oneshot_tiles.split(",")]
+               for frac in [float(a) for a in args.oneshot_coarse_tol.split(",")]]
+    for prec, n, frac in configs:
+        s = Solver(w.nx, w.ny, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=n, lx=w.lx, ly=w.ly,
+                   precision=prec, cycling="oneshot", coarse_tol=frac * bmax,
+                   fine_tol=1e-5 * bmax, max_cycles=200000)
+        x = x0.clone()
+        ic = fi = syncs = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for bt in steps:
+            x, st = s.solve(bt, x)
+            ic += st["coarse_iters"]
+            fi += st["fine_iters"]
+            syncs += st["host_syncs"]
+        dt = time.perf_counter() - t0
+        k = len(steps)
+        ncc_c, ncc_f = ic / k, 2.0 * fi / k
+        print(json.dumps({"workload": w.name, "precision": prec, "tile": n, "coarse_tol_frac": frac,
+                          "fine_tol_frac": 1e-5, "steps": k, "I_c": ic / k, "I_f": fi / k,
+                          "NCC_c": ncc_c, "NCC_f": ncc_f, "NCC_t": ncc_c + ncc_f,
+                          "N_Lap": ncc_f / 2.0 + ncc_c / float(n * n),
+                          "host_syncs_per_step": syncs / k,
+                          "ms_per_step": round(1e3 * dt / k, 2)}), flush=True)
 
 
 def schemes(args):

@@ -84,10 +84,16 @@ extern "C" {
  * coarse_tol, prolongate and add, then iterate
  * red-black Gauss-Seidel on the fine grid until the absolute maximum residual is below
  * fine_tol.  Both criteria are in the units of A x = b~ (the coarse residual divided by h^2),
- * which are the paper's on its h = 1 grids.  Every coarse iteration and every fine iteration
- * is followed by one convergence read-back.  FP64, ISM or GMG5 stencil only; rtol,
- * max_outer and nu are not used; max_cycles caps each stage's iterations.  The grids of a
- * batch iterate together until all of them meet a criterion. */
+ * which are the paper's on its h = 1 grids.  Every iteration's criterion is tested on the
+ * device right after it, and the first iteration that meets it stops the stage exactly
+ * (iterations enqueued past it return at once); the host reads the outcome back once per
+ * batch of 4, 8, 16, 32, then 64 iterations.  ISM or GMG5 stencil only.  ISM_PREC_FP64
+ * iterates x itself; ISM_PREC_MIXED runs the fine stage in FP32 (the paper's precision,
+ * Sec. 4.2) as a correction: e = P E and the sweeps on A'e = fp32(h^2 b~ - A'x), the
+ * criterion on that FP32 residual, then x += e in FP64 (the coarse stage stays FP64).
+ * rtol, max_outer and nu are not used; max_cycles caps each stage's iterations (status
+ * ISM_NOT_CONVERGED when a stage reaches it).  The grids of a batch iterate together until
+ * all of them meet a criterion. */
 #define ISM_CYCLE_REPEAT 0
 #define ISM_CYCLE_ONESHOT 1
 

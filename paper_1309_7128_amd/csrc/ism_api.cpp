@@ -26,11 +26,18 @@ using ism::Partials;
 namespace {
 
 // Slots of the per-grid device scalars; the array is slot-major, [kSlots][batch].
-enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, CMAX, MEAN_R, kSlots };
+// STOP and STOP_AT (entry 0 of each) hold the state of a device-checked loop: 0 running, 1
+// converged, 2 a non-finite value met, and the iteration it stopped at.
+enum Slot { MEAN_B = 0, RSQ, RMAX, BSQ, BMAX, ISQ, MEAN_X, CMAX, MEAN_R, STOP, STOP_AT, kSlots };
 
 // Adaptive convergence checks in flight at once (pinned read-back slots) and the number of
 // cycles the host enqueues past a check before it waits for that check's result.
 constexpr int kChecks = 8, kLag = 2;
+
+// Iterations a device-checked loop (the one-shot stages) enqueues between two read-backs: 4,
+// doubling to 64, so that a loop of I iterations reads back about log2(I) + I / 64 times and
+// enqueues at most 63 iterations past its stop, each of which exits at once.
+constexpr int kBatchFirst = 4, kBatchMax = 64;
 
 thread_local std::string g_create_error;
 
@@ -188,8 +195,8 @@ int validate(const ism_config* cfg, std::string& why) {
     if (!(cfg->coarse_tol > 0.0) || !(cfg->fine_tol > 0.0) || !std::isfinite(cfg->coarse_tol) ||
         !std::isfinite(cfg->fine_tol))
       return why = "coarse_tol and fine_tol must be positive and finite", ISM_ERR_INVALID;
-    if (cfg->precision != ISM_PREC_FP64 || cfg->coarse_stencil == ISM_COARSE_ACM)
-      return why = "one-shot cycling runs in FP64 with the ISM or GMG5 stencil", ISM_ERR_UNSUPPORTED;
+    if (cfg->coarse_stencil == ISM_COARSE_ACM)
+      return why = "one-shot cycling takes the ISM or GMG5 stencil", ISM_ERR_UNSUPPORTED;
   }
   if (cfg->stall_window < 1 || !(cfg->stall_drop >= 0.0) || !(cfg->stall_drop < 1.0))
     return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
@@ -563,39 +570,67 @@ Geo coarse_geo(const Geo& g) {
   return gc;
 }
 
-// Block Gauss-Seidel (Sec. 4) on every grid's A_c E = rc from E = 0, one synchronization per
-// iteration: each launch forms the residual of its incoming iterate and the next iterate;
-// the loop stops at the first iterate whose residual max is below tol on every grid (or
-// after max_iter updates).  The result stays in one of the t1 / t2 buffers (*E_out).
+// A device-checked iteration loop: iteration it (0, 1, ...) enqueues step(it), which also
+// leaves per-grid maxima of the residual of its incoming iterate in m, then a device-side
+// test against tol that records the first iteration at which every grid is below it (the
+// later steps then exit at once).  The host reads the state back once per batch of
+// iterations.  *stop_it: that iteration, or max_iter when none was below tol by then
+// (*converged false).
+template <typename Step>
+int device_checked_loop(ism_ctx* c, Step step, const double* m, double tol, int max_iter,
+                        const char* what, int* stop_it, bool* converged) {
+  const int B = c->g.batch;
+  double* state = c->scal + size_t(STOP) * B;
+  double* at = c->scal + size_t(STOP_AT) * B;
+  LAUNCH(c, ism::launch_fill(state, 1, 0.0, c->stream));
+  int it = 0, batch = kBatchFirst;
+  for (;;) {
+    const int end = std::min(max_iter, it + batch - 1);
+    for (; it <= end; ++it) {
+      int rcode = step(it, state);
+      if (rcode) return rcode;
+      LAUNCH(c, ism::launch_stop_check(m, B, tol, it, state, at, c->stream));
+    }
+    int rcode = read_scalars(c);
+    if (rcode) return rcode;
+    const double st = c->h_scal[size_t(STOP) * B], a = c->h_scal[size_t(STOP_AT) * B];
+    if (st == 2.0) return set_err(c, ISM_ERR_NONFINITE, std::string("non-finite ") + what);
+    if (st == 1.0) {
+      *stop_it = int(a);
+      *converged = true;
+      return ISM_OK;
+    }
+    if (it > max_iter) {
+      *stop_it = max_iter;
+      *converged = false;
+      return ISM_OK;
+    }
+    batch = std::min(2 * batch, kBatchMax);
+  }
+}
+
+// Block Gauss-Seidel (Sec. 4) on every grid's A_c E = rc from E = 0: iteration it forms the
+// residual of its incoming iterate E_it (in t1 for even it, t2 for odd) and E_it+1; the loop
+// stops at the first iterate whose residual max is below tol on every grid (or at max_iter).
+// The result stays in one of the t1 / t2 buffers (*E_out).
 int coarse_block_gs(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
                     int* iters, bool* converged) {
   const Geo& g = c->g;
   const int B = g.batch, tiles = ism::coarse_bgs_tiles(g);
   hipStream_t s = c->stream;
-  double* Ea = c->t1;
-  double* Eb = c->t2;
-  LAUNCH(c, ism::launch_fill(Ea, (long long)g.cplane * B, 0.0, s));
+  double* E[2] = {c->t1, c->t2};
+  LAUNCH(c, ism::launch_fill(E[0], (long long)g.cplane * B, 0.0, s));
+  double* m = c->scal + size_t(CMAX) * B;
+  auto step = [&](int it, const double* stop) {
+    LAUNCH(c, ism::launch_coarse_bgs(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max, s, stop));
+    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
+    return ISM_OK;
+  };
   int it = 0;
-  bool done = false;
-  for (;;) {
-    LAUNCH(c, ism::launch_coarse_bgs(g, c->coef, rc, Ea, Eb, c->p_max, s));
-    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0,
-                                   c->scal + size_t(CMAX) * B, 1, 0, c->fin, s));
-    int rcode = read_scalars(c);
-    if (rcode) return rcode;
-    done = true;
-    for (int k = 0; k < B; ++k) {
-      const double m = c->h_scal[size_t(CMAX) * B + k];
-      if (!std::isfinite(m)) return set_err(c, ISM_ERR_NONFINITE, "non-finite coarse residual");
-      done = done && m < tol;
-    }
-    if (done || it >= max_iter) break;
-    std::swap(Ea, Eb);
-    ++it;
-  }
-  *E_out = Ea;
+  const int rcode = device_checked_loop(c, step, m, tol, max_iter, "coarse residual", &it, converged);
+  if (rcode) return rcode;
+  *E_out = E[it & 1];
   *iters = it;
-  *converged = done;
   return ISM_OK;
 }
 
@@ -610,20 +645,27 @@ int project_coarse(ism_ctx* c, double* rc) {
 }
 
 // ISM_CYCLE_ONESHOT (Sec. 4.3.1): restrict once, block GS on the coarse grid to coarse_tol,
-// prolongate and add, then red-black sweeps until max |b~ - A x| < fine_tol.  FP64.
+// prolongate and add, then red-black sweeps until max |b~ - A x| < fine_tol.  T = double
+// iterates x itself; T = float (the paper's single precision, Sec. 4.2) iterates a correction
+// e on A'e = fp32(r), r = h^2 b~ - A'x in FP64, from e = P E, and adds it to x at the end.
+// Both stages are device-checked loops (one read-back per batch of iterations).
+template <typename T>
 int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   const auto t0 = std::chrono::steady_clock::now();
   c->launches = 0;
   c->syncs = 0;
   const Geo& g = c->g;
   const int B = g.batch;
+  constexpr bool F64 = sizeof(T) == 8;
   hipStream_t s = c->stream;
   const double* mean = c->scal + size_t(MEAN_B) * B;
   int rcode;
   if ((rcode = mean_of_b(c, b))) return rcode;
-  // r' = h^2 b~ - A'x and its tile sums, the coarse right-hand side
+  // r' = h^2 b~ - A'x and its tile sums, the coarse right-hand side (FP32 form: r' also as
+  // the fine right-hand side, in T)
   Partials p0{nullptr, nullptr, c->p_bsq, c->p_bmax};
-  LAUNCH(c, ism::launch_outer_residual<double>(g, b, x, mean, c->h2, (double*)nullptr, c->rc, p0, s));
+  LAUNCH(c, ism::launch_outer_residual<T>(g, b, x, mean, c->h2, F64 ? (T*)nullptr : (T*)c->rT,
+                                          c->rc, p0, s));
   if ((rcode = finalize(c, c->p_bsq, ism::SUM, 1.0, BSQ))) return rcode;
   if ((rcode = finalize(c, c->p_bmax, ism::MAX, 1.0, BMAX))) return rcode;
   if (c->singular && (rcode = project_coarse(c, c->rc))) return rcode;
@@ -633,45 +675,72 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   const double h = c->h;
   if ((rcode = coarse_block_gs(c, c->rc, c->cfg.coarse_tol * h * h, c->cfg.max_cycles, &E, &ic, &cconv)))
     return rcode;
-  LAUNCH(c, ism::launch_prolong<double>(g, E, x, 0, s));
-  // b' as an array: the residual of x = 0
-  double* rhs = (double*)c->rT;
-  double* zero = (double*)c->eB;
-  LAUNCH(c, ism::launch_fill(zero, (long long)g.plane * B, 0.0, s));
-  Partials none{nullptr, nullptr, nullptr, nullptr};
-  LAUNCH(c, ism::launch_outer_residual<double>(g, b, zero, mean, c->h2, rhs, nullptr, none, s));
-  double* cur = x;
-  double* nxt = (double*)c->eA;
-  int fi = 0;
-  bool fconv = false;
-  // each sweep also returns max |b' - A' cur| of its incoming iterate, per tile
+  // the fine iterates: x and eA (FP64: x += P E, right-hand side b' = h^2 b~, the residual of
+  // x = 0), or eA and eB (FP32: e = P E, right-hand side fp32(r'))
+  T* buf[2];
+  const T* rhs;
+  if constexpr (F64) {
+    LAUNCH(c, ism::launch_prolong<double>(g, E, x, 0, s));
+    double* bp = (double*)c->rT;
+    double* zero = (double*)c->eB;
+    LAUNCH(c, ism::launch_fill(zero, (long long)g.plane * B, 0.0, s));
+    Partials none{nullptr, nullptr, nullptr, nullptr};
+    LAUNCH(c, ism::launch_outer_residual<double>(g, b, zero, mean, c->h2, bp, nullptr, none, s));
+    buf[0] = x;
+    buf[1] = (double*)c->eA;
+    rhs = bp;
+  } else {
+    buf[0] = (T*)c->eA;
+    buf[1] = (T*)c->eB;
+    LAUNCH(c, ism::launch_prolong<T>(g, E, buf[0], 1, s));
+    rhs = (const T*)c->rT;
+  }
+  // Iteration i checks iterate i, held in buf[i & 1].  Unfused: one sweep kernel forms the
+  // residual maxima of its incoming iterate per tile and the next iterate.  Fused (16-byte
+  // aligned iterates): iteration i >= 1 is one pass of the fused kernel with a zero coarse
+  // correction, sweeping iterate i - 1 into iterate i and forming its residual maxima per
+  // coarse tile (the same values, bit for bit); iteration 0 takes the unfused form for the
+  // residual of the first iterate, and the sweep it also makes is made again by iteration 1.
   const int tiles = ism::rbgs_tiles(g);
   if (tiles > g.cplane) return set_err(c, ISM_ERR_UNSUPPORTED, "sweep tiles exceed the partials");
-  for (;;) {
-    hipEvent_t ev = prof_start(c, ISM_KERNEL_SMOOTH);
-    LAUNCH(c, ism::launch_rbgs<double>(g, rhs, cur, nxt, s, 1.0, c->p_max));
-    prof_stop(c, ISM_KERNEL_SMOOTH, ev);
-    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0,
-                                   c->scal + size_t(RMAX) * B, 1, 0, c->fin, s));
-    if ((rcode = read_scalars(c))) return rcode;
-    fconv = true;
-    for (int k = 0; k < B; ++k) {
-      const double m = c->h_scal[size_t(RMAX) * B + k];
-      if (!std::isfinite(m)) return set_err(c, ISM_ERR_NONFINITE, "non-finite value in b, x or the residual");
-      fconv = fconv && m < c->cfg.fine_tol * h * h;
+  const bool fused = c->cfg.fused && ((uintptr_t)buf[0] & 15) == 0;
+  double* zeroE = c->E;
+  if (fused) LAUNCH(c, ism::launch_fill(zeroE, (long long)g.cplane * B, 0.0, s));
+  double* m = c->scal + size_t(RMAX) * B;
+  auto step = [&](int i, const double* stop) {
+    if (!fused || i == 0) {
+      hipEvent_t ev = prof_start(c, ISM_KERNEL_SMOOTH);
+      LAUNCH(c, ism::launch_rbgs<T>(g, rhs, buf[i & 1], buf[(i + 1) & 1], s, T(1), c->p_max, stop));
+      prof_stop(c, ISM_KERNEL_SMOOTH, ev);
+      LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
+    } else {
+      hipEvent_t ev = prof_start(c, ISM_KERNEL_CYCLE);
+      LAUNCH(c, ism::launch_cycle_fused<T>(g, rhs, buf[(i - 1) & 1], buf[i & 1], zeroE, c->rc,
+                                           c->p_max, 1, 0, s, stop, 1));
+      prof_stop(c, ISM_KERNEL_CYCLE, ev);
+      LAUNCH(c, ism::launch_finalize(c->p_max, int(g.cplane), g.cplane, B, ism::MAX, 1.0, m, 1, 0,
+                                     c->fin, s));
     }
-    if (fconv || fi >= c->cfg.max_cycles) break;  // cur is the result (nxt one sweep past it)
-    std::swap(cur, nxt);
-    ++fi;
+    return ISM_OK;
+  };
+  int fi = 0;
+  bool fconv = false;
+  if ((rcode = device_checked_loop(c, step, m, c->cfg.fine_tol * h * h, c->cfg.max_cycles,
+                                   "value in b, x or the residual", &fi, &fconv)))
+    return rcode;
+  T* cur = buf[fi & 1];
+  if constexpr (F64) {
+    if (cur != x)
+      HIPCHK(c, hipMemcpyAsync(x, cur, sizeof(double) * size_t(g.plane) * B, hipMemcpyDeviceToDevice, s));
+  } else {
+    LAUNCH(c, ism::launch_add_to<T>(g, x, cur, s));
   }
   // the reported norms: one residual pass over the result
   Partials pc{c->p_sq, c->p_max, nullptr, nullptr};
-  LAUNCH(c, ism::launch_outer_residual<double>(g, b, cur, mean, c->h2, (double*)nullptr, nullptr, pc, s));
+  LAUNCH(c, ism::launch_outer_residual<double>(g, b, x, mean, c->h2, (double*)nullptr, nullptr, pc, s));
   if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, RSQ))) return rcode;
   if ((rcode = finalize(c, c->p_max, ism::MAX, 1.0, RMAX))) return rcode;
   if ((rcode = read_scalars(c))) return rcode;
-  if (cur != x)
-    HIPCHK(c, hipMemcpyAsync(x, cur, sizeof(double) * size_t(g.plane) * B, hipMemcpyDeviceToDevice, s));
   double rel_l2 = 0.0, rel_max = 0.0;
   for (int k = 0; k < B; ++k) {
     const double bn = std::sqrt(c->h_scal[size_t(BSQ) * B + k]), bm = c->h_scal[size_t(BMAX) * B + k];
@@ -1090,7 +1159,8 @@ int ism_solve(ism_handle c, const double* b, double* x, ism_stats* st) {
   if (!c) return ISM_ERR_INVALID;
   if (!b || !x) return set_err(c, ISM_ERR_INVALID, "b and x must be device pointers");
   if (st) *st = ism_stats{};
-  if (c->cfg.cycling == ISM_CYCLE_ONESHOT) return oneshot_solve(c, b, x, st);
+  if (c->cfg.cycling == ISM_CYCLE_ONESHOT)
+    return c->tsize == 4 ? oneshot_solve<float>(c, b, x, st) : oneshot_solve<double>(c, b, x, st);
   return c->tsize == 4 ? solve_impl<float>(c, b, x, st) : solve_impl<double>(c, b, x, st);
 }
 
@@ -1125,7 +1195,8 @@ int ism_solve_static(const ism_config* cfg, const double* b, double* x, ism_stat
   c.h_chk = c.h_scal + size_t(kSlots) * c.g.batch;
   rcode = init_device_state(&c);
   if (rcode == ISM_OK) {
-    if (c.cfg.cycling == ISM_CYCLE_ONESHOT) rcode = oneshot_solve(&c, b, x, st);
+    if (c.cfg.cycling == ISM_CYCLE_ONESHOT)
+      rcode = c.tsize == 4 ? oneshot_solve<float>(&c, b, x, st) : oneshot_solve<double>(&c, b, x, st);
     else rcode = c.tsize == 4 ? solve_impl<float>(&c, b, x, st) : solve_impl<double>(&c, b, x, st);
   }
   if (rcode < 0) g_create_error = c.err;

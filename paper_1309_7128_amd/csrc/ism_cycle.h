@@ -221,7 +221,7 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
                                            Vec4u* __restrict__ sR, long long coff, int zero_e,
                                            int xs, int y0, int L, bool down,
                                            const double2* __restrict__ tabx,
-                                           const double2* __restrict__ taby) {
+                                           const double2* __restrict__ taby, int maxmode) {
   using S = Stream<T, NU, LOG2N>;
   using V16 = typename Vec16<T>::type;
   constexpr bool EDGE = KIND == kEdge, PLAIN = KIND == kPlain;
@@ -344,17 +344,18 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   // Coarse rows J interpolated along x at the lane's cells (FP64, rounded to T), kept in LDS
   // buffer J & 1 (each lane reads back only what it wrote): [buffer][16-byte chunk][lane].
   constexpr int K16 = 16 / int(sizeof(T)), C16X = CPL / K16;
+  // with full rectangles, the lane's first lower centre relative to the staged block
+  const int crel = ((cu - N / 2) >> LOG2N) - I0;
   auto put_x = [&](int J) {
-    const double* q = sE + (J - J0) * S::NC - I0;
     V16* d = sX + (J & 1) * C16X * kWave + lane;
-    int c0 = cu;
-    asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
     if (!tab_x) {
       // full rectangles: for n >= 8 all of a lane's cells lie between the same two coarse
       // centres, for n = 4 its first and last two cells between consecutive pairs
       constexpr int NEC = N >= 8 ? 2 : 3;
       constexpr double inv2n = 1.0 / double(2 * N);
-      const double* qq = q + ((c0 - N / 2) >> LOG2N);
+      const double* qq = sE + (J - J0) * S::NC + crel;
+      int c0 = cu;
+      asm volatile("" : "+v"(c0));  // recomputed here, not held in registers for the walk
       double v[NEC];
 #pragma unroll
       for (int k = 0; k < NEC; ++k) v[k] = qq[k];
@@ -375,6 +376,9 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
       // one period of a periodic axis, nx being a multiple of CPL), one cell at a time and
       // each value stored at once: the ring holds most registers, and this path must not
       // raise the kernel's register count
+      const double* q = sE + (J - J0) * S::NC - I0;
+      int c0 = cu;
+      asm volatile("" : "+v"(c0));
       int cb = c0, shift = 0;
       if (g.per_x) {
         const int k = floordiv(c0, g.nx);
@@ -562,9 +566,15 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             }
             acc += d[p];
           }
-          if (psq) {  // squared sums only when a convergence check reads them
+          if (psq) {  // only when a convergence check reads them: squared sums, or maxima of |d|
+            // (the maxima only in the one-sweep kernel, the one-shot cycling's fine stage)
+            if (NU == 1 && maxmode) {
 #pragma unroll
-            for (int p = 0; p < CPL; ++p) acc2 += d[p] * d[p];
+              for (int p = 0; p < CPL; ++p) acc2 = fmax(acc2, fabs(d[p]));
+            } else {
+#pragma unroll
+              for (int p = 0; p < CPL; ++p) acc2 += d[p] * d[p];
+            }
           }
           if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
           // a tile's last row in walk order (walking up, the last row of the grid also ends a
@@ -575,8 +585,13 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
 #pragma unroll
             for (int k = 1; k < G; k <<= 1) a += __shfl_down(a, k, kWave);
             if (psq) {
+              if (NU == 1 && maxmode) {
 #pragma unroll
-              for (int k = 1; k < G; k <<= 1) q += __shfl_down(q, k, kWave);
+                for (int k = 1; k < G; k <<= 1) q = fmax(q, __shfl_down(q, k, kWave));
+              } else {
+#pragma unroll
+                for (int k = 1; k < G; k <<= 1) q += __shfl_down(q, k, kWave);
+              }
             }
             if (lane_out && ((lane - PX / CPL) & (G - 1)) == 0) {
               const long long oc = coff + (long long)(o >> LOG2N) * g.ncx + (cu >> LOG2N);
@@ -608,7 +623,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Stream<T
 void k_cycle(Geo g, const T* __restrict__ rhs, const T* __restrict__ ein, T* __restrict__ eout,
              const double* __restrict__ E, double* __restrict__ rc, double* __restrict__ psq,
              int zero_e, int nb, int Ci, int nstrip, int first, int Ce, int nstrip_e, int efirst,
-             int nblk_e) {
+             int nblk_e, const double* __restrict__ stop, int maxmode) {
+  // a launch enqueued past the iteration a device-side check stopped at does nothing
+  if (stop && *stop != 0.0) return;
   using S = Stream<T, NU, LOG2N>;
   constexpr int WPB = kBlock / kWave;
   __shared__ double sE[WPB][S::NR * S::NC];
@@ -631,7 +648,7 @@ void k_cycle(Geo g, const T* __restrict__ rhs, const T* __restrict__ ein, T* __r
     const int b0 = chunk * nb / Ce, b1 = (chunk + 1) * nb / Ce;
     cycle_walk<T, NU, LOG2N, kEdge>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
                                     sE[w], sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
-                                    b0 * S::N, (b1 - b0) * S::N, chunk & 1, tabx, taby);
+                                    b0 * S::N, (b1 - b0) * S::N, chunk & 1, tabx, taby, maxmode);
     return;
   }
   int bi = b - nblk_e;
@@ -654,16 +671,17 @@ void k_cycle(Geo g, const T* __restrict__ rhs, const T* __restrict__ ein, T* __r
   if (rows_ok && cols_ok)
     cycle_walk<T, NU, LOG2N, kPlain>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
                                      sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
-                                     taby);
+                                     taby, maxmode);
   else
     cycle_walk<T, NU, LOG2N, kRows>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
                                     sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
-                                    taby);
+                                    taby, maxmode);
 }
 
 template <typename T, int NU, int LOG2N>
 hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
-                           double* rc, double* psq, int zero_e, hipStream_t s) {
+                           double* rc, double* psq, int zero_e, hipStream_t s, const double* stop,
+                           int maxmode) {
   using S = Stream<T, NU, LOG2N>;
   constexpr int WPB = kBlock / kWave;
   auto kernel = k_cycle<T, NU, LOG2N>;
@@ -713,18 +731,20 @@ hipError_t cycle_dispatch3(const Geo& g, const T* rhs, const T* ein, T* eout, co
   const int nblk_i = (ni * Ci + WPB - 1) / WPB;
   if (nblk_e + nblk_i == 0) return hipSuccess;
   hipLaunchKernelGGL(kernel, dim3(nblk_e + nblk_i, 1, g.batch), dim3(kBlock), 0, s, g, rhs, ein,
-                     eout, E, rc, psq, zero_e, nb, Ci, ni, first, Ce, ne, efirst, nblk_e);
+                     eout, E, rc, psq, zero_e, nb, Ci, ni, first, Ce, ne, efirst, nblk_e, stop,
+                     maxmode);
   return hipGetLastError();
 }
 
 template <typename T, int NU>
 hipError_t cycle_dispatch2(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
-                           double* rc, double* psq, int zero_e, hipStream_t s) {
+                           double* rc, double* psq, int zero_e, hipStream_t s, const double* stop,
+                           int maxmode) {
   switch (g.log2n) {
-    case 2: return cycle_dispatch3<T, NU, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 3: return cycle_dispatch3<T, NU, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 4: return cycle_dispatch3<T, NU, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    case 5: return cycle_dispatch3<T, NU, 5>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
+    case 2: return cycle_dispatch3<T, NU, 2>(g, rhs, ein, eout, E, rc, psq, zero_e, s, stop, maxmode);
+    case 3: return cycle_dispatch3<T, NU, 3>(g, rhs, ein, eout, E, rc, psq, zero_e, s, stop, maxmode);
+    case 4: return cycle_dispatch3<T, NU, 4>(g, rhs, ein, eout, E, rc, psq, zero_e, s, stop, maxmode);
+    case 5: return cycle_dispatch3<T, NU, 5>(g, rhs, ein, eout, E, rc, psq, zero_e, s, stop, maxmode);
     default: return hipErrorInvalidValue;
   }
 }
@@ -734,12 +754,15 @@ hipError_t cycle_dispatch2(const Geo& g, const T* rhs, const T* ein, T* eout, co
 // Every sweep count 1 .. MAXNU of the fused kernel for fine type T.
 template <typename T, int MAXNU>
 hipError_t launch_cycle_upto(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
-                             double* rc, double* psq, int nu, int zero_e, hipStream_t s) {
+                             double* rc, double* psq, int nu, int zero_e, hipStream_t s,
+                             const double* stop, int maxmode) {
   if constexpr (MAXNU == 0) {
     return hipErrorInvalidValue;
   } else {
-    if (nu == MAXNU) return cycle_dispatch2<T, MAXNU>(g, rhs, ein, eout, E, rc, psq, zero_e, s);
-    return launch_cycle_upto<T, MAXNU - 1>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s);
+    if (nu == MAXNU)
+      return cycle_dispatch2<T, MAXNU>(g, rhs, ein, eout, E, rc, psq, zero_e, s, stop, maxmode);
+    return launch_cycle_upto<T, MAXNU - 1>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s, stop,
+                                           maxmode);
   }
 }
 

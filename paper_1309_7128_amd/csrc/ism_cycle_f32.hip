@@ -5,9 +5,10 @@ namespace ism {
 
 template <>
 hipError_t launch_cycle_fused<float>(const Geo& g, const float* rhs, const float* ein, float* eout,
-                                  const double* E, double* rc, double* psq, int nu, int zero_e,
-                                  hipStream_t s) {
-  return launch_cycle_upto<float, 5>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s);
+                                     const double* E, double* rc, double* psq, int nu, int zero_e,
+                                     hipStream_t s, const double* stop, int maxmode) {
+  if (maxmode && nu != 1) return hipErrorInvalidValue;  // the maxima exist for nu = 1 only
+  return launch_cycle_upto<float, 5>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s, stop, maxmode);
 }
 
 template <>

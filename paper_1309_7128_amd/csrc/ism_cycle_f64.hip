@@ -5,9 +5,10 @@ namespace ism {
 
 template <>
 hipError_t launch_cycle_fused<double>(const Geo& g, const double* rhs, const double* ein, double* eout,
-                                  const double* E, double* rc, double* psq, int nu, int zero_e,
-                                  hipStream_t s) {
-  return launch_cycle_upto<double, 4>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s);
+                                      const double* E, double* rc, double* psq, int nu, int zero_e,
+                                      hipStream_t s, const double* stop, int maxmode) {
+  if (maxmode && nu != 1) return hipErrorInvalidValue;  // the maxima exist for nu = 1 only
+  return launch_cycle_upto<double, 4>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s, stop, maxmode);
 }
 
 template <>

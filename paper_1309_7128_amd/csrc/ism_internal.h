@@ -42,10 +42,11 @@ struct Partials {
 // The right-hand side is multiplied by rscale as it is read (a power of two on the ACM
 // levels, so the product is exact).
 // With part_max, also max |rhs - A'e_in| per tile into part_max[grid][tile]
-// (rbgs_tiles(g) tiles per grid).
+// (rbgs_tiles(g) tiles per grid).  With stop, a device flag: the launch does nothing when
+// *stop != 0 (set by launch_stop_check).
 template <typename T>
 hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* e_in, T* e_out, hipStream_t s,
-                       T rscale = T(1), double* part_max = nullptr);
+                       T rscale = T(1), double* part_max = nullptr, const double* stop = nullptr);
 int rbgs_tiles(const Geo& g);
 
 // ACM (FP64): out = 2x2 sums of (r - scale A'e) on the level grid g (e may be null) with
@@ -63,19 +64,24 @@ hipError_t launch_prolong(const Geo& g, const double* E, T* e, int assign, hipSt
 
 // One fused cycle: e = (zero_e ? 0 : e) + P E, nu red-black sweeps on A'e = rhs, then
 // rc = R (rhs - A'e) and per-coarse-tile sums of squares (ism_cycle_f32.hip and
-// ism_cycle_f64.hip).  e_in and e_out must not alias.  nu <= fused_max_nu<T>().
+// ism_cycle_f64.hip).  e_in and e_out must not alias.  nu <= fused_max_nu<T>().  With
+// maxmode (nu = 1 only), psq receives per-tile maxima of |rhs - A'e| instead.  With stop, a
+// device flag: the launch does nothing when *stop != 0.
 template <typename T>
 hipError_t launch_cycle_fused(const Geo& g, const T* rhs, const T* e_in, T* e_out,
                               const double* E, double* rc, double* part_sumsq, int nu,
-                              int zero_e, hipStream_t s);
+                              int zero_e, hipStream_t s, const double* stop = nullptr,
+                              int maxmode = 0);
 template <typename T>
 int fused_max_nu();
 template <>
 hipError_t launch_cycle_fused<float>(const Geo&, const float*, const float*, float*,
-                                     const double*, double*, double*, int, int, hipStream_t);
+                                     const double*, double*, double*, int, int, hipStream_t,
+                                     const double*, int);
 template <>
 hipError_t launch_cycle_fused<double>(const Geo&, const double*, const double*, double*,
-                                      const double*, double*, double*, int, int, hipStream_t);
+                                      const double*, double*, double*, int, int, hipStream_t,
+                                      const double*, int);
 template <>
 int fused_max_nu<float>();
 template <>
@@ -139,7 +145,13 @@ hipError_t launch_fill(double* p, long long count, double v, hipStream_t s);
 // grid.
 int coarse_bgs_tiles(const Geo& g);
 hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, const double* Ein,
-                             double* Eout, double* part_max, hipStream_t s);
+                             double* Eout, double* part_max, hipStream_t s,
+                             const double* stop = nullptr);
+
+// Device-side stop test of iteration iter: if *state is 0 and every m[0 .. batch) is below
+// tol (or any is not finite), sets *state to 1 (2) and *at to iter.  One thread.
+hipError_t launch_stop_check(const double* m, int batch, double tol, int iter, double* state,
+                             double* at, hipStream_t s);
 
 hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
                       hipStream_t s);

@@ -26,7 +26,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rbgs(Geo g, const T* __restrict__ rhs,
                                                  const T* __restrict__ ein,
                                                  T* __restrict__ eout, T rscale,
-                                                 double* __restrict__ part_max) {
+                                                 double* __restrict__ part_max,
+                                                 const double* __restrict__ stop) {
+  // a sweep enqueued past the iteration a device-side check stopped at does nothing
+  if (stop && *stop != 0.0) return;
   constexpr int TX = 64, TY = 32;
   constexpr int LE = TX + 4, HE = TY + 4;
   constexpr int LR = TX + 2, HR = TY + 2;
@@ -564,7 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_bgs(Geo g, const double* __re
                                                        const double* __restrict__ Ein,
                                                        double* __restrict__ Eout,
                                                        double* __restrict__ part_max, int tx,
-                                                       int ty) {
+                                                       int ty, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;  // enqueued past a device-side stop
   constexpr int LW = kCB + 2;
   __shared__ double sE[LW * LW];
   __shared__ double smax[kBlock / kWave];
@@ -1009,6 +1013,24 @@ __global__ __launch_bounds__(kBlock) void k_interp_tables(Geo g, double2* __rest
   }
 }
 
+// Device-side convergence test of an iteration whose per-grid maxima m[0 .. batch) were just
+// reduced: the first iteration at which every grid is below tol (or any value is not finite)
+// sets state to 1 (2) and records the iteration; later calls leave both alone.
+__global__ void k_stop_check(const double* __restrict__ m, int batch, double tol, int iter,
+                             double* __restrict__ state, double* __restrict__ at) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *state != 0.0) return;
+  bool all = true, bad = false;
+  for (int k = 0; k < batch; ++k) {
+    const double v = m[k];
+    bad = bad || !isfinite(v);
+    all = all && v < tol;
+  }
+  if (bad || all) {
+    *state = bad ? 2.0 : 1.0;
+    *at = double(iter);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ p, long long count,
                                                  double v) {
   for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < count;
@@ -1022,9 +1044,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ p, long lo
 
 template <typename T>
 hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* ein, T* eout, hipStream_t s, T rscale,
-                       double* part_max) {
+                       double* part_max, const double* stop) {
   dim3 grid((g.nx + 63) / 64, (g.ny + 31) / 32, g.batch);
-  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout, rscale, part_max);
+  hipLaunchKernelGGL(k_rbgs<T>, grid, dim3(kBlock), 0, s, g, rhs, ein, eout, rscale, part_max, stop);
   return hipGetLastError();
 }
 
@@ -1155,11 +1177,17 @@ int coarse_bgs_tiles(const Geo& g) {
 }
 
 hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, const double* Ein,
-                             double* Eout, double* part_max, hipStream_t s) {
+                             double* Eout, double* part_max, hipStream_t s, const double* stop) {
   const int tx = bgs_tile(g.ncx, g.per_x), ty = bgs_tile(g.ncy, g.per_y);
   dim3 grid((g.ncx + tx - 1) / tx, (g.ncy + ty - 1) / ty, g.batch);
   hipLaunchKernelGGL(k_coarse_bgs, grid, dim3(kBlock), 0, s, g, coef, R, Ein, Eout, part_max, tx,
-                     ty);
+                     ty, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop_check(const double* m, int batch, double tol, int iter, double* state,
+                             double* at, hipStream_t s) {
+  hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(kWave), 0, s, m, batch, tol, iter, state, at);
   return hipGetLastError();
 }
 
@@ -1217,9 +1245,9 @@ hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv,
 }
 
 template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t, float,
-                                       double*);
+                                       double*, const double*);
 template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t,
-                                        double, double*);
+                                        double, double*, const double*);
 template hipError_t launch_restrict<float>(const Geo&, const float*, const float*, double*, double*, hipStream_t);
 template hipError_t launch_restrict<double>(const Geo&, const double*, const double*, double*, double*, hipStream_t);
 template hipError_t launch_prolong<float>(const Geo&, const double*, float*, int, hipStream_t);

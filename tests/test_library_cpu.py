@@ -86,7 +86,6 @@ def _create(**kw):
     (dict(cycling=2), L.ISM_ERR_INVALID),
     (dict(cycling=1, coarse_tol=0.0), L.ISM_ERR_INVALID),
     (dict(cycling=1, fine_tol=-1.0), L.ISM_ERR_INVALID),
-    (dict(cycling=1, precision=1), L.ISM_ERR_UNSUPPORTED),      # one-shot cycling is FP64
     (dict(cycling=1, coarse_stencil=2), L.ISM_ERR_UNSUPPORTED), # and needs a 9-point stencil
 ])
 def test_invalid_configs_rejected_before_device(kw, code):
