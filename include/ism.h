@@ -97,6 +97,17 @@ extern "C" {
 #define ISM_CYCLE_REPEAT 0
 #define ISM_CYCLE_ONESHOT 1
 
+/* The kernel a cycle takes (ism_config.fused).  Both fused kernels give the same e bit for
+ * bit (that of nu whole-grid red-black sweeps) and the same tile sums up to their summation
+ * order.  The row walk streams the grid once per cycle (the large-grid form); the LDS-tiled
+ * form stages 32 x 32 blocks with a halo of 2 nu + 1 and suits grids too small for the walk
+ * to hide its per-row latency.  AUTO takes the tiled form up to 1280^2 cells per launch
+ * (nx * ny * batch), the walk above. */
+#define ISM_FUSED_OFF 0  /* prolongation, nu sweeps, residual + restriction: one kernel each */
+#define ISM_FUSED_AUTO 1 /* default                                                          */
+#define ISM_FUSED_WALK 2 /* the row walk always                                              */
+#define ISM_FUSED_TILE 3 /* the LDS-tiled form always                                        */
+
 #define ISM_F64 0 /* element type selector of the stage entry points: double */
 #define ISM_F32 1 /*                                                  float  */
 
@@ -125,8 +136,8 @@ typedef struct {
   int32_t max_outer;  /* cap on FP64 defect-correction steps                                */
   int32_t check_every;/* cycles between convergence checks; 0 = adaptive (predicts the
                          cycle that meets the target from the measured rate)               */
-  int32_t fused;      /* 1: one fused kernel per cycle (prolongation, nu sweeps, residual
-                         and restriction); 0: one kernel per step                          */
+  int32_t fused;      /* ISM_FUSED_*: one fused kernel per cycle (prolongation, nu sweeps,
+                         residual and restriction), or one kernel per step                 */
   int32_t stall_window; /* an inner solve also stops when its residual fell by less than   */
   double stall_drop;    /* stall_drop (a fraction) over the last >= stall_window cycles     */
   int32_t coarse_stencil; /* ISM_COARSE_ISM (default), ISM_COARSE_GMG5 or ISM_COARSE_ACM    */
@@ -155,7 +166,7 @@ typedef struct {
 } ism_stats;
 
 /* Fill cfg with defaults for an nx x ny grid of unit cell size 1/nx (unit square), Neumann
- * walls, coarsen 16, FP64, nu 4, rtol 1e-10, inner_rtol 1e-3, adaptive checks, fused,
+ * walls, coarsen 16, FP64, nu 4, rtol 1e-10, inner_rtol 1e-3, adaptive checks, ISM_FUSED_AUTO,
  * stall_window 8, stall_drop 0.02. */
 int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch);
 

@@ -32,6 +32,10 @@ ISM_COARSE_GMG5 = 1
 ISM_COARSE_ACM = 2
 ISM_CYCLE_REPEAT = 0
 ISM_CYCLE_ONESHOT = 1
+ISM_FUSED_OFF = 0
+ISM_FUSED_AUTO = 1
+ISM_FUSED_WALK = 2
+ISM_FUSED_TILE = 3
 ISM_F64 = 0
 ISM_F32 = 1
 KERNEL_CLASSES = {"cycle": 0, "smooth": 1, "restrict": 2, "prolong": 3, "coarse": 4, "outer": 5}

@@ -183,7 +183,8 @@ int validate(const ism_config* cfg, std::string& why) {
     return why = "inner_rtol must lie in (0, 1)", ISM_ERR_INVALID;
   if (cfg->max_cycles < 1 || cfg->max_outer < 1 || cfg->check_every < 0)
     return why = "max_cycles and max_outer must be >= 1, check_every >= 0", ISM_ERR_INVALID;
-  if (cfg->fused != 0 && cfg->fused != 1) return why = "fused must be 0 or 1", ISM_ERR_INVALID;
+  if (cfg->fused < ISM_FUSED_OFF || cfg->fused > ISM_FUSED_TILE)
+    return why = "fused must be one of the ISM_FUSED_* values", ISM_ERR_INVALID;
   if (cfg->coarse_stencil != ISM_COARSE_ISM && cfg->coarse_stencil != ISM_COARSE_GMG5 &&
       cfg->coarse_stencil != ISM_COARSE_ACM)
     return why = "coarse_stencil must be ISM_COARSE_ISM, ISM_COARSE_GMG5 or ISM_COARSE_ACM", ISM_ERR_INVALID;
@@ -241,11 +242,38 @@ int coarse_solve(ism_ctx* c, const double* rc, double* E) {
   const int nx = g.ncx, ny = g.ncy, B = g.batch;
   const long long cp = g.cplane;
   hipStream_t s = c->stream;
+  if (ism::coarse_small_fits(g)) {
+    LAUNCH(c, ism::launch_coarse_small(g, rc, c->Fx, c->Fy, c->Vx, c->Vy, c->invLam, E, s));
+    return ISM_OK;
+  }
   LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, rc, cp, nx, 0, c->Fx, 0, nx, c->t1, cp, nx, nullptr, B, s));
   LAUNCH(c, ism::launch_gemm(ny, nx, ny, 1, c->Fy, 0, ny, 0, c->t1, cp, nx, c->t2, cp, nx, c->invLam, B, s));
   LAUNCH(c, ism::launch_gemm(ny, nx, ny, 0, c->Vy, 0, ny, 0, c->t2, cp, nx, c->t1, cp, nx, nullptr, B, s));
   LAUNCH(c, ism::launch_gemm(ny, nx, nx, 0, c->t1, cp, nx, 1, c->Vx, 0, nx, E, cp, nx, nullptr, B, s));
   return ISM_OK;
+}
+
+// Which fused kernel a cycle takes (ISM_FUSED_AUTO): the LDS-tiled one up to kTileCells cells
+// per launch, where the row walk has too few waves to hide its per-row latency, else the
+// walk.  Measured on MI355X (FP64, nu = 4, 16h, whole solves per cycle): 256^2 27 us tiled
+// against 62 us walked, 1024^2 62 against 76, 2048^2 190 against 85.
+constexpr double kTileCells = 1280.0 * 1280.0;
+
+bool tile_cycle(const ism_ctx* c) {
+  if (c->cfg.fused == ISM_FUSED_TILE) return true;
+  if (c->cfg.fused == ISM_FUSED_WALK) return false;
+  return double(c->g.plane) * c->g.batch <= kTileCells;
+}
+
+template <typename T>
+hipError_t launch_fused(ism_ctx* c, const T* rhs, const T* ein, T* eout, const double* E,
+                        double* rc, double* psq, int nu, int zero_e, const double* stop = nullptr,
+                        int maxmode = 0) {
+  if (tile_cycle(c))
+    return ism::launch_cycle_tile<T>(c->g, rhs, ein, eout, E, rc, psq, nu, zero_e, c->stream, stop,
+                                     maxmode);
+  return ism::launch_cycle_fused<T>(c->g, rhs, ein, eout, E, rc, psq, nu, zero_e, c->stream, stop,
+                                    maxmode);
 }
 
 int read_scalars(ism_ctx* c) {
@@ -284,7 +312,7 @@ int run_cycle(ism_ctx* c, const T* rhs, T** cur, T** spare, double* rc, double* 
   prof_stop(c, ISM_KERNEL_COARSE, ev);
   if (c->cfg.fused) {
     ev = prof_start(c, ISM_KERNEL_CYCLE);
-    LAUNCH(c, ism::launch_cycle_fused<T>(g, rhs, *cur, *spare, c->E, rc, psq, c->cfg.nu, zero_e, s));
+    LAUNCH(c, launch_fused<T>(c, rhs, *cur, *spare, c->E, rc, psq, c->cfg.nu, zero_e));
     prof_stop(c, ISM_KERNEL_CYCLE, ev);
     std::swap(*cur, *spare);
     return ISM_OK;
@@ -715,8 +743,8 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
       LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
     } else {
       hipEvent_t ev = prof_start(c, ISM_KERNEL_CYCLE);
-      LAUNCH(c, ism::launch_cycle_fused<T>(g, rhs, buf[(i - 1) & 1], buf[i & 1], zeroE, c->rc,
-                                           c->p_max, 1, 0, s, stop, 1));
+      LAUNCH(c, launch_fused<T>(c, rhs, buf[(i - 1) & 1], buf[i & 1], zeroE, c->rc, c->p_max, 1, 0,
+                                stop, 1));
       prof_stop(c, ISM_KERNEL_CYCLE, ev);
       LAUNCH(c, ism::launch_finalize(c->p_max, int(g.cplane), g.cplane, B, ism::MAX, 1.0, m, 1, 0,
                                      c->fin, s));

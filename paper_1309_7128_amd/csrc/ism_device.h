@@ -231,5 +231,36 @@ __host__ __device__ inline AxisMode axis_mode(int nc, bool per, bool dlo, bool d
 // (one linear step of it here).
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a * (1.0 - t) + b * t; }
 
+// (P E) at fine cell (i, j) of the grid (Eq. 5), from the grid's coarse values Eb: the x step
+// on the two coarse rows in FP64, rounded to T, the y step in T.  A ghost centre behind a wall
+// takes the mirrored value (negated behind a Dirichlet wall); the signs multiply exactly, so
+// negating a corner value commutes with the rounding.
+template <typename T>
+__device__ __forceinline__ T prolong_at(const Geo& g, const double* __restrict__ Eb, int i, int j) {
+  int ilo, jlo;
+  double X, Y;
+  interp_axis(i, g.nx, g.n, g.log2n, g.ncx, g.per_x, ilo, X);
+  interp_axis(j, g.ny, g.n, g.log2n, g.ncy, g.per_y, jlo, Y);
+  int ihi = ilo + 1, jhi = jlo + 1;
+  double sil = 1.0, sih = 1.0, sjl = 1.0, sjh = 1.0;
+  if (g.per_x) {
+    ilo = imod(ilo, g.ncx);
+    ihi = imod(ihi, g.ncx);
+  } else {
+    sil = ghost_clamp(ilo, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
+    sih = ghost_clamp(ihi, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
+  }
+  if (g.per_y) {
+    jlo = imod(jlo, g.ncy);
+    jhi = imod(jhi, g.ncy);
+  } else {
+    sjl = ghost_clamp(jlo, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
+    sjh = ghost_clamp(jhi, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
+  }
+  const T lo = T(lerp(sjl * sil * Eb[jlo * g.ncx + ilo], sjl * sih * Eb[jlo * g.ncx + ihi], X));
+  const T hi = T(lerp(sjh * sil * Eb[jhi * g.ncx + ilo], sjh * sih * Eb[jhi * g.ncx + ihi], X));
+  return lo * T(1.0 - Y) + hi * T(Y);
+}
+
 }  // namespace
 }  // namespace ism

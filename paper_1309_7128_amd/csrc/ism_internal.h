@@ -87,6 +87,22 @@ int fused_max_nu<float>();
 template <>
 int fused_max_nu<double>();
 
+// The fused cycle of launch_cycle_fused (same arguments and results, 1 <= nu <=
+// fused_max_nu<T>()), tiled in LDS: for grids too small for the row walk to hide its latency.
+// 32 x 32 cells per workgroup with a halo of 2 nu + 1.
+constexpr int kTile = 32;
+template <typename T>
+hipError_t launch_cycle_tile(const Geo& g, const T* rhs, const T* e_in, T* e_out, const double* E,
+                             double* rc, double* part_sumsq, int nu, int zero_e, hipStream_t s,
+                             const double* stop = nullptr, int maxmode = 0);
+
+// The exact coarse solve in one workgroup per grid, for coarse grids of at most 32 cells per
+// axis (coarse_small_fits); the same tables and result as the four products of k_gemm.
+int coarse_small_fits(const Geo& g);
+hipError_t launch_coarse_small(const Geo& g, const double* R, const double* Fx, const double* Fy,
+                               const double* Vx, const double* Vy, const double* invLam,
+                               double* E, hipStream_t s);
+
 template <typename T>
 hipError_t launch_outer_residual(const Geo& g, const double* b, const double* x,
                                  const double* mean_b, double h2, T* rT, double* rc,

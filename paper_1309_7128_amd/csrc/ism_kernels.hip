@@ -179,34 +179,158 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
   const int i = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
   const int j = blockIdx.y * 4 + threadIdx.x / kWave;
   if (i >= g.nx || j >= g.ny) return;
-  const double* Eb = E + (long long)blockIdx.z * g.cplane;
-  int ilo, jlo;
-  double X, Y;
-  interp_axis(i, g.nx, g.n, g.log2n, g.ncx, g.per_x, ilo, X);
-  interp_axis(j, g.ny, g.n, g.log2n, g.ncy, g.per_y, jlo, Y);
-  int ihi = ilo + 1, jhi = jlo + 1;
-  double sil = 1.0, sih = 1.0, sjl = 1.0, sjh = 1.0;  // -1 at a ghost behind a Dirichlet wall
-  if (g.per_x) {
-    ilo = imod(ilo, g.ncx);
-    ihi = imod(ihi, g.ncx);
-  } else {
-    sil = ghost_clamp(ilo, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
-    sih = ghost_clamp(ihi, g.ncx, g.dmask & kDirW, g.dmask & kDirE);
-  }
-  if (g.per_y) {
-    jlo = imod(jlo, g.ncy);
-    jhi = imod(jhi, g.ncy);
-  } else {
-    sjl = ghost_clamp(jlo, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
-    sjh = ghost_clamp(jhi, g.ncy, g.dmask & kDirS, g.dmask & kDirN);
-  }
-  // the signs multiply exactly, so negating a corner value commutes with the rounding; the
-  // x step on the coarse rows in FP64, rounded to T, the y step and the addition in T
-  const T lo = T(lerp(sjl * sil * Eb[jlo * g.ncx + ilo], sjl * sih * Eb[jlo * g.ncx + ihi], X));
-  const T hi = T(lerp(sjh * sil * Eb[jhi * g.ncx + ilo], sjh * sih * Eb[jhi * g.ncx + ihi], X));
-  const T p = lo * T(1.0 - Y) + hi * T(Y);
+  const T p = prolong_at<T>(g, E + (long long)blockIdx.z * g.cplane, i, j);
   T* ec = e + (long long)blockIdx.z * g.plane + (long long)j * g.nx + i;
   *ec = assign ? p : T(*ec + p);
+}
+
+// ----------------------------------------------------------------------------------------
+// Fused cycle for small grids, tiled in LDS.  A workgroup stages a kTile x kTile block of e
+// (with the coarse correction of Eq. 5 added) and of rhs, with a halo of H = 2 nu + 1 cells,
+// and runs the 2 nu half-steps of nu red-black sweeps on it in LDS: each half-step leaves one
+// more ring of the halo stale, so the block and the ring around it are exact after the last.
+// Then it forms the residual of the block, sums it over the n x n coarse tiles in a fixed
+// tree order and writes the block.  Every cell is set by the expressions of k_rbgs, so the
+// result is that of nu whole-grid sweeps bit for bit.  It serves grids whose row walk (the
+// other fused kernel) has too few waves to hide its per-row latency: a block's staging, 2 nu
+// barriers and its reduction take a few microseconds, against the walk's tens.
+// ----------------------------------------------------------------------------------------
+template <typename T, int NU>
+__global__ __launch_bounds__(kBlock) void k_cycle_tile(Geo g, const T* __restrict__ rhs,
+                                                       const T* __restrict__ ein,
+                                                       T* __restrict__ eout,
+                                                       const double* __restrict__ E,
+                                                       double* __restrict__ rc,
+                                                       double* __restrict__ psq, int zero_e,
+                                                       const double* __restrict__ stop,
+                                                       int maxmode) {
+  constexpr int H = 2 * NU + 1, W = kTile + 2 * H, WI = W - 2, HW = WI / 2;
+  static_assert(W % 2 == 0, "even staged width");
+  __shared__ T se[W * W], sr[W * W], si[W * W];  // e, rhs, 1 / diagonal (0 behind a wall)
+  __shared__ double p1[kBlock], p2[kBlock];       // per-thread partial sums, squares / maxima
+  if (stop && *stop != 0.0) return;  // enqueued past a device-side stop
+  const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+  const long long off = (long long)blockIdx.z * g.plane;
+  const double* Eb = E + (long long)blockIdx.z * g.cplane;
+  // stage: e (+)= P E, rhs and the inverse diagonal; cells behind a wall hold 0 throughout
+  for (int t = threadIdx.x; t < W * W; t += kBlock) {
+    const int ly = t / W, lx = t - ly * W;
+    int i = x0 + lx - H, j = y0 + ly - H;
+    T ev = T(0), rv = T(0), iv = T(0);
+    if (map_cell(g, i, j)) {
+      const long long a = off + (long long)j * g.nx + i;
+      rv = rhs[a];
+      const T p = prolong_at<T>(g, Eb, i, j);
+      ev = zero_e ? p : T(ein[a] + p);
+      iv = inv_count<T>(g, i, j);
+    }
+    se[t] = ev;
+    sr[t] = rv;
+    si[t] = iv;
+  }
+  __syncthreads();
+  // half-step k (red first) on the cells of its colour with four staged neighbours; x0 and
+  // y0 are even, so a cell's colour is the parity of its staged coordinates
+#pragma unroll 1
+  for (int k = 0; k < 2 * NU; ++k) {
+    for (int t = threadIdx.x; t < WI * HW; t += kBlock) {
+      const int ly = 1 + t / HW;
+      const int lx = 1 + 2 * (t - (ly - 1) * HW) + ((k + ly + 1) & 1);
+      const int idx = ly * W + lx;
+      const T sum = (se[idx - 1] + se[idx + 1]) + (se[idx - W] + se[idx + W]);
+      se[idx] = (sum - sr[idx]) * si[idx];
+    }
+    __syncthreads();
+  }
+  // the block's residual and write-back: thread t takes row t / 8 and four cells of it, which
+  // lie in one coarse tile (n >= 4)
+  const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
+  const int j = y0 + r;
+  double acc = 0.0, acc2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = x0 + c0 + q;
+    if (i >= g.nx || j >= g.ny) continue;
+    const int idx = (H + r) * W + H + c0 + q;
+    const double d = double(sr[idx] - lap5<T>(se[idx], se[idx - 1], se[idx + 1], se[idx - W],
+                                              se[idx + W], cell_faces(g, i, j)));
+    acc += d;
+    acc2 = maxmode ? fmax(acc2, fabs(d)) : acc2 + d * d;
+    eout[off + (long long)j * g.nx + i] = se[idx];
+  }
+  // per coarse tile: its n rows x n/4 threads reduce pairwise, in a fixed order
+  const int n = g.n, per = (n * n) >> 2;
+  const int tile = (r >> g.log2n) * (kTile >> g.log2n) + (c0 >> g.log2n);
+  const int k = (r & (n - 1)) * (n >> 2) + ((c0 & (n - 1)) >> 2);
+  p1[tile * per + k] = acc;
+  p2[tile * per + k] = acc2;
+  __syncthreads();
+  for (int st = per >> 1; st > 0; st >>= 1) {
+    if (k < st) {
+      p1[tile * per + k] += p1[tile * per + k + st];
+      p2[tile * per + k] = maxmode ? fmax(p2[tile * per + k], p2[tile * per + k + st])
+                                   : p2[tile * per + k] + p2[tile * per + k + st];
+    }
+    __syncthreads();
+  }
+  if (k == 0) {
+    const int I = (x0 + c0) >> g.log2n, J = j >> g.log2n;
+    if (I < g.ncx && J < g.ncy) {
+      const long long o = (long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I;
+      rc[o] = p1[tile * per];
+      if (psq) psq[o] = p2[tile * per];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// The exact coarse solve of a small coarse grid (at most kSmallCoarse cells per axis) in one
+// workgroup per grid: E = V_y ((F_y^T R_c F_x) .* Lambda^-1) V_x^T as four products through
+// LDS, each output entry one FP64 dot product in index order.  One launch instead of four.
+// ----------------------------------------------------------------------------------------
+constexpr int kSmallCoarse = 32;
+
+__global__ __launch_bounds__(kBlock) void k_coarse_small(int ncx, int ncy, long long cplane,
+                                                         const double* __restrict__ R,
+                                                         const double* __restrict__ Fx,
+                                                         const double* __restrict__ Fy,
+                                                         const double* __restrict__ Vx,
+                                                         const double* __restrict__ Vy,
+                                                         const double* __restrict__ invLam,
+                                                         double* __restrict__ E) {
+  __shared__ double A[kSmallCoarse * kSmallCoarse], B[kSmallCoarse * kSmallCoarse];
+  const double* Rb = R + (long long)blockIdx.x * cplane;
+  double* Eb = E + (long long)blockIdx.x * cplane;
+  const int N = ncx * ncy;
+  for (int t = threadIdx.x; t < N; t += kBlock) A[t] = Rb[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < N; t += kBlock) {  // T1 = R_c F_x
+    const int J = t / ncx, k = t - J * ncx;
+    double acc = 0.0;
+    for (int I = 0; I < ncx; ++I) acc = fma(A[J * ncx + I], Fx[I * ncx + k], acc);
+    B[t] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < N; t += kBlock) {  // T2 = (F_y^T T1) .* Lambda^-1
+    const int l = t / ncx, k = t - l * ncx;
+    double acc = 0.0;
+    for (int J = 0; J < ncy; ++J) acc = fma(Fy[J * ncy + l], B[J * ncx + k], acc);
+    A[t] = acc * invLam[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < N; t += kBlock) {  // T3 = V_y T2
+    const int J = t / ncx, k = t - J * ncx;
+    double acc = 0.0;
+    for (int l = 0; l < ncy; ++l) acc = fma(Vy[J * ncy + l], A[l * ncx + k], acc);
+    B[t] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < N; t += kBlock) {  // E = T3 V_x^T
+    const int J = t / ncx, I = t - J * ncx;
+    double acc = 0.0;
+    for (int k = 0; k < ncx; ++k) acc = fma(B[J * ncx + k], Vx[I * ncx + k], acc);
+    Eb[t] = acc;
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1185,6 +1309,42 @@ hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, 
   return hipGetLastError();
 }
 
+template <typename T, int NU>
+hipError_t cycle_tile_nu(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                         double* rc, double* psq, int nu, int zero_e, hipStream_t s,
+                         const double* stop, int maxmode) {
+  if constexpr (NU == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (nu != NU)
+      return cycle_tile_nu<T, NU - 1>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s, stop, maxmode);
+    dim3 grid((g.nx + kTile - 1) / kTile, (g.ny + kTile - 1) / kTile, g.batch);
+    hipLaunchKernelGGL((k_cycle_tile<T, NU>), grid, dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc, psq,
+                       zero_e, stop, maxmode);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_cycle_tile(const Geo& g, const T* rhs, const T* ein, T* eout, const double* E,
+                             double* rc, double* psq, int nu, int zero_e, hipStream_t s,
+                             const double* stop, int maxmode) {
+  if (g.n < 4 || g.n > kTile) return hipErrorInvalidValue;
+  return cycle_tile_nu<T, sizeof(T) == 4 ? 5 : 4>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s,
+                                                   stop, maxmode);
+}
+
+int coarse_small_fits(const Geo& g) { return g.ncx <= kSmallCoarse && g.ncy <= kSmallCoarse; }
+
+hipError_t launch_coarse_small(const Geo& g, const double* R, const double* Fx, const double* Fy,
+                               const double* Vx, const double* Vy, const double* invLam,
+                               double* E, hipStream_t s) {
+  if (!coarse_small_fits(g)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_small, dim3(g.batch), dim3(kBlock), 0, s, g.ncx, g.ncy, g.cplane, R,
+                     Fx, Fy, Vx, Vy, invLam, E);
+  return hipGetLastError();
+}
+
 hipError_t launch_stop_check(const double* m, int batch, double tol, int iter, double* state,
                              double* at, hipStream_t s) {
   hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(kWave), 0, s, m, batch, tol, iter, state, at);
@@ -1244,6 +1404,12 @@ hipError_t launch_grad_adjoint(const Geo& g, const double* gu, const double* gv,
   return hipGetLastError();
 }
 
+template hipError_t launch_cycle_tile<float>(const Geo&, const float*, const float*, float*,
+                                             const double*, double*, double*, int, int,
+                                             hipStream_t, const double*, int);
+template hipError_t launch_cycle_tile<double>(const Geo&, const double*, const double*, double*,
+                                              const double*, double*, double*, int, int,
+                                              hipStream_t, const double*, int);
 template hipError_t launch_rbgs<float>(const Geo&, const float*, const float*, float*, hipStream_t, float,
                                        double*, const double*);
 template hipError_t launch_rbgs<double>(const Geo&, const double*, const double*, double*, hipStream_t,

@@ -71,7 +71,13 @@ class Solver:
         cfg.max_cycles = max_cycles
         cfg.max_outer = max_outer
         cfg.check_every = check_every
-        cfg.fused = int(bool(fused))
+        # fused: True (the kernel chosen by grid size), False (one kernel per step), or
+        # "walk" / "tile" to force one of the two fused kernels
+        fused_modes = {True: L.ISM_FUSED_AUTO, False: L.ISM_FUSED_OFF, "auto": L.ISM_FUSED_AUTO,
+                       "walk": L.ISM_FUSED_WALK, "tile": L.ISM_FUSED_TILE}
+        if fused not in fused_modes:
+            raise ValueError("fused must be True, False, 'auto', 'walk' or 'tile'")
+        cfg.fused = fused_modes[fused]
         if stall_window is not None:
             cfg.stall_window = stall_window
         if stall_drop is not None:

@@ -152,7 +152,7 @@ def test_coarse_solve(case):
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 @pytest.mark.parametrize("nu", [1, 2, 3, 4, 5])
-@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
+@pytest.mark.parametrize("fused", ["walk", "tile", False], ids=["walk", "tile", "unfused"])
 @pytest.mark.parametrize("tdt,ndt", DTYPES, ids=["f64", "f32"])
 def test_cycle_sweeps_bitwise(case, nu, fused, tdt, ndt):
     """A zero coarse right-hand side gives an exactly zero correction: the cycle is nu
@@ -176,7 +176,7 @@ def test_cycle_sweeps_bitwise(case, nu, fused, tdt, ndt):
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
-@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
+@pytest.mark.parametrize("fused", ["walk", "tile", False], ids=["walk", "tile", "unfused"])
 @pytest.mark.parametrize("tdt,ndt", DTYPES, ids=["f64", "f32"])
 @pytest.mark.parametrize("zero_e", [False, True], ids=["e", "zero_e"])
 def test_cycle_matches_oracle(case, fused, tdt, ndt, zero_e):
@@ -220,7 +220,7 @@ def test_fused_and_unfused_cycles_agree(case, tdt):
     e0 = rng.standard_normal((ny, nx))
     rc0 = rng.standard_normal((1, ncy, ncx))
     first, outs = [], []
-    for fused in (True, False):
+    for fused in ("walk", "tile", False):  # the two fused kernels and the unfused steps
         s = _mk(case, nu=3, fused=fused)
         e = dev(e0, tdt)
         rc = dev(rc0)
@@ -229,15 +229,16 @@ def test_fused_and_unfused_cycles_agree(case, tdt):
             if k == 0:
                 first.append(host(e))
         outs.append((host(e), host(rc)))
-    np.testing.assert_array_equal(first[0], first[1])
-    if tdt == torch.float32:
-        np.testing.assert_array_equal(outs[0][0], outs[1][0])
-        np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-12, atol=1e-14)
-    else:
-        np.testing.assert_allclose(outs[0][0], outs[1][0], rtol=0,
-                                   atol=1e-11 * np.abs(outs[1][0]).max())
-        np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=0,
-                                   atol=1e-10 * np.abs(outs[1][1]).max())
+    for k in (1, 2):
+        np.testing.assert_array_equal(first[0], first[k])
+        if tdt == torch.float32:
+            np.testing.assert_array_equal(outs[0][0], outs[k][0])
+            np.testing.assert_allclose(outs[0][1], outs[k][1], rtol=1e-12, atol=1e-14)
+        else:
+            np.testing.assert_allclose(outs[0][0], outs[k][0], rtol=0,
+                                       atol=1e-11 * np.abs(outs[k][0]).max())
+            np.testing.assert_allclose(outs[0][1], outs[k][1], rtol=0,
+                                       atol=1e-10 * np.abs(outs[k][1]).max())
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)

@@ -131,7 +131,7 @@ def test_coarse_solve(case):
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 @pytest.mark.parametrize("nu", [1, 2, 3, 4, 5])
-@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
+@pytest.mark.parametrize("fused", ["walk", "tile", False], ids=["walk", "tile", "unfused"])
 @pytest.mark.parametrize("tdt,ndt", DTYPES, ids=["f64", "f32"])
 def test_cycle_sweeps_bitwise(case, nu, fused, tdt, ndt):
     """With a zero coarse right-hand side the correction is exactly zero, so a cycle is nu
@@ -161,7 +161,7 @@ def test_cycle_sweeps_bitwise(case, nu, fused, tdt, ndt):
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
-@pytest.mark.parametrize("fused", [True, False], ids=["fused", "unfused"])
+@pytest.mark.parametrize("fused", ["walk", "tile", False], ids=["walk", "tile", "unfused"])
 @pytest.mark.parametrize("tdt,ndt", DTYPES, ids=["f64", "f32"])
 @pytest.mark.parametrize("zero_e", [False, True], ids=["e", "zero_e"])
 def test_cycle_matches_oracle(case, fused, tdt, ndt, zero_e):
@@ -199,15 +199,16 @@ def test_fused_and_unfused_cycles_agree_bitwise(case):
     e0 = rng.standard_normal((ny, nx))
     rc0 = rng.standard_normal((1, ny // n, nx // n))
     outs = []
-    for fused in (True, False):
+    for fused in ("walk", "tile", False):  # the two fused kernels and the unfused steps
         s = _mk(case, nu=3, fused=fused)
         e = dev(e0, torch.float32)
         rc = dev(rc0)
         for _ in range(3):
             s.cycle(rhs, e, rc)
         outs.append((host(e), host(rc)))
-    np.testing.assert_array_equal(outs[0][0], outs[1][0])
-    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-12, atol=1e-14)
+    for k in (1, 2):
+        np.testing.assert_array_equal(outs[0][0], outs[k][0])
+        np.testing.assert_allclose(outs[0][1], outs[k][1], rtol=1e-12, atol=1e-14)
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)

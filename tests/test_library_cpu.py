@@ -79,6 +79,8 @@ def _create(**kw):
     (dict(ly=2.0), L.ISM_ERR_UNSUPPORTED),                    # non-square cells
     (dict(nu=5, fused=1), L.ISM_ERR_UNSUPPORTED),              # FP64 fused kernel: nu <= 4
     (dict(nu=6, fused=1, precision=1), L.ISM_ERR_UNSUPPORTED), # FP32 fused kernel: nu <= 5
+    (dict(fused=4), L.ISM_ERR_INVALID),
+    (dict(fused=-1), L.ISM_ERR_INVALID),
     (dict(stall_window=0), L.ISM_ERR_INVALID),
     (dict(stall_drop=1.0), L.ISM_ERR_INVALID),
     (dict(coarse_stencil=3), L.ISM_ERR_INVALID),
