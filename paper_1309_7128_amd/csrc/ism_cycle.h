@@ -195,8 +195,11 @@ __device__ __forceinline__ void unpack_cells(const Vec4u (&v)[K], int c0, T (&ou
 // Kinds of walk.  PLAIN: every row and column the walk reads exists in the grid (possibly
 // wrapped), so every cell has four neighbours and diagonal 4.  ROWS: the rows may reach
 // past a wall in y (or off the grid); every column exists.  EDGE: the strip also reads
-// columns behind a wall in x, handled lane by lane.
-enum WalkKind { kPlain = 0, kRows = 1, kEdge = 2 };
+// columns behind a wall in x, handled lane by lane.  The *_TAB kinds are ROWS and EDGE on a
+// grid that the tile size does not divide, which read the interpolation tables; keeping
+// them apart keeps the walks that other grids run compact (their code shares the
+// instruction cache with the plain walks).
+enum WalkKind { kPlain = 0, kRows = 1, kEdge = 2, kRowsTab = 3, kEdgeTab = 4 };
 
 // One wave's walk along its strip: output rows y0 .. y0 + min(L, ny - y0) - 1 of the strip
 // whose first read column is xs, walking up (rows ys = y0 - H .. y0 + L + H - 1) or, with
@@ -224,7 +227,8 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
                                            const double2* __restrict__ taby, int maxmode) {
   using S = Stream<T, NU, LOG2N>;
   using V16 = typename Vec16<T>::type;
-  constexpr bool EDGE = KIND == kEdge, PLAIN = KIND == kPlain;
+  constexpr bool EDGE = KIND == kEdge || KIND == kEdgeTab, PLAIN = KIND == kPlain;
+  constexpr bool TAB = KIND == kRowsTab || KIND == kEdgeTab;
   constexpr int CPL = S::CPL, N = S::N, H = S::H, PX = S::PX, VW = S::VW, P = S::P;
   constexpr int G = N / CPL;  // lanes per coarse tile
   const int lane = threadIdx.x & (kWave - 1);
@@ -268,7 +272,7 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
   // weight, also for rows past a wall or a periodic seam.  On an axis with a short last tile
   // the walk reads the axis's table (entry .x the weight, .y the lower centre of the
   // wrapped or clamped row), the lower centre unwrapped again on a periodic axis.
-  const bool tab_y = !PLAIN && (g.ny & (N - 1)), tab_x = !PLAIN && (g.nx & (N - 1));
+  const bool tab_y = TAB && (g.ny & (N - 1)), tab_x = TAB && (g.nx & (N - 1));
   auto row_interp = [&](int t, int& lo, double& w) {
     if (!tab_y) {
       lo = (t - N / 2) >> LOG2N;
@@ -386,7 +390,7 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
         shift = k * g.ncx;
       }
       T* dt = reinterpret_cast<T*>(d);
-#pragma unroll
+#pragma unroll 1
       for (int p = 0; p < CPL; ++p) {
         const double2 e = tabx[g.per_x ? cb + p : min(max(cb + p, 0), g.nx - 1)];
         const int lo = int(e.y) + shift;
@@ -469,9 +473,10 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
             }
           }
           // the y step of Eq. 5 in T (weights from FP64, dyadic and exact unless the row lies
-          // next to a short last tile; exact in T in a plain walk, so 1 - Y is too)
+          // next to a short last tile, which only the table walks read; exact in T otherwise,
+          // so 1 - Y is too)
           T Y, Y1;
-          if constexpr (PLAIN) {
+          if constexpr (!TAB) {
             Y = T(Yd);
             Y1 = T(1) - Y;
           } else {
@@ -578,10 +583,10 @@ __device__ __forceinline__ void cycle_walk(const Geo& g, const T* __restrict__ r
           }
           if (lane_out) store_cells(ob + (long long)o * g.nx + cu, e[so]);
           // a tile's last row in walk order (walking up, the last row of the grid also ends a
-          // short last tile, which a plain walk never reaches)
-          if (((o - y0) & (N - 1)) == (down ? 0 : N - 1) || (!PLAIN && !down && o == g.ny - 1)) {
-            // a plain walk's lane groups lie wholly inside or wholly outside the grid
-            double a = PLAIN || lane_sum ? acc : 0.0, q = PLAIN || lane_sum ? acc2 : 0.0;
+          // short last tile, which only the table walks reach)
+          if (((o - y0) & (N - 1)) == (down ? 0 : N - 1) || (TAB && !down && o == g.ny - 1)) {
+            // with full tiles a lane group lies wholly inside or wholly outside the grid
+            double a = !TAB || lane_sum ? acc : 0.0, q = !TAB || lane_sum ? acc2 : 0.0;
 #pragma unroll
             for (int k = 1; k < G; k <<= 1) a += __shfl_down(a, k, kWave);
             if (psq) {
@@ -646,9 +651,15 @@ void k_cycle(Geo g, const T* __restrict__ rhs, const T* __restrict__ ein, T* __r
     const int chunk = u / nstrip_e, sl = u - chunk * nstrip_e;
     const int strip = sl == 0 ? 0 : efirst + sl;
     const int b0 = chunk * nb / Ce, b1 = (chunk + 1) * nb / Ce;
-    cycle_walk<T, NU, LOG2N, kEdge>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
-                                    sE[w], sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
-                                    b0 * S::N, (b1 - b0) * S::N, chunk & 1, tabx, taby, maxmode);
+    if ((g.nx | g.ny) & (S::N - 1))
+      cycle_walk<T, NU, LOG2N, kEdgeTab>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
+                                         sE[w], sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
+                                         b0 * S::N, (b1 - b0) * S::N, chunk & 1, tabx, taby,
+                                         maxmode);
+    else
+      cycle_walk<T, NU, LOG2N, kEdge>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
+                                      sE[w], sX[w], sR[w], coff, zero_e, strip * S::VW - S::PX,
+                                      b0 * S::N, (b1 - b0) * S::N, chunk & 1, tabx, taby, maxmode);
     return;
   }
   int bi = b - nblk_e;
@@ -672,6 +683,10 @@ void k_cycle(Geo g, const T* __restrict__ rhs, const T* __restrict__ ein, T* __r
     cycle_walk<T, NU, LOG2N, kPlain>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
                                      sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
                                      taby, maxmode);
+  else if (pad_x || pad_y)
+    cycle_walk<T, NU, LOG2N, kRowsTab>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
+                                       sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
+                                       taby, maxmode);
   else
     cycle_walk<T, NU, LOG2N, kRows>(g, rhs + off, ein + off, eout + off, E + coff, rc, psq,
                                     sE[w], sX[w], sR[w], coff, zero_e, xs, y0, len, down, tabx,
