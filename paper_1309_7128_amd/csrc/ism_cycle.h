@@ -44,9 +44,11 @@ struct Stream {
   static constexpr int PX = stream_pad(H, N, CPL, LW);
   static constexpr int VW = LW - 2 * PX;  // valid columns per strip
   // rows read ahead, through a per-wave LDS ring of DL slots (16-byte chunks per lane of e
-  // and rhs in each)
+  // and rhs in each); 4 in FP32 at n = 16, where a fifth slot would leave room for only two
+  // workgroups per CU (the staged coarse block is larger there): 107 us against 119 us per
+  // launch on the 4096 x 8192 jet
   static constexpr int C16 = CPL * int(sizeof(T)) / 16;
-  static constexpr int DL = sizeof(T) == 4 ? 5 : 3;
+  static constexpr int DL = sizeof(T) == 4 ? (N == 16 ? 4 : 5) : 3;
   static constexpr int SLOT = 2 * C16 * kWave * 16;  // bytes per ring slot
   // register ring rows: 2 NU + 3 live, even (fixed row parity per slot)
   static constexpr int P = 2 * NU + 4;

@@ -129,6 +129,24 @@ def test_coarse_solve(case):
         assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(Rc[b])
 
 
+@pytest.mark.parametrize("case", [(1280, 1088, 16, N, D), (2560, 1600, 32, P, N)], ids=_ids)
+def test_coarse_solve_mfma_path(case):
+    """Coarse grids beyond 32 cells per axis (80 x 68, 80 x 50) take the four MFMA products
+    instead of the one-workgroup solve; the same parity bar."""
+    announce("coarse_solve_mfma", case)
+    nx, ny, n, bx, by = case
+    ncx, ncy = nx // n, ny // n
+    rng = np.random.default_rng(113)
+    Rc = rng.standard_normal((2, ncy, ncx))
+    s = _mk(case, batch=2)
+    E = host(s.coarse_solve(dev(Rc)))
+    Ac = O.coarse_matrix(O.coarse_stencil_ism(ncx, ncy, n, bx, by), bx, by)
+    cs = O.CoarseSolver(Ac)
+    for b in range(2):
+        ref = cs.solve(Rc[b])
+        np.testing.assert_allclose(E[b], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 @pytest.mark.parametrize("nu", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("fused", ["walk", "tile", False], ids=["walk", "tile", "unfused"])
