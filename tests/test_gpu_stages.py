@@ -129,10 +129,11 @@ def test_coarse_solve(case):
         assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(Rc[b])
 
 
-@pytest.mark.parametrize("case", [(1280, 1088, 16, N, D), (2560, 1600, 32, P, N)], ids=_ids)
+@pytest.mark.parametrize("case", [(1280, 1088, 16, N, D), (2560, 1600, 32, P, N),
+                                  (2304, 2112, 16, N, D), (4352, 1024, 32, P, DN)], ids=_ids)
 def test_coarse_solve_mfma_path(case):
-    """Coarse grids beyond 32 cells per axis (80 x 68, 80 x 50) take the four MFMA products
-    instead of the one-workgroup solve; the same parity bar."""
+    """Coarse grids beyond 32 cells per axis (80 x 68, 80 x 50, 144 x 132, 136 x 32) take the
+    four MFMA products instead of the one-workgroup solve; the same parity bar."""
     announce("coarse_solve_mfma", case)
     nx, ny, n, bx, by = case
     ncx, ncy = nx // n, ny // n
