@@ -11,6 +11,8 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse
+import scipy.sparse.linalg
 
 from oracle import ism_oracle as O
 
@@ -588,6 +590,99 @@ def test_block_gauss_seidel_converges_to_exact(bcx, bcy):
     np.testing.assert_allclose(got, ref, atol=1e-8 * np.abs(ref).max())
 
 
+def _mcgs_loop(C, R, iters, bcx, bcy):
+    """Multicolour GS written cell by cell: the cells one after another, colour by colour
+    (lexicographic inside a colour), each set from its own equation with the newest value
+    of every neighbour.  This equals the colour-parallel form only if no two cells of one
+    colour are coupled."""
+    ncy, ncx = R.shape
+    qx, Qx = O.axis_colours(ncx, bcx)
+    qy, _ = O.axis_colours(ncy, bcy)
+    cells = sorted(((qy[J] * Qx + qx[I], J, I) for J in range(ncy) for I in range(ncx)))
+    order = [(dj, di) for dj in (-1, 0, 1) for di in (-1, 0, 1) if (dj, di) != (0, 0)]
+    E = np.zeros((ncy, ncx))
+    for _ in range(iters):
+        for _, J, I in cells:
+            s = 0.0
+            for dj, di in order:
+                jj, ii = J + dj, I + di
+                if bcx == P:
+                    ii %= ncx
+                if bcy == P:
+                    jj %= ncy
+                if not (0 <= jj < ncy and 0 <= ii < ncx):
+                    continue
+                s = s + C[J, I, dj + 1, di + 1] * E[jj, ii]
+            E[J, I] = (R[J, I] - s) / C[J, I, 1, 1]
+    return E
+
+
+# (ncx, ncy, bc_x, bc_y, colours): even and odd axes, walled and periodic; an odd periodic
+# axis takes a third colour
+MC_CASES = [(7, 6, N, N, 4), (6, 6, P, P, 4), (7, 6, P, D, 6), (6, 5, ND, P, 6),
+            (5, 7, P, P, 9), (2, 3, P, P, 6), (9, 4, DN, ND, 4)]
+
+
+@pytest.mark.parametrize("ncx,ncy,bcx,bcy,colours", MC_CASES)
+def test_multicolour_colouring_separates_coupled_cells(ncx, ncy, bcx, bcy, colours):
+    # Sec. 3.1: multicolour ordering lets a wider stencil be iterated concurrently, which
+    # needs every coupling of the assembled 9-point matrix to join cells of different
+    # colours; a 2 x 2 block is fully coupled, so no ordering does with fewer than 4
+    qx, Qx = O.axis_colours(ncx, bcx)
+    qy, Qy = O.axis_colours(ncy, bcy)
+    assert Qx * Qy == colours
+    colour = (qy[:, None] * Qx + qx[None, :]).ravel()
+    A = O.coarse_matrix(O.coarse_stencil_ism(ncx, ncy, 8, bcx, bcy), bcx, bcy).tocoo()
+    off = A.row != A.col
+    assert off.any()
+    assert np.all(colour[A.row[off]] != colour[A.col[off]])
+
+
+@pytest.mark.parametrize("ncx,ncy,bcx,bcy,colours", MC_CASES)
+def test_multicolour_gauss_seidel_matches_cell_loop(ncx, ncy, bcx, bcy, colours):
+    C = O.coarse_stencil_ism(ncx, ncy, 8, bcx, bcy)
+    R = np.random.default_rng(35).standard_normal((ncy, ncx))
+    Rp = R - R.mean() if O.singular(bcx, bcy) else R
+    E, it, q = O.multicolour_gauss_seidel(C, R, 0.0, bcx, bcy, max_iter=3)
+    assert it == 3 and q == colours
+    np.testing.assert_array_equal(E, _mcgs_loop(C, Rp, 3, bcx, bcy))
+
+
+@pytest.mark.parametrize("ncx,ncy,bcx,bcy,colours", MC_CASES)
+def test_multicolour_gauss_seidel_is_gs_in_colour_order(ncx, ncy, bcx, bcy, colours):
+    # one iteration is lexicographic GS on the system permuted to colour order: forward
+    # substitution with the permuted matrix's lower triangle (a library routine)
+    C = O.coarse_stencil_ism(ncx, ncy, 8, bcx, bcy)
+    R = np.random.default_rng(36).standard_normal((ncy, ncx))
+    Rp = (R - R.mean() if O.singular(bcx, bcy) else R).ravel()
+    qx, Qx = O.axis_colours(ncx, bcx)
+    qy, _ = O.axis_colours(ncy, bcy)
+    perm = np.argsort((qy[:, None] * Qx + qx[None, :]).ravel(), kind="stable")
+    A = O.coarse_matrix(C, bcx, bcy).tocsr()[perm][:, perm]
+    L = scipy.sparse.tril(A, format="csr")
+    U = A - L
+    Ep = np.zeros(ncx * ncy)
+    for k in range(1, 4):
+        Ep = scipy.sparse.linalg.spsolve_triangular(L, Rp[perm] - U @ Ep, lower=True)
+        E, it, _ = O.multicolour_gauss_seidel(C, R, 0.0, bcx, bcy, max_iter=k)
+        ref = np.empty_like(Ep)
+        ref[perm] = Ep
+        np.testing.assert_allclose(E.ravel(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, D), (P, P)])
+def test_multicolour_gauss_seidel_converges_to_exact(bcx, bcy):
+    C = O.coarse_stencil_ism(11, 10, 8, bcx, bcy)
+    R = np.random.default_rng(37).standard_normal((10, 11))
+    E, it, _ = O.multicolour_gauss_seidel(C, R, 1e-10, bcx, bcy)
+    cs = O.CoarseSolver(O.coarse_matrix(C, bcx, bcy))
+    ref = cs.solve(R)
+    got = E - E.mean() if cs.singular else E
+    np.testing.assert_allclose(got, ref, atol=1e-8 * np.abs(ref).max())
+    Rp = R - R.mean() if cs.singular else R
+    assert np.abs(Rp - (cs.Ac @ E.ravel()).reshape(R.shape)).max() < 1e-10
+
+
 @pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND)])
 def test_oneshot_accommodative_solve(bcx, bcy):
     # Sec. 4.3.1: one coarse visit to tol_c, then fine red-black iterations until the
@@ -606,6 +701,30 @@ def test_oneshot_accommodative_solve(bcx, bcy):
         assert info["ncc_f"] == 2 * info["fine_iters"] and info["ncc_c"] == info["coarse_iters"]
     assert info_t["coarse_iters"] > info_l["coarse_iters"]
     assert info_t["fine_iters"] <= info_l["fine_iters"]
+
+
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND)])
+def test_oneshot_multicolour_coarse_stage(bcx, bcy):
+    # the same cycling with multicolour GS on the coarse grid: the criteria hold, each
+    # iteration costs one synchronization per colour (Sec. 4.3), and with tol_c -> 0 both
+    # coarse iterations reach the exact coarse correction, so the fine stages agree
+    nf, n = 64, 8
+    h = 1.0 / nf
+    b = O.div(*[np.random.default_rng(38).standard_normal(s) for s in
+                (((nf, nf) if bcx == P else (nf, nf + 1)), (nf + 1, nf))], h, bcx)
+    tol_f = 1e-6 * np.abs(b).max()
+    x, info = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-2, tol_f=tol_f,
+                                  coarse_gs="multicolour")
+    bt = b - b.mean() if O.singular(bcx, bcy) else b
+    assert np.abs(bt - O.laplacian(x, bcx, bcy) / h**2).max() < tol_f
+    assert info["ncc_c"] == 4 * info["coarse_iters"] and info["ncc_f"] == 2 * info["fine_iters"]
+    xm, im = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-11, tol_f=tol_f,
+                                 coarse_gs="multicolour")
+    xb, ib = O.ism_solve_oneshot(b, h, n, bcx, bcy, tol_c=1e-11, tol_f=tol_f)
+    assert im["fine_iters"] == ib["fine_iters"]
+    np.testing.assert_allclose(xm, xb, rtol=0, atol=1e-8 * np.abs(xb).max())
+    with pytest.raises(ValueError):
+        O.ism_solve_oneshot(b, h, n, bcx, bcy, coarse_gs="jacobi")
 
 
 @pytest.mark.parametrize("bcx,bcy", [(N, N), (P, ND), (D, D)])
