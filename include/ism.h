@@ -77,8 +77,9 @@ extern "C" {
 /* Cycling (Sec. 4.3.1).  REPEAT: {restrict, exact coarse solve, prolongate, nu sweeps} until
  * rtol, as described for ism_solve.  ONESHOT: the paper's simplest accommodative cycling,
  * once per solve: restrict the residual, iterate the coarse grid by block Gauss-Seidel
- * (Sec. 4; tiles of 16 x 16 coarse cells, aligned at cell 0, updated concurrently and
- * lexicographic inside; a periodic axis of at most 16 coarse cells is cut into two tiles of
+ * (Sec. 4; or multicolour Gauss-Seidel, see ism_config.coarse_gs; block GS takes tiles of
+ * 16 x 16 coarse cells, aligned at cell 0, updated concurrently and lexicographic inside;
+ * a periodic axis of at most 16 coarse cells is cut into two tiles of
  * ceil(nc / 2), so that no tile spans a whole periodic axis and a neighbour reached across a
  * periodic seam always belongs to another tile) until its absolute maximum residual is below
  * coarse_tol, prolongate and add, then iterate
@@ -96,6 +97,20 @@ extern "C" {
  * all of them meet a criterion. */
 #define ISM_CYCLE_REPEAT 0
 #define ISM_CYCLE_ONESHOT 1
+
+/* The coarse iteration of ISM_CYCLE_ONESHOT and ism_coarse_gs (ism_config.coarse_gs).
+ * BLOCK: block-iterative Gauss-Seidel as described above (Sec. 4; one synchronization per
+ * iteration).  MULTICOLOUR: Gauss-Seidel in multicolour order, the ordering Sec. 3.1 names
+ * for stencils wider than five points: along each axis cell i has colour i mod 2, except
+ * that the last cell of an odd periodic axis takes colour 2; cell (J, I) has colour
+ * qy(J) * Qx + qx(I) (4 colours; 6 or 9 with one or two odd periodic axes), so no two
+ * coupled cells share one.  An iteration sets the cells colour by colour in increasing
+ * order, all cells of a colour at once from the newest values, one synchronization per
+ * colour (Sec. 4.3).  Both iterations update a cell as E_C = (R_C - sum of c_nb E_nb) / c_C
+ * with the neighbours in the order (dj, di) = (-1,-1) .. (1,1) and summed left to right,
+ * and test max |R - A_c E| against the tolerance before each iteration. */
+#define ISM_COARSE_GS_BLOCK 0
+#define ISM_COARSE_GS_MULTICOLOUR 1
 
 /* The kernel a cycle takes (ism_config.fused).  Both fused kernels give the same e bit for
  * bit (that of nu whole-grid red-black sweeps) and the same tile sums up to their summation
@@ -146,6 +161,8 @@ typedef struct {
                              max |R (b~ - A x) - R A P E| < coarse_tol (default 1e-5)       */
   double fine_tol;        /* ISM_CYCLE_ONESHOT: the fine sweeps stop once
                              max |b~ - A x| < fine_tol (default 1e-6)                       */
+  int32_t coarse_gs;      /* ISM_COARSE_GS_BLOCK (default) or ISM_COARSE_GS_MULTICOLOUR: the
+                             coarse iteration of ISM_CYCLE_ONESHOT and ism_coarse_gs        */
 } ism_config;
 
 typedef struct {
@@ -159,15 +176,18 @@ typedef struct {
                           form) of the returned x (after its final mean removal)            */
   double rel_res_max;  /* max over the batch of max|b~ - A x| / max|b~|                     */
   double seconds;      /* wall time of the call                                              */
-  int32_t coarse_iters; /* ISM_CYCLE_ONESHOT: block Gauss-Seidel iterations on the coarse
-                           grid (I_c; one synchronization each, NCC_c = I_c, Sec. 4.3)      */
+  int32_t coarse_iters; /* ISM_CYCLE_ONESHOT: Gauss-Seidel iterations on the coarse grid
+                           (I_c; one synchronization each for block GS, NCC_c = I_c, one per
+                           colour for multicolour GS, Sec. 4.3)                            */
   int32_t fine_iters;   /* ISM_CYCLE_ONESHOT: red-black iterations on the fine grid (I_f;
                            two synchronizations each, NCC_f = 2 I_f)                       */
+  int32_t coarse_syncs; /* ISM_CYCLE_ONESHOT: synchronizations of the coarse stage, NCC_c:
+                           coarse_iters (block GS) or colours x coarse_iters (multicolour)  */
 } ism_stats;
 
 /* Fill cfg with defaults for an nx x ny grid of unit cell size 1/nx (unit square), Neumann
  * walls, coarsen 16, FP64, nu 4, rtol 1e-10, inner_rtol 1e-3, adaptive checks, ISM_FUSED_AUTO,
- * stall_window 8, stall_drop 0.02. */
+ * stall_window 8, stall_drop 0.02, block coarse Gauss-Seidel. */
 int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch);
 
 /* Validate cfg, allocate the handle's device workspace and build the coarse tables
@@ -281,8 +301,9 @@ int ism_coarse_solve(ism_handle h, const double* rc, double* E);
 int ism_cycle(ism_handle h, int32_t dtype, const void* rhs, void* e, double* rc,
               int32_t zero_e, double* sumsq);
 
-/* Block Gauss-Seidel on each grid's coarse system A_c E = rc (the handle's ISM or GMG5
- * stencil), as the ISM_CYCLE_ONESHOT coarse stage runs it (Sec. 4): from E = 0, one
+/* Gauss-Seidel on each grid's coarse system A_c E = rc (the handle's ISM or GMG5 stencil;
+ * block or multicolour by ism_config.coarse_gs), as the ISM_CYCLE_ONESHOT coarse stage runs
+ * it (Sec. 4, Sec. 3.1): from E = 0, one
  * iteration at a time, until max |rc - A_c E| < tol (in the units of rc) on every grid or
  * max_iter iterations.  Without a Dirichlet face rc is first projected to zero mean (the
  * compatibility condition of the singular system; rc itself is not modified).  rc, E: FP64

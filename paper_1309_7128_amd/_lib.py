@@ -32,6 +32,8 @@ ISM_COARSE_GMG5 = 1
 ISM_COARSE_ACM = 2
 ISM_CYCLE_REPEAT = 0
 ISM_CYCLE_ONESHOT = 1
+ISM_COARSE_GS_BLOCK = 0
+ISM_COARSE_GS_MULTICOLOUR = 1
 ISM_FUSED_OFF = 0
 ISM_FUSED_AUTO = 1
 ISM_FUSED_WALK = 2
@@ -53,6 +55,7 @@ class IsmConfig(ctypes.Structure):
         ("stall_window", ctypes.c_int32), ("stall_drop", ctypes.c_double),
         ("coarse_stencil", ctypes.c_int32), ("cycling", ctypes.c_int32),
         ("coarse_tol", ctypes.c_double), ("fine_tol", ctypes.c_double),
+        ("coarse_gs", ctypes.c_int32),
     ]
 
 
@@ -64,6 +67,7 @@ class IsmStats(ctypes.Structure):
         ("rel_res_l2", ctypes.c_double), ("rel_res_max", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("coarse_iters", ctypes.c_int32), ("fine_iters", ctypes.c_int32),
+        ("coarse_syncs", ctypes.c_int32),
     ]
 
     def as_dict(self):

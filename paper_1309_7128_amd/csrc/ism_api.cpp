@@ -199,6 +199,8 @@ int validate(const ism_config* cfg, std::string& why) {
     if (cfg->coarse_stencil == ISM_COARSE_ACM)
       return why = "one-shot cycling takes the ISM or GMG5 stencil", ISM_ERR_UNSUPPORTED;
   }
+  if (cfg->coarse_gs != ISM_COARSE_GS_BLOCK && cfg->coarse_gs != ISM_COARSE_GS_MULTICOLOUR)
+    return why = "coarse_gs must be ISM_COARSE_GS_BLOCK or ISM_COARSE_GS_MULTICOLOUR", ISM_ERR_INVALID;
   if (cfg->stall_window < 1 || !(cfg->stall_drop >= 0.0) || !(cfg->stall_drop < 1.0))
     return why = "stall_window must be >= 1 and stall_drop in [0, 1)", ISM_ERR_INVALID;
   if (!is_pow2_coarsen(cfg->coarsen))
@@ -662,6 +664,45 @@ int coarse_block_gs(ism_ctx* c, const double* rc, double tol, int max_iter, doub
   return ISM_OK;
 }
 
+// Multicolour Gauss-Seidel (Sec. 3.1, Sec. 4.3) on every grid's A_c E = rc from E = 0, with
+// the same loop, buffers and stopping rule as coarse_block_gs: iteration it forms the
+// residual of E_it (in t1 for even it, t2 for odd) and E_it+1, one launch per colour.
+int coarse_mc_gs(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
+                 int* iters, bool* converged) {
+  const Geo& g = c->g;
+  const int B = g.batch, tiles = ism::coarse_mc_tiles(g);
+  hipStream_t s = c->stream;
+  double* E[2] = {c->t1, c->t2};
+  LAUNCH(c, ism::launch_fill(E[0], (long long)g.cplane * B, 0.0, s));
+  double* m = c->scal + size_t(CMAX) * B;
+  auto step = [&](int it, const double* stop) {
+    hipError_t err = hipSuccess;
+    c->launches += ism::launch_coarse_mc(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max, s,
+                                         stop, &err);
+    HIPCHK(c, err);
+    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
+    return ISM_OK;
+  };
+  int it = 0;
+  const int rcode = device_checked_loop(c, step, m, tol, max_iter, "coarse residual", &it, converged);
+  if (rcode) return rcode;
+  *E_out = E[it & 1];
+  *iters = it;
+  return ISM_OK;
+}
+
+// The coarse iteration the handle was created with (ism_config.coarse_gs); *syncs_per_iter:
+// its synchronizations per iteration (Sec. 4.3: one for block GS, one per colour).
+int coarse_gs_loop(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
+                   int* iters, bool* converged, int* syncs_per_iter) {
+  if (c->cfg.coarse_gs == ISM_COARSE_GS_MULTICOLOUR) {
+    *syncs_per_iter = ism::coarse_mc_colours(c->g);
+    return coarse_mc_gs(c, rc, tol, max_iter, E_out, iters, converged);
+  }
+  *syncs_per_iter = 1;
+  return coarse_block_gs(c, rc, tol, max_iter, E_out, iters, converged);
+}
+
 // rc -= its mean, per grid (the compatibility projection of a singular coarse system).
 int project_coarse(ism_ctx* c, double* rc) {
   const Geo& g = c->g;
@@ -672,8 +713,9 @@ int project_coarse(ism_ctx* c, double* rc) {
   return ISM_OK;
 }
 
-// ISM_CYCLE_ONESHOT (Sec. 4.3.1): restrict once, block GS on the coarse grid to coarse_tol,
-// prolongate and add, then red-black sweeps until max |b~ - A x| < fine_tol.  T = double
+// ISM_CYCLE_ONESHOT (Sec. 4.3.1): restrict once, block (or multicolour) GS on the coarse grid
+// to coarse_tol, prolongate and add, then red-black sweeps until max |b~ - A x| < fine_tol.
+// T = double
 // iterates x itself; T = float (the paper's single precision, Sec. 4.2) iterates a correction
 // e on A'e = fp32(r), r = h^2 b~ - A'x in FP64, from e = P E, and adds it to x at the end.
 // Both stages are device-checked loops (one read-back per batch of iterations).
@@ -701,7 +743,9 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   int ic = 0;
   bool cconv = false;
   const double h = c->h;
-  if ((rcode = coarse_block_gs(c, c->rc, c->cfg.coarse_tol * h * h, c->cfg.max_cycles, &E, &ic, &cconv)))
+  int cper = 1;
+  if ((rcode = coarse_gs_loop(c, c->rc, c->cfg.coarse_tol * h * h, c->cfg.max_cycles, &E, &ic,
+                              &cconv, &cper)))
     return rcode;
   // the fine iterates: x and eA (FP64: x += P E, right-hand side b' = h^2 b~, the residual of
   // x = 0), or eA and eB (FP32: e = P E, right-hand side fp32(r'))
@@ -796,6 +840,7 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     st->coarse_iters = ic;
     st->fine_iters = fi;
+    st->coarse_syncs = ic * cper;
   }
   return status;
 }
@@ -1082,6 +1127,7 @@ int ism_config_init(ism_config* cfg, int32_t nx, int32_t ny, int32_t batch) {
   cfg->cycling = ISM_CYCLE_REPEAT;
   cfg->coarse_tol = 1e-5;  // the paper's coarse and fine criteria (Sec. 4.3.1, Fig. 3)
   cfg->fine_tol = 1e-6;
+  cfg->coarse_gs = ISM_COARSE_GS_BLOCK;
   return ISM_OK;
 }
 
@@ -1395,7 +1441,8 @@ int ism_coarse_gs(ism_handle c, const double* rc, double* E, double tol, int32_t
   double* out = nullptr;
   int it = 0;
   bool conv = false;
-  if ((rcode = coarse_block_gs(c, c->rc, tol, max_iter, &out, &it, &conv))) return rcode;
+  int per = 1;
+  if ((rcode = coarse_gs_loop(c, c->rc, tol, max_iter, &out, &it, &conv, &per))) return rcode;
   HIPCHK(c, hipMemcpyAsync(E, out, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   *iters = it;

@@ -164,6 +164,17 @@ hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, 
                              double* Eout, double* part_max, hipStream_t s,
                              const double* stop = nullptr);
 
+// One multicolour Gauss-Seidel iteration on each grid's coarse system: Eout from Ein (which
+// must not alias), the colours in increasing order, one launch each; part_max[grid][tile] =
+// max |R - A_c Ein| over coarse_mc_tiles(g) tiles of cells per grid.  coarse_mc_colours(g)
+// colours: 4, or 6 / 9 with one / two odd periodic axes.  Returns the number of kernels
+// enqueued; *err the first launch error (hipSuccess if none).
+int coarse_mc_colours(const Geo& g);
+int coarse_mc_tiles(const Geo& g);
+int launch_coarse_mc(const Geo& g, const double* coef, const double* R, const double* Ein,
+                     double* Eout, double* part_max, hipStream_t s, const double* stop,
+                     hipError_t* err);
+
 // Device-side stop test of iteration iter: if *state is 0 and every m[0 .. batch) is below
 // tol (or any is not finite), sets *state to 1 (2) and *at to iter.  One thread.
 hipError_t launch_stop_check(const double* m, int batch, double tol, int iter, double* state,

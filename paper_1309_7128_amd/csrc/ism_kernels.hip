@@ -759,6 +759,112 @@ __global__ __launch_bounds__(kBlock) void k_coarse_bgs(Geo g, const double* __re
 }
 
 // ----------------------------------------------------------------------------------------
+// Multicolour Gauss-Seidel on the coarse system A_c E = R (Sec. 3.1: multicolour ordering
+// iterates stencils wider than five points concurrently; Sec. 4.3: one synchronization per
+// colour).  Along each axis cell i has colour i mod 2, except that the last cell of an odd
+// periodic axis takes colour 2 (its wrapped neighbour is cell 0); cell (J, I) has colour
+// qy(J) * Qx + qx(I).  Two cells the 9-point stencil couples never share a colour, so a
+// colour's cells are updated concurrently, each reading only cells of other colours.  An
+// iteration is one launch per colour, in increasing colour order: the first launch forms
+// the residual of the incoming iterate at every cell (maxima per workgroup) and writes
+// Eout, colour 0 updated and every other cell copied; the next launches update their
+// colour in place in Eout.  Residual: R_C - (c_C E_C + sum of c_nb E_nb); update:
+// E_C = (R_C - sum of c_nb E_nb) / c_C, both with the neighbours in the order
+// (dj, di) = (-1,-1) .. (1,1) without the centre and summed left to right, as block GS.
+// ----------------------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int mc_axis_colours(int nc, bool per) {
+  return per && (nc & 1) ? 3 : 2;
+}
+// cells of colour q along an axis of nc cells that has Q colours, and the m-th of them
+__host__ __device__ __forceinline__ int mc_axis_count(int nc, int Q, int q) {
+  return q == 2 ? 1 : (Q == 3 && q == 0 ? (nc - 1) / 2 : (nc - q + 1) / 2);
+}
+__device__ __forceinline__ int mc_axis_cell(int nc, int q, int m) { return q == 2 ? nc - 1 : q + 2 * m; }
+__device__ __forceinline__ int mc_axis_colour(int i, int nc, int Q) {
+  return (Q == 3 && i == nc - 1) ? 2 : (i & 1);
+}
+
+// The 8 neighbour values of cell (J, I) of plane Eb in stencil order (0 off a walled grid).
+__device__ __forceinline__ void mc_neighbours(const Geo& g, const double* __restrict__ Eb, int J,
+                                              int I, double v[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) continue;
+    int jj = J + k / 3 - 1, ii = I + k % 3 - 1;
+    bool ok = true;
+    if (g.per_y) jj = jj < 0 ? jj + g.ncy : (jj >= g.ncy ? jj - g.ncy : jj);
+    else ok = jj >= 0 && jj < g.ncy;
+    if (g.per_x) ii = ii < 0 ? ii + g.ncx : (ii >= g.ncx ? ii - g.ncx : ii);
+    else ok = ok && ii >= 0 && ii < g.ncx;
+    v[k] = ok ? Eb[(long long)jj * g.ncx + ii] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_coarse_mc_first(Geo g, const double* __restrict__ coef,
+                                                            const double* __restrict__ R,
+                                                            const double* __restrict__ Ein,
+                                                            double* __restrict__ Eout,
+                                                            double* __restrict__ part_max, int Qx,
+                                                            int Qy, const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;  // enqueued past a device-side stop
+  __shared__ double smax[kBlock / kWave];
+  const int cell = blockIdx.x * kBlock + threadIdx.x;
+  const long long cb = (long long)blockIdx.z * g.cplane;
+  double amax = 0.0;
+  if (cell < g.cplane) {
+    const int J = cell / g.ncx, I = cell - J * g.ncx;
+    const double* c = coef + (long long)cell * 9;
+    double v[9];
+    mc_neighbours(g, Ein + cb, J, I, v);
+    const double r = R[cb + cell], e = Ein[cb + cell];
+    double acc = c[4] * e, sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (k == 4) continue;
+      acc = acc + c[k] * v[k];
+      sum = sum + c[k] * v[k];
+    }
+    amax = fabs(r - acc);
+    const bool first = mc_axis_colour(J, g.ncy, Qy) == 0 && mc_axis_colour(I, g.ncx, Qx) == 0;
+    Eout[cb + cell] = first ? (r - sum) / c[4] : e;
+  }
+  amax = wave_max_group(amax, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) smax[threadIdx.x / kWave] = amax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smax[0];
+    for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, smax[w]);
+    part_max[(long long)blockIdx.z * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+// Colour (qy, qx) of one iteration, in place: thread t updates the t-th cell of the colour
+// (cx cells of it per row of the colour).
+__global__ __launch_bounds__(kBlock) void k_coarse_mc_colour(Geo g, const double* __restrict__ coef,
+                                                             const double* __restrict__ R,
+                                                             double* __restrict__ E, int qy, int qx,
+                                                             int cx, int count,
+                                                             const double* __restrict__ stop) {
+  if (stop && *stop != 0.0) return;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= count) return;
+  const int my = t / cx, mx = t - my * cx;
+  const int J = mc_axis_cell(g.ncy, qy, my), I = mc_axis_cell(g.ncx, qx, mx);
+  const long long cb = (long long)blockIdx.z * g.cplane;
+  const long long cell = (long long)J * g.ncx + I;
+  const double* c = coef + cell * 9;
+  double v[9];
+  mc_neighbours(g, E + cb, J, I, v);
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) continue;
+    sum = sum + c[k] * v[k];
+  }
+  E[cb + cell] = (R[cb + cell] - sum) / c[4];
+}
+
+// ----------------------------------------------------------------------------------------
 // Staggered-grid operators (FP64).  nxu = number of u faces per row.
 // ----------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_div(Geo g, const double* __restrict__ u,
@@ -1307,6 +1413,32 @@ hipError_t launch_coarse_bgs(const Geo& g, const double* coef, const double* R, 
   hipLaunchKernelGGL(k_coarse_bgs, grid, dim3(kBlock), 0, s, g, coef, R, Ein, Eout, part_max, tx,
                      ty, stop);
   return hipGetLastError();
+}
+
+int coarse_mc_colours(const Geo& g) {
+  return mc_axis_colours(g.ncx, g.per_x) * mc_axis_colours(g.ncy, g.per_y);
+}
+
+int coarse_mc_tiles(const Geo& g) { return int((g.cplane + kBlock - 1) / kBlock); }
+
+int launch_coarse_mc(const Geo& g, const double* coef, const double* R, const double* Ein,
+                     double* Eout, double* part_max, hipStream_t s, const double* stop,
+                     hipError_t* err) {
+  const int Qx = mc_axis_colours(g.ncx, g.per_x), Qy = mc_axis_colours(g.ncy, g.per_y);
+  hipLaunchKernelGGL(k_coarse_mc_first, dim3(coarse_mc_tiles(g), 1, g.batch), dim3(kBlock), 0, s,
+                     g, coef, R, Ein, Eout, part_max, Qx, Qy, stop);
+  int launched = 1;
+  if ((*err = hipGetLastError()) != hipSuccess) return launched;
+  for (int k = 1; k < Qx * Qy; ++k) {
+    const int qy = k / Qx, qx = k - qy * Qx;
+    const int cx = mc_axis_count(g.ncx, Qx, qx), count = cx * mc_axis_count(g.ncy, Qy, qy);
+    if (count == 0) continue;  // a coarse axis of one cell has no cell of colour 0 or 1
+    hipLaunchKernelGGL(k_coarse_mc_colour, dim3((count + kBlock - 1) / kBlock, 1, g.batch),
+                       dim3(kBlock), 0, s, g, coef, R, Eout, qy, qx, cx, count, stop);
+    ++launched;
+    if ((*err = hipGetLastError()) != hipSuccess) return launched;
+  }
+  return launched;
 }
 
 template <typename T, int NU>

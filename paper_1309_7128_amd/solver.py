@@ -52,7 +52,8 @@ class Solver:
                  ly=None, precision="fp64", nu=4, rtol=1e-10, inner_rtol=1e-3,
                  max_cycles=100000, max_outer=50, check_every=0, fused=True, device=None,
                  raise_not_converged=False, stall_window=None, stall_drop=None,
-                 coarse_stencil="ism", cycling="repeat", coarse_tol=None, fine_tol=None):
+                 coarse_stencil="ism", cycling="repeat", coarse_tol=None, fine_tol=None,
+                 coarse_gs="block"):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the ISM solver runs on a GPU; torch.cuda is not available")
@@ -84,13 +85,17 @@ class Solver:
             cfg.stall_drop = stall_drop
         cfg.coarse_stencil = {"ism": L.ISM_COARSE_ISM, "gmg5": L.ISM_COARSE_GMG5,
                               "acm": L.ISM_COARSE_ACM}[coarse_stencil]
-        # "oneshot": the paper's accommodative cycling once per solve (block GS on the coarse
-        # grid to coarse_tol, then fine sweeps to fine_tol; both absolute max-norms)
+        # "oneshot": the paper's accommodative cycling once per solve (block or multicolour GS
+        # on the coarse grid to coarse_tol, then fine sweeps to fine_tol; both absolute
+        # max-norms)
         cfg.cycling = {"repeat": L.ISM_CYCLE_REPEAT, "oneshot": L.ISM_CYCLE_ONESHOT}[cycling]
         if coarse_tol is not None:
             cfg.coarse_tol = coarse_tol
         if fine_tol is not None:
             cfg.fine_tol = fine_tol
+        # the coarse iteration of one-shot cycling and coarse_gs(): "block" or "multicolour"
+        cfg.coarse_gs = {"block": L.ISM_COARSE_GS_BLOCK,
+                         "multicolour": L.ISM_COARSE_GS_MULTICOLOUR}[coarse_gs]
         self.cfg = cfg
         self.nx, self.ny, self.batch = nx, ny, batch
         self.bc_x, self.bc_y = bc_x, bc_y
@@ -296,8 +301,8 @@ class Solver:
         return (e, rc, sq) if want_sumsq else (e, rc)
 
     def coarse_gs(self, rc, tol, max_iter=100000):
-        """Block Gauss-Seidel on the coarse systems A_c E = rc to max |rc - A_c E| < tol.
-        Returns (E, iterations, converged)."""
+        """Block or multicolour Gauss-Seidel (the handle's coarse_gs) on the coarse systems
+        A_c E = rc to max |rc - A_c E| < tol.  Returns (E, iterations, converged)."""
         E = self._new(self.coarse_shape)
         it = ctypes.c_int32()
         code = _check(self._lib.ism_coarse_gs(self.handle, self._arg(rc, self.coarse_shape, name="rc"),

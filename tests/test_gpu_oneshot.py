@@ -79,6 +79,74 @@ def test_coarse_block_gs_matches_oracle(case):
         np.testing.assert_array_equal(E, ref)
 
 
+# (nx, ny, n, bc_x, bc_y): multicolour GS on coarse grids of 4 colours, 6 and 9 (odd periodic
+# axes), a coarse axis of one cell, and a grid of many workgroups per colour
+MC_CASES = [
+    (192, 160, 16, D, D),        # 12 x 10, 4 colours
+    (208, 160, 16, P, D),        # 13 x 10: odd periodic x, 6 colours
+    (208, 176, 16, P, P),        # 13 x 11: 9 colours, singular
+    (512, 384, 16, D, ND),       # 32 x 24
+    (640, 320, 16, P, DN),       # 40 x 20
+    (16, 96, 16, P, D),          # 1 x 6: the single x cell takes colour 2
+    (320, 256, 16, N, N),
+]
+
+
+@pytest.mark.parametrize("case", MC_CASES, ids=_ids)
+def test_coarse_multicolour_gs_matches_oracle(case):
+    """Multicolour GS (Sec. 3.1, Sec. 4.3): both sides update each colour's cells from the same
+    values with the same arithmetic, so the iterates agree bit for bit with a Dirichlet face
+    (and to rounding, counts within one, without: each side removes the mean of R itself)."""
+    announce("coarse_mcgs", case)
+    nx, ny, n, bx, by = case
+    ncx, ncy = nx // n, ny // n
+    rng = np.random.default_rng(403)
+    Rc = rng.standard_normal((ncy, ncx))
+    tol = 2e-3 * np.abs(Rc).max()
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, bc_y=by, coarse_gs="multicolour")
+    E, it, conv = s.coarse_gs(dev(Rc[None]), tol, max_iter=5000)
+    E = host(E).reshape(ncy, ncx)
+    C = O.coarse_stencil_ism(ncx, ncy, n, bx, by)
+    ref, it_ref, _ = O.multicolour_gauss_seidel(C, Rc, tol, bx, by)
+    assert conv
+    if O.singular(bx, by):
+        assert abs(it - it_ref) <= 1
+        if it == it_ref:
+            np.testing.assert_allclose(E, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    else:
+        assert it == it_ref
+        np.testing.assert_array_equal(E, ref)
+
+
+def test_coarse_multicolour_gs_many_workgroups():
+    """256 x 128 coarse cells (128 workgroups in the residual launch, 32 per colour), batch of
+    two: 40 iterations (tolerance 0, so the cap stops them) bit for bit, per grid."""
+    announce("coarse_mcgs_large")
+    nx, ny, n = 4096, 2048, 16
+    s = solver(nx=nx, ny=ny, batch=2, coarsen=n, bc_x=D, bc_y=N, coarse_gs="multicolour")
+    Rc = np.random.default_rng(404).standard_normal((2, ny // n, nx // n))
+    E, it, conv = s.coarse_gs(dev(Rc), 0.0, max_iter=40)
+    assert it == 40 and not conv
+    C = O.coarse_stencil_ism(nx // n, ny // n, n, D, N)
+    for k in range(2):
+        ref, _, _ = O.multicolour_gauss_seidel(C, Rc[k], 0.0, D, N, max_iter=40)
+        np.testing.assert_array_equal(host(E)[k], ref)
+
+
+def test_coarse_multicolour_gs_gmg5_stencil():
+    announce("coarse_mcgs_gmg5")
+    nx, ny, n = 512, 384, 16
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=D, bc_y=ND, coarse_stencil="gmg5",
+               coarse_gs="multicolour")
+    Rc = np.random.default_rng(405).standard_normal((1, ny // n, nx // n))
+    tol = 1e-3 * np.abs(Rc).max()
+    E, it, conv = s.coarse_gs(dev(Rc), tol, max_iter=5000)
+    ref, it_ref, _ = O.multicolour_gauss_seidel(O.coarse_stencil_gmg5(nx // n, ny // n, n, D, ND),
+                                                Rc[0], tol, D, ND)
+    assert conv and it == it_ref
+    np.testing.assert_array_equal(host(E)[0], ref)
+
+
 def test_coarse_block_gs_gmg5_stencil():
     """Block GS on the 5-point coarse stencil of the GMG variant (Sec. 4.3.2), bitwise."""
     announce("coarse_bgs_gmg5")
@@ -179,6 +247,47 @@ def test_oneshot_coarse_criterion_trades_fine_work():
               flush=True)
     assert out[0][0] < out[1][0] < out[2][0]
     assert out[2][1] < out[0][1]
+
+
+@pytest.mark.parametrize("bx,by,n,prec", [(D, D, 8, "fp64"), (P, ND, 16, "mixed"),
+                                          (N, N, 8, "fp64"), (DN, P, 16, "mixed")])
+def test_oneshot_multicolour_matches_oracle(bx, by, n, prec):
+    """One-shot cycling with multicolour GS on the coarse grid: the counts, the coarse
+    synchronizations (one per colour, Sec. 4.3) and the result against the oracle."""
+    announce("oneshot_mc", bx, by, n, prec)
+    nx, ny = 144, 96
+    h = 1.0 / nx
+    b = _mac_rhs(414, nx, ny, h, bx)
+    tol_c, tol_f = 1e-4 * np.abs(b).max(), 1e-3 * np.abs(b).max()
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=bx, bc_y=by, cycling="oneshot", coarse_tol=tol_c,
+               fine_tol=tol_f, lx=1.0, precision=prec, coarse_gs="multicolour")
+    x, st = s.solve(dev(b))
+    x = host(x).reshape(ny, nx)
+    xo, info = O.ism_solve_oneshot(b, h, n, bx, by, tol_c=tol_c, tol_f=tol_f,
+                                   precision="fp32" if prec == "mixed" else "fp64",
+                                   coarse_gs="multicolour")
+    print(st, info, flush=True)
+    assert st["status"] == 0
+    exact = not O.singular(bx, by)
+    assert abs(st["coarse_iters"] - info["coarse_iters"]) <= (0 if exact else 1)
+    assert abs(st["fine_iters"] - info["fine_iters"]) <= (0 if exact else 1)
+    colours = info["ncc_c"] // max(info["coarse_iters"], 1)
+    assert st["coarse_syncs"] == colours * st["coarse_iters"]
+    bt = b - b.mean() if O.singular(bx, by) else b
+    assert np.abs(bt - O.laplacian(x, bx, by) / h**2).max() < (1.01 if prec == "mixed" else 1.0) * tol_f
+    if exact and st["fine_iters"] == info["fine_iters"]:
+        np.testing.assert_allclose(x, xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+
+
+def test_coarse_multicolour_gs_iteration_cap():
+    announce("coarse_mcgs_cap")
+    s = solver(nx=256, ny=256, coarsen=16, bc_x=D, bc_y=D, coarse_gs="multicolour")
+    Rc = np.random.default_rng(406).standard_normal((1, 16, 16))
+    E, it, conv = s.coarse_gs(dev(Rc), 1e-14, max_iter=7)
+    assert it == 7 and not conv
+    C = O.coarse_stencil_ism(16, 16, 16, D, D)
+    ref, _, _ = O.multicolour_gauss_seidel(C, Rc[0], 0.0, D, D, max_iter=7)
+    np.testing.assert_array_equal(host(E)[0], ref)
 
 
 @pytest.mark.parametrize("bx,by,n", [(D, D, 8), (P, ND, 16), (N, N, 8), (DN, N, 16)])

@@ -28,13 +28,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout():
     # C layout: 6 int32, 2 double, 2 int32, 2 double, 5 int32 (+4 padding), 1 double,
-    # 2 int32, 2 double
-    assert ctypes.sizeof(L.IsmConfig) == 120
+    # 2 int32, 2 double, 1 int32 (+4 padding)
+    assert ctypes.sizeof(L.IsmConfig) == 128
     assert L.IsmConfig.stall_drop.offset == 88 and L.IsmConfig.coarse_stencil.offset == 96
     assert L.IsmConfig.lx.offset == 24 and L.IsmConfig.rtol.offset == 48
     assert L.IsmConfig.cycling.offset == 100 and L.IsmConfig.fine_tol.offset == 112
-    # 4 int32, 2 int64, 3 double, 2 int32
-    assert ctypes.sizeof(L.IsmStats) == 64 and L.IsmStats.coarse_iters.offset == 56
+    assert L.IsmConfig.coarse_gs.offset == 120
+    # 4 int32, 2 int64, 3 double, 3 int32 (+4 padding)
+    assert ctypes.sizeof(L.IsmStats) == 72 and L.IsmStats.coarse_iters.offset == 56
+    assert L.IsmStats.coarse_syncs.offset == 64
 
 
 def test_config_defaults():
@@ -44,6 +46,7 @@ def test_config_defaults():
     assert (cfg.nx, cfg.ny, cfg.batch, cfg.coarsen, cfg.nu) == (256, 128, 2, 16, 4)
     assert cfg.lx == 1.0 and cfg.ly == 0.5 and cfg.rtol == 1e-10 and cfg.fused == 1
     assert cfg.cycling == L.ISM_CYCLE_REPEAT and cfg.coarse_tol == 1e-5 and cfg.fine_tol == 1e-6
+    assert cfg.coarse_gs == L.ISM_COARSE_GS_BLOCK
     assert lib.ism_config_init(None, 1, 1, 1) == L.ISM_ERR_INVALID
 
 
@@ -86,6 +89,8 @@ def _create(**kw):
     (dict(coarse_stencil=3), L.ISM_ERR_INVALID),
     (dict(coarse_stencil=2, precision=1), L.ISM_ERR_UNSUPPORTED),  # ACM is FP64 only
     (dict(cycling=2), L.ISM_ERR_INVALID),
+    (dict(coarse_gs=2), L.ISM_ERR_INVALID),
+    (dict(cycling=1, coarse_gs=-1), L.ISM_ERR_INVALID),
     (dict(cycling=1, coarse_tol=0.0), L.ISM_ERR_INVALID),
     (dict(cycling=1, fine_tol=-1.0), L.ISM_ERR_INVALID),
     (dict(cycling=1, coarse_stencil=2), L.ISM_ERR_UNSUPPORTED), # and needs a 9-point stencil
