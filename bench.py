@@ -81,6 +81,8 @@ def parse():
                          "paper's one-shot accommodative cycling, for each tile size and coarse "
                          "criterion of --oneshot-tiles / --oneshot-coarse-tol, one JSON line each")
     ap.add_argument("--oneshot-tiles", default="16,32")
+    ap.add_argument("--oneshot-coarse-gs", default="block",
+                    help="coarse iteration of the one-shot table: block and/or multicolour")
     ap.add_argument("--oneshot-precision", default="fp64,mixed",
                     help="fine-stage precision of the one-shot table: fp64 and/or mixed (FP32)")
     ap.add_argument("--time-loop", type=int, default=0,
@@ -119,9 +121,10 @@ def oneshot_table(w, args):
     synthetic time loop: step 0 is solved to the workload's tolerance with the default
     cycling, then each step t = 1 .. K solves the right-hand side of step t (the jet's
     perturbation moved t cells) warm-started from step t-1, with one-shot accommodative
-    cycling (block GS on the coarse grid to the coarse criterion, then fine red-black
-    iterations to the fine one).  Per configuration: mean I_c, I_f, NCC_c = I_c,
-    NCC_f = 2 I_f, NCC_t and N_Lap = NCC_f / 2 + NCC_c / n^2 per step, and wall time."""
+    cycling (block or multicolour GS on the coarse grid to the coarse criterion, then fine
+    red-black iterations to the fine one).  Per configuration: mean I_c, I_f, NCC_c (I_c for
+    block GS, colours x I_c for multicolour GS), NCC_f = 2 I_f, NCC_t and
+    N_Lap = NCC_f / 2 + NCC_c / n^2 per step, and wall time."""
     import torch
 
     from paper_1309_7128_amd import inputs
@@ -135,15 +138,16 @@ def oneshot_table(w, args):
     bmax = float(b0.abs().max())
     steps = [torch.roll(b0, t, dims=-1) if w.bc_x == "periodic" else b0
              for t in range(1, args.oneshot_table + 1)]
-    configs = [(prec, n, frac) for prec in args.oneshot_precision.split(",")
+    configs = [(gs, prec, n, frac) for gs in args.oneshot_coarse_gs.split(",")
+               for prec in args.oneshot_precision.split(",")
                for n in [int(a) for a in args.oneshot_tiles.split(",")]
                for frac in [float(a) for a in args.oneshot_coarse_tol.split(",")]]
-    for prec, n, frac in configs:
+    for gs, prec, n, frac in configs:
         s = Solver(w.nx, w.ny, bc_x=w.bc_x, bc_y=w.bc_y, coarsen=n, lx=w.lx, ly=w.ly,
                    precision=prec, cycling="oneshot", coarse_tol=frac * bmax,
-                   fine_tol=1e-5 * bmax, max_cycles=200000)
+                   fine_tol=1e-5 * bmax, max_cycles=200000, coarse_gs=gs)
         x = x0.clone()
-        ic = fi = syncs = 0
+        ic = fi = syncs = csyncs = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for bt in steps:
@@ -151,10 +155,12 @@ def oneshot_table(w, args):
             ic += st["coarse_iters"]
             fi += st["fine_iters"]
             syncs += st["host_syncs"]
+            csyncs += st["coarse_syncs"]
         dt = time.perf_counter() - t0
         k = len(steps)
-        ncc_c, ncc_f = ic / k, 2.0 * fi / k
-        print(json.dumps({"workload": w.name, "precision": prec, "tile": n, "coarse_tol_frac": frac,
+        ncc_c, ncc_f = csyncs / k, 2.0 * fi / k
+        print(json.dumps({"workload": w.name, "coarse_gs": gs, "precision": prec, "tile": n,
+                          "coarse_tol_frac": frac,
                           "fine_tol_frac": 1e-5, "steps": k, "I_c": ic / k, "I_f": fi / k,
                           "NCC_c": ncc_c, "NCC_f": ncc_f, "NCC_t": ncc_c + ncc_f,
                           "N_Lap": ncc_f / 2.0 + ncc_c / float(n * n),
