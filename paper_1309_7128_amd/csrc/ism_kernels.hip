@@ -195,8 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo g, const double* __restr
 // other fused kernel) has too few waves to hide its per-row latency: a block's staging, 2 nu
 // barriers and its reduction take a few microseconds, against the walk's tens.
 // ----------------------------------------------------------------------------------------
+constexpr int kTileBlock = 1024;  // threads of a k_cycle_tile workgroup
+
 template <typename T, int NU>
-__global__ __launch_bounds__(kBlock) void k_cycle_tile(Geo g, const T* __restrict__ rhs,
+__global__ __launch_bounds__(kTileBlock) void k_cycle_tile(Geo g, const T* __restrict__ rhs,
                                                        const T* __restrict__ ein,
                                                        T* __restrict__ eout,
                                                        const double* __restrict__ E,
@@ -212,45 +214,72 @@ __global__ __launch_bounds__(kBlock) void k_cycle_tile(Geo g, const T* __restric
   const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
   const long long off = (long long)blockIdx.z * g.plane;
   const double* Eb = E + (long long)blockIdx.z * g.cplane;
-  // stage: e (+)= P E, rhs and the inverse diagonal; cells behind a wall hold 0 throughout
-  for (int t = threadIdx.x; t < W * W; t += kBlock) {
+  // stage: e (+)= P E, rhs and the inverse diagonal; cells behind a wall hold 0 throughout.
+  // A thread's NS cells are formed first and stored after, so that their global reads are
+  // all in flight together rather than one cell's latency after another's.
+  constexpr int NS = (W * W + kTileBlock - 1) / kTileBlock;
+  T ev[NS], rv[NS], iv[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int t = threadIdx.x + q * kTileBlock;
     const int ly = t / W, lx = t - ly * W;
     int i = x0 + lx - H, j = y0 + ly - H;
-    T ev = T(0), rv = T(0), iv = T(0);
-    if (map_cell(g, i, j)) {
+    ev[q] = T(0);
+    rv[q] = T(0);
+    iv[q] = T(0);
+    if (t < W * W && map_cell(g, i, j)) {
       const long long a = off + (long long)j * g.nx + i;
-      rv = rhs[a];
+      rv[q] = rhs[a];
       const T p = prolong_at<T>(g, Eb, i, j);
-      ev = zero_e ? p : T(ein[a] + p);
-      iv = inv_count<T>(g, i, j);
+      ev[q] = zero_e ? p : T(ein[a] + p);
+      iv[q] = inv_count<T>(g, i, j);
     }
-    se[t] = ev;
-    sr[t] = rv;
-    si[t] = iv;
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int t = threadIdx.x + q * kTileBlock;
+    if (t < W * W) {
+      se[t] = ev[q];
+      sr[t] = rv[q];
+      si[t] = iv[q];
+    }
   }
   __syncthreads();
   // half-step k (red first) on the cells of its colour with four staged neighbours; x0 and
-  // y0 are even, so a cell's colour is the parity of its staged coordinates
+  // y0 are even, so a cell's colour is the parity of its staged coordinates.  A cell reads
+  // only cells of the other colour, so a thread forms all its NH cells before storing any.
+  constexpr int NH = (WI * HW + kTileBlock - 1) / kTileBlock;
 #pragma unroll 1
   for (int k = 0; k < 2 * NU; ++k) {
-    for (int t = threadIdx.x; t < WI * HW; t += kBlock) {
+    T nv[NH];
+    int ni[NH];
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      const int t = threadIdx.x + q * kTileBlock;
       const int ly = 1 + t / HW;
       const int lx = 1 + 2 * (t - (ly - 1) * HW) + ((k + ly + 1) & 1);
-      const int idx = ly * W + lx;
-      const T sum = (se[idx - 1] + se[idx + 1]) + (se[idx - W] + se[idx + W]);
-      se[idx] = (sum - sr[idx]) * si[idx];
+      ni[q] = ly * W + lx;
+      if (t < WI * HW) {
+        const int idx = ni[q];
+        const T sum = (se[idx - 1] + se[idx + 1]) + (se[idx - W] + se[idx + W]);
+        nv[q] = (sum - sr[idx]) * si[idx];
+      }
     }
+#pragma unroll
+    for (int q = 0; q < NH; ++q)
+      if (threadIdx.x + q * kTileBlock < WI * HW) se[ni[q]] = nv[q];
     __syncthreads();
   }
-  // the block's residual and write-back: thread t takes row t / 8 and four cells of it, which
-  // lie in one coarse tile (n >= 4)
-  const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
+  // the block's residual and write-back: thread t < kBlock takes row t / 8 and four cells of
+  // it, which lie in one coarse tile (n >= 4); the other threads only join the barriers
+  const bool rt = threadIdx.x < kBlock;
+  const int r = (threadIdx.x >> 3) & (kTile - 1), c0 = (threadIdx.x & 7) * 4;
   const int j = y0 + r;
   double acc = 0.0, acc2 = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = x0 + c0 + q;
-    if (i >= g.nx || j >= g.ny) continue;
+    if (!rt || i >= g.nx || j >= g.ny) continue;
     const int idx = (H + r) * W + H + c0 + q;
     const double d = double(sr[idx] - lap5<T>(se[idx], se[idx - 1], se[idx + 1], se[idx - W],
                                               se[idx + W], cell_faces(g, i, j)));
@@ -262,18 +291,20 @@ __global__ __launch_bounds__(kBlock) void k_cycle_tile(Geo g, const T* __restric
   const int n = g.n, per = (n * n) >> 2;
   const int tile = (r >> g.log2n) * (kTile >> g.log2n) + (c0 >> g.log2n);
   const int k = (r & (n - 1)) * (n >> 2) + ((c0 & (n - 1)) >> 2);
-  p1[tile * per + k] = acc;
-  p2[tile * per + k] = acc2;
+  if (rt) {
+    p1[tile * per + k] = acc;
+    p2[tile * per + k] = acc2;
+  }
   __syncthreads();
   for (int st = per >> 1; st > 0; st >>= 1) {
-    if (k < st) {
+    if (rt && k < st) {
       p1[tile * per + k] += p1[tile * per + k + st];
       p2[tile * per + k] = maxmode ? fmax(p2[tile * per + k], p2[tile * per + k + st])
                                    : p2[tile * per + k] + p2[tile * per + k + st];
     }
     __syncthreads();
   }
-  if (k == 0) {
+  if (rt && k == 0) {
     const int I = (x0 + c0) >> g.log2n, J = j >> g.log2n;
     if (I < g.ncx && J < g.ncy) {
       const long long o = (long long)blockIdx.z * g.cplane + (long long)J * g.ncx + I;
@@ -1451,7 +1482,7 @@ hipError_t cycle_tile_nu(const Geo& g, const T* rhs, const T* ein, T* eout, cons
     if (nu != NU)
       return cycle_tile_nu<T, NU - 1>(g, rhs, ein, eout, E, rc, psq, nu, zero_e, s, stop, maxmode);
     dim3 grid((g.nx + kTile - 1) / kTile, (g.ny + kTile - 1) / kTile, g.batch);
-    hipLaunchKernelGGL((k_cycle_tile<T, NU>), grid, dim3(kBlock), 0, s, g, rhs, ein, eout, E, rc, psq,
+    hipLaunchKernelGGL((k_cycle_tile<T, NU>), grid, dim3(kTileBlock), 0, s, g, rhs, ein, eout, E, rc, psq,
                        zero_e, stop, maxmode);
     return hipGetLastError();
   }
