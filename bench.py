@@ -106,7 +106,7 @@ def parse():
 
 # The library's default (ISM_FUSED_AUTO) takes the LDS-tiled cycle kernel up to this many
 # cells per launch (include/ism.h), the row walk above.
-TILE_CELLS = 1280 * 1280
+TILE_CELLS = 1024 * 1024
 
 
 def cycle_kernel_name(w, cells, nu):

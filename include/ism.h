@@ -116,7 +116,7 @@ extern "C" {
  * bit (that of nu whole-grid red-black sweeps) and the same tile sums up to their summation
  * order.  The row walk streams the grid once per cycle (the large-grid form); the LDS-tiled
  * form stages 32 x 32 blocks with a halo of 2 nu + 1 and suits grids too small for the walk
- * to hide its per-row latency.  AUTO takes the tiled form up to 1280^2 cells per launch
+ * to hide its per-row latency.  AUTO takes the tiled form up to 1024^2 cells per launch
  * (nx * ny * batch), the walk above. */
 #define ISM_FUSED_OFF 0  /* prolongation, nu sweeps, residual + restriction: one kernel each */
 #define ISM_FUSED_AUTO 1 /* default                                                          */

@@ -257,9 +257,11 @@ int coarse_solve(ism_ctx* c, const double* rc, double* E) {
 
 // Which fused kernel a cycle takes (ISM_FUSED_AUTO): the LDS-tiled one up to kTileCells cells
 // per launch, where the row walk has too few waves to hide its per-row latency, else the
-// walk.  Measured on MI355X (FP64, nu = 4, 16h, whole solves per cycle): 256^2 27 us tiled
-// against 62 us walked, 1024^2 62 against 76, 2048^2 190 against 85.
-constexpr double kTileCells = 1280.0 * 1280.0;
+// walk.  Measured on MI355X (whole solves per cycle, tiled against walked; FP64 nu = 4, FP32
+// nu = 5): 256^2 at 16h 17 against 56 us (FP64), 20 against 46 (FP32); 1024^2 at 16h 56
+// against 71 (FP64), 64 against 61 (FP32); 1280^2 at 16h 84 against 74 (FP64), 96 against
+// 63 (FP32); 2048^2 171 against 78 (FP64).
+constexpr double kTileCells = 1024.0 * 1024.0;
 
 bool tile_cycle(const ism_ctx* c) {
   if (c->cfg.fused == ISM_FUSED_TILE) return true;
