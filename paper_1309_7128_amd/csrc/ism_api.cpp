@@ -641,68 +641,42 @@ int device_checked_loop(ism_ctx* c, Step step, const double* m, double tol, int 
   }
 }
 
-// Block Gauss-Seidel (Sec. 4) on every grid's A_c E = rc from E = 0: iteration it forms the
-// residual of its incoming iterate E_it (in t1 for even it, t2 for odd) and E_it+1; the loop
-// stops at the first iterate whose residual max is below tol on every grid (or at max_iter).
-// The result stays in one of the t1 / t2 buffers (*E_out).
-int coarse_block_gs(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
-                    int* iters, bool* converged) {
-  const Geo& g = c->g;
-  const int B = g.batch, tiles = ism::coarse_bgs_tiles(g);
-  hipStream_t s = c->stream;
-  double* E[2] = {c->t1, c->t2};
-  LAUNCH(c, ism::launch_fill(E[0], (long long)g.cplane * B, 0.0, s));
-  double* m = c->scal + size_t(CMAX) * B;
-  auto step = [&](int it, const double* stop) {
-    LAUNCH(c, ism::launch_coarse_bgs(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max, s, stop));
-    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
-    return ISM_OK;
-  };
-  int it = 0;
-  const int rcode = device_checked_loop(c, step, m, tol, max_iter, "coarse residual", &it, converged);
-  if (rcode) return rcode;
-  *E_out = E[it & 1];
-  *iters = it;
-  return ISM_OK;
-}
-
-// Multicolour Gauss-Seidel (Sec. 3.1, Sec. 4.3) on every grid's A_c E = rc from E = 0, with
-// the same loop, buffers and stopping rule as coarse_block_gs: iteration it forms the
-// residual of E_it (in t1 for even it, t2 for odd) and E_it+1, one launch per colour.
-int coarse_mc_gs(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
-                 int* iters, bool* converged) {
-  const Geo& g = c->g;
-  const int B = g.batch, tiles = ism::coarse_mc_tiles(g);
-  hipStream_t s = c->stream;
-  double* E[2] = {c->t1, c->t2};
-  LAUNCH(c, ism::launch_fill(E[0], (long long)g.cplane * B, 0.0, s));
-  double* m = c->scal + size_t(CMAX) * B;
-  auto step = [&](int it, const double* stop) {
-    hipError_t err = hipSuccess;
-    c->launches += ism::launch_coarse_mc(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max, s,
-                                         stop, &err);
-    HIPCHK(c, err);
-    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
-    return ISM_OK;
-  };
-  int it = 0;
-  const int rcode = device_checked_loop(c, step, m, tol, max_iter, "coarse residual", &it, converged);
-  if (rcode) return rcode;
-  *E_out = E[it & 1];
-  *iters = it;
-  return ISM_OK;
-}
-
-// The coarse iteration the handle was created with (ism_config.coarse_gs); *syncs_per_iter:
-// its synchronizations per iteration (Sec. 4.3: one for block GS, one per colour).
+// Gauss-Seidel on every grid's A_c E = rc from E = 0, block-iterative (Sec. 4) or in
+// multicolour order (Sec. 3.1) as the handle was created (ism_config.coarse_gs): iteration it
+// forms the residual of its incoming iterate E_it (in t1 for even it, t2 for odd) and E_it+1,
+// one launch for block GS, one per colour for multicolour GS; the loop stops at the first
+// iterate whose residual max is below tol on every grid (or at max_iter).  The result stays
+// in one of the t1 / t2 buffers (*E_out).  *syncs_per_iter: the synchronizations of one
+// iteration (Sec. 4.3: one for block GS, one per colour).
 int coarse_gs_loop(ism_ctx* c, const double* rc, double tol, int max_iter, double** E_out,
                    int* iters, bool* converged, int* syncs_per_iter) {
-  if (c->cfg.coarse_gs == ISM_COARSE_GS_MULTICOLOUR) {
-    *syncs_per_iter = ism::coarse_mc_colours(c->g);
-    return coarse_mc_gs(c, rc, tol, max_iter, E_out, iters, converged);
-  }
-  *syncs_per_iter = 1;
-  return coarse_block_gs(c, rc, tol, max_iter, E_out, iters, converged);
+  const Geo& g = c->g;
+  const bool mc = c->cfg.coarse_gs == ISM_COARSE_GS_MULTICOLOUR;
+  const int B = g.batch, tiles = mc ? ism::coarse_mc_tiles(g) : ism::coarse_bgs_tiles(g);
+  *syncs_per_iter = mc ? ism::coarse_mc_colours(g) : 1;
+  hipStream_t s = c->stream;
+  double* E[2] = {c->t1, c->t2};
+  LAUNCH(c, ism::launch_fill(E[0], (long long)g.cplane * B, 0.0, s));
+  double* m = c->scal + size_t(CMAX) * B;
+  auto step = [&](int it, const double* stop) {
+    if (mc) {
+      hipError_t err = hipSuccess;
+      c->launches += ism::launch_coarse_mc(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max,
+                                           s, stop, &err);
+      HIPCHK(c, err);
+    } else {
+      LAUNCH(c, ism::launch_coarse_bgs(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max, s,
+                                       stop));
+    }
+    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
+    return ISM_OK;
+  };
+  int it = 0;
+  const int rcode = device_checked_loop(c, step, m, tol, max_iter, "coarse residual", &it, converged);
+  if (rcode) return rcode;
+  *E_out = E[it & 1];
+  *iters = it;
+  return ISM_OK;
 }
 
 // rc -= its mean, per grid (the compatibility projection of a singular coarse system).
@@ -717,9 +691,9 @@ int project_coarse(ism_ctx* c, double* rc) {
 
 // ISM_CYCLE_ONESHOT (Sec. 4.3.1): restrict once, block (or multicolour) GS on the coarse grid
 // to coarse_tol, prolongate and add, then red-black sweeps until max |b~ - A x| < fine_tol.
-// T = double
-// iterates x itself; T = float (the paper's single precision, Sec. 4.2) iterates a correction
-// e on A'e = fp32(r), r = h^2 b~ - A'x in FP64, from e = P E, and adds it to x at the end.
+// T = double iterates x itself; T = float (the paper's single precision, Sec. 4.2) iterates a
+// correction e on A'e = fp32(r), r = h^2 b~ - A'x in FP64, from e = P E, and adds it to x at
+// the end.
 // Both stages are device-checked loops (one read-back per batch of iterations).
 template <typename T>
 int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
