@@ -321,42 +321,38 @@ __global__ __launch_bounds__(kTileBlock) void k_cycle_tile(Geo g, const T* __res
 // ----------------------------------------------------------------------------------------
 constexpr int kSmallCoarse = 32;
 
-__global__ __launch_bounds__(kBlock) void k_coarse_small(int ncx, int ncy, long long cplane,
-                                                         const double* __restrict__ R,
-                                                         const double* __restrict__ Fx,
-                                                         const double* __restrict__ Fy,
-                                                         const double* __restrict__ Vx,
-                                                         const double* __restrict__ Vy,
-                                                         const double* __restrict__ invLam,
-                                                         double* __restrict__ E) {
+__global__ __launch_bounds__(kSmallCoarse * kSmallCoarse) void k_coarse_small(
+    int ncx, int ncy, long long cplane, const double* __restrict__ R, const double* __restrict__ Fx,
+    const double* __restrict__ Fy, const double* __restrict__ Vx, const double* __restrict__ Vy,
+    const double* __restrict__ invLam, double* __restrict__ E) {
   __shared__ double A[kSmallCoarse * kSmallCoarse], B[kSmallCoarse * kSmallCoarse];
   const double* Rb = R + (long long)blockIdx.x * cplane;
   double* Eb = E + (long long)blockIdx.x * cplane;
-  const int N = ncx * ncy;
-  for (int t = threadIdx.x; t < N; t += kBlock) A[t] = Rb[t];
+  const int N = ncx * ncy, step = blockDim.x;
+  for (int t = threadIdx.x; t < N; t += step) A[t] = Rb[t];
   __syncthreads();
-  for (int t = threadIdx.x; t < N; t += kBlock) {  // T1 = R_c F_x
+  for (int t = threadIdx.x; t < N; t += step) {  // T1 = R_c F_x
     const int J = t / ncx, k = t - J * ncx;
     double acc = 0.0;
     for (int I = 0; I < ncx; ++I) acc = fma(A[J * ncx + I], Fx[I * ncx + k], acc);
     B[t] = acc;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < N; t += kBlock) {  // T2 = (F_y^T T1) .* Lambda^-1
+  for (int t = threadIdx.x; t < N; t += step) {  // T2 = (F_y^T T1) .* Lambda^-1
     const int l = t / ncx, k = t - l * ncx;
     double acc = 0.0;
     for (int J = 0; J < ncy; ++J) acc = fma(Fy[J * ncy + l], B[J * ncx + k], acc);
     A[t] = acc * invLam[t];
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < N; t += kBlock) {  // T3 = V_y T2
+  for (int t = threadIdx.x; t < N; t += step) {  // T3 = V_y T2
     const int J = t / ncx, k = t - J * ncx;
     double acc = 0.0;
     for (int l = 0; l < ncy; ++l) acc = fma(Vy[J * ncy + l], A[l * ncx + k], acc);
     B[t] = acc;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < N; t += kBlock) {  // E = T3 V_x^T
+  for (int t = threadIdx.x; t < N; t += step) {  // E = T3 V_x^T
     const int J = t / ncx, I = t - J * ncx;
     double acc = 0.0;
     for (int k = 0; k < ncx; ++k) acc = fma(B[J * ncx + k], Vx[I * ncx + k], acc);
@@ -1503,7 +1499,10 @@ hipError_t launch_coarse_small(const Geo& g, const double* R, const double* Fx, 
                                const double* Vx, const double* Vy, const double* invLam,
                                double* E, hipStream_t s) {
   if (!coarse_small_fits(g)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coarse_small, dim3(g.batch), dim3(kBlock), 0, s, g.ncx, g.ncy, g.cplane, R,
+  // one thread per coarse cell (at least kBlock): the four products' dot products then run
+  // side by side rather than several after one another in each thread
+  const int cells = int(g.cplane), threads = std::max(kBlock, (cells + kWave - 1) / kWave * kWave);
+  hipLaunchKernelGGL(k_coarse_small, dim3(g.batch), dim3(threads), 0, s, g.ncx, g.ncy, g.cplane, R,
                      Fx, Fy, Vx, Vy, invLam, E);
   return hipGetLastError();
 }
