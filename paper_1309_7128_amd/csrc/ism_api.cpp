@@ -602,14 +602,15 @@ Geo coarse_geo(const Geo& g) {
   return gc;
 }
 
-// A device-checked iteration loop: iteration it (0, 1, ...) enqueues step(it), which also
-// leaves per-grid maxima of the residual of its incoming iterate in m, then a device-side
-// test against tol that records the first iteration at which every grid is below it (the
-// later steps then exit at once).  The host reads the state back once per batch of
-// iterations.  *stop_it: that iteration, or max_iter when none was below tol by then
-// (*converged false).
+// A device-checked iteration loop: iteration it (0, 1, ...) enqueues step(it, state, &part,
+// &count), which leaves per-tile maxima of the residual of its incoming iterate in part
+// (count per grid, grid k at k count), then one workgroup reduces them to the per-grid maxima
+// m and tests them against tol on the device, recording the first iteration at which every
+// grid is below it (the later steps then exit at once).  The host reads the state back once
+// per batch of iterations.  *stop_it: that iteration, or max_iter when none was below tol by
+// then (*converged false).
 template <typename Step>
-int device_checked_loop(ism_ctx* c, Step step, const double* m, double tol, int max_iter,
+int device_checked_loop(ism_ctx* c, Step step, double* m, double tol, int max_iter,
                         const char* what, int* stop_it, bool* converged) {
   const int B = c->g.batch;
   double* state = c->scal + size_t(STOP) * B;
@@ -619,9 +620,14 @@ int device_checked_loop(ism_ctx* c, Step step, const double* m, double tol, int 
   for (;;) {
     const int end = std::min(max_iter, it + batch - 1);
     for (; it <= end; ++it) {
-      int rcode = step(it, state);
+      const double* part = nullptr;
+      int count = 0;
+      int rcode = step(it, state, &part, &count);
       if (rcode) return rcode;
-      LAUNCH(c, ism::launch_stop_check(m, B, tol, it, state, at, c->stream));
+      hipError_t err = hipSuccess;
+      c->launches += ism::launch_max_stop(part, count, count, B, m, tol, it, state, at, c->fin,
+                                          c->stream, &err);
+      HIPCHK(c, err);
     }
     int rcode = read_scalars(c);
     if (rcode) return rcode;
@@ -658,7 +664,7 @@ int coarse_gs_loop(ism_ctx* c, const double* rc, double tol, int max_iter, doubl
   double* E[2] = {c->t1, c->t2};
   LAUNCH(c, ism::launch_fill(E[0], (long long)g.cplane * B, 0.0, s));
   double* m = c->scal + size_t(CMAX) * B;
-  auto step = [&](int it, const double* stop) {
+  auto step = [&](int it, const double* stop, const double** part, int* count) {
     if (mc) {
       hipError_t err = hipSuccess;
       c->launches += ism::launch_coarse_mc(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max,
@@ -668,7 +674,8 @@ int coarse_gs_loop(ism_ctx* c, const double* rc, double tol, int max_iter, doubl
       LAUNCH(c, ism::launch_coarse_bgs(g, c->coef, rc, E[it & 1], E[(it + 1) & 1], c->p_max, s,
                                        stop));
     }
-    LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
+    *part = c->p_max;
+    *count = tiles;
     return ISM_OK;
   };
   int it = 0;
@@ -755,20 +762,20 @@ int oneshot_solve(ism_ctx* c, const double* b, double* x, ism_stats* st) {
   double* zeroE = c->E;
   if (fused) LAUNCH(c, ism::launch_fill(zeroE, (long long)g.cplane * B, 0.0, s));
   double* m = c->scal + size_t(RMAX) * B;
-  auto step = [&](int i, const double* stop) {
+  auto step = [&](int i, const double* stop, const double** part, int* count) {
     if (!fused || i == 0) {
       hipEvent_t ev = prof_start(c, ISM_KERNEL_SMOOTH);
       LAUNCH(c, ism::launch_rbgs<T>(g, rhs, buf[i & 1], buf[(i + 1) & 1], s, T(1), c->p_max, stop));
       prof_stop(c, ISM_KERNEL_SMOOTH, ev);
-      LAUNCH(c, ism::launch_finalize(c->p_max, tiles, tiles, B, ism::MAX, 1.0, m, 1, 0, c->fin, s));
+      *count = tiles;
     } else {
       hipEvent_t ev = prof_start(c, ISM_KERNEL_CYCLE);
       LAUNCH(c, launch_fused<T>(c, rhs, buf[(i - 1) & 1], buf[i & 1], zeroE, c->rc, c->p_max, 1, 0,
                                 stop, 1));
       prof_stop(c, ISM_KERNEL_CYCLE, ev);
-      LAUNCH(c, ism::launch_finalize(c->p_max, int(g.cplane), g.cplane, B, ism::MAX, 1.0, m, 1, 0,
-                                     c->fin, s));
+      *count = int(g.cplane);
     }
+    *part = c->p_max;
     return ISM_OK;
   };
   int fi = 0;

@@ -43,7 +43,7 @@ struct Partials {
 // levels, so the product is exact).
 // With part_max, also max |rhs - A'e_in| per tile into part_max[grid][tile]
 // (rbgs_tiles(g) tiles per grid).  With stop, a device flag: the launch does nothing when
-// *stop != 0 (set by launch_stop_check).
+// *stop != 0 (set by launch_max_stop).
 template <typename T>
 hipError_t launch_rbgs(const Geo& g, const T* rhs, const T* e_in, T* e_out, hipStream_t s,
                        T rscale = T(1), double* part_max = nullptr, const double* stop = nullptr);
@@ -175,10 +175,14 @@ int launch_coarse_mc(const Geo& g, const double* coef, const double* R, const do
                      double* Eout, double* part_max, hipStream_t s, const double* stop,
                      hipError_t* err);
 
-// Device-side stop test of iteration iter: if *state is 0 and every m[0 .. batch) is below
-// tol (or any is not finite), sets *state to 1 (2) and *at to iter.  One thread.
-hipError_t launch_stop_check(const double* m, int batch, double tol, int iter, double* state,
-                             double* at, hipStream_t s);
+// m[k] = max of part[k part_stride .. + count) for every grid k (values as launch_finalize's
+// MAX), then the device-side stop test of iteration iter: if *state is 0 and every m[k] is
+// below tol (or any is not finite), *state becomes 1 (2) and *at iter.  One workgroup (after
+// launch_finalize's first stage into scratch when count exceeds one chunk).  Returns the
+// kernels enqueued; *err the first launch error.
+int launch_max_stop(const double* part, int count, long long part_stride, int batch, double* m,
+                    double tol, int iter, double* state, double* at, double* scratch,
+                    hipStream_t s, hipError_t* err);
 
 hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
                       hipStream_t s);

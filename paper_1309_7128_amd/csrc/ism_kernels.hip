@@ -1270,19 +1270,35 @@ __global__ __launch_bounds__(kBlock) void k_interp_tables(Geo g, double2* __rest
   }
 }
 
-// Device-side convergence test of an iteration whose per-grid maxima m[0 .. batch) were just
-// reduced: the first iteration at which every grid is below tol (or any value is not finite)
-// sets state to 1 (2) and records the iteration; later calls leave both alone.
-__global__ void k_stop_check(const double* __restrict__ m, int batch, double tol, int iter,
-                             double* __restrict__ state, double* __restrict__ at) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || *state != 0.0) return;
+// The per-grid maxima of an iteration's partials and its device-side convergence test in one
+// workgroup: m[k] = max of part[k stride .. k stride + count) for every grid k (strided per
+// thread, then a fixed tree, as k_finalize), then the first iteration at which every grid is
+// below tol (or any value is not finite) sets state to 1 (2) and records the iteration; later
+// iterations leave both alone.
+__global__ __launch_bounds__(kBlock) void k_max_stop(const double* __restrict__ part, int count,
+                                                     long long stride, int batch,
+                                                     double* __restrict__ m, double tol, int iter,
+                                                     double* __restrict__ state,
+                                                     double* __restrict__ at) {
+  __shared__ double sh[kBlock];
   bool all = true, bad = false;
   for (int k = 0; k < batch; ++k) {
-    const double v = m[k];
+    const double* p = part + (long long)k * stride;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) a = fmax(a, p[i]);
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+      __syncthreads();
+    }
+    const double v = sh[0];
+    if (threadIdx.x == 0) m[k] = v;
     bad = bad || !isfinite(v);
     all = all && v < tol;
+    __syncthreads();  // sh is reused by the next grid
   }
-  if (bad || all) {
+  if (threadIdx.x == 0 && *state == 0.0 && (bad || all)) {
     *state = bad ? 2.0 : 1.0;
     *at = double(iter);
   }
@@ -1507,10 +1523,24 @@ hipError_t launch_coarse_small(const Geo& g, const double* R, const double* Fx, 
   return hipGetLastError();
 }
 
-hipError_t launch_stop_check(const double* m, int batch, double tol, int iter, double* state,
-                             double* at, hipStream_t s) {
-  hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(kWave), 0, s, m, batch, tol, iter, state, at);
-  return hipGetLastError();
+int launch_max_stop(const double* part, int count, long long part_stride, int batch, double* m,
+                    double tol, int iter, double* state, double* at, double* scratch,
+                    hipStream_t s, hipError_t* err) {
+  const int chunks = (count + kChunk - 1) / kChunk;
+  int launched = 0;
+  if (chunks > 1) {  // first stage as launch_finalize's
+    hipLaunchKernelGGL(k_finalize, dim3(chunks, batch), dim3(kBlock), 0, s, part, count,
+                       part_stride, int(MAX), 1.0, scratch, 0, 0);
+    ++launched;
+    if ((*err = hipGetLastError()) != hipSuccess) return launched;
+    part = scratch;
+    count = chunks;
+    part_stride = chunks;
+  }
+  hipLaunchKernelGGL(k_max_stop, dim3(1), dim3(kBlock), 0, s, part, count, part_stride, batch, m,
+                     tol, iter, state, at);
+  *err = hipGetLastError();
+  return launched + 1;
 }
 
 hipError_t launch_div(const Geo& g, const double* u, const double* v, double h, double* b,
