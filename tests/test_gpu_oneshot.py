@@ -279,6 +279,31 @@ def test_oneshot_multicolour_matches_oracle(bx, by, n, prec):
         np.testing.assert_allclose(x, xo, rtol=0, atol=1e-9 * np.abs(xo).max())
 
 
+@pytest.mark.parametrize("prec,gs", [("fp64", "block"), ("mixed", "multicolour")])
+def test_oneshot_many_coarse_tiles_matches_oracle(prec, gs):
+    """320 x 256 at 4h: 5120 coarse tiles, so each fused fine pass leaves more per-tile maxima
+    than one reduction chunk (4096) and the criterion takes the two-stage reduction.  A
+    Dirichlet face: both counts exactly the oracle's."""
+    announce("oneshot_many_tiles", prec, gs)
+    nx, ny, n = 320, 256, 4
+    h = 1.0 / nx
+    b = _mac_rhs(415, nx, ny, h, D)
+    tol_c, tol_f = 1e-2 * np.abs(b).max(), 1e-3 * np.abs(b).max()
+    s = solver(nx=nx, ny=ny, coarsen=n, bc_x=D, bc_y=ND, cycling="oneshot", coarse_tol=tol_c,
+               fine_tol=tol_f, lx=1.0, precision=prec, coarse_gs=gs)
+    x, st = s.solve(dev(b))
+    xo, info = O.ism_solve_oneshot(b, h, n, D, ND, tol_c=tol_c, tol_f=tol_f,
+                                   block=bgs_block(nx // n, ny // n, D, ND),
+                                   precision="fp32" if prec == "mixed" else "fp64", coarse_gs=gs)
+    print(st, info, flush=True)
+    assert st["status"] == 0
+    assert st["coarse_iters"] == info["coarse_iters"] and st["fine_iters"] == info["fine_iters"]
+    assert st["coarse_syncs"] == info["ncc_c"]
+    x = host(x).reshape(ny, nx)
+    assert np.abs(b - O.laplacian(x, D, ND) / h**2).max() < (1.01 if prec == "mixed" else 1.0) * tol_f
+    np.testing.assert_allclose(x, xo, rtol=0, atol=1e-9 * np.abs(xo).max())
+
+
 def test_coarse_multicolour_gs_iteration_cap():
     announce("coarse_mcgs_cap")
     s = solver(nx=256, ny=256, coarsen=16, bc_x=D, bc_y=D, coarse_gs="multicolour")
