@@ -463,6 +463,29 @@ __global__ __launch_bounds__(kBlock) void k_tile_sum(Geo g, const double* __rest
 // workgroup per grid) reduces the chunk results when there is more than one chunk.
 constexpr int kChunk = 4096;
 
+// One thread's share of a strided reduction: a = op(a, p[i]) for i = first, first + kBlock,
+// ... below end, in that order.  The loads of kChunk / kBlock consecutive terms are all issued
+// before the first of them is combined, so the thread waits on memory once per group instead
+// of once per term; the result is the same as term by term.
+__device__ __forceinline__ double strided_reduce(const double* __restrict__ p, int first, int end,
+                                                 bool is_max) {
+  constexpr int K = kChunk / kBlock;
+  double a = 0.0;
+  for (int base = first; base < end; base += K * kBlock) {
+    double v[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int i = base + j * kBlock;
+      v[j] = i < end ? p[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (base + j * kBlock < end) a = is_max ? fmax(a, v[j]) : a + v[j];
+    }
+  }
+  return a;
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ part, int count,
                                                      long long stride, int op, double scale,
                                                      double* __restrict__ out, int out_stride,
@@ -470,9 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
   __shared__ double sh[kBlock];
   const double* p = part + (long long)blockIdx.y * stride;
   const int lo = blockIdx.x * kChunk, hi = min(count, lo + kChunk);
-  double a = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += kBlock) a = op == MAX ? fmax(a, p[i]) : a + p[i];
-  sh[threadIdx.x] = a;
+  sh[threadIdx.x] = strided_reduce(p, lo + int(threadIdx.x), hi, op == MAX);
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
@@ -1284,9 +1305,7 @@ __global__ __launch_bounds__(kBlock) void k_max_stop(const double* __restrict__ 
   bool all = true, bad = false;
   for (int k = 0; k < batch; ++k) {
     const double* p = part + (long long)k * stride;
-    double a = 0.0;
-    for (int i = threadIdx.x; i < count; i += kBlock) a = fmax(a, p[i]);
-    sh[threadIdx.x] = a;
+    sh[threadIdx.x] = strided_reduce(p, int(threadIdx.x), count, true);
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
