@@ -80,6 +80,7 @@ struct ism_ctx {
   // device and read back synchronously when the check is acted on.
   bool pinned = true;
   double* d_chk = nullptr;    // device check slots [kChecks][batch]
+  double* d_hchk = nullptr;   // device address of the pinned h_chk (hipHostGetDevicePointer)
   std::vector<double> h_mem;  // pageable h_scal when not pinned
   std::vector<hipEvent_t> chk_ev;  // one per check slot (created on first use)
   // ACM hierarchy (coarse_stencil == ISM_COARSE_ACM): per level l = 1..L-1 the agglomerated
@@ -476,15 +477,12 @@ int inner_solve(ism_ctx* c, const std::vector<double>& target, int& cycles, T** 
     ++k;
     ++cycles;
     if (due) {
-      if ((rcode = finalize(c, c->p_sq, ism::SUM, 1.0, ISQ))) return rcode;
-      if (c->pinned) {
-        HIPCHK(c, hipMemcpyAsync(c->h_chk + size_t(slot) * B, c->scal + size_t(ISQ) * B,
-                                 sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipEventRecord(c->chk_ev[slot], c->stream));
-      } else {
-        HIPCHK(c, hipMemcpyAsync(c->d_chk + size_t(slot) * B, c->scal + size_t(ISQ) * B,
-                                 sizeof(double) * B, hipMemcpyDeviceToDevice, c->stream));
-      }
+      // the check's norms are reduced straight into its read-back slot: the pinned host
+      // slot through its device address, or the device slot
+      double* dst = (c->pinned ? c->d_hchk : c->d_chk) + size_t(slot) * B;
+      LAUNCH(c, ism::launch_finalize(c->p_sq, int(c->g.cplane), c->g.cplane, B, ism::SUM, 1.0,
+                                     dst, 1, 0, c->fin, c->stream));
+      if (c->pinned) HIPCHK(c, hipEventRecord(c->chk_ev[slot], c->stream));
       pend.push_back({k, cycles, slot});
       slot = (slot + 1) % kChecks;
       sched = k + gap;  // provisional, until this check's own evaluation reschedules
@@ -1147,6 +1145,18 @@ int ism_create(const ism_config* cfg, void* stream, ism_handle* out) {
     (void)hipFree(c->block);
     delete c;
     return set_err(nullptr, ISM_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(he));
+  }
+  {
+    double* dh = nullptr;
+    he = hipHostGetDevicePointer((void**)&dh, c->h_scal, 0);
+    if (he != hipSuccess || !dh) {
+      (void)hipHostFree(c->h_scal);
+      (void)hipFree(c->block);
+      delete c;
+      return set_err(nullptr, ISM_ERR_HIP,
+                     std::string("hipHostGetDevicePointer: ") + hipGetErrorString(he));
+    }
+    c->d_hchk = dh + size_t(kSlots) * g.batch;
   }
 
   auto align = [](size_t n) { return (n + 255) & ~size_t(255); };
