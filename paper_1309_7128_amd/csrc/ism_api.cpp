@@ -431,8 +431,8 @@ struct Monitor {
 // its target, or the residual stagnates, or the cycle cap is reached.  rc holds R rT on entry.
 //
 // With a fixed check interval every check stops the stream and is evaluated at once.  With
-// adaptive checks the stream never waits on the host: a check's norms are copied to a pinned
-// slot behind an event and the host keeps enqueuing cycles, evaluating each check after
+// adaptive checks the stream never waits on the host: a check's norms are reduced into a
+// pinned slot behind an event and the host keeps enqueuing cycles, evaluating each check after
 // exactly kLag more cycles (waiting for its event then).  A stop decision therefore lands
 // kLag cycles late; the cycles already enqueued only reduce the residual further and are
 // counted.  The squared-residual partials are formed only by the cycles a
