@@ -460,7 +460,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_sum(Geo g, const double* __rest
 
 // Second reduction stage: the partials of each grid are reduced in chunks of kChunk by
 // gridDim.x workgroups, in a fixed order (reproducible); a further pass (same kernel, one
-// workgroup per grid) reduces the chunk results when there is more than one chunk.
+// workgroup per grid, over all the chunk results however many there are) reduces them when
+// there is more than one chunk.
 constexpr int kChunk = 4096;
 
 // One thread's share of a strided reduction: a = op(a, p[i]) for i = first, first + kBlock,
@@ -492,7 +493,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
                                                      int slot) {
   __shared__ double sh[kBlock];
   const double* p = part + (long long)blockIdx.y * stride;
-  const int lo = blockIdx.x * kChunk, hi = min(count, lo + kChunk);
+  // one workgroup per grid (a single stage, or the pass over the chunk results) takes every
+  // term, however many chunks the first stage made
+  const int lo = blockIdx.x * kChunk, hi = gridDim.x == 1 ? count : min(count, lo + kChunk);
   sh[threadIdx.x] = strided_reduce(p, lo + int(threadIdx.x), hi, op == MAX);
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {

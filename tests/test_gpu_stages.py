@@ -246,6 +246,24 @@ def test_outer_residual(case):
         np.testing.assert_allclose(r[k], ref, rtol=0, atol=1e-14 * np.abs(ref).max())
 
 
+def test_reduction_over_more_than_4096_chunks():
+    """Grid means and norms are reduced in two stages: chunks of 4096 coarse-tile partials,
+    then one workgroup per grid over the chunk results.  16400^2 cells at 4h make 4100^2
+    tiles, 4105 chunks, and the second stage has to take all of them.  With b constant and
+    x = 0 the outer residual h^2 (b - mean b) - A' x is zero up to the rounding of the mean;
+    a chunk left out of the mean would leave h^2 times about 2e-3 in every cell."""
+    n = 16400
+    announce("reduction_4105_chunks", n)
+    s = solver(nx=n, ny=n, coarsen=4)
+    b = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    r = s.outer_residual(b, x)
+    torch.cuda.synchronize()
+    worst = float(r.abs().max())
+    del r, b, x, s
+    assert worst <= 4 * np.finfo(np.float64).eps * (1.0 / n) ** 2, worst
+
+
 @pytest.mark.parametrize("bx,by", [(N, N), (P, N), (D, D), (ND, DN), (P, ND)])
 def test_mac_operators_bitwise(bx, by):
     announce("mac", bx, by)
