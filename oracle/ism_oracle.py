@@ -662,8 +662,9 @@ class CoarseSolver:
     def gauss_seidel(self, Rc, E0=None, tol_c=1e-6, max_iter=100000):
         """Lexicographic Gauss-Seidel on A_c E = R_c until the absolute maximum residual is
         below tol_c (Sec. 4: block-iterative GS on the host, which reduces to serial GS on
-        one node; Sec. 4.3.1 accommodative criterion).  Returns (E, iterations).  Parity
-        unpinned (an option of the oracle, not used by the library)."""
+        one node; Sec. 4.3.1 accommodative criterion).  Returns (E, iterations).  An option of
+        the oracle's ISM solve, not used by the library; pinned by Gauss-Seidel written row by
+        row on the dense assembled matrix."""
         A = self.Ac
         b = np.asarray(Rc, dtype=np.float64).ravel()
         if self.singular:

@@ -523,6 +523,42 @@ def test_coarse_gauss_seidel_option():
     assert it > 1
 
 
+@pytest.mark.parametrize("bcx,bcy", [(N, N), (D, N), (P, ND)])
+@pytest.mark.parametrize("iters", [1, 3])
+def test_coarse_gauss_seidel_is_the_lexicographic_loop(bcx, bcy, iters):
+    """The oracle's plain coarse GS option against Gauss-Seidel from its definition: row i
+    of A_c E = R_c solved for E_i in index order, with the newest values of every other
+    unknown, on the dense assembled matrix (without a Dirichlet face R_c is first projected
+    to zero mean and the result returned with zero mean)."""
+    ncx, ncy, n = 6, 5, 8
+    C = O.coarse_stencil_ism(ncx, ncy, n, bcx, bcy)
+    Ac = O.coarse_matrix(C, bcx, bcy)
+    cs = O.CoarseSolver(Ac)
+    Rc = np.random.default_rng(16).standard_normal((ncy, ncx))
+    E, it = cs.gauss_seidel(Rc, tol_c=0.0, max_iter=iters)
+    assert it == iters
+    A = Ac.toarray()
+    b = Rc.ravel() - (Rc.mean() if cs.singular else 0.0)
+    e = np.zeros(A.shape[0])
+    for _ in range(iters):
+        for i in range(A.shape[0]):
+            off = sum(A[i, j] * e[j] for j in range(A.shape[0]) if j != i)
+            e[i] = (b[i] - off) / A[i, i]
+    if cs.singular:
+        e = e - e.mean()
+    np.testing.assert_allclose(E.ravel(), e, rtol=0, atol=1e-12 * np.abs(e).max())
+
+
+def test_coarse_gauss_seidel_stops_before_iterating_when_already_below_tolerance():
+    Ac = O.coarse_matrix(O.coarse_stencil_ism(4, 4, 8, D, N), D, N)
+    cs = O.CoarseSolver(Ac)
+    Rc = np.random.default_rng(17).standard_normal((4, 4))
+    E0 = cs.solve(Rc)
+    E, it = cs.gauss_seidel(Rc, E0=E0, tol_c=1e-8)
+    assert it == 0
+    np.testing.assert_array_equal(E, E0)
+
+
 def _blockgs_loop(C, R, block, iters, bcx, bcy):
     """Block-iterative GS written cell by cell: tiles in any order (they only read the
     previous iteration outside themselves), lexicographic inside a tile."""
