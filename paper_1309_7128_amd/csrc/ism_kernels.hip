@@ -533,7 +533,8 @@ __global__ __launch_bounds__(kBlock) void k_sub_scalar(long long plane, int batc
 // Small batched FP64 GEMM for the separable coarse solve: C = op(A) op(B) [.* S].
 // A 16 x 16 output tile per workgroup (a 256 x 256 product spreads over 256 workgroups, one
 // per CU).  The whole K panel of A and B (up to 256 deep per pass) is loaded in one batch so
-// that all loads are in flight together; the 4 waves then each accumulate a quarter of K on
+// that all loads are in flight together, the next panel's while the current one is being
+// multiplied; the 4 waves each accumulate a quarter of K on
 // the matrix cores (V_MFMA_F64_16X16X4F64: a 16 x 4 by 4 x 16 product per instruction) and
 // the quarters are added in wave order through LDS.
 // ----------------------------------------------------------------------------------------
@@ -560,11 +561,11 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
   typedef double Vec4d __attribute__((ext_vector_type(4)));
   Vec4d acc = {0.0, 0.0, 0.0, 0.0};
   constexpr int PER = kGemmTile * kGemmK / kBlock;  // panel elements per thread and operand
-  for (int k0 = 0; k0 < K; k0 += kGemmK) {
+  // every load of both panels is issued before any is stored, so that one memory latency
+  // covers the whole panel; loads are coalesced along the contiguous index of the matrix
+  double ra[PER], rb[PER];
+  auto load_panel = [&](int k0) {
     const int kc = min(kGemmK, K - k0);
-    // every load of both panels is issued before any is stored, so that one memory latency
-    // covers the whole panel; loads are coalesced along the contiguous index of the matrix
-    double ra[PER], rb[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int t = threadIdx.x + i * kBlock;
@@ -583,6 +584,10 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
                                    : 0.0;
       }
     }
+  };
+  load_panel(0);
+  for (int k0 = 0; k0 < K; k0 += kGemmK) {
+    const int kc = min(kGemmK, K - k0);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int t = threadIdx.x + i * kBlock;
@@ -590,6 +595,8 @@ __global__ __launch_bounds__(kBlock) void k_gemm(int M, int N, int K, const doub
       Bs[TB ? (t & (kGemmK - 1)) : (t / kGemmTile)][TB ? (t / kGemmK) : (t & (kGemmTile - 1))] = rb[i];
     }
     __syncthreads();
+    // the next panel's loads are in flight while this one runs on the matrix cores
+    if (k0 + kGemmK < K) load_panel(k0 + kGemmK);
     // this wave's quarter of the panel, in steps of 4 (rows past kc hold zeros)
     const int q = (kc + 15) / 16 * 4;
     const int ka = wave * q;
